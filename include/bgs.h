@@ -1,0 +1,225 @@
+/*
+ * bgs.h - C ABI of the MI355X (gfx950) balanced 3DGS tile rasterizer.
+ *
+ * The library renders 3D Gaussian splats with the tile-based pipeline of
+ * Balanced 3DGS (Gui et al., arXiv 2412.17378):
+ *
+ *   bgs_project  -> bgs_bin -> bgs_sort -> bgs_ranges -> bgs_render_fwd
+ *                                                      -> bgs_render_bwd
+ *
+ * and its load-balanced forward renderer: a persistent work queue of
+ * sub-tiles fed by a global atomic counter (Sec. 4.1, 4.3), pixel-wise and
+ * Gaussian-wise wavefront modes (Sec. 4.2), a static one-workgroup-per-tile
+ * baseline (Sec. 5.2.1, naive kernel) and a timing-based variant selector
+ * (Sec. 4.4).
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller, unless a
+ *     comment says "host".  The library allocates no device memory inside a
+ *     call except where noted (bgs_plan_*); scratch comes from a caller
+ *     workspace sized by the matching *_workspace_bytes function.
+ *   - Every call enqueues work on `stream` and returns without waiting,
+ *     except where a comment says it synchronizes.
+ *   - Floating point is IEEE fp32; indices are 32-bit unsigned.
+ *   - Errors: a non-zero bgs_status; no exception crosses the ABI;
+ *     bgs_last_error() gives a thread-local message.  Invalid sizes or a
+ *     missing required pointer -> BGS_EINVAL; a HIP runtime failure ->
+ *     BGS_EHIP; an output too small for the data -> BGS_ECAPACITY.
+ *   - Images are planar: colour [3][H][W], single channels [H][W], row-major.
+ *   - Pixel (px, py) is sampled at integer coordinates (px, py).
+ */
+#ifndef BGS_H
+#define BGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bgs_status {
+    BGS_OK = 0,
+    BGS_EINVAL = -1,
+    BGS_ECAPACITY = -2,
+    BGS_EHIP = -3,
+    BGS_EUNSUPPORTED = -4,
+    BGS_EINTERNAL = -5
+} bgs_status;
+
+/* Pinhole camera, HOST memory.  camera = R * world + t, R row-major.
+ * Pixel centre of the camera ray (x, y, z) is (fx x/z + cx - 1/2, fy y/z + cy - 1/2).
+ * Gaussians with camera depth z <= znear are culled. */
+typedef struct bgs_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float znear;
+} bgs_camera;
+
+/* Render inputs of one view (Alg. 1-4 inputs XY, PL, CO, F, D), HOST struct
+ * holding DEVICE pointers.  P Gaussians, n_tiles = ceil(W/tile)*ceil(H/tile). */
+typedef struct bgs_frame {
+    int32_t width, height;        /* image size in pixels, >= 1 */
+    int32_t tile;                 /* binning tile edge in pixels: 16 */
+    const uint32_t* ranges;       /* [n_tiles][2] start, end into point_list */
+    const uint32_t* point_list;   /* [n_pairs] Gaussian ids, per tile front to back */
+    const float* means2D;         /* [P][2] pixel-space centre (XY) */
+    const float* conic_opacity;   /* [P][4] (a, b, c, o): inverse 2D covariance
+                                     [[a, b], [b, c]] and opacity (CO) */
+    const float* rgb;             /* [P][3] colour (F) */
+    const float* depth;           /* [P] camera depth (D) */
+} bgs_frame;
+
+/* Forward / backward kernel variants. */
+typedef enum bgs_variant {
+    BGS_STATIC = 0,           /* one 256-lane workgroup per 16x16 tile, grid-static */
+    BGS_BALANCED_PIXEL = 1,   /* persistent waves, atomic sub-tile queue, lane = pixel */
+    BGS_BALANCED_GAUSS = 2,   /* persistent waves, atomic sub-tile queue, lane = Gaussian */
+    BGS_BALANCED_HYBRID = 3   /* lane = pixel, stragglers finished lane = Gaussian */
+} bgs_variant;
+
+/* Queue order of the balanced variants. */
+typedef enum bgs_order {
+    BGS_ORDER_RASTER = 0,     /* sub-tiles in raster order */
+    BGS_ORDER_COST = 1        /* heaviest estimated sub-tile first */
+} bgs_order;
+
+/* Flags of bgs_render_cfg. */
+enum {
+    /* the workspace already holds a queue from bgs_queue_build for this frame
+       and cfg (with the counter reset); render calls then skip building it */
+    BGS_FLAG_QUEUE_READY = 1
+};
+
+typedef struct bgs_render_cfg {
+    int32_t variant;          /* bgs_variant */
+    int32_t subtile;          /* balanced variants: sub-tile edge, 8 (one wave) */
+    int32_t order;            /* bgs_order */
+    int32_t flags;            /* BGS_FLAG_* */
+    float bg[3];              /* background colour */
+} bgs_render_cfg;
+
+/* Thread-local text for the last non-OK status of this thread. */
+const char* bgs_last_error(void);
+
+/* Library version string. */
+const char* bgs_version(void);
+
+/*
+ * Projection, Eq. (1)-(3) (Sec. 2.1).  Per Gaussian i < P: camera transform,
+ * 3D covariance R_q diag(exp(2 s)) R_q^T from log-scales s and the unit
+ * quaternion (w, x, y, z), EWA covariance J W Sigma W^T J^T + 0.3 I (J
+ * evaluated with x/z, y/z clamped to 1.3x the half field of view), its
+ * inverse (conic), radius = ceil(3 sqrt(lambda_max)), colour, and the number
+ * of tile x tile tiles its square [u-r, u+r] x [v-r, v+r] meets.
+ *   means3D [P][3], log_scales [P][3], quats [P][4], opacity [P].
+ *   colors: sh_degree < 0 -> RGB [P][3] used as is;
+ *           0..3 -> SH coefficients [P][(d+1)^2][3], colour =
+ *           max(0, sum_lm k_lm Y_lm(ray) + 1/2), Y_lm the real spherical
+ *           harmonics without Condon-Shortley phase, index l*l + l + m.
+ *   Outputs: means2D [P][2], conic_opacity [P][4], rgb [P][3], depth [P],
+ *   radius [P] (0 = culled), tiles_touched [P].  Culled Gaussians get
+ *   radius 0 and tiles_touched 0.
+ */
+bgs_status bgs_project(const bgs_camera* cam, int64_t P, const float* means3D, const float* log_scales,
+                       const float* quats, const float* opacity, const float* colors, int32_t sh_degree,
+                       int32_t tile, float* means2D, float* conic_opacity, float* rgb, float* depth,
+                       int32_t* radius, uint32_t* tiles_touched, hipStream_t stream);
+
+/* Workspace bytes for bgs_bin with P Gaussians. */
+size_t bgs_bin_workspace_bytes(int64_t P);
+
+/*
+ * Tile binning (the pre-processing "patch" step of Sec. 4.3, producing the
+ * sorted point list PL of Alg. 1-4).  Emits one (tile id, Gaussian id) pair
+ * for every tile a Gaussian's square meets, Gaussians visited in increasing
+ * depth (ties: increasing id), so a later stable sort by tile id yields, per
+ * tile, the front-to-back order Eq. (4) needs.
+ *   keys [capacity] tile ids, values [capacity] Gaussian ids.
+ *   *n_pairs_host (HOST) receives the pair count M.  This call SYNCHRONIZES
+ *   the stream to read M; if M > capacity nothing is written to keys/values
+ *   and BGS_ECAPACITY is returned (M still reported).
+ */
+bgs_status bgs_bin(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
+                   const int32_t* radius, const float* depth, const uint32_t* tiles_touched, uint32_t* keys,
+                   uint32_t* values, int64_t capacity, int64_t* n_pairs_host, void* ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/* Workspace bytes for bgs_sort of n pairs. */
+size_t bgs_sort_workspace_bytes(int64_t n);
+
+/*
+ * Stable ascending sort of n (key, value) pairs by the low key_bits bits of
+ * the key (1..32).  Input and output buffers must not alias.
+ */
+bgs_status bgs_sort(const uint32_t* keys_in, const uint32_t* values_in, uint32_t* keys_out,
+                    uint32_t* values_out, int64_t n, int32_t key_bits, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/*
+ * Per-tile [start, end) of a key array sorted by tile id (the range of PL a
+ * tile's workgroup walks, Alg. 1 "Load XY, PL, CO").  ranges [n_tiles][2];
+ * empty tiles get (0, 0).
+ */
+bgs_status bgs_ranges(const uint32_t* sorted_keys, int64_t n, int32_t n_tiles, uint32_t* ranges,
+                      hipStream_t stream);
+
+/* Workspace bytes for bgs_queue_build / bgs_render_fwd / bgs_render_bwd. */
+size_t bgs_render_workspace_bytes(const bgs_frame* frame, const bgs_render_cfg* cfg);
+
+/*
+ * Task pool of the balanced renderer (Sec. 4.1 steps 1-4, Sec. 4.3): writes
+ * the sub-tile work items of `frame` into the workspace in the order
+ * cfg->order asks for and resets the global fetch counter.  For
+ * BGS_ORDER_COST the forward cost estimate of a sub-tile is its tile's list
+ * length; when n_contrib (nullable, [H][W] from the forward pass) is given the
+ * cost is the largest n_contrib in the sub-tile (the backward's exact walk).
+ * bgs_render_fwd / bgs_render_bwd call this themselves.
+ */
+bgs_status bgs_queue_build(const bgs_frame* frame, const bgs_render_cfg* cfg, const int32_t* n_contrib,
+                           void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Forward render, Eq. (4) per pixel front to back with the rules of the
+ * paper's naive per-pixel loop (Appendix): an entry is skipped when its
+ * exponent is positive or alpha = min(0.99, o exp(power)) < 1/255; the pixel
+ * stops, without blending the entry, once T (1 - alpha) < 1e-4.
+ *   out_color [3][H][W] = sum rgb alpha T + T_final bg
+ *   out_alpha [H][W]    = 1 - T_final   (= sum alpha T)
+ *   out_depth [H][W]    = sum depth alpha T
+ *   final_T   [H][W]    = T_final
+ *   n_contrib [H][W]    = 1 + list position of the last blended entry (0 if none)
+ * The variant in cfg only changes speed; all variants give the same result up
+ * to fp32 rounding.
+ */
+bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cfg* cfg, float* out_color, float* out_alpha,
+                          float* out_depth, float* final_T, int32_t* n_contrib, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/*
+ * Backward render: the derivative of bgs_render_fwd for
+ * L = <dL_dcolor, out_color> + <dL_dalpha, out_alpha> + <dL_ddepth, out_depth>
+ * with every skip / stop decision of the forward held fixed.  Per pixel it
+ * walks the list back to front from n_contrib, recovering T by division
+ * T_{k-1} = T_k / (1 - alpha_k) from final_T.  Gradients are ADDED (+=) into
+ * the caller's buffers (zero them first):
+ *   dL_dmeans2D [P][2]; dL_dconic_opacity [P][4] laid out like
+ *   conic_opacity: d/da, d/db, d/dc of power = -(a dx^2 + c dy^2)/2 - b dx dy,
+ *   then d/do; dL_drgb [P][3]; dL_ddepths [P] (nullable).
+ * dL_dalpha and dL_ddepth are nullable (zero).  final_T and n_contrib are the
+ * forward's outputs for the same frame.
+ */
+bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cfg* cfg, const float* final_T,
+                          const int32_t* n_contrib, const float* dL_dcolor, const float* dL_dalpha,
+                          const float* dL_ddepth, float* dL_dmeans2D, float* dL_dconic_opacity, float* dL_drgb,
+                          float* dL_ddepths, void* ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BGS_H */

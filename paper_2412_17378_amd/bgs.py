@@ -1,0 +1,257 @@
+"""ctypes binding of libbgs.so (include/bgs.h): the same entry points, taking
+torch CUDA tensors.  Argument marshalling only: every step runs in the HIP
+library; this module checks shapes/dtypes, passes device pointers and the
+current HIP stream, and turns a non-OK status into BgsError.
+
+The library must be built (``python -m paper_2412_17378_amd.build``); when it
+is missing, importing the binding's loader raises instead of falling back to
+anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbgs.so")
+
+BGS_OK, BGS_EINVAL, BGS_ECAPACITY, BGS_EHIP, BGS_EUNSUPPORTED, BGS_EINTERNAL = 0, -1, -2, -3, -4, -5
+STATIC, BALANCED_PIXEL, BALANCED_GAUSS, BALANCED_HYBRID = 0, 1, 2, 3
+ORDER_RASTER, ORDER_COST = 0, 1
+FLAG_QUEUE_READY = 1
+TILE = 16
+
+VARIANTS = {"static": STATIC, "pixel": BALANCED_PIXEL, "gauss": BALANCED_GAUSS, "hybrid": BALANCED_HYBRID}
+ORDERS = {"raster": ORDER_RASTER, "cost": ORDER_COST}
+
+
+class BgsError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} failed with status {status}: {msg}")
+        self.status = status
+
+
+class Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("R", C.c_float * 9), ("t", C.c_float * 3),
+                ("znear", C.c_float)]
+
+
+class Frame(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("tile", C.c_int32),
+                ("ranges", C.c_void_p), ("point_list", C.c_void_p), ("means2D", C.c_void_p),
+                ("conic_opacity", C.c_void_p), ("rgb", C.c_void_p), ("depth", C.c_void_p)]
+
+
+class RenderCfg(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("subtile", C.c_int32), ("order", C.c_int32), ("flags", C.c_int32),
+                ("bg", C.c_float * 3)]
+
+
+_LIB = None
+_vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2412_17378_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "bgs_last_error": ([], C.c_char_p),
+            "bgs_version": ([], C.c_char_p),
+            "bgs_project": ([_vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+                            C.c_int),
+            "bgs_bin_workspace_bytes": ([_i64], _sz),
+            "bgs_bin": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp], C.c_int),
+            "bgs_sort_workspace_bytes": ([_i64], _sz),
+            "bgs_sort": ([_vp, _vp, _vp, _vp, _i64, _i32, _vp, _sz, _vp], C.c_int),
+            "bgs_ranges": ([_vp, _i64, _i32, _vp, _vp], C.c_int),
+            "bgs_render_workspace_bytes": ([_vp, _vp], _sz),
+            "bgs_queue_build": ([_vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
+            "bgs_render_fwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
+            "bgs_render_bwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = L
+    return _LIB
+
+
+def exported_symbols():
+    """Names the header declares (used by the load test)."""
+    return ["bgs_last_error", "bgs_version", "bgs_project", "bgs_bin_workspace_bytes", "bgs_bin",
+            "bgs_sort_workspace_bytes", "bgs_sort", "bgs_ranges", "bgs_render_workspace_bytes", "bgs_queue_build",
+            "bgs_render_fwd", "bgs_render_bwd"]
+
+
+def _check(fn: str, st: int):
+    if st != BGS_OK:
+        raise BgsError(fn, st, lib().bgs_last_error().decode(errors="replace"))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _expect(t, shape, dtype, name):
+    if t is None:
+        return
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+        raise ValueError(f"{name}: expected {tuple(shape)} {dtype}, got {tuple(t.shape)} {t.dtype}")
+
+
+def make_camera(cam) -> Camera:
+    c = Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = [float(x) for x in list(getattr(cam.R, "reshape")(9))]
+    t = [float(x) for x in list(getattr(cam.t, "reshape")(3))]
+    for k in range(9):
+        c.R[k] = R[k]
+    for k in range(3):
+        c.t[k] = t[k]
+    c.znear = float(getattr(cam, "znear", 0.2))
+    return c
+
+
+def make_cfg(variant="pixel", subtile: int = 8, order="raster", bg=(0.0, 0.0, 0.0), flags: int = 0) -> RenderCfg:
+    c = RenderCfg()
+    c.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    c.subtile = int(subtile)
+    c.order = ORDERS[order] if isinstance(order, str) else int(order)
+    c.flags = int(flags)
+    for k in range(3):
+        c.bg[k] = float(bg[k])
+    return c
+
+
+def n_tiles(width: int, height: int) -> int:
+    return ((width + TILE - 1) // TILE) * ((height + TILE - 1) // TILE)
+
+
+def make_frame(width, height, ranges, point_list, means2D, conic_opacity, rgb, depth) -> Frame:
+    P = means2D.shape[0]
+    _expect(ranges, (n_tiles(width, height), 2), torch.int32, "ranges")
+    _expect(means2D, (P, 2), torch.float32, "means2D")
+    _expect(conic_opacity, (P, 4), torch.float32, "conic_opacity")
+    _expect(rgb, (P, 3), torch.float32, "rgb")
+    _expect(depth, (P,), torch.float32, "depth")
+    if point_list.dtype != torch.int32 or point_list.dim() != 1:
+        raise ValueError("point_list must be a 1-D int32 tensor")
+    f = Frame()
+    f.width, f.height, f.tile = int(width), int(height), TILE
+    # a frame with no pairs still needs a valid pointer
+    pl = point_list if point_list.numel() > 0 else ranges
+    f.ranges, f.point_list = _ptr(ranges), _ptr(pl)
+    f.means2D, f.conic_opacity, f.rgb, f.depth = _ptr(means2D), _ptr(conic_opacity), _ptr(rgb), _ptr(depth)
+    return f
+
+
+# ------------------------------------------------------------------ calls
+def bgs_project(cam, means3D, log_scales, quats, opacity, colors, sh_degree: int, means2D, conic_opacity, rgb,
+                depth, radius, tiles_touched, stream=None):
+    P = means3D.shape[0]
+    _expect(means3D, (P, 3), torch.float32, "means3D")
+    _expect(log_scales, (P, 3), torch.float32, "log_scales")
+    _expect(quats, (P, 4), torch.float32, "quats")
+    _expect(opacity, (P,), torch.float32, "opacity")
+    ncol = 3 if sh_degree < 0 else 3 * (sh_degree + 1) ** 2
+    if colors.numel() != P * ncol or colors.dtype != torch.float32:
+        raise ValueError("colors: wrong size or dtype")
+    _expect(means2D, (P, 2), torch.float32, "means2D")
+    _expect(conic_opacity, (P, 4), torch.float32, "conic_opacity")
+    _expect(radius, (P,), torch.int32, "radius")
+    _expect(tiles_touched, (P,), torch.int32, "tiles_touched")
+    c = make_camera(cam) if not isinstance(cam, Camera) else cam
+    _check("bgs_project", lib().bgs_project(C.byref(c), P, _ptr(means3D), _ptr(log_scales), _ptr(quats),
+                                            _ptr(opacity), _ptr(colors), int(sh_degree), TILE, _ptr(means2D),
+                                            _ptr(conic_opacity), _ptr(rgb), _ptr(depth), _ptr(radius),
+                                            _ptr(tiles_touched), _stream(stream)))
+
+
+def bgs_bin_workspace_bytes(P: int) -> int:
+    return int(lib().bgs_bin_workspace_bytes(int(P)))
+
+
+def bgs_bin(width, height, means2D, radius, depth, tiles_touched, keys, values, ws, stream=None) -> int:
+    """Returns the pair count M.  Synchronizes the stream.  Raises BgsError
+    with status BGS_ECAPACITY (and .n_pairs) when keys/values are too small."""
+    P = means2D.shape[0]
+    n = C.c_int64(0)
+    cap = 0 if keys is None else keys.numel()
+    st = lib().bgs_bin(int(width), int(height), TILE, P, _ptr(means2D), _ptr(radius), _ptr(depth),
+                       _ptr(tiles_touched), _ptr(keys) if cap else None, _ptr(values) if cap else None, cap,
+                       C.byref(n), _ptr(ws), ws.numel(), _stream(stream))
+    if st == BGS_ECAPACITY:
+        e = BgsError("bgs_bin", st, lib().bgs_last_error().decode())
+        e.n_pairs = int(n.value)
+        raise e
+    _check("bgs_bin", st)
+    return int(n.value)
+
+
+def bgs_sort_workspace_bytes(n: int) -> int:
+    return int(lib().bgs_sort_workspace_bytes(int(n)))
+
+
+def bgs_sort(keys_in, values_in, keys_out, values_out, n: int, key_bits: int, ws, stream=None):
+    _check("bgs_sort", lib().bgs_sort(_ptr(keys_in), _ptr(values_in), _ptr(keys_out), _ptr(values_out), int(n),
+                                      int(key_bits), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def bgs_ranges(sorted_keys, n: int, n_tiles_: int, ranges, stream=None):
+    _check("bgs_ranges", lib().bgs_ranges(_ptr(sorted_keys) if n > 0 else None, int(n), int(n_tiles_),
+                                          _ptr(ranges), _stream(stream)))
+
+
+def bgs_render_workspace_bytes(frame: Frame, cfg: RenderCfg) -> int:
+    return int(lib().bgs_render_workspace_bytes(C.byref(frame), C.byref(cfg)))
+
+
+def bgs_queue_build(frame: Frame, cfg: RenderCfg, n_contrib, ws, stream=None):
+    _check("bgs_queue_build", lib().bgs_queue_build(C.byref(frame), C.byref(cfg), _ptr(n_contrib), _ptr(ws),
+                                                    ws.numel(), _stream(stream)))
+
+
+def bgs_render_fwd(frame: Frame, cfg: RenderCfg, out_color, out_alpha, out_depth, final_T, n_contrib, ws,
+                   stream=None):
+    H, W = frame.height, frame.width
+    _expect(out_color, (3, H, W), torch.float32, "out_color")
+    for t, nm in ((out_alpha, "out_alpha"), (out_depth, "out_depth"), (final_T, "final_T")):
+        _expect(t, (H, W), torch.float32, nm)
+    _expect(n_contrib, (H, W), torch.int32, "n_contrib")
+    _check("bgs_render_fwd", lib().bgs_render_fwd(C.byref(frame), C.byref(cfg), _ptr(out_color), _ptr(out_alpha),
+                                                  _ptr(out_depth), _ptr(final_T), _ptr(n_contrib), _ptr(ws),
+                                                  ws.numel(), _stream(stream)))
+
+
+def bgs_render_bwd(frame: Frame, cfg: RenderCfg, final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dmeans2D,
+                   dL_dconic_opacity, dL_drgb, dL_ddepths, ws, stream=None):
+    H, W = frame.height, frame.width
+    _expect(final_T, (H, W), torch.float32, "final_T")
+    _expect(n_contrib, (H, W), torch.int32, "n_contrib")
+    _expect(dL_dcolor, (3, H, W), torch.float32, "dL_dcolor")
+    _expect(dL_dalpha, (H, W), torch.float32, "dL_dalpha")
+    _expect(dL_ddepth, (H, W), torch.float32, "dL_ddepth")
+    _check("bgs_render_bwd", lib().bgs_render_bwd(C.byref(frame), C.byref(cfg), _ptr(final_T), _ptr(n_contrib),
+                                                  _ptr(dL_dcolor), _ptr(dL_dalpha), _ptr(dL_ddepth),
+                                                  _ptr(dL_dmeans2D), _ptr(dL_dconic_opacity), _ptr(dL_drgb),
+                                                  _ptr(dL_ddepths), _ptr(ws), ws.numel(), _stream(stream)))

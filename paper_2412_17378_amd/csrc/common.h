@@ -1,0 +1,122 @@
+// Internal helpers of the bgs HIP library (gfx950 / CDNA4, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "bgs.h"
+
+namespace bgs {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+bgs_status fail(bgs_status code, const std::string& msg);
+
+#define BGS_HIP(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return ::bgs::fail(BGS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define BGS_REQUIRE(cond, msg)                                   \
+    do {                                                         \
+        if (!(cond)) return ::bgs::fail(BGS_EINVAL, (msg));      \
+    } while (0)
+
+// Number of compute units of the current device (cached per device).
+int cu_count();
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- device math
+constexpr int WAVE = 64;
+constexpr int TILE = 16;             // binning tile edge
+constexpr float ALPHA_MIN = 1.0f / 255.0f;
+constexpr float ALPHA_MAX = 0.99f;
+constexpr float T_MIN = 1e-4f;
+constexpr float LOG2E = 1.4426950408889634f;
+
+// floor(a / b) for b > 0
+__host__ __device__ inline int64_t floor_div(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    return (q * b > a) ? q - 1 : q;
+}
+
+// Inclusive tile rectangle of a screen square [u-r, u+r] x [v-r, v+r]: tiles
+// k with [k*TILE, (k+1)*TILE) meeting [u-r, u+r].  Because r is an integer,
+// floor((u +- r)/TILE) = floor((floor(u) +- r)/TILE), so the rectangle is
+// exact integer arithmetic on floor(u).  Returns false when empty.
+__device__ inline bool tile_rect(float u, float v, int r, int TX, int TY, int& x0, int& y0, int& x1,
+                                 int& y1) {
+    if (r <= 0) return false;
+    // clamp far off-screen centres so that the integer conversion is defined;
+    // any clamped value lies far outside every tile either way
+    const float lim = 1.0e9f;
+    float uc = fminf(fmaxf(u, -lim), lim), vc = fminf(fmaxf(v, -lim), lim);
+    int64_t fu = (int64_t)floorf(uc), fv = (int64_t)floorf(vc);
+    int64_t a0 = floor_div(fu - r, TILE), a1 = floor_div(fu + r, TILE);
+    int64_t b0 = floor_div(fv - r, TILE), b1 = floor_div(fv + r, TILE);
+    if (a0 < 0) a0 = 0;
+    if (b0 < 0) b0 = 0;
+    if (a1 > TX - 1) a1 = TX - 1;
+    if (b1 > TY - 1) b1 = TY - 1;
+    if (a0 > a1 || b0 > b1) return false;
+    x0 = (int)a0; y0 = (int)b0; x1 = (int)a1; y1 = (int)b1;
+    return true;
+}
+
+// Gaussian as staged in LDS for the render loops.  The conic is pre-scaled so
+// that the exponent comes out in base 2:  power2 = log2(e) * power with
+// (a2, b2, c2) = (-log2e a / 2, -log2e b, -log2e c / 2).
+struct Splat {
+    float x, y, a2, b2, c2, o, r, g, b, d;
+};
+
+// Exponent of one (pixel, Gaussian) pair, base 2.  Written with explicit fma
+// so that forward and backward kernels evaluate bit-identical values (the
+// backward re-takes the forward's skip decisions).
+__device__ __forceinline__ float splat_power2(float dx, float dy, float a2, float b2, float c2) {
+    float t = __builtin_fmaf(a2, dx, b2 * dy);
+    float cdy = c2 * dy;
+    float cdd = cdy * dy;
+    return __builtin_fmaf(dx, t, cdd);
+}
+
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// ---------------------------------------------------------------- wave ops
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf,
+                                                                 false));
+}
+
+// Sum over the 64 lanes of a wave (all lanes must be active); the total is
+// returned in every lane (through lane 63).
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp<0xB1>(v);        // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);        // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);       // row_half_mirror
+    v += dpp<0x140>(v);       // row_mirror        -> every lane holds its row's sum
+    v += dpp<0x142, 0xA>(v);  // row_bcast:15      -> rows 1, 3 hold pair sums
+    v += dpp<0x143, 0xC>(v);  // row_bcast:31      -> row 3 holds the total
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+    for (int off = 32; off >= 1; off >>= 1) {
+        int o = __shfl_xor(v, off, 64);
+        v = v > o ? v : o;
+    }
+    return v;
+}
+
+}  // namespace bgs

@@ -1,0 +1,190 @@
+"""The rasterizer pipeline over the C ABI: project -> bin -> sort -> ranges ->
+render_fwd / render_bwd, plus the differentiable render as a
+torch.autograd.Function.
+
+torch provides device memory (outputs, workspaces) and the stream; every
+step of the path runs in libbgs.so.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import torch
+
+from . import bgs as B
+
+
+@dataclasses.dataclass
+class Prepared:
+    """Screen-space splats and per-tile sorted lists of one view."""
+    width: int
+    height: int
+    means2D: torch.Tensor        # [P,2] f32
+    conic_opacity: torch.Tensor  # [P,4] f32
+    rgb: torch.Tensor            # [P,3] f32
+    depth: torch.Tensor          # [P] f32
+    radius: torch.Tensor         # [P] i32
+    tiles_touched: torch.Tensor  # [P] i32
+    n_pairs: int
+    tile_keys: torch.Tensor      # [n_pairs] i32, sorted tile ids
+    point_list: torch.Tensor     # [n_pairs] i32
+    ranges: torch.Tensor         # [n_tiles,2] i32
+
+    @property
+    def P(self) -> int:
+        return int(self.means2D.shape[0])
+
+    def frame(self) -> B.Frame:
+        return B.make_frame(self.width, self.height, self.ranges, self.point_list, self.means2D,
+                            self.conic_opacity, self.rgb, self.depth)
+
+
+class Workspace:
+    """Grow-only device byte buffers, one per role."""
+
+    def __init__(self, device):
+        self.device = device
+        self._bufs = {}
+
+    def get(self, role: str, nbytes: int) -> torch.Tensor:
+        nbytes = max(int(nbytes), 256)
+        b = self._bufs.get(role)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._bufs[role] = b
+        return b
+
+
+def key_bits_for(n_tiles: int) -> int:
+    return max(1, int(n_tiles - 1).bit_length())
+
+
+class Rasterizer:
+    def __init__(self, device: str = "cuda", reuse_pairs: bool = False):
+        """reuse_pairs: the sorted lists of a prepared frame live in buffers
+        that the next prepare() overwrites (no per-frame allocation); off by
+        default so that several prepared frames can coexist."""
+        B.lib()
+        self.device = torch.device(device)
+        self.ws = Workspace(self.device)
+        self.pair_capacity = 0
+        self.reuse_pairs = reuse_pairs
+
+    def _t(self, a, dtype=torch.float32):
+        if isinstance(a, torch.Tensor):
+            return a.to(device=self.device, dtype=dtype).contiguous()
+        return torch.as_tensor(a, dtype=dtype).to(self.device).contiguous()
+
+    def project(self, cam, means3D, log_scales, quats, opacity, colors, sh_degree: int) -> dict:
+        means3D, log_scales, quats = self._t(means3D), self._t(log_scales), self._t(quats)
+        opacity, colors = self._t(opacity), self._t(colors)
+        P = means3D.shape[0]
+        dev = self.device
+        out = dict(means2D=torch.empty(P, 2, device=dev), conic_opacity=torch.empty(P, 4, device=dev),
+                   rgb=torch.empty(P, 3, device=dev), depth=torch.empty(P, device=dev),
+                   radius=torch.empty(P, dtype=torch.int32, device=dev),
+                   tiles_touched=torch.empty(P, dtype=torch.int32, device=dev))
+        B.bgs_project(cam, means3D, log_scales, quats, opacity, colors, sh_degree, out["means2D"],
+                      out["conic_opacity"], out["rgb"], out["depth"], out["radius"], out["tiles_touched"])
+        return out
+
+    def bin_sort_ranges(self, width: int, height: int, pr: dict) -> Prepared:
+        P = pr["means2D"].shape[0]
+        dev = self.device
+        nt = B.n_tiles(width, height)
+        ws = self.ws.get("bin", B.bgs_bin_workspace_bytes(P))
+
+        def pair_bufs(cap):
+            return [self.ws.get(r, 4 * cap).view(torch.int32)[:cap] for r in ("keys", "vals", "skeys", "svals")]
+
+        cap = self.pair_capacity
+        keys, vals, skeys, svals = pair_bufs(cap)
+        try:
+            M = B.bgs_bin(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
+                          keys if cap else None, vals if cap else None, ws)
+        except B.BgsError as e:
+            if e.status != B.BGS_ECAPACITY:
+                raise
+            # grow with headroom and emit again
+            self.pair_capacity = cap = int(e.n_pairs * 1.25) + 1024
+            keys, vals, skeys, svals = pair_bufs(cap)
+            M = B.bgs_bin(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], keys, vals,
+                          ws)
+        if M > 0:
+            sws = self.ws.get("sort", B.bgs_sort_workspace_bytes(M))
+            B.bgs_sort(keys, vals, skeys, svals, M, key_bits_for(nt), sws)
+        ranges = torch.empty(nt, 2, dtype=torch.int32, device=dev)
+        B.bgs_ranges(skeys, M, nt, ranges)
+        if not self.reuse_pairs:
+            skeys, svals = skeys[:M].clone(), svals[:M].clone()
+        return Prepared(width=width, height=height, means2D=pr["means2D"], conic_opacity=pr["conic_opacity"],
+                        rgb=pr["rgb"], depth=pr["depth"], radius=pr["radius"], tiles_touched=pr["tiles_touched"],
+                        n_pairs=M, tile_keys=skeys[:M], point_list=svals[:M], ranges=ranges)
+
+    def prepare(self, cam, means3D, log_scales, quats, opacity, colors, sh_degree: int) -> Prepared:
+        pr = self.project(cam, means3D, log_scales, quats, opacity, colors, sh_degree)
+        return self.bin_sort_ranges(int(cam.width), int(cam.height), pr)
+
+    def prepare_scene(self, scene, view: int = 0) -> Prepared:
+        return self.prepare(scene.cameras[view], scene.means3D, scene.log_scales, scene.quats, scene.opacity,
+                            scene.colors, scene.sh_degree)
+
+    def render_fwd(self, prep: Prepared, cfg: B.RenderCfg, out: Optional[dict] = None) -> dict:
+        H, W = prep.height, prep.width
+        dev = self.device
+        if out is None:
+            out = dict(color=torch.empty(3, H, W, device=dev), alpha=torch.empty(H, W, device=dev),
+                       depth=torch.empty(H, W, device=dev), final_T=torch.empty(H, W, device=dev),
+                       n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
+        f = prep.frame()
+        ws = self.ws.get("render", B.bgs_render_workspace_bytes(f, cfg))
+        B.bgs_render_fwd(f, cfg, out["color"], out["alpha"], out["depth"], out["final_T"], out["n_contrib"], ws)
+        return out
+
+    def render_bwd(self, prep: Prepared, cfg: B.RenderCfg, fwd: dict, dL_dcolor, dL_dalpha=None, dL_ddepth=None,
+                   grads: Optional[dict] = None, want_depth: bool = True) -> dict:
+        P = prep.P
+        dev = self.device
+        if grads is None:
+            grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
+                         rgb=torch.zeros(P, 3, device=dev),
+                         depth=torch.zeros(P, device=dev) if want_depth else None)
+        f = prep.frame()
+        ws = self.ws.get("render", B.bgs_render_workspace_bytes(f, cfg))
+        B.bgs_render_bwd(f, cfg, fwd["final_T"], fwd["n_contrib"], dL_dcolor, dL_dalpha, dL_ddepth,
+                         grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], ws)
+        return grads
+
+
+class RenderFn(torch.autograd.Function):
+    """Differentiable render of prepared splats: inputs means2D [P,2],
+    conic_opacity [P,4], rgb [P,3], depth [P] (the per-tile lists are taken
+    from ``prep``); outputs color [3,H,W], alpha [H,W], depth [H,W].  The
+    backward returns gradients for all four inputs."""
+
+    @staticmethod
+    def forward(ctx, means2D, conic_opacity, rgb, depth, prep: Prepared, cfg: B.RenderCfg, rast: Rasterizer):
+        p2 = dataclasses.replace(prep, means2D=means2D.contiguous(), conic_opacity=conic_opacity.contiguous(),
+                                 rgb=rgb.contiguous(), depth=depth.contiguous())
+        out = rast.render_fwd(p2, cfg)
+        ctx.prep, ctx.cfg, ctx.rast = p2, cfg, rast
+        ctx.save_for_backward(out["final_T"], out["n_contrib"])
+        ctx.mark_non_differentiable(out["final_T"], out["n_contrib"])
+        return out["color"], out["alpha"], out["depth"]
+
+    @staticmethod
+    def backward(ctx, g_color, g_alpha, g_depth):
+        final_T, n_contrib = ctx.saved_tensors
+        prep, rast = ctx.prep, ctx.rast
+        H, W = prep.height, prep.width
+        dev = final_T.device
+        g_color = torch.zeros(3, H, W, device=dev) if g_color is None else g_color.contiguous()
+        g_alpha = None if g_alpha is None else g_alpha.contiguous()
+        g_depth = None if g_depth is None else g_depth.contiguous()
+        grads = rast.render_bwd(prep, ctx.cfg, dict(final_T=final_T, n_contrib=n_contrib), g_color, g_alpha, g_depth)
+        return grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], None, None, None
+
+
+def render(means2D, conic_opacity, rgb, depth, prep: Prepared, cfg: B.RenderCfg, rast: Rasterizer):
+    return RenderFn.apply(means2D, conic_opacity, rgb, depth, prep, cfg, rast)

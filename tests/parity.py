@@ -1,0 +1,102 @@
+"""Shared pieces of the parity tests: running the HIP path and the oracle on
+the same seeded inputs, and the comparison rules.
+
+Tolerance (fp32 kernel vs fp64 oracle): per element
+    |x - y| <= 1e-4 * max(|y|, s)
+with s = 1e-2 for image channels and s = RMS(y) of the tensor for gradients
+and projected quantities.
+
+Discrete decisions (skip at alpha < 1/255, stop at T < 1e-4, the 0.99 clamp)
+are taken by each side in its own precision.  A pixel whose oracle decisions
+lie within MARGIN (relative) of a threshold may legitimately differ; such
+pixels are excluded from the element-wise image check, counted, and their
+upstream gradient is zeroed on both sides for the gradient check.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+RTOL = 1e-4
+MARGIN = 1e-4
+MAX_FLAGGED_FRACTION = 2e-3
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def check_close(x, y, s_floor, name, rtol=RTOL, mask=None):
+    """Assert |x-y| <= rtol*max(|y|, s_floor) elementwise (optionally only
+    where mask is True).  Returns (max ratio, p99.9 ratio)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    assert x.shape == y.shape, (name, x.shape, y.shape)
+    tol = rtol * np.maximum(np.abs(y), s_floor)
+    ratio = np.abs(x - y) / tol
+    if mask is not None:
+        ratio = ratio[np.broadcast_to(mask, ratio.shape)]
+    if ratio.size == 0:
+        return 0.0, 0.0
+    worst = float(ratio.max())
+    if not worst <= 1.0:
+        idx = int(np.argmax(ratio))
+        raise AssertionError(f"{name}: max |x-y|/tol = {worst:.3g} at flat index {idx} "
+                             f"(x={x.reshape(-1)[idx] if mask is None else 'masked'})")
+    return worst, float(np.quantile(ratio, 0.999))
+
+
+def rms(y):
+    y = np.asarray(y, np.float64)
+    return float(np.sqrt(np.mean(y * y))) if y.size else 0.0
+
+
+def oracle_render_from_gpu(prep, bg=(0.0, 0.0, 0.0), window=None):
+    """Oracle forward on the GPU path's own fp32 splats and lists (widened)."""
+    return oracle.render_fwd(prep.width, prep.height, to_np(prep.ranges), to_np(prep.point_list),
+                             to_np(prep.means2D), to_np(prep.conic_opacity), to_np(prep.rgb), to_np(prep.depth),
+                             bg=bg, window=window)
+
+
+def oracle_bwd_from_gpu(prep, gC, gA=None, gD=None, bg=(0.0, 0.0, 0.0), window=None):
+    return oracle.render_bwd(prep.width, prep.height, to_np(prep.ranges), to_np(prep.point_list),
+                             to_np(prep.means2D), to_np(prep.conic_opacity), to_np(prep.rgb), to_np(prep.depth),
+                             gC, gA, gD, bg=bg, window=window)
+
+
+def compare_forward(gpu, orc, window=None, name=""):
+    """Image parity on unflagged pixels (inside window, if given)."""
+    H, W = orc["final_T"].shape
+    valid = np.ones((H, W), bool)
+    if window is not None:
+        x0, y0, x1, y1 = window
+        valid[:] = False
+        valid[y0:y1, x0:x1] = True
+    flagged = (orc["margin"] < MARGIN) & valid
+    ok = valid & ~flagged
+    n_valid = int(valid.sum())
+    assert flagged.sum() <= max(2, MAX_FLAGGED_FRACTION * n_valid), (name, int(flagged.sum()), n_valid)
+    stats = {}
+    stats["color"] = check_close(to_np(gpu["color"]), orc["color"], 1e-2, name + " color", mask=ok[None])
+    stats["alpha"] = check_close(to_np(gpu["alpha"]), orc["alpha"], 1e-2, name + " alpha", mask=ok)
+    stats["depth"] = check_close(to_np(gpu["depth"]), orc["depth"], 1e-2, name + " depth", mask=ok)
+    stats["final_T"] = check_close(to_np(gpu["final_T"]), orc["final_T"], 1e-2, name + " final_T", mask=ok)
+    nc_g = to_np(gpu["n_contrib"])
+    bad = (nc_g != orc["n_contrib"]) & ok
+    assert not bad.any(), (name, "n_contrib differs at", np.argwhere(bad)[:5])
+    return flagged, stats
+
+
+def compare_grads(gpu, orc, name=""):
+    stats = {}
+    pairs = [("means2D", gpu["means2D"], orc["means2D"]),
+             ("conic", to_np(gpu["conic_opacity"])[:, :3], orc["conic"]),
+             ("opacity", to_np(gpu["conic_opacity"])[:, 3], orc["opacity"]),
+             ("rgb", gpu["rgb"], orc["rgb"])]
+    if gpu.get("depth") is not None:
+        pairs.append(("depth", gpu["depth"], orc["depth"]))
+    for nm, g, o in pairs:
+        g = to_np(g) if not isinstance(g, np.ndarray) else g
+        stats[nm] = check_close(g, o, max(rms(o), 1e-30), f"{name} d{nm}")
+    return stats

@@ -1,0 +1,66 @@
+"""CPU checks of the boundary: libbgs.so loads and exports every entry point
+include/bgs.h declares; invalid arguments come back as status codes (no GPU
+work is launched by these calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bgs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bgs_[a-z0-9_]+)\s*\(", src)))
+
+
+def _lib():
+    from paper_2412_17378_amd import bgs
+    if not os.path.exists(bgs.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return bgs.lib()
+
+
+def test_header_declares_the_pipeline():
+    names = _declared()
+    for n in ("bgs_project", "bgs_bin", "bgs_sort", "bgs_ranges", "bgs_queue_build", "bgs_render_fwd",
+              "bgs_render_bwd"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_invalid_arguments_are_status_codes():
+    from paper_2412_17378_amd import bgs as B
+    L = _lib()
+    cam = B.Camera()
+    cam.width, cam.height = 0, 10
+    st = L.bgs_project(ctypes.byref(cam), 1, None, None, None, None, None, -1, 16, None, None, None, None, None,
+                       None, None)
+    assert st == B.BGS_EINVAL
+    assert b"image size" in L.bgs_last_error()
+    cam.width = 10
+    st = L.bgs_project(ctypes.byref(cam), 1, None, None, None, None, None, -1, 8, None, None, None, None, None,
+                       None, None)
+    assert st == B.BGS_EUNSUPPORTED
+    st = L.bgs_render_fwd(None, None, None, None, None, None, None, None, 0, None)
+    assert st == B.BGS_EINVAL
+    f = B.Frame()
+    f.width, f.height, f.tile = 32, 32, 16
+    cfg = B.make_cfg("pixel", 8)
+    st = L.bgs_render_fwd(ctypes.byref(f), ctypes.byref(cfg), None, None, None, None, None, None, 0, None)
+    assert st == B.BGS_EINVAL  # null frame arrays
+    st = L.bgs_sort(None, None, None, None, 10, 0, None, 0, None)
+    assert st == B.BGS_EINVAL
+    assert L.bgs_render_workspace_bytes(ctypes.byref(f), ctypes.byref(cfg)) > 0
+
+
+def test_version():
+    assert _lib().bgs_version().startswith(b"bgs")

@@ -41,6 +41,7 @@ OPS_PER_FWD_BLEND = 20.0      # VALU lane-ops per examined (pixel, Gaussian) pai
 OPS_PER_BWD_BLEND = 45.0      # VALU lane-ops per contributor walked back to front
 BYTES_PER_PAIR_SORT = 16.0    # read + write of a (u32 key, u32 value) pair
 BYTES_PER_PAIR_BIN = 8.0      # write of a (u32 key, u32 value) pair
+BYTES_PER_PAIR_LISTS = 4.0    # write of the u32 Gaussian id of a pair into its tile's list
 BYTES_PER_GAUSS_PROJECT = 104.0
 
 WORKLOAD_NAME = ("imbalanced 1080p: 1920x1080, 500k Gaussians (69% uniform, 30% clustered in 5% of the screen, "
@@ -55,6 +56,8 @@ def parse():
     ap.add_argument("--scene", default="1", help="workload scene id (default: the imbalanced 1080p scene)")
     ap.add_argument("--variant", default="pixel")
     ap.add_argument("--order", default="cost")
+    ap.add_argument("--lists", default="fused", choices=["fused", "sort"],
+                    help="tile lists by the fused counting pass or by bin + radix sort + ranges")
     ap.add_argument("--no-static", action="store_true", help="skip the static-kernel comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", default="720,360,1200,600",
@@ -109,6 +112,7 @@ def main():
         grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
                      rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
         ranges = torch.empty(nt, 2, dtype=torch.int32, device=dev)
+        n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         state = {}
 
         def step(ev=None):
@@ -120,18 +124,32 @@ def main():
                           scene.sh_degree, pr["means2D"], pr["conic_opacity"], pr["rgb"], pr["depth"], pr["radius"],
                           pr["tiles_touched"])
             mark(1)
-            ws = rast.ws.get("bin", B.bgs_bin_workspace_bytes(P))
-            cap = rast.pair_capacity
-            bufs = [rast.ws.get(r, 4 * cap).view(torch.int32)[:cap] for r in ("keys", "vals", "skeys", "svals")]
-            M = B.bgs_bin(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], bufs[0], bufs[1], ws)
-            mark(2)
-            sws = rast.ws.get("sort", B.bgs_sort_workspace_bytes(M))
-            B.bgs_sort(bufs[0], bufs[1], bufs[2], bufs[3], M, key_bits_for(nt), sws)
-            mark(3)
-            B.bgs_ranges(bufs[2], M, nt, ranges)
-            mark(4)
-            frame = B.make_frame(W, H, ranges, bufs[3][:M], pr["means2D"], pr["conic_opacity"], pr["rgb"],
-                                 pr["depth"])
+            if args.lists == "fused":
+                lws = rast.ws.get("lists", B.bgs_tile_lists_workspace_bytes(W, H, P))
+                pl = rast.ws.get("svals", 4 * rast.pair_capacity).view(torch.int32)[:rast.pair_capacity]
+                B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], pl, ranges,
+                                 n_dev, lws)
+                mark(2)
+                M = int(n_dev.item())  # the host needs M to size the frame (one sync, as in bgs_bin)
+                if M > rast.pair_capacity:
+                    raise RuntimeError("pair capacity exceeded")
+                mark(3)
+                mark(4)
+                plist = pl[:M]
+            else:
+                ws = rast.ws.get("bin", B.bgs_bin_workspace_bytes(P))
+                cap = rast.pair_capacity
+                bufs = [rast.ws.get(r, 4 * cap).view(torch.int32)[:cap] for r in ("keys", "vals", "skeys", "svals")]
+                M = B.bgs_bin(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], bufs[0], bufs[1],
+                              ws)
+                mark(2)
+                sws = rast.ws.get("sort", B.bgs_sort_workspace_bytes(M))
+                B.bgs_sort(bufs[0], bufs[1], bufs[2], bufs[3], M, key_bits_for(nt), sws)
+                mark(3)
+                B.bgs_ranges(bufs[2], M, nt, ranges)
+                mark(4)
+                plist = bufs[3][:M]
+            frame = B.make_frame(W, H, ranges, plist, pr["means2D"], pr["conic_opacity"], pr["rgb"], pr["depth"])
             rws = rast.ws.get("render", B.bgs_render_workspace_bytes(frame, cfg))
             if variant != "static":
                 B.bgs_queue_build(frame, cfg, None, rws)
@@ -148,21 +166,17 @@ def main():
                              grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], rws)
             mark(8)
             state["M"] = M
-            state["frame_bufs"] = (ranges, bufs[3][:M])
+            state["frame_bufs"] = (ranges, plist)
             return M
 
         # size the pair buffers once, outside any timed region
-        ws0 = rast.ws.get("bin", B.bgs_bin_workspace_bytes(P))
         B.bgs_project(cam, g_in["means3D"], g_in["log_scales"], g_in["quats"], g_in["opacity"], g_in["colors"],
                       scene.sh_degree, pr["means2D"], pr["conic_opacity"], pr["rgb"], pr["depth"], pr["radius"],
                       pr["tiles_touched"])
-        try:
-            B.bgs_bin(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], None, None, ws0)
-        except B.BgsError as e:
-            if e.status != B.BGS_ECAPACITY:
-                raise
-            if e.n_pairs > rast.pair_capacity:
-                rast.pair_capacity = e.n_pairs
+        lws0 = rast.ws.get("lists", B.bgs_tile_lists_workspace_bytes(W, H, P))
+        B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], None, ranges, n_dev,
+                         lws0)
+        rast.pair_capacity = max(rast.pair_capacity, int(n_dev.item()))
         return step, state, pr, fwd, grads
 
     def run(variant, order, steps, warmup):
@@ -177,7 +191,8 @@ def main():
             step(evs[k])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        names = ["project", "bin", "sort", "ranges", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"]
+        names = ["project", "lists" if args.lists == "fused" else "bin", "host_sync" if args.lists == "fused" else "sort",
+                 "ranges", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"]
         stages = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
                   for i, n in enumerate(names)}
         return (t1 - t0) * 1e3 / steps, stages, state, pr, fwd, grads
@@ -226,6 +241,8 @@ def main():
             return dict(bound="hbm", achieved=M * BYTES_PER_PAIR_SORT / t / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
         if stage == "bin":
             return dict(bound="hbm", achieved=M * BYTES_PER_PAIR_BIN / t / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
+        if stage == "lists":
+            return dict(bound="hbm", achieved=M * BYTES_PER_PAIR_LISTS / t / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
         if stage == "project":
             return dict(bound="hbm", achieved=scene.P * BYTES_PER_GAUSS_PROJECT / t / 1e9, peak=PEAK_HBM_GBS,
                         unit="GB/s")
@@ -263,7 +280,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_NAME, "scene": scene.name, "seed": scene.seed, "P": scene.P,
                    "width": W, "height": H, "n_pairs": M, "variant": args.variant, "order": args.order,
-                   "subtile": 8},
+                   "subtile": 8, "lists": args.lists},
         "blends": {"fwd": fwd_blends, "bwd": bwd_blends},
         "stages_ms": stages,
         "render_ms": render_ms,

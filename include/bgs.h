@@ -168,6 +168,28 @@ bgs_status bgs_sort(const uint32_t* keys_in, const uint32_t* values_in, uint32_t
 bgs_status bgs_ranges(const uint32_t* sorted_keys, int64_t n, int32_t n_tiles, uint32_t* ranges,
                       hipStream_t stream);
 
+/* Workspace bytes for bgs_tile_lists. */
+size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P);
+
+/*
+ * bgs_bin + bgs_sort + bgs_ranges fused into one stable counting pass (the
+ * same point list and ranges, bit for bit), without materializing or sorting
+ * the (tile, Gaussian) keys.  The Gaussians are put in depth order, cut into
+ * chunks of 256; per chunk a tile histogram (2D difference array), a column
+ * scan over chunks and a scan over tiles give every (chunk, tile) its base
+ * slot, and one wave per chunk places its pairs in depth order.
+ * Asynchronous: n_pairs_dev (DEVICE, uint64[1]) receives M.  Pairs at
+ * positions >= capacity are dropped, so when M > capacity the caller must
+ * grow point_list and call again before rendering.  Supports tile grids of
+ * up to 16384 tiles whose (TX+1)*(TY+1) difference grid fits 64 KiB of LDS;
+ * larger grids return BGS_EUNSUPPORTED (use the three separate calls).
+ *   point_list [capacity] Gaussian ids, ranges [n_tiles][2].
+ */
+bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
+                          const int32_t* radius, const float* depth, const uint32_t* tiles_touched,
+                          uint32_t* point_list, int64_t capacity, uint32_t* ranges, uint64_t* n_pairs_dev, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
+
 /* Workspace bytes for bgs_queue_build / bgs_render_fwd / bgs_render_bwd. */
 size_t bgs_render_workspace_bytes(const bgs_frame* frame, const bgs_render_cfg* cfg);
 

@@ -71,6 +71,9 @@ def lib() -> C.CDLL:
             "bgs_sort_workspace_bytes": ([_i64], _sz),
             "bgs_sort": ([_vp, _vp, _vp, _vp, _i64, _i32, _vp, _sz, _vp], C.c_int),
             "bgs_ranges": ([_vp, _i64, _i32, _vp, _vp], C.c_int),
+            "bgs_tile_lists_workspace_bytes": ([_i32, _i32, _i64], _sz),
+            "bgs_tile_lists": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp],
+                               C.c_int),
             "bgs_render_workspace_bytes": ([_vp, _vp], _sz),
             "bgs_queue_build": ([_vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_render_fwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
@@ -87,7 +90,8 @@ def lib() -> C.CDLL:
 def exported_symbols():
     """Names the header declares (used by the load test)."""
     return ["bgs_last_error", "bgs_version", "bgs_project", "bgs_bin_workspace_bytes", "bgs_bin",
-            "bgs_sort_workspace_bytes", "bgs_sort", "bgs_ranges", "bgs_render_workspace_bytes", "bgs_queue_build",
+            "bgs_sort_workspace_bytes", "bgs_sort", "bgs_ranges", "bgs_tile_lists_workspace_bytes", "bgs_tile_lists",
+            "bgs_render_workspace_bytes", "bgs_queue_build",
             "bgs_render_fwd", "bgs_render_bwd"]
 
 
@@ -147,6 +151,26 @@ def n_tiles(width: int, height: int) -> int:
     return ((width + TILE - 1) // TILE) * ((height + TILE - 1) // TILE)
 
 
+def tile_lists_supported(width: int, height: int) -> bool:
+    """Whether bgs_tile_lists handles this tile grid (see include/bgs.h)."""
+    tx, ty = (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
+    return tx * ty <= 16384 and (tx + 1) * (ty + 1) * 4 <= 65536
+
+
+_DUMMY = {}
+
+
+def _nonempty(t: torch.Tensor) -> torch.Tensor:
+    """An empty array still has to be passed as a valid, aligned device
+    pointer (nothing is read through it)."""
+    if t.numel() > 0:
+        return t
+    d = _DUMMY.get(t.device)
+    if d is None:
+        d = _DUMMY[t.device] = torch.zeros(64, dtype=torch.float32, device=t.device)
+    return d
+
+
 def make_frame(width, height, ranges, point_list, means2D, conic_opacity, rgb, depth) -> Frame:
     P = means2D.shape[0]
     _expect(ranges, (n_tiles(width, height), 2), torch.int32, "ranges")
@@ -158,10 +182,9 @@ def make_frame(width, height, ranges, point_list, means2D, conic_opacity, rgb, d
         raise ValueError("point_list must be a 1-D int32 tensor")
     f = Frame()
     f.width, f.height, f.tile = int(width), int(height), TILE
-    # a frame with no pairs still needs a valid pointer
-    pl = point_list if point_list.numel() > 0 else ranges
-    f.ranges, f.point_list = _ptr(ranges), _ptr(pl)
-    f.means2D, f.conic_opacity, f.rgb, f.depth = _ptr(means2D), _ptr(conic_opacity), _ptr(rgb), _ptr(depth)
+    f.ranges, f.point_list = _ptr(ranges), _ptr(_nonempty(point_list))
+    f.means2D, f.conic_opacity = _ptr(_nonempty(means2D)), _ptr(_nonempty(conic_opacity))
+    f.rgb, f.depth = _ptr(_nonempty(rgb)), _ptr(_nonempty(depth))
     return f
 
 
@@ -222,6 +245,21 @@ def bgs_ranges(sorted_keys, n: int, n_tiles_: int, ranges, stream=None):
                                           _ptr(ranges), _stream(stream)))
 
 
+def bgs_tile_lists_workspace_bytes(width: int, height: int, P: int) -> int:
+    return int(lib().bgs_tile_lists_workspace_bytes(int(width), int(height), int(P)))
+
+
+def bgs_tile_lists(width, height, means2D, radius, depth, tiles_touched, point_list, ranges, n_pairs_dev, ws,
+                   stream=None):
+    """Asynchronous; n_pairs_dev (int64 [>=1] device tensor) receives M."""
+    cap = 0 if point_list is None else point_list.numel()
+    _expect(ranges, (n_tiles(width, height), 2), torch.int32, "ranges")
+    _check("bgs_tile_lists", lib().bgs_tile_lists(int(width), int(height), TILE, means2D.shape[0], _ptr(means2D),
+                                                  _ptr(radius), _ptr(depth), _ptr(tiles_touched),
+                                                  _ptr(point_list) if cap else None, cap, _ptr(ranges),
+                                                  _ptr(n_pairs_dev), _ptr(ws), ws.numel(), _stream(stream)))
+
+
 def bgs_render_workspace_bytes(frame: Frame, cfg: RenderCfg) -> int:
     return int(lib().bgs_render_workspace_bytes(C.byref(frame), C.byref(cfg)))
 
@@ -253,5 +291,7 @@ def bgs_render_bwd(frame: Frame, cfg: RenderCfg, final_T, n_contrib, dL_dcolor, 
     _expect(dL_ddepth, (H, W), torch.float32, "dL_ddepth")
     _check("bgs_render_bwd", lib().bgs_render_bwd(C.byref(frame), C.byref(cfg), _ptr(final_T), _ptr(n_contrib),
                                                   _ptr(dL_dcolor), _ptr(dL_dalpha), _ptr(dL_ddepth),
-                                                  _ptr(dL_dmeans2D), _ptr(dL_dconic_opacity), _ptr(dL_drgb),
-                                                  _ptr(dL_ddepths), _ptr(ws), ws.numel(), _stream(stream)))
+                                                  _ptr(_nonempty(dL_dmeans2D)), _ptr(_nonempty(dL_dconic_opacity)),
+                                                  _ptr(_nonempty(dL_drgb)),
+                                                  None if dL_ddepths is None else _ptr(_nonempty(dL_ddepths)),
+                                                  _ptr(ws), ws.numel(), _stream(stream)))

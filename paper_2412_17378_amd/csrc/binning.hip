@@ -43,28 +43,52 @@ __global__ void k_total(int64_t P, const uint64_t* __restrict__ offsets, const u
         total[0] = P > 0 ? offsets[P - 1] + tiles_touched[order[P - 1]] : 0;
 }
 
-// One thread per Gaussian (in depth order) writes its run of pairs.
+// Pair emission, wave-cooperative so that stores are coalesced: each wave
+// owns 64 consecutive Gaussians of the depth order and walks them one at a
+// time; the 64 lanes write consecutive pairs of the current Gaussian's run
+// (pair j of a w x h rectangle is tile (x0 + j % w, y0 + j / w)).
 __global__ __launch_bounds__(256) void k_emit(int64_t P, int TX, int TY, const uint32_t* __restrict__ order,
                                               const uint64_t* __restrict__ offsets, const float* __restrict__ means2D,
                                               const int* __restrict__ radius,
                                               const uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ keys,
                                               uint32_t* __restrict__ values) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= P) return;
-    const uint32_t g = order[k];
-    if (tiles_touched[g] == 0) return;
-    int x0, y0, x1, y1;
-    if (!tile_rect(means2D[2 * g], means2D[2 * g + 1], radius[g], TX, TY, x0, y0, x1, y1)) return;
-    uint64_t o = offsets[k];
-    // never write past this Gaussian's own run, whatever tiles_touched says
-    const uint64_t o_end = o + tiles_touched[g];
-    for (int ty = y0; ty <= y1; ++ty)
-        for (int tx = x0; tx <= x1; ++tx) {
-            if (o >= o_end) return;
-            keys[o] = (uint32_t)(ty * TX + tx);
-            values[o] = g;
-            ++o;
+    const int lane = threadIdx.x & 63;
+    const int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;  // first Gaussian of this wave
+    if (base >= P) return;
+    const int64_t k = base + lane;
+    uint32_t g = 0, n = 0;
+    int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+    uint64_t o = 0;
+    if (k < P) {
+        g = order[k];
+        if (tiles_touched[g] != 0 &&
+            tile_rect(means2D[2 * g], means2D[2 * g + 1], radius[g], TX, TY, x0, y0, x1, y1)) {
+            // never more than this Gaussian's own run, whatever tiles_touched says
+            const uint32_t area = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+            n = area < tiles_touched[g] ? area : tiles_touched[g];
+            o = offsets[k];
         }
+    }
+    const int cnt = (int)((P - base) < 64 ? (P - base) : 64);
+    for (int i = 0; i < cnt; ++i) {
+        const uint32_t ni = __builtin_amdgcn_readlane(n, i);
+        if (ni == 0) continue;
+        const uint32_t gi = __builtin_amdgcn_readlane(g, i);
+        const int xi = __builtin_amdgcn_readlane(x0, i), yi = __builtin_amdgcn_readlane(y0, i);
+        const int wi = __builtin_amdgcn_readlane(x1, i) - xi + 1;
+        const uint64_t oi = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(o >> 32), i) << 32) |
+                            (uint64_t)__builtin_amdgcn_readlane((uint32_t)o, i);
+        const float inv_w = 1.0f / (float)wi;
+        for (uint32_t j = lane; j < ni; j += 64) {
+            // j / wi via a float estimate and one correction step (j < 2^24)
+            int q = (int)((float)j * inv_w);
+            int r = (int)j - q * wi;
+            if (r >= wi) { ++q; r -= wi; }
+            if (r < 0) { --q; r += wi; }
+            keys[oi + j] = (uint32_t)((yi + q) * TX + xi + r);
+            values[oi + j] = gi;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
@@ -208,5 +232,309 @@ extern "C" bgs_status bgs_ranges(const uint32_t* sorted_keys, int64_t n, int32_t
     BGS_REQUIRE(sorted_keys != nullptr, "bgs_ranges: keys is null");
     hipLaunchKernelGGL(k_ranges, dim3(blocks_for(n)), dim3(256), 0, stream, sorted_keys, n, (int)n_tiles, ranges);
     BGS_HIP(hipGetLastError());
+    return BGS_OK;
+}
+
+// ======================================================================
+// Fused tile lists: bin + stable sort by tile + ranges in one counting pass.
+//
+// The Gaussians are first put in depth order (a P-element sort).  That order
+// is cut into chunks of CHUNK Gaussians.  For every chunk c and tile t,
+// h[c][t] = number of the chunk's Gaussians whose square meets t (a 2D
+// difference array per chunk in LDS: four updates per Gaussian, then a 2D
+// prefix sum).  A column scan over chunks gives each (chunk, tile) its base
+// position inside the tile's segment, and an exclusive scan over tiles gives
+// the segments (= ranges).  Finally one wave per chunk walks its Gaussians in
+// depth order and drops each into its tiles at base + running count, which
+// reproduces a stable sort by tile of the depth-ordered pairs without ever
+// materializing or sorting the M (tile, Gaussian) keys.
+// ======================================================================
+namespace bgs {
+
+constexpr int CHUNK = 256;       // Gaussians per chunk
+constexpr int PART = 64;         // chunks per column-scan block
+constexpr int MAX_FUSED_TILES = 16384;
+
+__global__ __launch_bounds__(256) void k_chunk_hist(int64_t P, int TX, int TY, const uint32_t* __restrict__ order,
+                                                    const float* __restrict__ means2D, const int* __restrict__ radius,
+                                                    const uint32_t* __restrict__ tiles_touched,
+                                                    uint32_t* __restrict__ h) {
+    extern __shared__ int d[];  // (TY+1) x (TX+1) difference grid
+    const int GX = TX + 1, GY = TY + 1, nt = TX * TY;
+    const int c = blockIdx.x;
+    for (int i = threadIdx.x; i < GX * GY; i += blockDim.x) d[i] = 0;
+    __syncthreads();
+    const int64_t k = (int64_t)c * CHUNK + threadIdx.x;
+    if (k < P) {
+        const uint32_t g = order[k];
+        int x0, y0, x1, y1;
+        if (tiles_touched[g] != 0 && tile_rect(means2D[2 * g], means2D[2 * g + 1], radius[g], TX, TY, x0, y0, x1, y1)) {
+            atomicAdd(&d[y0 * GX + x0], 1);
+            atomicAdd(&d[y0 * GX + x1 + 1], -1);
+            atomicAdd(&d[(y1 + 1) * GX + x0], -1);
+            atomicAdd(&d[(y1 + 1) * GX + x1 + 1], 1);
+        }
+    }
+    __syncthreads();
+    for (int y = threadIdx.x; y < GY; y += blockDim.x) {
+        int run = 0;
+        for (int x = 0; x < GX; ++x) {
+            run += d[y * GX + x];
+            d[y * GX + x] = run;
+        }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < GX; x += blockDim.x) {
+        int run = 0;
+        for (int y = 0; y < GY; ++y) {
+            run += d[y * GX + x];
+            d[y * GX + x] = run;
+        }
+    }
+    __syncthreads();
+    uint32_t* hc = h + (int64_t)c * nt;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) hc[t] = (uint32_t)d[(t / TX) * GX + (t % TX)];
+}
+
+// part[b][t] = sum of h[c][t] over the chunks c of block b
+__global__ __launch_bounds__(256) void k_part_sums(int C, int nt, const uint32_t* __restrict__ h,
+                                                   uint32_t* __restrict__ part) {
+    const int nb = (C + PART - 1) / PART;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nb * nt) return;
+    const int b = (int)(i / nt), t = (int)(i % nt);
+    const int c1 = min(C, (b + 1) * PART);
+    uint32_t s = 0;
+    for (int c = b * PART; c < c1; ++c) s += h[(int64_t)c * nt + t];
+    part[i] = s;
+}
+
+// exclusive scan of part[.][t] over blocks; total[t] = column sum
+__global__ __launch_bounds__(256) void k_part_scan(int nb, int nt, uint32_t* __restrict__ part,
+                                                   uint32_t* __restrict__ total) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    uint32_t run = 0;
+    for (int b = 0; b < nb; ++b) {
+        const uint32_t v = part[(int64_t)b * nt + t];
+        part[(int64_t)b * nt + t] = run;
+        run += v;
+    }
+    total[t] = run;
+}
+
+// Single workgroup: exclusive scan of total over tiles -> start; ranges; M.
+__global__ __launch_bounds__(1024) void k_tile_scan(int nt, const uint32_t* __restrict__ total,
+                                                    uint32_t* __restrict__ start, uint32_t* __restrict__ ranges,
+                                                    uint64_t* __restrict__ n_pairs) {
+    __shared__ uint64_t sums[1024];
+    const int per = (nt + 1023) / 1024;
+    const int t0 = threadIdx.x * per, t1 = min(nt, t0 + per);
+    uint64_t s = 0;
+    for (int t = t0; t < t1; ++t) s += total[t];
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t run = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const uint64_t v = sums[i];
+            sums[i] = run;
+            run += v;
+        }
+        n_pairs[0] = run;
+    }
+    __syncthreads();
+    uint64_t run = sums[threadIdx.x];
+    for (int t = t0; t < t1; ++t) {
+        const uint32_t n = total[t];
+        start[t] = (uint32_t)run;
+        ranges[2 * t] = n ? (uint32_t)run : 0u;  // empty tiles: (0, 0)
+        run += n;
+        ranges[2 * t + 1] = n ? (uint32_t)run : 0u;
+    }
+}
+
+// h[c][t] <- start[t] + (number of pairs of tile t in chunks before c)
+__global__ __launch_bounds__(256) void k_chunk_base(int C, int nt, const uint32_t* __restrict__ start,
+                                                    const uint32_t* __restrict__ part, uint32_t* __restrict__ h) {
+    const int nb = (C + PART - 1) / PART;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nb * nt) return;
+    const int b = (int)(i / nt), t = (int)(i % nt);
+    const int c1 = min(C, (b + 1) * PART);
+    uint32_t run = start[t] + part[i];
+    for (int c = b * PART; c < c1; ++c) {
+        const uint32_t v = h[(int64_t)c * nt + t];
+        h[(int64_t)c * nt + t] = run;
+        run += v;
+    }
+}
+
+// One wave per chunk: place the chunk's pairs, Gaussians in depth order.
+// LDS holds the next free slot of every tile for this chunk (initialized
+// from the chunk's bases), so a pair costs one LDS read-increment and one
+// global store.  The tiles of one Gaussian are distinct, so UNROLL groups of
+// 64 of them are read first and written back after, which keeps several LDS
+// round trips in flight; program order still completes a Gaussian before the
+// next one reads the counters.
+constexpr int UNROLL = 4;
+
+__global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int TX, int TY, const uint32_t* __restrict__ order,
+                                                   const float* __restrict__ means2D, const int* __restrict__ radius,
+                                                   const uint32_t* __restrict__ tiles_touched,
+                                                   const uint32_t* __restrict__ base, uint32_t* __restrict__ point_list,
+                                                   uint64_t capacity) {
+    extern __shared__ uint32_t nextpos[];
+    const int nt = TX * TY;
+    const int lane = threadIdx.x;
+    const int c = blockIdx.x;
+    const uint32_t* bc = base + (int64_t)c * nt;
+    for (int t = lane; t < nt; t += 64) nextpos[t] = bc[t];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int m = 0; m < CHUNK / 64; ++m) {
+        const int64_t k0 = (int64_t)c * CHUNK + m * 64;
+        if (k0 >= P) break;
+        const int64_t k = k0 + lane;
+        uint32_t g = 0, n = 0;
+        int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+        if (k < P) {
+            g = order[k];
+            if (tiles_touched[g] != 0 &&
+                tile_rect(means2D[2 * g], means2D[2 * g + 1], radius[g], TX, TY, x0, y0, x1, y1))
+                n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+        }
+        const int cntk = (int)((P - k0) < 64 ? (P - k0) : 64);
+        for (int i = 0; i < cntk; ++i) {
+            const uint32_t ni = __builtin_amdgcn_readlane(n, i);
+            if (ni == 0) continue;
+            const uint32_t gi = __builtin_amdgcn_readlane(g, i);
+            const int xi = __builtin_amdgcn_readlane(x0, i), yi = __builtin_amdgcn_readlane(y0, i);
+            const int wi = __builtin_amdgcn_readlane(x1, i) - xi + 1;
+            const float inv_w = 1.0f / (float)wi;
+            for (uint32_t jb = 0; jb < ni; jb += 64 * UNROLL) {
+                int t[UNROLL];
+                uint32_t pos[UNROLL];
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) {
+                    const uint32_t j = jb + u * 64 + lane;
+                    int q = (int)((float)j * inv_w);
+                    int r = (int)j - q * wi;
+                    if (r >= wi) { ++q; r -= wi; }
+                    if (r < 0) { --q; r += wi; }
+                    t[u] = j < ni ? (yi + q) * TX + xi + r : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) pos[u] = t[u] >= 0 ? nextpos[t[u]] : 0u;
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) {
+                    if (t[u] >= 0) {
+                        nextpos[t[u]] = pos[u] + 1;
+                        if (pos[u] < capacity) point_list[pos[u]] = gi;
+                    }
+                }
+            }
+        }
+    }
+}
+
+struct ListsLayout {
+    size_t dkeys, ids, dkeys2, order, h, part, total, start, temp, temp_bytes, bytes;
+    int C, nb, nt;
+};
+
+static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P) {
+    ListsLayout L{};
+    const size_t n = (size_t)(P > 0 ? P : 1);
+    L.nt = ((width + TILE - 1) / TILE) * ((height + TILE - 1) / TILE);
+    L.C = (int)((n + CHUNK - 1) / CHUNK);
+    L.nb = (L.C + PART - 1) / PART;
+    size_t sort_bytes = 0;
+    (void)rocprim::radix_sort_pairs((void*)nullptr, sort_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                    (uint32_t*)nullptr, (uint32_t*)nullptr, n, 0, 32);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L.dkeys = take(4 * n);
+    L.ids = take(4 * n);
+    L.dkeys2 = take(4 * n);
+    L.order = take(4 * n);
+    L.h = take(4 * (size_t)L.C * L.nt);
+    L.part = take(4 * (size_t)L.nb * L.nt);
+    L.total = take(4 * (size_t)L.nt);
+    L.start = take(4 * (size_t)L.nt);
+    L.temp_bytes = sort_bytes;
+    L.temp = take(sort_bytes);
+    L.bytes = off;
+    return L;
+}
+
+}  // namespace bgs
+
+extern "C" size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P) {
+    if (width <= 0 || height <= 0 || P < 0) return 0;
+    return lists_layout(width, height, P).bytes;
+}
+
+extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
+                                     const int32_t* radius, const float* depth, const uint32_t* tiles_touched,
+                                     uint32_t* point_list, int64_t capacity, uint32_t* ranges, uint64_t* n_pairs_dev,
+                                     void* ws, size_t ws_bytes, hipStream_t stream) {
+    BGS_REQUIRE(width > 0 && height > 0, "bgs_tile_lists: image size must be positive");
+    BGS_REQUIRE(P >= 0 && capacity >= 0, "bgs_tile_lists: negative size");
+    if (tile != TILE) return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: only 16x16 tiles are supported");
+    BGS_REQUIRE(ranges && n_pairs_dev, "bgs_tile_lists: null ranges or n_pairs");
+    BGS_REQUIRE(P < ((int64_t)1 << 31), "bgs_tile_lists: P must be < 2^31");
+    const int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
+    const ListsLayout L = lists_layout(width, height, P);
+    if (L.nt > MAX_FUSED_TILES || (size_t)(TX + 1) * (TY + 1) * sizeof(int) > 65536)
+        return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: tile grid too large for the LDS counters; use bgs_bin + "
+                                      "bgs_sort + bgs_ranges");
+    BGS_REQUIRE(ws && ws_bytes >= L.bytes, "bgs_tile_lists: workspace too small");
+    BGS_REQUIRE(capacity == 0 || point_list != nullptr, "bgs_tile_lists: null point_list");
+    char* w = static_cast<char*>(ws);
+    auto* dkeys = reinterpret_cast<uint32_t*>(w + L.dkeys);
+    auto* ids = reinterpret_cast<uint32_t*>(w + L.ids);
+    auto* dkeys2 = reinterpret_cast<uint32_t*>(w + L.dkeys2);
+    auto* order = reinterpret_cast<uint32_t*>(w + L.order);
+    auto* h = reinterpret_cast<uint32_t*>(w + L.h);
+    auto* part = reinterpret_cast<uint32_t*>(w + L.part);
+    auto* total = reinterpret_cast<uint32_t*>(w + L.total);
+    auto* start = reinterpret_cast<uint32_t*>(w + L.start);
+    if (P == 0) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * (int64_t)L.nt)), dim3(256), 0, stream, ranges,
+                           2 * (int64_t)L.nt, 0u);
+        BGS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t*>(n_pairs_dev),
+                           (int64_t)2, 0u);
+        BGS_HIP(hipGetLastError());
+        return BGS_OK;
+    }
+    size_t temp_bytes = L.temp_bytes;
+    hipLaunchKernelGGL(k_depth_keys, dim3(blocks_for(P)), dim3(256), 0, stream, P, depth, tiles_touched, dkeys, ids);
+    BGS_HIP(hipGetLastError());
+    BGS_HIP(rocprim::radix_sort_pairs(w + L.temp, temp_bytes, dkeys, dkeys2, ids, order, (size_t)P, 0, 32, stream));
+    const size_t lds_hist = sizeof(int) * (size_t)(TX + 1) * (TY + 1);
+    hipLaunchKernelGGL(k_chunk_hist, dim3(L.C), dim3(256), lds_hist, stream, P, TX, TY, order, means2D, radius,
+                       tiles_touched, h);
+    BGS_HIP(hipGetLastError());
+    const int64_t nbt = (int64_t)L.nb * L.nt;
+    hipLaunchKernelGGL(k_part_sums, dim3(blocks_for(nbt)), dim3(256), 0, stream, L.C, L.nt, h, part);
+    BGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_part_scan, dim3(blocks_for(L.nt)), dim3(256), 0, stream, L.nb, L.nt, part, total);
+    BGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.nt, total, start, ranges, n_pairs_dev);
+    BGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(nbt)), dim3(256), 0, stream, L.C, L.nt, start, part, h);
+    BGS_HIP(hipGetLastError());
+    if (capacity > 0) {
+        hipLaunchKernelGGL(k_chunk_emit, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.nt, stream, P, TX, TY,
+                           order, means2D, radius, tiles_touched, h, point_list, (uint64_t)capacity);
+        BGS_HIP(hipGetLastError());
+    }
     return BGS_OK;
 }

@@ -111,6 +111,49 @@ __device__ __forceinline__ float wave_sum(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
+// Transposed reduction of 10 per-lane values over the 64 lanes of a wave
+// (all lanes active).  Each butterfly stage halves the values a lane keeps
+// while it adds its partner's copy (xor 32: 10 -> 5, xor 16: 5 -> 3 (padded),
+// xor 8: 3 -> 2, xor 4: 2 -> 1), then xor 2 and xor 1 finish the sum, so 13
+// exchanges replace 10 full 64-lane reductions.  Value k's total ends in the
+// lanes whose bits (5,4,3,2) = (b5,b4,b3,b2) satisfy
+// k = 5 b5 + 3 b4 + 2 b3 + b2 (with 2 b3 + b2 < 3 and 3 b4 + 2 b3 + b2 < 5).
+// Returns k in the first lane of that quad (others: -1) and the total in out.
+__device__ __forceinline__ int wave_reduce_scatter10(const float (&v)[10], int lane, float& out) {
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+    float a[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const float keep = b5 ? v[5 + i] : v[i];
+        const float send = b5 ? v[i] : v[5 + i];
+        a[i] = keep + __shfl_xor(send, 32, 64);
+    }
+    float c[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float hi = i < 2 ? a[3 + i] : 0.0f;
+        const float keep = b4 ? hi : a[i];
+        const float send = b4 ? a[i] : hi;
+        c[i] = keep + __shfl_xor(send, 16, 64);
+    }
+    float d[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float hi = i == 0 ? c[2] : 0.0f;
+        const float keep = b3 ? hi : c[i];
+        const float send = b3 ? c[i] : hi;
+        d[i] = keep + __shfl_xor(send, 8, 64);
+    }
+    float e = (b2 ? d[1] : d[0]) + __shfl_xor(b2 ? d[0] : d[1], 4, 64);
+    e += __shfl_xor(e, 2, 64);
+    e += __shfl_xor(e, 1, 64);
+    out = e;
+    const int p3 = 2 * (int)b3 + (int)b2;
+    const int p5 = 3 * (int)b4 + p3;
+    const bool valid = p3 < 3 && p5 < 5 && (lane & 3) == 0;
+    return valid ? 5 * (int)b5 + p5 : -1;
+}
+
 __device__ __forceinline__ int wave_max(int v) {
     for (int off = 32; off >= 1; off >>= 1) {
         int o = __shfl_xor(v, off, 64);

@@ -160,6 +160,70 @@ __device__ __forceinline__ void item_pixel(const FrameArgs& F, uint32_t item, in
     any_inside = ox < F.W && oy < F.H;
 }
 
+// Raw (unscaled) splat data of one list entry, held in registers while it is
+// in flight.
+struct SplatRegs {
+    float2 xy;
+    float4 co;
+    float4 cd;
+};
+
+__device__ __forceinline__ void gather_splat(const FrameArgs& F, bool valid, uint32_t g, SplatRegs& r) {
+    if (valid) load_splat(F, g, r.xy, r.co, r.cd);
+}
+
+// ---------------------------------------------------------------- work queue
+// The task pool is NQ = 64 queues, each with its own fetch counter in its own
+// 128-byte line.  Tiles are ranked by cost (heaviest first) and dealt
+// round-robin to 16 groups of 4 queues; the 4 8x8 sub-tiles of a tile go to
+// the 4 queues of its group.  A wave's home queue is (global wave id) mod 64;
+// because workgroups are dispatched to the 8 XCDs round-robin, the 4 waves of
+// a workgroup share one group, so a tile's sub-tiles stay on one XCD's L2.
+// A wave whose queue is empty reads all 64 counters with one vector load
+// (lane q reads counter q), picks the next non-empty queue and claims from it;
+// it leaves when none is left.  One global counter serving every wave of all
+// 8 XCDs was the bottleneck of the first design (same-address device atomics
+// serialize), so the counters are spread over 64 lines.
+constexpr int NQ = 64;
+constexpr int QSTRIDE = 32;  // u32 words between two counters (128 bytes)
+constexpr int QGROUPS = NQ / 4;
+
+struct WorkQueue {
+    uint32_t* ctr;           // ctr[q * QSTRIDE], q < NQ; ctr[NQ * QSTRIDE] = number of items
+    const uint32_t* items;   // items[i * NQ + q] = i-th item of queue q
+    uint32_t n;
+    int cur;
+    __device__ __forceinline__ uint32_t size(int q) const { return n > (uint32_t)q ? (n - q - 1) / NQ + 1 : 0u; }
+};
+
+__device__ __forceinline__ WorkQueue make_queue(uint32_t* ctr, const uint32_t* items, int wave_global) {
+    WorkQueue Q;
+    Q.ctr = ctr;
+    Q.items = items;
+    Q.n = ctr[NQ * QSTRIDE];
+    Q.cur = wave_global & (NQ - 1);
+    return Q;
+}
+
+// Claim the next item for this wave (all 64 lanes active); false when every
+// queue is drained.  Counters only grow, so the exit is final.
+__device__ __forceinline__ bool queue_next(WorkQueue& Q, int lane, uint32_t& item) {
+    for (;;) {
+        uint32_t q = 0;
+        if (lane == 0) q = atomicAdd(&Q.ctr[Q.cur * QSTRIDE], 1u);
+        q = __builtin_amdgcn_readfirstlane(q);
+        if (q < Q.size(Q.cur)) {
+            item = Q.items[(size_t)q * NQ + Q.cur];
+            return true;
+        }
+        const uint32_t c = __hip_atomic_load(&Q.ctr[lane * QSTRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t m = ballot(c < Q.size(lane));
+        if (m == 0) return false;
+        const uint64_t rot = Q.cur ? ((m >> Q.cur) | (m << (64 - Q.cur))) : m;
+        Q.cur = (Q.cur + (int)__builtin_ctzll(rot)) & (NQ - 1);
+    }
+}
+
 template <bool PERSISTENT>
 __global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F, FwdOut O, const uint32_t* __restrict__ items,
                                                    uint32_t* __restrict__ ctr) {
@@ -167,15 +231,12 @@ __global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F, FwdOut O, const 
     __shared__ float4 s_co[4][64];
     __shared__ float4 s_cd[4][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t n_items = PERSISTENT ? ctr[1] : 0u;
+    WorkQueue Q;
+    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
     for (;;) {
         uint32_t item;
         if (PERSISTENT) {
-            uint32_t q = 0;
-            if (lane == 0) q = atomicAdd(&ctr[0], 1u);
-            q = __builtin_amdgcn_readfirstlane(q);
-            if (q >= n_items) break;
-            item = items[q];
+            if (!queue_next(Q, lane, item)) break;
         } else {
             item = blockIdx.x * 4 + wv;
         }
@@ -187,17 +248,23 @@ __global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F, FwdOut O, const 
             const uint32_t start = F.ranges[2 * tile], end = F.ranges[2 * tile + 1];
             Pix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
             const float fx = (float)px, fy = (float)py;
+            // two-stage prefetch: ids two chunks ahead, splat data one chunk ahead
+            SplatRegs cur{}, nxt{};
+            {
+                const uint32_t k0 = start + lane;
+                gather_splat(F, k0 < end, k0 < end ? F.point_list[k0] : 0u, cur);
+            }
+            uint32_t k1 = start + 64 + lane;
+            uint32_t id1 = k1 < end ? F.point_list[k1] : 0u;
             for (uint32_t base = start; base < end; base += 64) {
                 if (ballot(!s.done) == 0) break;
-                const uint32_t k = base + lane;
-                if (k < end) {
-                    float2 xy; float4 co, cd;
-                    load_splat(F, F.point_list[k], xy, co, cd);
-                    s_xy[wv][lane] = xy;
-                    s_co[wv][lane] = co;
-                    s_cd[wv][lane] = cd;
-                }
+                s_xy[wv][lane] = cur.xy;
+                s_co[wv][lane] = cur.co;
+                s_cd[wv][lane] = cur.cd;
                 wave_sync();
+                gather_splat(F, k1 < end, id1, nxt);
+                k1 += 64;
+                id1 = k1 < end ? F.point_list[k1] : 0u;
                 const int cnt = (int)min(64u, end - base);
                 const int pos0 = (int)(base - start);
                 for (int j = 0; j < cnt; ++j) {
@@ -205,6 +272,7 @@ __global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F, FwdOut O, const 
                     blend(fx, fy, s_xy[wv][j], s_co[wv][j], s_cd[wv][j], pos0 + j, s);
                 }
                 wave_sync();
+                cur = nxt;
             }
             if (inside) write_pixel(F, O, px, py, s);
         }
@@ -221,16 +289,13 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F, BwdIO B, const u
     __shared__ float4 s_cd[4][64];
     __shared__ float4 s_abc[4][64];  // raw conic a, b, c and the Gaussian id (bits)
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t n_items = PERSISTENT ? ctr[1] : 0u;
     const int64_t HW = (int64_t)F.W * F.H;
+    WorkQueue Q;
+    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
     for (;;) {
         uint32_t item;
         if (PERSISTENT) {
-            uint32_t q = 0;
-            if (lane == 0) q = atomicAdd(&ctr[0], 1u);
-            q = __builtin_amdgcn_readfirstlane(q);
-            if (q >= n_items) break;
-            item = items[q];
+            if (!queue_next(Q, lane, item)) break;
         } else {
             item = blockIdx.x * 4 + wv;
         }
@@ -309,21 +374,17 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F, BwdIO B, const u
                             v1 = (abc.y * dx + abc.z * dy) * dP;
                         }
                     }
-                    v0 = wave_sum(v0); v1 = wave_sum(v1); v2 = wave_sum(v2); v3 = wave_sum(v3);
-                    v4 = wave_sum(v4); v5 = wave_sum(v5); v6 = wave_sum(v6); v7 = wave_sum(v7);
-                    v8 = wave_sum(v8); v9 = wave_sum(v9);
-                    if (lane == 0) {
+                    const float vals[10] = {v0, v1, v2, v3, v4, v5, v6, v7, v8, v9};
+                    float tot;
+                    const int slot = wave_reduce_scatter10(vals, lane, tot);
+                    if (slot >= 0) {
                         const uint32_t g = __float_as_uint(s_abc[wv][jj].w);
-                        unsafeAtomicAdd(&B.g_means2D[2 * g], v0);
-                        unsafeAtomicAdd(&B.g_means2D[2 * g + 1], v1);
-                        unsafeAtomicAdd(&B.g_conic_opacity[4 * g], v2);
-                        unsafeAtomicAdd(&B.g_conic_opacity[4 * g + 1], v3);
-                        unsafeAtomicAdd(&B.g_conic_opacity[4 * g + 2], v4);
-                        unsafeAtomicAdd(&B.g_conic_opacity[4 * g + 3], v5);
-                        unsafeAtomicAdd(&B.g_rgb[3 * g], v6);
-                        unsafeAtomicAdd(&B.g_rgb[3 * g + 1], v7);
-                        unsafeAtomicAdd(&B.g_rgb[3 * g + 2], v8);
-                        if (B.g_depth) unsafeAtomicAdd(&B.g_depth[g], v9);
+                        float* dst;
+                        if (slot < 2) dst = B.g_means2D + 2 * (size_t)g + slot;
+                        else if (slot < 6) dst = B.g_conic_opacity + 4 * (size_t)g + (slot - 2);
+                        else if (slot < 9) dst = B.g_rgb + 3 * (size_t)g + (slot - 6);
+                        else dst = B.g_depth ? B.g_depth + g : nullptr;
+                        if (dst) unsafeAtomicAdd(dst, tot);
                     }
                 }
                 wave_sync();
@@ -340,42 +401,45 @@ __device__ __forceinline__ int cost_bucket(uint32_t c) {
     return b < NBUCKET - 1 ? b : NBUCKET - 1;
 }
 
-// Cost of every item: forward = list length of its tile; backward = the
-// largest n_contrib among its 64 pixels (one wave per item).
-__global__ __launch_bounds__(256) void k_item_costs(FrameArgs F, const int* __restrict__ n_contrib, uint32_t n_items,
+// Cost of every tile: forward = its list length; backward = the largest
+// n_contrib among its 256 pixels (one workgroup per tile).
+__global__ __launch_bounds__(256) void k_tile_costs(FrameArgs F, const int* __restrict__ n_contrib,
                                                     uint32_t* __restrict__ cost) {
-    const int lane = threadIdx.x & 63;
-    const uint32_t item = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (item >= n_items) return;
-    int tile, px, py;
-    bool any_inside;
-    item_pixel(F, item, lane, tile, px, py, any_inside);
+    __shared__ int wmax[4];
+    const int tile = blockIdx.x;
     uint32_t c = 0;
-    if (any_inside) {
-        if (n_contrib) {
-            const bool inside = px < F.W && py < F.H;
-            const int nc = inside ? n_contrib[(int64_t)py * F.W + px] : 0;
-            c = (uint32_t)wave_max(nc);
-        } else {
-            c = F.ranges[2 * tile + 1] - F.ranges[2 * tile];
-        }
+    if (n_contrib) {
+        const int tx = tile % F.TX, ty = tile / F.TX;
+        const int px = tx * TILE + (threadIdx.x & 15), py = ty * TILE + (threadIdx.x >> 4);
+        const int nc = (px < F.W && py < F.H) ? n_contrib[(int64_t)py * F.W + px] : 0;
+        const int m = wave_max(nc);
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+        __syncthreads();
+        c = (uint32_t)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    } else {
+        c = F.ranges[2 * tile + 1] - F.ranges[2 * tile];
     }
-    if (lane == 0) cost[item] = c;
+    if (threadIdx.x == 0) cost[tile] = c;
 }
 
-// Single workgroup: raster order, or a counting sort by descending cost
-// bucket (largest first).  Also resets the fetch counter: ctr[0] = 0,
-// ctr[1] = number of items.
-__global__ __launch_bounds__(1024) void k_queue(uint32_t n_items, const uint32_t* __restrict__ cost, int by_cost,
+// Single workgroup: rank tiles (raster order, or by descending cost bucket)
+// and deal them: tile of rank r goes to queue group r mod 16, its sub-tile s
+// to queue 4 (r mod 16) + s, at queue position r / 16.  Also resets the 64
+// fetch counters and stores the item count.
+__global__ __launch_bounds__(1024) void k_queue(int n_tiles, const uint32_t* __restrict__ cost, int by_cost,
                                                 uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
     __shared__ uint32_t hist[NBUCKET];
+    auto deal = [&](uint32_t r, uint32_t tile) {
+        const uint32_t grp = r % QGROUPS, pos = r / QGROUPS;
+        for (uint32_t sub = 0; sub < 4; ++sub) items[(size_t)pos * NQ + grp * 4 + sub] = tile * 4 + sub;
+    };
     if (!by_cost) {
-        for (uint32_t i = threadIdx.x; i < n_items; i += blockDim.x) items[i] = i;
+        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x) deal(t, t);
     } else {
         for (int b = threadIdx.x; b < NBUCKET; b += blockDim.x) hist[b] = 0;
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < n_items; i += blockDim.x)
-            atomicAdd(&hist[NBUCKET - 1 - cost_bucket(cost[i])], 1u);
+        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x)
+            atomicAdd(&hist[NBUCKET - 1 - cost_bucket(cost[t])], 1u);
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t run = 0;
@@ -386,15 +450,11 @@ __global__ __launch_bounds__(1024) void k_queue(uint32_t n_items, const uint32_t
             }
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < n_items; i += blockDim.x) {
-            const uint32_t pos = atomicAdd(&hist[NBUCKET - 1 - cost_bucket(cost[i])], 1u);
-            items[pos] = i;
-        }
+        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x)
+            deal(atomicAdd(&hist[NBUCKET - 1 - cost_bucket(cost[t])], 1u), t);
     }
-    if (threadIdx.x == 0) {
-        ctr[0] = 0;
-        ctr[1] = n_items;
-    }
+    for (int q = threadIdx.x; q < NQ; q += blockDim.x) ctr[q * QSTRIDE] = 0;
+    if (threadIdx.x == 0) ctr[NQ * QSTRIDE] = (uint32_t)n_tiles * 4u;
 }
 
 // ---------------------------------------------------------------- host side
@@ -412,9 +472,11 @@ static RenderLayout render_layout(int n_tiles) {
         off = align_up(off + b, 256);
         return o;
     };
-    L.ctr = take(256);
-    L.items = take(4 * (size_t)(L.n_items ? L.n_items : 1));
-    L.cost = take(4 * (size_t)(L.n_items ? L.n_items : 1));
+    L.ctr = take(4 * (size_t)(NQ * QSTRIDE + QSTRIDE));
+    // the item array is padded to whole rounds of NQ
+    const size_t rounds = ((size_t)n_tiles + QGROUPS - 1) / QGROUPS;
+    L.items = take(4 * (rounds * NQ > 0 ? rounds * NQ : 1));
+    L.cost = take(4 * (size_t)(n_tiles ? n_tiles : 1));
     L.bytes = off;
     return L;
 }
@@ -468,11 +530,10 @@ static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, con
     auto* cost = reinterpret_cast<uint32_t*>(ws + L.cost);
     const int by_cost = cfg->order == BGS_ORDER_COST;
     if (by_cost) {
-        hipLaunchKernelGGL(k_item_costs, dim3((L.n_items + 3) / 4), dim3(256), 0, stream, A, n_contrib, L.n_items,
-                           cost);
+        hipLaunchKernelGGL(k_tile_costs, dim3(A.n_tiles), dim3(256), 0, stream, A, n_contrib, cost);
         BGS_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, L.n_items, cost, by_cost, items, ctr);
+    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, A.n_tiles, cost, by_cost, items, ctr);
     BGS_HIP(hipGetLastError());
     return BGS_OK;
 }

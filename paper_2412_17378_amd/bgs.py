@@ -71,7 +71,7 @@ def lib() -> C.CDLL:
             "bgs_sort_workspace_bytes": ([_i64], _sz),
             "bgs_sort": ([_vp, _vp, _vp, _vp, _i64, _i32, _vp, _sz, _vp], C.c_int),
             "bgs_ranges": ([_vp, _i64, _i32, _vp, _vp], C.c_int),
-            "bgs_tile_lists_workspace_bytes": ([_i32, _i32, _i64], _sz),
+            "bgs_tile_lists_workspace_bytes": ([_i32, _i32, _i64, _i64], _sz),
             "bgs_tile_lists": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp],
                                C.c_int),
             "bgs_render_workspace_bytes": ([_vp, _vp], _sz),
@@ -154,7 +154,8 @@ def n_tiles(width: int, height: int) -> int:
 def tile_lists_supported(width: int, height: int) -> bool:
     """Whether bgs_tile_lists handles this tile grid (see include/bgs.h)."""
     tx, ty = (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
-    return tx * ty <= 16384 and (tx + 1) * (ty + 1) * 4 <= 65536
+    gx, gy = (tx + 3) // 4, (ty + 3) // 4
+    return gx * gy <= 8192 and (gx + 1) * (gy + 1) * 4 <= 65536 and tx <= 65535 and ty <= 65535
 
 
 _DUMMY = {}
@@ -245,19 +246,24 @@ def bgs_ranges(sorted_keys, n: int, n_tiles_: int, ranges, stream=None):
                                           _ptr(ranges), _stream(stream)))
 
 
-def bgs_tile_lists_workspace_bytes(width: int, height: int, P: int) -> int:
-    return int(lib().bgs_tile_lists_workspace_bytes(int(width), int(height), int(P)))
+def bgs_tile_lists_workspace_bytes(width: int, height: int, P: int, capacity: int) -> int:
+    return int(lib().bgs_tile_lists_workspace_bytes(int(width), int(height), int(P), int(capacity)))
 
 
 def bgs_tile_lists(width, height, means2D, radius, depth, tiles_touched, point_list, ranges, n_pairs_dev, ws,
-                   stream=None):
-    """Asynchronous; n_pairs_dev (int64 [>=1] device tensor) receives M."""
+                   stream=None) -> bool:
+    """n_pairs_dev (int64 [>=1] device tensor) receives M (or a lower bound).
+    Returns False when the capacity was visibly too small (BGS_ECAPACITY);
+    the caller then compares n_pairs_dev with the capacity and grows."""
     cap = 0 if point_list is None else point_list.numel()
     _expect(ranges, (n_tiles(width, height), 2), torch.int32, "ranges")
-    _check("bgs_tile_lists", lib().bgs_tile_lists(int(width), int(height), TILE, means2D.shape[0], _ptr(means2D),
-                                                  _ptr(radius), _ptr(depth), _ptr(tiles_touched),
-                                                  _ptr(point_list) if cap else None, cap, _ptr(ranges),
-                                                  _ptr(n_pairs_dev), _ptr(ws), ws.numel(), _stream(stream)))
+    st = lib().bgs_tile_lists(int(width), int(height), TILE, means2D.shape[0], _ptr(means2D), _ptr(radius),
+                              _ptr(depth), _ptr(tiles_touched), _ptr(point_list) if cap else None, cap, _ptr(ranges),
+                              _ptr(n_pairs_dev), _ptr(ws), ws.numel(), _stream(stream))
+    if st == BGS_ECAPACITY:
+        return False
+    _check("bgs_tile_lists", st)
+    return True
 
 
 def bgs_render_workspace_bytes(frame: Frame, cfg: RenderCfg) -> int:

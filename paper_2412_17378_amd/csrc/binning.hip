@@ -236,64 +236,93 @@ extern "C" bgs_status bgs_ranges(const uint32_t* sorted_keys, int64_t n, int32_t
 }
 
 // ======================================================================
-// Fused tile lists: bin + stable sort by tile + ranges in one counting pass.
-//
-// The Gaussians are first put in depth order (a P-element sort).  That order
-// is cut into chunks of CHUNK Gaussians.  For every chunk c and tile t,
-// h[c][t] = number of the chunk's Gaussians whose square meets t (a 2D
-// difference array per chunk in LDS: four updates per Gaussian, then a 2D
-// prefix sum).  A column scan over chunks gives each (chunk, tile) its base
-// position inside the tile's segment, and an exclusive scan over tiles gives
-// the segments (= ranges).  Finally one wave per chunk walks its Gaussians in
-// depth order and drops each into its tiles at base + running count, which
-// reproduces a stable sort by tile of the depth-ordered pairs without ever
+// Fused tile lists: bin + stable sort by tile + ranges, without ever
 // materializing or sorting the M (tile, Gaussian) keys.
+//
+// 1. The Gaussians are put in depth order (a P-element sort) and each one's
+//    tile rectangle is computed once.
+// 2. Coarse lists per group of 4x4 tiles (64x64 px): a stable counting sort of
+//    the (group, Gaussian) pairs.  The depth order is cut into chunks of
+//    CHUNK Gaussians; per chunk a group histogram (2D difference array in LDS,
+//    four updates per Gaussian, then a 2D prefix sum), a column scan over
+//    chunks and a scan over groups give every (chunk, group) its base slot,
+//    and one wave per chunk drops the chunk's pairs, in depth order, at base +
+//    running count.  With 510 groups at 1080p the runs a chunk writes per
+//    group are long enough for the stores to combine in L2.
+// 3. Fine lists: one workgroup per group reads its coarse list (in depth
+//    order) and splits it into its 16 tile lists; each wave owns 4 tiles and
+//    appends, with a ballot and a prefix count, the Gaussians whose rectangle
+//    contains the tile -- coalesced sequential appends, first counting (to
+//    size the tiles), then writing.
+// The result is exactly the list a stable sort of the depth-ordered
+// (tile, Gaussian) pairs by tile gives.
 // ======================================================================
 namespace bgs {
 
-constexpr int CHUNK = 256;       // Gaussians per chunk
+constexpr int CHUNK = 256;       // Gaussians per chunk of the coarse sort
 constexpr int PART = 64;         // chunks per column-scan block
-constexpr int MAX_FUSED_TILES = 16384;
+constexpr int GSHIFT = 2;        // group = 4x4 tiles
+constexpr int GTILES = 1 << GSHIFT;
+constexpr int MAX_GROUPS = 8192;
 
-__global__ __launch_bounds__(256) void k_chunk_hist(int64_t P, int TX, int TY, const uint32_t* __restrict__ order,
-                                                    const float* __restrict__ means2D, const int* __restrict__ radius,
-                                                    const uint32_t* __restrict__ tiles_touched,
-                                                    uint32_t* __restrict__ h) {
-    extern __shared__ int d[];  // (TY+1) x (TX+1) difference grid
-    const int GX = TX + 1, GY = TY + 1, nt = TX * TY;
+// rect[g] = (x0 | y0 << 16, x1 | y1 << 16) of Gaussian g's tile rectangle;
+// an empty one has x0 > x1.
+__global__ __launch_bounds__(256) void k_rects(int64_t P, int TX, int TY, const float* __restrict__ means2D,
+                                               const int* __restrict__ radius,
+                                               const uint32_t* __restrict__ tiles_touched, uint2* __restrict__ rect) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= P) return;
+    int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
+    if (tiles_touched[g] == 0 || !tile_rect(means2D[2 * g], means2D[2 * g + 1], radius[g], TX, TY, x0, y0, x1, y1)) {
+        x0 = 1; y0 = 0; x1 = 0; y1 = 0;
+    }
+    rect[g] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
+}
+
+__device__ __forceinline__ bool group_rect(uint2 r, int& x0, int& y0, int& x1, int& y1) {
+    x0 = (int)(r.x & 0xFFFF); y0 = (int)(r.x >> 16); x1 = (int)(r.y & 0xFFFF); y1 = (int)(r.y >> 16);
+    if (x0 > x1) return false;
+    x0 >>= GSHIFT; y0 >>= GSHIFT; x1 >>= GSHIFT; y1 >>= GSHIFT;
+    return true;
+}
+
+// h[c][grp] = number of chunk c's Gaussians whose rectangle meets group grp
+__global__ __launch_bounds__(256) void k_chunk_hist(int64_t P, int GX, int GY, const uint32_t* __restrict__ order,
+                                                    const uint2* __restrict__ rect, uint32_t* __restrict__ h) {
+    extern __shared__ int d[];  // (GY+1) x (GX+1) difference grid
+    const int W1 = GX + 1, H1 = GY + 1, ng = GX * GY;
     const int c = blockIdx.x;
-    for (int i = threadIdx.x; i < GX * GY; i += blockDim.x) d[i] = 0;
+    for (int i = threadIdx.x; i < W1 * H1; i += blockDim.x) d[i] = 0;
     __syncthreads();
     const int64_t k = (int64_t)c * CHUNK + threadIdx.x;
     if (k < P) {
-        const uint32_t g = order[k];
         int x0, y0, x1, y1;
-        if (tiles_touched[g] != 0 && tile_rect(means2D[2 * g], means2D[2 * g + 1], radius[g], TX, TY, x0, y0, x1, y1)) {
-            atomicAdd(&d[y0 * GX + x0], 1);
-            atomicAdd(&d[y0 * GX + x1 + 1], -1);
-            atomicAdd(&d[(y1 + 1) * GX + x0], -1);
-            atomicAdd(&d[(y1 + 1) * GX + x1 + 1], 1);
+        if (group_rect(rect[order[k]], x0, y0, x1, y1)) {
+            atomicAdd(&d[y0 * W1 + x0], 1);
+            atomicAdd(&d[y0 * W1 + x1 + 1], -1);
+            atomicAdd(&d[(y1 + 1) * W1 + x0], -1);
+            atomicAdd(&d[(y1 + 1) * W1 + x1 + 1], 1);
         }
     }
     __syncthreads();
-    for (int y = threadIdx.x; y < GY; y += blockDim.x) {
+    for (int y = threadIdx.x; y < H1; y += blockDim.x) {
         int run = 0;
-        for (int x = 0; x < GX; ++x) {
-            run += d[y * GX + x];
-            d[y * GX + x] = run;
+        for (int x = 0; x < W1; ++x) {
+            run += d[y * W1 + x];
+            d[y * W1 + x] = run;
         }
     }
     __syncthreads();
-    for (int x = threadIdx.x; x < GX; x += blockDim.x) {
+    for (int x = threadIdx.x; x < W1; x += blockDim.x) {
         int run = 0;
-        for (int y = 0; y < GY; ++y) {
-            run += d[y * GX + x];
-            d[y * GX + x] = run;
+        for (int y = 0; y < H1; ++y) {
+            run += d[y * W1 + x];
+            d[y * W1 + x] = run;
         }
     }
     __syncthreads();
-    uint32_t* hc = h + (int64_t)c * nt;
-    for (int t = threadIdx.x; t < nt; t += blockDim.x) hc[t] = (uint32_t)d[(t / TX) * GX + (t % TX)];
+    uint32_t* hc = h + (int64_t)c * ng;
+    for (int t = threadIdx.x; t < ng; t += blockDim.x) hc[t] = (uint32_t)d[(t / GX) * W1 + (t % GX)];
 }
 
 // part[b][t] = sum of h[c][t] over the chunks c of block b
@@ -323,7 +352,8 @@ __global__ __launch_bounds__(256) void k_part_scan(int nb, int nt, uint32_t* __r
     total[t] = run;
 }
 
-// Single workgroup: exclusive scan of total over tiles -> start; ranges; M.
+// Single workgroup: exclusive scan of total -> start; ranges (empty: (0, 0));
+// the grand total in n_pairs[0].
 __global__ __launch_bounds__(1024) void k_tile_scan(int nt, const uint32_t* __restrict__ total,
                                                     uint32_t* __restrict__ start, uint32_t* __restrict__ ranges,
                                                     uint64_t* __restrict__ n_pairs) {
@@ -348,13 +378,15 @@ __global__ __launch_bounds__(1024) void k_tile_scan(int nt, const uint32_t* __re
     for (int t = t0; t < t1; ++t) {
         const uint32_t n = total[t];
         start[t] = (uint32_t)run;
-        ranges[2 * t] = n ? (uint32_t)run : 0u;  // empty tiles: (0, 0)
+        if (ranges) {
+            ranges[2 * t] = n ? (uint32_t)run : 0u;
+            ranges[2 * t + 1] = n ? (uint32_t)(run + n) : 0u;
+        }
         run += n;
-        ranges[2 * t + 1] = n ? (uint32_t)run : 0u;
     }
 }
 
-// h[c][t] <- start[t] + (number of pairs of tile t in chunks before c)
+// h[c][t] <- start[t] + (number of pairs of t in chunks before c)
 __global__ __launch_bounds__(256) void k_chunk_base(int C, int nt, const uint32_t* __restrict__ start,
                                                     const uint32_t* __restrict__ part, uint32_t* __restrict__ h) {
     const int nb = (C + PART - 1) / PART;
@@ -370,26 +402,18 @@ __global__ __launch_bounds__(256) void k_chunk_base(int C, int nt, const uint32_
     }
 }
 
-// One wave per chunk: place the chunk's pairs, Gaussians in depth order.
-// LDS holds the next free slot of every tile for this chunk (initialized
-// from the chunk's bases), so a pair costs one LDS read-increment and one
-// global store.  The tiles of one Gaussian are distinct, so UNROLL groups of
-// 64 of them are read first and written back after, which keeps several LDS
-// round trips in flight; program order still completes a Gaussian before the
-// next one reads the counters.
-constexpr int UNROLL = 4;
-
-__global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int TX, int TY, const uint32_t* __restrict__ order,
-                                                   const float* __restrict__ means2D, const int* __restrict__ radius,
-                                                   const uint32_t* __restrict__ tiles_touched,
-                                                   const uint32_t* __restrict__ base, uint32_t* __restrict__ point_list,
-                                                   uint64_t capacity) {
-    extern __shared__ uint32_t nextpos[];
-    const int nt = TX * TY;
+// One wave per chunk: drop the chunk's (group, Gaussian) pairs, Gaussians in
+// depth order, at the chunk's base slot of each group plus a running count
+// kept in LDS.
+__global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, const uint32_t* __restrict__ order,
+                                                   const uint2* __restrict__ rect, const uint32_t* __restrict__ base,
+                                                   uint32_t* __restrict__ coarse) {
+    extern __shared__ uint32_t nextpos[];  // ng running slots
+    const int ng = GX * GY;
     const int lane = threadIdx.x;
     const int c = blockIdx.x;
-    const uint32_t* bc = base + (int64_t)c * nt;
-    for (int t = lane; t < nt; t += 64) nextpos[t] = bc[t];
+    const uint32_t* bc = base + (int64_t)c * ng;
+    for (int t = lane; t < ng; t += 64) nextpos[t] = bc[t];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -401,9 +425,7 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int TX, int TY, co
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
         if (k < P) {
             g = order[k];
-            if (tiles_touched[g] != 0 &&
-                tile_rect(means2D[2 * g], means2D[2 * g + 1], radius[g], TX, TY, x0, y0, x1, y1))
-                n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+            if (group_rect(rect[g], x0, y0, x1, y1)) n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
         }
         const int cntk = (int)((P - k0) < 64 ? (P - k0) : 64);
         for (int i = 0; i < cntk; ++i) {
@@ -413,41 +435,142 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int TX, int TY, co
             const int xi = __builtin_amdgcn_readlane(x0, i), yi = __builtin_amdgcn_readlane(y0, i);
             const int wi = __builtin_amdgcn_readlane(x1, i) - xi + 1;
             const float inv_w = 1.0f / (float)wi;
-            for (uint32_t jb = 0; jb < ni; jb += 64 * UNROLL) {
-                int t[UNROLL];
-                uint32_t pos[UNROLL];
-#pragma unroll
-                for (int u = 0; u < UNROLL; ++u) {
-                    const uint32_t j = jb + u * 64 + lane;
-                    int q = (int)((float)j * inv_w);
-                    int r = (int)j - q * wi;
-                    if (r >= wi) { ++q; r -= wi; }
-                    if (r < 0) { --q; r += wi; }
-                    t[u] = j < ni ? (yi + q) * TX + xi + r : -1;
-                }
-#pragma unroll
-                for (int u = 0; u < UNROLL; ++u) pos[u] = t[u] >= 0 ? nextpos[t[u]] : 0u;
-#pragma unroll
-                for (int u = 0; u < UNROLL; ++u) {
-                    if (t[u] >= 0) {
-                        nextpos[t[u]] = pos[u] + 1;
-                        if (pos[u] < capacity) point_list[pos[u]] = gi;
-                    }
-                }
+            for (uint32_t j = lane; j < ni; j += 64) {
+                int q = (int)((float)j * inv_w);
+                int r = (int)j - q * wi;
+                if (r >= wi) { ++q; r -= wi; }
+                if (r < 0) { --q; r += wi; }
+                const int t = (yi + q) * GX + xi + r;
+                const uint32_t pos = nextpos[t];
+                nextpos[t] = pos + 1;
+                coarse[pos] = gi;
             }
         }
     }
 }
 
+// The fine split runs on segments of SEG consecutive coarse entries of one
+// group, so that a heavily covered group does not serialize on one
+// workgroup.  nseg[g] = ceil(gtotal[g] / SEG).
+constexpr int SEG = 2048;
+
+__global__ __launch_bounds__(256) void k_seg_count(int ng, const uint32_t* __restrict__ gtotal,
+                                                   uint32_t* __restrict__ nseg) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < ng) nseg[g] = (gtotal[g] + SEG - 1) / SEG;
+}
+
+// segmap[segstart[g] + s] = (g, s)
+__global__ __launch_bounds__(256) void k_seg_map(int ng, const uint32_t* __restrict__ nseg,
+                                                 const uint32_t* __restrict__ segstart, uint2* __restrict__ segmap) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const uint32_t n = nseg[g], b = segstart[g];
+    for (uint32_t q = 0; q < n; ++q) segmap[b + q] = make_uint2((uint32_t)g, q);
+}
+
+// One workgroup per segment; wave w owns the group's tiles 4w .. 4w+3 (local
+// (i % 4, i / 4)) and walks the segment's entries in order.
+// COUNT: segcnt[seg][i] = entries whose rectangle contains local tile i.
+// WRITE: append each such entry at segcnt[seg][i] (by then the slot where
+// this segment's run of tile i starts) + running count.
+template <bool WRITE>
+__global__ __launch_bounds__(256) void k_seg_split(int TX, int TY, int GX, const uint64_t* __restrict__ n_segs,
+                                                   const uint2* __restrict__ segmap,
+                                                   const uint32_t* __restrict__ coarse,
+                                                   const uint32_t* __restrict__ gstart,
+                                                   const uint32_t* __restrict__ gtotal,
+                                                   const uint2* __restrict__ rect, uint32_t* __restrict__ segcnt,
+                                                   uint32_t* __restrict__ point_list, uint64_t capacity) {
+    const uint32_t sidx = blockIdx.x;
+    if (sidx >= n_segs[0]) return;
+    const uint2 gs = segmap[sidx];
+    const int grp = (int)gs.x;
+    const int gx = grp % GX, gy = grp / GX;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int tx[4], ty[4];
+    bool ok[4];
+    uint32_t run[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int li = wv * 4 + u;
+        tx[u] = gx * GTILES + (li % GTILES);
+        ty[u] = gy * GTILES + (li / GTILES);
+        ok[u] = tx[u] < TX && ty[u] < TY;
+        run[u] = WRITE ? segcnt[(size_t)sidx * 16 + li] : 0u;
+    }
+    const uint32_t gt = gtotal[grp];
+    const uint32_t e0 = gs.y * SEG;
+    const uint32_t e1 = min(gt, e0 + SEG);
+    const uint32_t b0 = gstart[grp];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (uint32_t k0 = e0; k0 < e1; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        uint32_t g = 0;
+        int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
+        if (k < e1) {
+            g = coarse[b0 + k];
+            const uint2 r = rect[g];
+            x0 = (int)(r.x & 0xFFFF); y0 = (int)(r.x >> 16); x1 = (int)(r.y & 0xFFFF); y1 = (int)(r.y >> 16);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool in = ok[u] && x0 <= tx[u] && tx[u] <= x1 && y0 <= ty[u] && ty[u] <= y1;
+            const uint64_t m = ballot(in);
+            if (WRITE && in) {
+                const uint64_t pos = (uint64_t)run[u] + __builtin_popcountll(m & lt);
+                if (pos < capacity) point_list[pos] = g;
+            }
+            run[u] += (uint32_t)__builtin_popcountll(m);
+        }
+    }
+    if (!WRITE && lane == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) segcnt[(size_t)sidx * 16 + wv * 4 + u] = run[u];
+    }
+}
+
+// One thread per (group, local tile i).  OFFSETS = false: ttotal[tile] = sum
+// of the tile's segment counts.  OFFSETS = true: the counts become the
+// tile's slot at the start of each segment's run (from tstart).
+template <bool OFFSETS>
+__global__ __launch_bounds__(256) void k_seg_scan(int TX, int TY, int GX, int ng, const uint32_t* __restrict__ nseg,
+                                                  const uint32_t* __restrict__ segstart, uint32_t* __restrict__ segcnt,
+                                                  const uint32_t* __restrict__ tstart, uint32_t* __restrict__ ttotal) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ng * 16) return;
+    const int grp = idx >> 4, li = idx & 15;
+    const int tx = (grp % GX) * GTILES + (li % GTILES), ty = (grp / GX) * GTILES + (li / GTILES);
+    if (tx >= TX || ty >= TY) return;
+    const int tile = ty * TX + tx;
+    const uint32_t n = nseg[grp], b = segstart[grp];
+    uint32_t run = OFFSETS ? tstart[tile] : 0u;
+    for (uint32_t q = 0; q < n; ++q) {
+        uint32_t& c = segcnt[(size_t)(b + q) * 16 + li];
+        const uint32_t v = c;
+        if (OFFSETS) c = run;
+        run += v;
+    }
+    if (!OFFSETS) ttotal[tile] = run;
+}
+
 struct ListsLayout {
-    size_t dkeys, ids, dkeys2, order, h, part, total, start, temp, temp_bytes, bytes;
-    int C, nb, nt;
+    size_t dkeys, ids, dkeys2, order, rect, h, part, gtotal, gstart, nseg, segstart, nsegs, coarse_cap, coarse, ttotal,
+        tstart, temp, temp_bytes, bytes;
+    size_t max_segs, segmap, segcnt;
+    int C, nb, GX, GY, ng, nt;
 };
 
-static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P) {
+// the coarse list is at most a fraction of M; its capacity is sized from the
+// pairs of the previous call through coarse_cap (grown on demand by the host)
+static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P, size_t coarse_cap) {
     ListsLayout L{};
     const size_t n = (size_t)(P > 0 ? P : 1);
-    L.nt = ((width + TILE - 1) / TILE) * ((height + TILE - 1) / TILE);
+    const int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
+    L.nt = TX * TY;
+    L.GX = (TX + GTILES - 1) / GTILES;
+    L.GY = (TY + GTILES - 1) / GTILES;
+    L.ng = L.GX * L.GY;
     L.C = (int)((n + CHUNK - 1) / CHUNK);
     L.nb = (L.C + PART - 1) / PART;
     size_t sort_bytes = 0;
@@ -463,10 +586,22 @@ static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P) {
     L.ids = take(4 * n);
     L.dkeys2 = take(4 * n);
     L.order = take(4 * n);
-    L.h = take(4 * (size_t)L.C * L.nt);
-    L.part = take(4 * (size_t)L.nb * L.nt);
-    L.total = take(4 * (size_t)L.nt);
-    L.start = take(4 * (size_t)L.nt);
+    L.rect = take(8 * n);
+    L.h = take(4 * (size_t)L.C * L.ng);
+    L.part = take(4 * (size_t)L.nb * L.ng);
+    L.gtotal = take(4 * (size_t)L.ng);
+    L.gstart = take(4 * (size_t)L.ng);
+    L.nseg = take(4 * (size_t)L.ng);
+    L.segstart = take(4 * (size_t)L.ng);
+    L.nsegs = take(8);
+    L.ttotal = take(4 * (size_t)L.nt);
+    L.tstart = take(4 * (size_t)L.nt);
+    L.coarse_cap = coarse_cap;
+    L.coarse = take(4 * (coarse_cap > 0 ? coarse_cap : 1));
+    // segments: at most coarse_cap / SEG + ng of them
+    L.max_segs = coarse_cap / SEG + (size_t)L.ng + 1;
+    L.segmap = take(8 * L.max_segs);
+    L.segcnt = take(4 * 16 * L.max_segs);
     L.temp_bytes = sort_bytes;
     L.temp = take(sort_bytes);
     L.bytes = off;
@@ -475,9 +610,11 @@ static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P) {
 
 }  // namespace bgs
 
-extern "C" size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P) {
-    if (width <= 0 || height <= 0 || P < 0) return 0;
-    return lists_layout(width, height, P).bytes;
+// Every (group, Gaussian) pair stands for at least one (tile, Gaussian) pair,
+// so a coarse list of the point list's capacity always suffices.
+extern "C" size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P, int64_t capacity) {
+    if (width <= 0 || height <= 0 || P < 0 || capacity < 0) return 0;
+    return lists_layout(width, height, P, (size_t)capacity).bytes;
 }
 
 extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
@@ -490,10 +627,10 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
     BGS_REQUIRE(ranges && n_pairs_dev, "bgs_tile_lists: null ranges or n_pairs");
     BGS_REQUIRE(P < ((int64_t)1 << 31), "bgs_tile_lists: P must be < 2^31");
     const int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
-    const ListsLayout L = lists_layout(width, height, P);
-    if (L.nt > MAX_FUSED_TILES || (size_t)(TX + 1) * (TY + 1) * sizeof(int) > 65536)
-        return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: tile grid too large for the LDS counters; use bgs_bin + "
-                                      "bgs_sort + bgs_ranges");
+    const ListsLayout L = lists_layout(width, height, P, (size_t)capacity);
+    if (L.ng > MAX_GROUPS || (size_t)(L.GX + 1) * (L.GY + 1) * sizeof(int) > 65536 || TX > 65535 || TY > 65535)
+        return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: tile grid too large (over 8192 groups of 4x4 tiles); use "
+                                      "bgs_bin + bgs_sort + bgs_ranges");
     BGS_REQUIRE(ws && ws_bytes >= L.bytes, "bgs_tile_lists: workspace too small");
     BGS_REQUIRE(capacity == 0 || point_list != nullptr, "bgs_tile_lists: null point_list");
     char* w = static_cast<char*>(ws);
@@ -501,10 +638,14 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
     auto* ids = reinterpret_cast<uint32_t*>(w + L.ids);
     auto* dkeys2 = reinterpret_cast<uint32_t*>(w + L.dkeys2);
     auto* order = reinterpret_cast<uint32_t*>(w + L.order);
+    auto* rect = reinterpret_cast<uint2*>(w + L.rect);
     auto* h = reinterpret_cast<uint32_t*>(w + L.h);
     auto* part = reinterpret_cast<uint32_t*>(w + L.part);
-    auto* total = reinterpret_cast<uint32_t*>(w + L.total);
-    auto* start = reinterpret_cast<uint32_t*>(w + L.start);
+    auto* gtotal = reinterpret_cast<uint32_t*>(w + L.gtotal);
+    auto* gstart = reinterpret_cast<uint32_t*>(w + L.gstart);
+    auto* ttotal = reinterpret_cast<uint32_t*>(w + L.ttotal);
+    auto* tstart = reinterpret_cast<uint32_t*>(w + L.tstart);
+    auto* coarse = reinterpret_cast<uint32_t*>(w + L.coarse);
     if (P == 0) {
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * (int64_t)L.nt)), dim3(256), 0, stream, ranges,
                            2 * (int64_t)L.nt, 0u);
@@ -518,22 +659,65 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
     hipLaunchKernelGGL(k_depth_keys, dim3(blocks_for(P)), dim3(256), 0, stream, P, depth, tiles_touched, dkeys, ids);
     BGS_HIP(hipGetLastError());
     BGS_HIP(rocprim::radix_sort_pairs(w + L.temp, temp_bytes, dkeys, dkeys2, ids, order, (size_t)P, 0, 32, stream));
-    const size_t lds_hist = sizeof(int) * (size_t)(TX + 1) * (TY + 1);
-    hipLaunchKernelGGL(k_chunk_hist, dim3(L.C), dim3(256), lds_hist, stream, P, TX, TY, order, means2D, radius,
-                       tiles_touched, h);
+    hipLaunchKernelGGL(k_rects, dim3(blocks_for(P)), dim3(256), 0, stream, P, TX, TY, means2D, radius, tiles_touched,
+                       rect);
     BGS_HIP(hipGetLastError());
-    const int64_t nbt = (int64_t)L.nb * L.nt;
-    hipLaunchKernelGGL(k_part_sums, dim3(blocks_for(nbt)), dim3(256), 0, stream, L.C, L.nt, h, part);
+    // coarse (group) lists
+    hipLaunchKernelGGL(k_chunk_hist, dim3(L.C), dim3(256), sizeof(int) * (size_t)(L.GX + 1) * (L.GY + 1), stream, P,
+                       L.GX, L.GY, order, rect, h);
     BGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_part_scan, dim3(blocks_for(L.nt)), dim3(256), 0, stream, L.nb, L.nt, part, total);
+    const int64_t nbg = (int64_t)L.nb * L.ng;
+    hipLaunchKernelGGL(k_part_sums, dim3(blocks_for(nbg)), dim3(256), 0, stream, L.C, L.ng, h, part);
     BGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.nt, total, start, ranges, n_pairs_dev);
+    hipLaunchKernelGGL(k_part_scan, dim3(blocks_for(L.ng)), dim3(256), 0, stream, L.nb, L.ng, part, gtotal);
     BGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(nbt)), dim3(256), 0, stream, L.C, L.nt, start, part, h);
+    // the group scan reuses n_pairs_dev[0] for the coarse total; it is
+    // overwritten by the tile scan below
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.ng, gtotal, gstart, (uint32_t*)nullptr,
+                       n_pairs_dev);
     BGS_HIP(hipGetLastError());
-    if (capacity > 0) {
-        hipLaunchKernelGGL(k_chunk_emit, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.nt, stream, P, TX, TY,
-                           order, means2D, radius, tiles_touched, h, point_list, (uint64_t)capacity);
+    uint64_t Mg = 0;
+    BGS_HIP(hipMemcpyAsync(&Mg, n_pairs_dev, sizeof(Mg), hipMemcpyDeviceToHost, stream));
+    BGS_HIP(hipStreamSynchronize(stream));
+    if (Mg > L.coarse_cap)  // then M >= Mg > capacity as well; n_pairs_dev holds the lower bound Mg
+        return fail(BGS_ECAPACITY, "bgs_tile_lists: at least " + std::to_string(Mg) + " pairs exceed capacity " +
+                                       std::to_string(capacity));
+    hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(nbg)), dim3(256), 0, stream, L.C, L.ng, gstart, part, h);
+    BGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_chunk_emit, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX, L.GY,
+                       order, rect, h, coarse);
+    BGS_HIP(hipGetLastError());
+    // fine (tile) lists, on segments of the coarse lists
+    auto* nseg = reinterpret_cast<uint32_t*>(w + L.nseg);
+    auto* segstart = reinterpret_cast<uint32_t*>(w + L.segstart);
+    auto* nsegs = reinterpret_cast<uint64_t*>(w + L.nsegs);
+    auto* segmap = reinterpret_cast<uint2*>(w + L.segmap);
+    auto* segcnt = reinterpret_cast<uint32_t*>(w + L.segcnt);
+    const size_t grid_segs = (size_t)(Mg / SEG) + (size_t)L.ng;  // >= the real segment count
+    if (grid_segs > L.max_segs) return fail(BGS_EINTERNAL, "bgs_tile_lists: segment table overflow");
+    hipLaunchKernelGGL(k_seg_count, dim3(blocks_for(L.ng)), dim3(256), 0, stream, L.ng, gtotal, nseg);
+    BGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.ng, nseg, segstart, (uint32_t*)nullptr, nsegs);
+    BGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_seg_map, dim3(blocks_for(L.ng)), dim3(256), 0, stream, L.ng, nseg, segstart, segmap);
+    BGS_HIP(hipGetLastError());
+    if (grid_segs > 0) {
+        hipLaunchKernelGGL(k_seg_split<false>, dim3((unsigned)grid_segs), dim3(256), 0, stream, TX, TY, L.GX, nsegs,
+                           segmap, coarse, gstart, gtotal, rect, segcnt, (uint32_t*)nullptr, (uint64_t)0);
+        BGS_HIP(hipGetLastError());
+    }
+    const int n_gt = L.ng * 16;
+    hipLaunchKernelGGL(k_seg_scan<false>, dim3(blocks_for(n_gt)), dim3(256), 0, stream, TX, TY, L.GX, L.ng, nseg,
+                       segstart, segcnt, (const uint32_t*)nullptr, ttotal);
+    BGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.nt, ttotal, tstart, ranges, n_pairs_dev);
+    BGS_HIP(hipGetLastError());
+    if (capacity > 0 && grid_segs > 0) {
+        hipLaunchKernelGGL(k_seg_scan<true>, dim3(blocks_for(n_gt)), dim3(256), 0, stream, TX, TY, L.GX, L.ng, nseg,
+                           segstart, segcnt, tstart, (uint32_t*)nullptr);
+        BGS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_seg_split<true>, dim3((unsigned)grid_segs), dim3(256), 0, stream, TX, TY, L.GX, nsegs,
+                           segmap, coarse, gstart, gtotal, rect, segcnt, point_list, (uint64_t)capacity);
         BGS_HIP(hipGetLastError());
     }
     return BGS_OK;

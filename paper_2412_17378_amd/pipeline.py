@@ -106,18 +106,18 @@ class Rasterizer:
             return [self.ws.get(r, 4 * cap).view(torch.int32)[:cap] for r in ("keys", "vals", "skeys", "svals")]
 
         if method == "fused":
-            ws = self.ws.get("lists", B.bgs_tile_lists_workspace_bytes(width, height, P))
             n_dev = self.ws.get("n_pairs", 8).view(torch.int64)[:1]
-            cap = self.pair_capacity
-            pl = self.ws.get("svals", 4 * cap).view(torch.int32)[:cap]
-            B.bgs_tile_lists(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
-                             pl if cap else None, ranges, n_dev, ws)
-            M = int(n_dev.item())
-            if M > cap:
-                self.pair_capacity = cap = int(M * 1.25) + 1024
+            while True:
+                cap = self.pair_capacity
+                ws = self.ws.get("lists", B.bgs_tile_lists_workspace_bytes(width, height, P, cap))
                 pl = self.ws.get("svals", 4 * cap).view(torch.int32)[:cap]
-                B.bgs_tile_lists(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], pl,
-                                 ranges, n_dev, ws)
+                B.bgs_tile_lists(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
+                                 pl if cap else None, ranges, n_dev, ws)
+                M = int(n_dev.item())
+                if M <= cap:
+                    break
+                # grow with headroom and build again
+                self.pair_capacity = int(M * 1.25) + 1024
             skeys, svals = None, pl
         else:
             ws = self.ws.get("bin", B.bgs_bin_workspace_bytes(P))

@@ -29,6 +29,7 @@ namespace bgs {
 constexpr float KA = -0.5f * LOG2E;  // a -> a2
 constexpr float KB = -LOG2E;         // b -> b2
 constexpr int NBUCKET = 136;         // cost buckets: 0 and quarter-octaves of 1 .. 2^33
+constexpr int HYBRID_SWITCH = 16;    // hybrid: Gaussian-wise once <= 16 of 64 pixels are active
 
 struct FrameArgs {
     int W, H, TX, TY, n_tiles;
@@ -280,6 +281,192 @@ __global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F, FwdOut O, const 
     }
 }
 
+// --------------------------------------------------- Gaussian-wise / hybrid
+// Gaussian-wise mode (Sec. 4.2, Alg. 2 and 6): the 64 lanes hold 64
+// consecutive list entries and one pixel is blended at a time.  Each entry's
+// transmittance factor (1 - alpha, or 1 for a skipped entry) goes through an
+// inclusive product scan across the wave; the first non-skipped lane whose
+// T_in * prefix drops below 1e-4 stops the pixel (that entry is not blended),
+// entries before it blend with weight alpha * T_in * (exclusive prefix), and
+// the weighted colour/depth are summed across the wave.  The pixel's state
+// lives in lane p, which is exactly where the pixel-wise mode keeps it, so the
+// hybrid switches a wave from pixel-wise to Gaussian-wise at a chunk boundary
+// once few of its 64 pixels are still active (the stragglers then no longer
+// hold 64 lanes hostage).
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_or(float v, float identity) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, identity),
+                                                                 __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf,
+                                                                 false));
+}
+
+// inclusive product over lanes 0..lane (all 64 lanes active)
+__device__ __forceinline__ float wave_incl_prod(float x) {
+    x *= dpp_or<0x111>(x, 1.0f);        // row_shr:1
+    x *= dpp_or<0x112>(x, 1.0f);        // row_shr:2
+    x *= dpp_or<0x114>(x, 1.0f);        // row_shr:4
+    x *= dpp_or<0x118>(x, 1.0f);        // row_shr:8   -> prefix within each row of 16
+    x *= dpp_or<0x142, 0xA>(x, 1.0f);   // row_bcast:15 -> rows 1, 3 include the previous row
+    x *= dpp_or<0x143, 0xC>(x, 1.0f);   // row_bcast:31 -> rows 2, 3 include rows 0-1
+    return x;
+}
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// Pixel p (state in lane p of s) blends the 64 entries the lanes hold; pos0 is
+// the list position of lane 0.  Clears bit p of act when the pixel stops.
+__device__ __forceinline__ void gw_step(float fx, float fy, float2 xy, float4 co, float4 cd, bool valid, int lane,
+                                        int p, int pos0, Pix& s, uint64_t& act) {
+    const float dx = fx - xy.x, dy = fy - xy.y;
+    const float p2 = splat_power2(dx, dy, co.x, co.y, co.z);
+    const float alpha = fminf(ALPHA_MAX, co.w * exp2_fast(p2));
+    const bool take = valid & !((p2 > 0.0f) | (alpha < ALPHA_MIN));
+    const float incl = wave_incl_prod(take ? 1.0f - alpha : 1.0f);
+    float excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 1.0f;
+    const float Tin = readlane_f(s.T, p);
+    const float Tafter = Tin * incl;
+    const uint64_t stopm = ballot(take & (Tafter < T_MIN));
+    const int f = stopm ? (int)__builtin_ctzll(stopm) : 64;
+    const bool contrib = take & (lane < f);
+    const float Tbefore = Tin * excl;
+    const float w = contrib ? alpha * Tbefore : 0.0f;
+    const float c0 = wave_sum(w * cd.x), c1 = wave_sum(w * cd.y), c2 = wave_sum(w * cd.z), dd = wave_sum(w * cd.w);
+    const uint64_t cm = ballot(contrib);
+    const float Tout = stopm ? readlane_f(Tbefore, f) : readlane_f(Tafter, 63);
+    if (lane == p) {
+        s.T = Tout;
+        s.C0 += c0;
+        s.C1 += c1;
+        s.C2 += c2;
+        s.D += dd;
+        if (cm) s.last = pos0 + 64 - (int)__builtin_clzll(cm);
+        if (stopm) s.done = true;
+    }
+    if (stopm) act &= ~(1ull << p);
+}
+
+// SWITCH_AT = 64: Gaussian-wise from the first chunk; otherwise pixel-wise
+// while more than SWITCH_AT pixels of the wave are active.
+template <int SWITCH_AT>
+__global__ __launch_bounds__(256) void k_fwd_hybrid(FrameArgs F, FwdOut O, const uint32_t* __restrict__ items,
+                                                    uint32_t* __restrict__ ctr) {
+    __shared__ float2 s_xy[4][64];
+    __shared__ float4 s_co[4][64];
+    __shared__ float4 s_cd[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    WorkQueue Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
+    for (;;) {
+        uint32_t item;
+        if (!queue_next(Q, lane, item)) break;
+        int tile, px, py;
+        bool any_inside;
+        item_pixel(F, item, lane, tile, px, py, any_inside);
+        if (!any_inside) continue;
+        const bool inside = px < F.W && py < F.H;
+        const uint32_t start = F.ranges[2 * tile], end = F.ranges[2 * tile + 1];
+        Pix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
+        const float fx = (float)px, fy = (float)py;
+        const int ox = px - (lane & 7), oy = py - (lane >> 3);
+        uint32_t base = start;
+        for (; base < end; base += 64) {  // pixel-wise phase
+            const uint64_t act = ballot(!s.done);
+            if (act == 0 || __builtin_popcountll(act) <= SWITCH_AT) break;
+            const uint32_t k = base + lane;
+            if (k < end) {
+                float2 xy; float4 co, cd;
+                load_splat(F, F.point_list[k], xy, co, cd);
+                s_xy[wv][lane] = xy;
+                s_co[wv][lane] = co;
+                s_cd[wv][lane] = cd;
+            }
+            wave_sync();
+            const int cnt = (int)min(64u, end - base);
+            const int pos0 = (int)(base - start);
+            for (int j = 0; j < cnt; ++j) {
+                if (s.done) break;
+                blend(fx, fy, s_xy[wv][j], s_co[wv][j], s_cd[wv][j], pos0 + j, s);
+            }
+            wave_sync();
+        }
+        uint64_t act = ballot(!s.done);
+        for (; base < end && act; base += 64) {  // Gaussian-wise phase
+            const uint32_t k = base + lane;
+            const bool valid = k < end;
+            float2 xy = make_float2(0.f, 0.f);
+            float4 co = make_float4(0.f, 0.f, 0.f, 0.f), cd = co;
+            if (valid) load_splat(F, F.point_list[k], xy, co, cd);
+            const int pos0 = (int)(base - start);
+            uint64_t todo = act;
+            while (todo) {
+                const int p = (int)__builtin_ctzll(todo);
+                todo &= todo - 1;
+                gw_step((float)(ox + (p & 7)), (float)(oy + (p >> 3)), xy, co, cd, valid, lane, p, pos0, s, act);
+            }
+        }
+        if (inside) write_pixel(F, O, px, py, s);
+    }
+}
+
+// ------------------------------------------------- tile-granular persistent
+// Inter-block dynamic distribution at tile granularity (Sec. 4.1, Alg. 1):
+// persistent 256-lane workgroups take whole 16x16 tiles from the queue and
+// render them like the static kernel (shared 256-Gaussian LDS batches).
+__global__ __launch_bounds__(256) void k_fwd_tile(FrameArgs F, FwdOut O, const uint32_t* __restrict__ items,
+                                                  uint32_t* __restrict__ ctr) {
+    __shared__ float2 s_xy[256];
+    __shared__ float4 s_co[256];
+    __shared__ float4 s_cd[256];
+    __shared__ uint32_t s_item;
+    __shared__ int s_ok;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    WorkQueue Q = make_queue(ctr, items, blockIdx.x);
+    for (;;) {
+        if (wv == 0) {
+            uint32_t it = 0;
+            const bool ok = queue_next(Q, lane, it);
+            if (lane == 0) {
+                s_item = it;
+                s_ok = ok;
+            }
+        }
+        __syncthreads();
+        const bool ok = s_ok;
+        const int tile = (int)s_item;
+        __syncthreads();
+        if (!ok) break;
+        const int tx = tile % F.TX, ty = tile / F.TX;
+        const int px = tx * TILE + (threadIdx.x & 15), py = ty * TILE + (threadIdx.x >> 4);
+        const bool inside = px < F.W && py < F.H;
+        const uint32_t start = F.ranges[2 * tile], end = F.ranges[2 * tile + 1];
+        Pix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
+        const float fx = (float)px, fy = (float)py;
+        for (uint32_t base = start; base < end; base += 256) {
+            if (__syncthreads_count(s.done) == 256) break;
+            const uint32_t k = base + threadIdx.x;
+            if (k < end) {
+                float2 xy; float4 co, cd;
+                load_splat(F, F.point_list[k], xy, co, cd);
+                s_xy[threadIdx.x] = xy;
+                s_co[threadIdx.x] = co;
+                s_cd[threadIdx.x] = cd;
+            }
+            __syncthreads();
+            const int cnt = (int)min(256u, end - base);
+            const int pos0 = (int)(base - start);
+            for (int j = 0; j < cnt; ++j) {
+                if (s.done) break;
+                blend(fx, fy, s_xy[j], s_co[j], s_cd[j], pos0 + j, s);
+            }
+        }
+        __syncthreads();  // LDS batch reads done before the next tile stages
+        if (inside) write_pixel(F, O, px, py, s);
+    }
+}
+
 // ------------------------------------------------------------------ backward
 template <bool PERSISTENT>
 __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F, BwdIO B, const uint32_t* __restrict__ items,
@@ -423,13 +610,19 @@ __global__ __launch_bounds__(256) void k_tile_costs(FrameArgs F, const int* __re
 }
 
 // Single workgroup: rank tiles (raster order, or by descending cost bucket)
-// and deal them: tile of rank r goes to queue group r mod 16, its sub-tile s
-// to queue 4 (r mod 16) + s, at queue position r / 16.  Also resets the 64
-// fetch counters and stores the item count.
+// and deal them.  Sub-tile items: tile of rank r goes to queue group r mod 16,
+// its sub-tile s to queue 4 (r mod 16) + s, at queue position r / 16.  Tile
+// items (per_tile): queue r mod 64, position r / 64.  Also resets the 64 fetch
+// counters and stores the item count.
 __global__ __launch_bounds__(1024) void k_queue(int n_tiles, const uint32_t* __restrict__ cost, int by_cost,
-                                                uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
+                                                int per_tile, uint32_t* __restrict__ items,
+                                                uint32_t* __restrict__ ctr) {
     __shared__ uint32_t hist[NBUCKET];
     auto deal = [&](uint32_t r, uint32_t tile) {
+        if (per_tile) {  // tile of rank r: queue r mod 64, position r / 64, i.e. items[r]
+            items[r] = tile;
+            return;
+        }
         const uint32_t grp = r % QGROUPS, pos = r / QGROUPS;
         for (uint32_t sub = 0; sub < 4; ++sub) items[(size_t)pos * NQ + grp * 4 + sub] = tile * 4 + sub;
     };
@@ -454,7 +647,7 @@ __global__ __launch_bounds__(1024) void k_queue(int n_tiles, const uint32_t* __r
             deal(atomicAdd(&hist[NBUCKET - 1 - cost_bucket(cost[t])], 1u), t);
     }
     for (int q = threadIdx.x; q < NQ; q += blockDim.x) ctr[q * QSTRIDE] = 0;
-    if (threadIdx.x == 0) ctr[NQ * QSTRIDE] = (uint32_t)n_tiles * 4u;
+    if (threadIdx.x == 0) ctr[NQ * QSTRIDE] = (uint32_t)n_tiles * (per_tile ? 1u : 4u);
 }
 
 // ---------------------------------------------------------------- host side
@@ -491,10 +684,8 @@ static bgs_status check_frame(const bgs_frame* f, const bgs_render_cfg* cfg, Fra
         return fail(BGS_EINVAL, std::string(who) + ": means2D must be 8-byte and conic_opacity 16-byte aligned");
     if (cfg->variant < BGS_STATIC || cfg->variant > BGS_BALANCED_HYBRID)
         return fail(BGS_EINVAL, std::string(who) + ": unknown variant");
-    if (cfg->variant != BGS_STATIC && cfg->variant != BGS_BALANCED_PIXEL)
-        return fail(BGS_EUNSUPPORTED, std::string(who) + ": variant not built yet");
-    if (cfg->variant != BGS_STATIC && cfg->subtile != 8)
-        return fail(BGS_EUNSUPPORTED, std::string(who) + ": balanced variants take 8x8 sub-tiles");
+    if (cfg->variant != BGS_STATIC && cfg->subtile != 8 && !(cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 16))
+        return fail(BGS_EUNSUPPORTED, std::string(who) + ": sub-tile must be 8, or 16 with the pixel-wise variant");
     if (cfg->order != BGS_ORDER_RASTER && cfg->order != BGS_ORDER_COST)
         return fail(BGS_EINVAL, std::string(who) + ": unknown order");
     A.W = f->width;
@@ -523,6 +714,10 @@ static int persistent_blocks(K kernel, uint32_t n_items) {
     return (int)(want < cap ? want : (cap > 0 ? cap : 1));
 }
 
+static bool tile_items(const bgs_render_cfg* cfg, bool backward) {
+    return !backward && cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 16;
+}
+
 static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, const int* n_contrib, char* ws,
                               const RenderLayout& L, hipStream_t stream) {
     auto* ctr = reinterpret_cast<uint32_t*>(ws + L.ctr);
@@ -533,7 +728,8 @@ static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, con
         hipLaunchKernelGGL(k_tile_costs, dim3(A.n_tiles), dim3(256), 0, stream, A, n_contrib, cost);
         BGS_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, A.n_tiles, cost, by_cost, items, ctr);
+    const int per_tile = tile_items(cfg, n_contrib != nullptr) ? 1 : 0;
+    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, A.n_tiles, cost, by_cost, per_tile, items, ctr);
     BGS_HIP(hipGetLastError());
     return BGS_OK;
 }
@@ -581,8 +777,19 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
     }
     auto* ctr = reinterpret_cast<uint32_t*>(w + L.ctr);
     auto* items = reinterpret_cast<const uint32_t*>(w + L.items);
-    const int blocks = persistent_blocks(k_fwd_pixel<true>, L.n_items);
-    hipLaunchKernelGGL(k_fwd_pixel<true>, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
+    if (tile_items(cfg, false)) {
+        const int blocks = persistent_blocks(k_fwd_tile, (uint32_t)A.n_tiles * 4u);
+        hipLaunchKernelGGL(k_fwd_tile, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
+    } else if (cfg->variant == BGS_BALANCED_GAUSS) {
+        const int blocks = persistent_blocks(k_fwd_hybrid<64>, L.n_items);
+        hipLaunchKernelGGL(k_fwd_hybrid<64>, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
+    } else if (cfg->variant == BGS_BALANCED_HYBRID) {
+        const int blocks = persistent_blocks(k_fwd_hybrid<HYBRID_SWITCH>, L.n_items);
+        hipLaunchKernelGGL(k_fwd_hybrid<HYBRID_SWITCH>, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
+    } else {
+        const int blocks = persistent_blocks(k_fwd_pixel<true>, L.n_items);
+        hipLaunchKernelGGL(k_fwd_pixel<true>, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
+    }
     BGS_HIP(hipGetLastError());
     return BGS_OK;
 }

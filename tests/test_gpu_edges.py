@@ -15,7 +15,8 @@ from workloads import scenes
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-VARIANTS = [("static", "raster"), ("pixel", "raster"), ("pixel", "cost")]
+VARIANTS = [("static", 16, "raster"), ("pixel", 8, "raster"), ("pixel", 8, "cost"), ("pixel", 16, "cost"),
+            ("gauss", 8, "cost"), ("hybrid", 8, "cost")]
 
 
 @pytest.fixture(scope="module")
@@ -27,8 +28,8 @@ def rast():
 def _render_all(rast, prep, bg=(0.0, 0.0, 0.0)):
     from paper_2412_17378_amd import make_cfg
     outs = {}
-    for v, o in VARIANTS:
-        outs[(v, o)] = rast.render_fwd(prep, make_cfg(v, 8, o, bg))
+    for v, sub, o in VARIANTS:
+        outs[(v, sub, o)] = rast.render_fwd(prep, make_cfg(v, sub, o, bg))
     torch.cuda.synchronize()
     return outs
 

@@ -68,6 +68,17 @@ def test_full_forward_in_windows(full):
         compare_forward(fwd, orc, window=w, name=f"full fwd {w}")
 
 
+@pytest.mark.parametrize("variant,sub", [("gauss", 8), ("hybrid", 8), ("pixel", 16)])
+def test_full_other_variants_in_windows(full, variant, sub):
+    from paper_2412_17378_amd import make_cfg
+    s, rast, prep, cfg, fwd, wins = full
+    out = rast.render_fwd(prep, make_cfg(variant, sub, "cost"))
+    torch.cuda.synchronize()
+    for w in wins[:2]:
+        orc = oracle_render_from_gpu(prep, window=w)
+        compare_forward(out, orc, window=w, name=f"full {variant}/{sub} {w}")
+
+
 def test_full_static_equals_balanced(full):
     from paper_2412_17378_amd import make_cfg
     s, rast, prep, cfg, fwd, wins = full

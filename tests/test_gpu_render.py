@@ -17,7 +17,9 @@ from workloads import scenes
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [("static", "raster"), ("pixel", "raster"), ("pixel", "cost")]
+# (variant, sub-tile, queue order)
+VARIANTS = [("static", 16, "raster"), ("pixel", 8, "raster"), ("pixel", 8, "cost"), ("pixel", 16, "cost"),
+            ("gauss", 8, "cost"), ("hybrid", 8, "cost")]
 
 
 @pytest.fixture(scope="module")
@@ -35,17 +37,17 @@ def _scene(name):
 
 
 @pytest.mark.parametrize("name", ["tiny-60", "ragged", "0", "sh3"])
-@pytest.mark.parametrize("variant,order", VARIANTS)
-def test_forward_parity(rast, name, variant, order):
+@pytest.mark.parametrize("variant,sub,order", VARIANTS)
+def test_forward_parity(rast, name, variant, sub, order):
     from paper_2412_17378_amd import make_cfg
     s = _scene(name)
     bg = (0.1, 0.2, 0.3)
-    print(f"[fwd] case={name} variant={variant} order={order}", flush=True)
+    print(f"[fwd] case={name} variant={variant}/{sub} order={order}", flush=True)
     prep = rast.prepare_scene(s)
-    out = rast.render_fwd(prep, make_cfg(variant, 8, order, bg))
+    out = rast.render_fwd(prep, make_cfg(variant, sub, order, bg))
     torch.cuda.synchronize()
     orc = oracle_render_from_gpu(prep, bg=bg)
-    compare_forward(out, orc, name=f"{name}/{variant}/{order}")
+    compare_forward(out, orc, name=f"{name}/{variant}/{sub}/{order}")
 
 
 @pytest.mark.parametrize("name", ["tiny-60", "ragged", "0"])
@@ -55,21 +57,22 @@ def test_static_and_balanced_bit_identical(rast, name):
     print(f"[fwd-bitwise] case={name}", flush=True)
     prep = rast.prepare_scene(s)
     a = rast.render_fwd(prep, make_cfg("static"))
-    b = rast.render_fwd(prep, make_cfg("pixel", 8, "cost"))
-    torch.cuda.synchronize()
-    for k in a:
-        assert torch.equal(a[k], b[k]), k
+    for sub in (8, 16):
+        b = rast.render_fwd(prep, make_cfg("pixel", sub, "cost"))
+        torch.cuda.synchronize()
+        for k in a:
+            assert torch.equal(a[k], b[k]), (k, sub)
 
 
 @pytest.mark.parametrize("name", ["tiny-60", "ragged", "0", "sh3"])
-@pytest.mark.parametrize("variant,order", VARIANTS)
-def test_backward_parity(rast, name, variant, order):
+@pytest.mark.parametrize("variant,sub,order", [v for v in VARIANTS if v[0] in ("static", "pixel")])
+def test_backward_parity(rast, name, variant, sub, order):
     from paper_2412_17378_amd import make_cfg
     s = _scene(name)
     bg = (0.3, 0.1, 0.2)
-    print(f"[bwd] case={name} variant={variant} order={order}", flush=True)
+    print(f"[bwd] case={name} variant={variant}/{sub} order={order}", flush=True)
     prep = rast.prepare_scene(s)
-    cfg = make_cfg(variant, 8, order, bg)
+    cfg = make_cfg(variant, sub, order, bg)
     fwd = rast.render_fwd(prep, cfg)
     torch.cuda.synchronize()
     orc_f = oracle_render_from_gpu(prep, bg=bg)
@@ -86,7 +89,7 @@ def test_backward_parity(rast, name, variant, order):
                             torch.from_numpy(gD).to(dev))
     torch.cuda.synchronize()
     orc = oracle_bwd_from_gpu(prep, gC, gA, gD, bg=bg)
-    compare_grads(grads, orc, name=f"{name}/{variant}/{order}")
+    compare_grads(grads, orc, name=f"{name}/{variant}/{sub}/{order}")
 
 
 def test_autograd_function(rast):

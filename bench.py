@@ -54,7 +54,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scene", default="1", help="workload scene id (default: the imbalanced 1080p scene)")
-    ap.add_argument("--variant", default="pixel")
+    ap.add_argument("--variant", default="auto",
+                    help="auto (bgs_autotune picks the forward and backward variants on this frame), or a fixed "
+                         "variant: static | pixel | gauss | hybrid")
+    ap.add_argument("--subtile", type=int, default=8)
     ap.add_argument("--order", default="cost")
     ap.add_argument("--lists", default="fused", choices=["fused", "sort"],
                     help="tile lists by the fused counting pass or by bin + radix sort + ranges")
@@ -100,9 +103,10 @@ def main():
     rast = Rasterizer(dev, reuse_pairs=True)
     stream = torch.cuda.current_stream()
 
-    def make_step(variant, order):
-        cfg = B.make_cfg(variant, 8, order, tuple(scene.bg))
-        cfg_ready = B.make_cfg(variant, 8, order, tuple(scene.bg), flags=B.FLAG_QUEUE_READY)
+    def make_step(fcfg, bcfg):
+        cfg, bcfg_ = fcfg, bcfg
+        cfg_ready = B.make_cfg(fcfg.variant, fcfg.subtile, fcfg.order, tuple(scene.bg), flags=B.FLAG_QUEUE_READY)
+        bcfg_ready = B.make_cfg(bcfg.variant, bcfg.subtile, bcfg.order, tuple(scene.bg), flags=B.FLAG_QUEUE_READY)
         nt = B.n_tiles(W, H)
         P = scene.P
         pr = dict(means2D=torch.empty(P, 2, device=dev), conic_opacity=torch.empty(P, 4, device=dev),
@@ -154,7 +158,7 @@ def main():
                 plist = bufs[3][:M]
             frame = B.make_frame(W, H, ranges, plist, pr["means2D"], pr["conic_opacity"], pr["rgb"], pr["depth"])
             rws = rast.ws.get("render", B.bgs_render_workspace_bytes(frame, cfg))
-            if variant != "static":
+            if cfg.variant != B.STATIC:
                 B.bgs_queue_build(frame, cfg, None, rws)
             mark(5)
             B.bgs_render_fwd(frame, cfg_ready, fwd["color"], fwd["alpha"], fwd["depth"], fwd["final_T"],
@@ -162,14 +166,16 @@ def main():
             mark(6)
             for g in grads.values():
                 g.zero_()
-            if variant != "static":
-                B.bgs_queue_build(frame, cfg, fwd["n_contrib"], rws)
+            if bcfg_.variant != B.STATIC:
+                B.bgs_queue_build(frame, bcfg_, fwd["n_contrib"], rws)
             mark(7)
-            B.bgs_render_bwd(frame, cfg_ready, fwd["final_T"], fwd["n_contrib"], dL_dcolor, None, None,
+            B.bgs_render_bwd(frame, bcfg_ready, fwd["final_T"], fwd["n_contrib"], dL_dcolor, None, None,
                              grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], rws)
             mark(8)
             state["M"] = M
             state["frame_bufs"] = (ranges, plist)
+            state["frame"] = frame
+            state["rws"] = rws
             return M
 
         # size the pair buffers once, outside any timed region
@@ -188,8 +194,8 @@ def main():
             rast.pair_capacity = need
         return step, state, pr, fwd, grads
 
-    def run(variant, order, steps, warmup):
-        step, state, pr, fwd, grads = make_step(variant, order)
+    def run(fcfg, bcfg, steps, warmup):
+        step, state, pr, fwd, grads = make_step(fcfg, bcfg)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -206,9 +212,23 @@ def main():
                   for i, n in enumerate(names)}
         return (t1 - t0) * 1e3 / steps, stages, state, pr, fwd, grads
 
-    print(f"[bench] balanced run: variant={args.variant} order={args.order} warmup={args.warmup} "
+    bg = tuple(scene.bg)
+    tuned = None
+    if args.variant == "auto":
+        # one step with a default configuration builds the frame, then the autotuner picks
+        default = B.make_cfg("pixel", 8, "cost", bg)
+        step0, st0, _, fwd0, grads0 = make_step(default, default)
+        step0()
+        torch.cuda.synchronize()
+        fcfg, bcfg, fms, bms = B.bgs_autotune(st0["frame"], default, fwd0, dL_dcolor, grads0, st0["rws"])
+        tuned = {"forward": B.cfg_name(fcfg), "backward": B.cfg_name(bcfg), "forward_ms": fms, "backward_ms": bms}
+        print(f"[bench] autotune: forward {tuned['forward']} ({fms:.3f} ms), backward {tuned['backward']} "
+              f"({bms:.3f} ms)", flush=True)
+    else:
+        fcfg = bcfg = B.make_cfg(args.variant, args.subtile, args.order, bg)
+    print(f"[bench] timed run: forward {B.cfg_name(fcfg)} backward {B.cfg_name(bcfg)} warmup={args.warmup} "
           f"steps={args.steps}", flush=True)
-    ms_step, stages, state, pr, fwd, grads = run(args.variant, args.order, args.steps, args.warmup)
+    ms_step, stages, state, pr, fwd, grads = run(fcfg, bcfg, args.steps, args.warmup)
     M = state["M"]
     print(f"[bench] balanced: {ms_step:.3f} ms/step, M={M}, stages " +
           ", ".join(f"{k}={v:.3f}" for k, v in stages.items()), flush=True)
@@ -223,6 +243,7 @@ def main():
     ofwd = oracle.render_fwd(W, H, ranges_np, pl_np, m2, co, rgb, dep, bg=scene.bg)
     fwd_blends = int(ofwd["blends"])
     bwd_blends = int(ofwd["n_contrib"].astype(np.int64).sum())
+    wstats = workload_stats(ofwd["n_examined"], ranges_np)
     n_contrib_gpu = fwd["n_contrib"].cpu().numpy()
     agree = float(np.mean(n_contrib_gpu == ofwd["n_contrib"]))
     print(f"[bench] blends fwd={fwd_blends} bwd={bwd_blends} (oracle, {time.time() - t_o:.1f}s; "
@@ -232,7 +253,8 @@ def main():
     static = None
     if not args.no_static:
         print("[bench] static run", flush=True)
-        ms_s, st_s, _, _, _, _ = run("static", "raster", max(3, args.steps // 2), 2)
+        scfg = B.make_cfg("static", 16, "raster", bg)
+        ms_s, st_s, _, _, _, _ = run(scfg, scfg, max(3, args.steps // 2), 2)
         static = dict(ms_per_step=ms_s, render_fwd_ms=st_s["render_fwd"], render_bwd_ms=st_s["render_bwd"])
         print(f"[bench] static: {ms_s:.3f} ms/step, fwd {st_s['render_fwd']:.3f} ms, bwd {st_s['render_bwd']:.3f} ms",
               flush=True)
@@ -296,8 +318,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_NAME, "scene": scene.name, "seed": scene.seed, "P": scene.P,
-                   "width": W, "height": H, "n_pairs": M, "variant": args.variant, "order": args.order,
-                   "subtile": 8, "lists": args.lists},
+                   "width": W, "height": H, "n_pairs": M, "forward": B.cfg_name(fcfg),
+                   "backward": B.cfg_name(bcfg), "lists": args.lists},
+        "autotune": tuned,
+        "workload_stats": wstats,
         "blends": {"fwd": fwd_blends, "bwd": bwd_blends},
         "stages_ms": stages,
         "render_ms": render_ms,
@@ -356,6 +380,35 @@ def measured_traffic(kernel):
     if not rec or rec.get("source_sha256_16") != source_digest(kernel):
         return None
     return rec["bytes_per_launch"]
+
+
+def workload_stats(n_examined, ranges):
+    """Shape of the per-pixel work: list lengths, examined entries per pixel,
+    and the tail ratio R = (critical path of the heaviest work item) /
+    (total work / 1024 SIMDs), with a wave's work = the most entries any of
+    its 64 pixels examines.  R > 1 means the static schedule is tail-bound."""
+    import numpy as np
+    H, W = n_examined.shape
+    lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)
+    Hp, Wp = (H + 15) // 16 * 16, (W + 15) // 16 * 16
+    ex = np.zeros((Hp, Wp), np.int64)
+    ex[:H, :W] = n_examined
+
+    def wave_costs(wy, wx):
+        return ex.reshape(Hp // wy, wy, Wp // wx, wx).max(axis=(1, 3))
+
+    static_waves = wave_costs(4, 16)   # the static kernel: 4 waves of 16x4 pixels per tile
+    balanced_waves = wave_costs(8, 8)  # the balanced kernel: one 8x8 sub-tile per wave
+    q = lambda a, p: float(np.percentile(a, p))
+    return {
+        "list_len": {"p50": q(lens, 50), "p99": q(lens, 99), "max": int(lens.max())},
+        "examined_per_pixel": {"mean": float(n_examined.mean()), "p50": q(n_examined, 50), "p99": q(n_examined, 99),
+                               "max": int(n_examined.max())},
+        "tail_ratio_static": float(static_waves.max() / (static_waves.sum() / 1024.0)),
+        "tail_ratio_balanced": float(balanced_waves.max() / (balanced_waves.sum() / 1024.0)),
+        "lane_waste_static": float(static_waves.sum() * 64 / max(1, n_examined.sum())),
+        "lane_waste_balanced": float(balanced_waves.sum() * 64 / max(1, n_examined.sum())),
+    }
 
 
 def cpu_baseline(scene, window_px):

@@ -244,6 +244,29 @@ bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cfg* cfg, con
                           const float* dL_ddepth, float* dL_dmeans2D, float* dL_dconic_opacity, float* dL_drgb,
                           float* dL_ddepths, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Variant selection by measurement (the self-adaptive kernel selection of
+ * Sec. 4.4, generalized): runs every forward candidate (static; pixel-wise 8x8
+ * raster and cost-ordered; tile-granular persistent; hybrid; Gaussian-wise) on
+ * `frame` with base's background, times each with HIP events (one warm-up,
+ * two timed runs) and returns the fastest in *best_fwd; then renders once with
+ * it and, if dL_dcolor and the gradient buffers are given, times the backward
+ * candidates (static; balanced raster and cost-ordered) into *best_bwd.  The
+ * output and gradient buffers are scratch (the gradients end up holding sums
+ * of several runs).  When cache_path (HOST string, nullable) names a file,
+ * the winners are appended to it under a workload signature (image size and
+ * log2 buckets of the pair count and of the median / 99th percentile /
+ * largest tile list), and a later call with a matching signature returns the
+ * cached winners without timing.  fwd_ms / bwd_ms (HOST, nullable) receive the
+ * winners' times (cached values on a hit; bwd -1 when not tuned).
+ * SYNCHRONIZES the stream.
+ */
+bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg* base, float* out_color, float* out_alpha,
+                        float* out_depth, float* final_T, int32_t* n_contrib, const float* dL_dcolor,
+                        float* dL_dmeans2D, float* dL_dconic_opacity, float* dL_drgb, void* ws, size_t ws_bytes,
+                        const char* cache_path, bgs_render_cfg* best_fwd, bgs_render_cfg* best_bwd, float* fwd_ms,
+                        float* bwd_ms, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

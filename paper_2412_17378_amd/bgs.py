@@ -78,6 +78,8 @@ def lib() -> C.CDLL:
             "bgs_queue_build": ([_vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_render_fwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_render_bwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
+            "bgs_autotune": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, C.c_char_p, _vp, _vp,
+                              _vp, _vp, _vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -91,7 +93,7 @@ def exported_symbols():
     """Names the header declares (used by the load test)."""
     return ["bgs_last_error", "bgs_version", "bgs_project", "bgs_bin_workspace_bytes", "bgs_bin",
             "bgs_sort_workspace_bytes", "bgs_sort", "bgs_ranges", "bgs_tile_lists_workspace_bytes", "bgs_tile_lists",
-            "bgs_render_workspace_bytes", "bgs_queue_build",
+            "bgs_render_workspace_bytes", "bgs_queue_build", "bgs_autotune",
             "bgs_render_fwd", "bgs_render_bwd"]
 
 
@@ -285,6 +287,26 @@ def bgs_render_fwd(frame: Frame, cfg: RenderCfg, out_color, out_alpha, out_depth
     _check("bgs_render_fwd", lib().bgs_render_fwd(C.byref(frame), C.byref(cfg), _ptr(out_color), _ptr(out_alpha),
                                                   _ptr(out_depth), _ptr(final_T), _ptr(n_contrib), _ptr(ws),
                                                   ws.numel(), _stream(stream)))
+
+
+def bgs_autotune(frame: Frame, base: RenderCfg, out: dict, dL_dcolor, grads: Optional[dict], ws,
+                 cache_path: Optional[str] = None, stream=None):
+    """Returns (best_fwd, best_bwd, fwd_ms, bwd_ms); out / grads are scratch."""
+    bf, bb = RenderCfg(), RenderCfg()
+    fms, bms = C.c_float(0), C.c_float(0)
+    g = grads or {}
+    _check("bgs_autotune", lib().bgs_autotune(
+        C.byref(frame), C.byref(base), _ptr(out["color"]), _ptr(out["alpha"]), _ptr(out["depth"]),
+        _ptr(out["final_T"]), _ptr(out["n_contrib"]), _ptr(dL_dcolor) if grads is not None else None,
+        _ptr(g.get("means2D")), _ptr(g.get("conic_opacity")), _ptr(g.get("rgb")), _ptr(ws), ws.numel(),
+        None if cache_path is None else cache_path.encode(), C.byref(bf), C.byref(bb), C.byref(fms), C.byref(bms),
+        _stream(stream)))
+    return bf, bb, float(fms.value), float(bms.value)
+
+
+def cfg_name(c: RenderCfg) -> str:
+    names = {v: k for k, v in VARIANTS.items()}
+    return f"{names.get(c.variant, c.variant)}{c.subtile}/{'cost' if c.order == ORDER_COST else 'raster'}"
 
 
 def bgs_render_bwd(frame: Frame, cfg: RenderCfg, final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dmeans2D,

@@ -182,6 +182,39 @@ class Rasterizer:
         return grads
 
 
+    def autotune(self, prep: Prepared, base: B.RenderCfg, dL_dcolor=None, cache_path: Optional[str] = None):
+        """Time the kernel variants on this frame (bgs_autotune) and return
+        (best_fwd_cfg, best_bwd_cfg, fwd_ms, bwd_ms)."""
+        H, W, P, dev = prep.height, prep.width, prep.P, self.device
+        out = dict(color=torch.empty(3, H, W, device=dev), alpha=torch.empty(H, W, device=dev),
+                   depth=torch.empty(H, W, device=dev), final_T=torch.empty(H, W, device=dev),
+                   n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
+        grads = None
+        if dL_dcolor is not None:
+            grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
+                         rgb=torch.zeros(P, 3, device=dev))
+        f = prep.frame()
+        ws = self.ws.get("render", B.bgs_render_workspace_bytes(f, base))
+        return B.bgs_autotune(f, base, out, dL_dcolor, grads, ws, cache_path)
+
+
+class AdaptiveSelector:
+    """The training-time selection policy of Sec. 4.4: start from the given
+    configuration and, every `interval` calls, re-measure the candidates on
+    the current frame and switch to the fastest."""
+
+    def __init__(self, rast: Rasterizer, base: B.RenderCfg, interval: int = 1000):
+        self.rast, self.base, self.interval = rast, base, interval
+        self.calls = 0
+        self.fwd_cfg, self.bwd_cfg = base, base
+
+    def select(self, prep: Prepared, dL_dcolor=None):
+        if self.calls % self.interval == 0:
+            self.fwd_cfg, self.bwd_cfg, _, _ = self.rast.autotune(prep, self.base, dL_dcolor)
+        self.calls += 1
+        return self.fwd_cfg, self.bwd_cfg
+
+
 class RenderFn(torch.autograd.Function):
     """Differentiable render of prepared splats: inputs means2D [P,2],
     conic_opacity [P,4], rgb [P,3], depth [P] (the per-tile lists are taken

@@ -259,6 +259,32 @@ def main():
         print(f"[bench] static: {ms_s:.3f} ms/step, fwd {st_s['render_fwd']:.3f} ms, bwd {st_s['render_bwd']:.3f} ms",
               flush=True)
 
+    # per-CU load balance of the render kernels: one traced run of each (untimed)
+    def cu_balance(fcfg_, bcfg_):
+        frame, rws = state["frame"], state["rws"]
+        out = {}
+        for name, c in (("render_fwd", fcfg_), ("render_bwd", bcfg_)):
+            cap = 4 * max(B.n_tiles(W, H), 16384)
+            rec = torch.zeros(cap, 3, dtype=torch.int64, device=dev)
+            tc = B.make_cfg(c.variant, c.subtile, c.order, bg)
+            tc.wg_trace, tc.wg_trace_cap = rec.data_ptr(), cap
+            if name == "render_fwd":
+                B.bgs_render_fwd(frame, tc, fwd["color"], fwd["alpha"], fwd["depth"], fwd["final_T"],
+                                 fwd["n_contrib"], rws)
+            else:
+                B.bgs_render_bwd(frame, tc, fwd["final_T"], fwd["n_contrib"], dL_dcolor, None, None,
+                                 grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], rws)
+            torch.cuda.synchronize()
+            out[name] = balance_stats(rec.cpu().numpy())
+        return out
+
+    balance = cu_balance(fcfg, bcfg)
+    balance_static = cu_balance(B.make_cfg("static", 16, "raster", bg), B.make_cfg("static", 16, "raster", bg))
+    for k in balance:
+        print(f"[bench] {k} per-CU finish spread: tuned {balance[k]['spread']:.3f} "
+              f"(CU busy {balance[k]['mean_busy']:.3f}), static {balance_static[k]['spread']:.3f} "
+              f"(CU busy {balance_static[k]['mean_busy']:.3f})", flush=True)
+
     # roofline of the dominant kernel
     def roof(stage):
         t = stages[stage] * 1e-3
@@ -285,9 +311,10 @@ def main():
     dom = max(single, key=single.get)
     rl = roof(dom)
     rl["frac"] = rl["achieved"] / rl["peak"]
-    rl["kernel"] = KERNEL_OF_STAGE[dom]
+    kname = kernel_of(dom, fcfg if dom == "render_fwd" else bcfg, B)
+    rl["kernel"] = kname
     rl["ms"] = stages[dom]
-    rl["traffic"] = measured_traffic(KERNEL_OF_STAGE[dom])
+    rl["traffic"] = measured_traffic(kname)
     stage_roofs = {}
     for k in stages:
         r = roof(k)
@@ -329,6 +356,7 @@ def main():
         "render_roofline": render_roofs,
         "stage_roofline": stage_roofs,
         "static": static,
+        "cu_balance": {"tuned": balance, "static": balance_static},
         "speedup_vs_static": (None if static is None else
                               {"render_fwd": static["render_fwd_ms"] / stages["render_fwd"],
                                "render_bwd": static["render_bwd_ms"] / stages["render_bwd"],
@@ -348,15 +376,47 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-KERNEL_OF_STAGE = {"project": "k_project", "render_fwd": "k_fwd_pixel", "render_bwd": "k_bwd_pixel"}
-KERNEL_SOURCES = {"k_project": ["project.hip", "common.h"], "k_fwd_pixel": ["render.hip", "common.h"],
-                  "k_bwd_pixel": ["render.hip", "common.h"]}
+def balance_stats(rec):
+    """Per-CU load balance from per-wave trace records (location + 1, start,
+    end; 100 MHz ticks): each CU's busy time is from the kernel's first wave
+    start to the CU's last wave end.  spread = (max - min) / max over CUs;
+    mean_busy = mean / max (the CU-time utilization of the kernel's span)."""
+    import numpy as np
+    rec = rec[rec[:, 0] != 0]
+    if rec.size == 0:
+        return None
+    t0 = rec[:, 1].min()
+    keys, inv = np.unique(rec[:, 0], return_inverse=True)
+    end = np.zeros(len(keys), np.int64)
+    np.maximum.at(end, inv, rec[:, 2] - t0)
+    busy = end.astype(np.float64)
+    return {"n_cu": int(len(keys)), "n_waves": int(len(rec)), "span_ms": float(busy.max()) * 1e-5,
+            "spread": float((busy.max() - busy.min()) / busy.max()), "mean_busy": float(busy.mean() / busy.max())}
+
+
+def kernel_of(stage, cfg, B):
+    """Name of the kernel a stage launches for a render configuration."""
+    if stage == "project":
+        return "k_project"
+    wide = cfg.variant == B.BALANCED_PIXEL and cfg.subtile == 16
+    if stage == "render_fwd":
+        if cfg.variant == B.STATIC:
+            return "k_fwd_static"
+        if wide:
+            return "k_fwd_tile"
+        return "k_fwd_pixel" if cfg.variant == B.BALANCED_PIXEL else "k_fwd_hybrid"
+    if cfg.variant == B.STATIC:
+        return "k_bwd_pixel<false>"
+    return "k_bwd_wide" if wide else "k_bwd_pixel<true>"
+
+
+KERNEL_SOURCES = {"k_project": ["project.hip", "common.h"]}
 
 
 def source_digest(kernel):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES[kernel]:
+    for f in KERNEL_SOURCES.get(kernel, ["render.hip", "common.h"]):
         with open(os.path.join(ROOT, "paper_2412_17378_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

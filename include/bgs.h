@@ -97,10 +97,22 @@ enum {
 
 typedef struct bgs_render_cfg {
     int32_t variant;          /* bgs_variant */
-    int32_t subtile;          /* balanced variants: sub-tile edge, 8 (one wave) */
+    int32_t subtile;          /* balanced variants: work-item edge.  8: one wave per
+                                 8x8 sub-tile (one pixel per lane).  16 (BGS_BALANCED_PIXEL
+                                 only): whole 16x16 tiles -- the forward gives each to a
+                                 256-lane workgroup, the backward to one wave with four
+                                 pixels per lane */
     int32_t order;            /* bgs_order */
     int32_t flags;            /* BGS_FLAG_* */
     float bg[3];              /* background colour */
+    /* Optional load-balance trace (DEVICE, nullable): render kernels write
+       one record of three uint64 per wave, record w for wave
+       (workgroup * 4 + wave in workgroup) while w < wg_trace_cap:
+       [0] = 1 + (XCC id << 8 | HW_ID bits 15..8: shader engine, shader array,
+       CU), [1] / [2] = the 100 MHz real-time counter at the wave's start / end.
+       Records of waves not launched are left untouched (zero the buffer). */
+    uint64_t* wg_trace;
+    int64_t wg_trace_cap;
 } bgs_render_cfg;
 
 /* Thread-local text for the last non-OK status of this thread. */
@@ -251,7 +263,8 @@ bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cfg* cfg, con
  * `frame` with base's background, times each with HIP events (one warm-up,
  * two timed runs) and returns the fastest in *best_fwd; then renders once with
  * it and, if dL_dcolor and the gradient buffers are given, times the backward
- * candidates (static; balanced raster and cost-ordered) into *best_bwd.  The
+ * candidates (static; balanced 8x8 raster and cost-ordered; wave per 16x16
+ * tile) into *best_bwd.  The
  * output and gradient buffers are scratch (the gradients end up holding sums
  * of several runs).  When cache_path (HOST string, nullable) names a file,
  * the winners are appended to it under a workload signature (image size and
@@ -266,6 +279,51 @@ bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg* base, floa
                         float* dL_dmeans2D, float* dL_dconic_opacity, float* dL_drgb, void* ws, size_t ws_bytes,
                         const char* cache_path, bgs_render_cfg* best_fwd, bgs_render_cfg* best_bwd, float* fwd_ms,
                         float* bwd_ms, hipStream_t stream);
+
+/* Per-view buffers of a batched plan (all DEVICE pointers, caller-owned). */
+typedef struct bgs_view_io {
+    int64_t P;                  /* Gaussians of this view's frame (size of the gradient arrays) */
+    float* out_color;           /* [3][H][W] */
+    float* out_alpha;           /* [H][W] */
+    float* out_depth;           /* [H][W] */
+    float* final_T;             /* [H][W] */
+    int32_t* n_contrib;         /* [H][W] */
+    const float* dL_dcolor;     /* [3][H][W] upstream gradient */
+    const float* dL_dalpha;     /* [H][W] or NULL */
+    const float* dL_ddepth;     /* [H][W] or NULL */
+    float* dL_dmeans2D;         /* [P][2]   zeroed and accumulated by every launch */
+    float* dL_dconic_opacity;   /* [P][4]   (16-byte aligned) */
+    float* dL_drgb;             /* [P][3] */
+    float* dL_ddepths;          /* [P] or NULL */
+} bgs_view_io;
+
+typedef struct bgs_plan bgs_plan;
+
+/*
+ * Batched multi-view render: records, into one hipGraph, the gradient
+ * zero-fill, the cost pass and queue build of a cross-view work queue (every
+ * work item of every view, heaviest first across views), one persistent
+ * balanced forward over all views, the backward queue, and one persistent
+ * backward over all views.  frames / io are HOST arrays of n_views (1..64)
+ * entries; the device buffers they point to must stay valid (their contents
+ * may change between launches, e.g. per-tile lists rebuilt in place).
+ * cfg_fwd must select BGS_BALANCED_PIXEL with subtile 8; cfg_bwd (nullable:
+ * same as cfg_fwd) BGS_BALANCED_PIXEL with subtile 8 or 16; each gives its
+ * pass's queue order, cfg_fwd the background.  Other variants return
+ * BGS_EUNSUPPORTED.  The plan owns its queue memory and graph
+ * (allocated here, freed by bgs_plan_destroy).  The graph is recorded on a
+ * private stream; `stream` only receives the descriptor uploads and is
+ * synchronized.
+ */
+bgs_status bgs_plan_create(bgs_plan** plan, int32_t n_views, const bgs_frame* frames, const bgs_view_io* io,
+                           const bgs_render_cfg* cfg_fwd, const bgs_render_cfg* cfg_bwd, hipStream_t stream);
+
+/* One forward + backward over all views of the plan: a single hipGraphLaunch
+ * on `stream` (asynchronous). */
+bgs_status bgs_plan_launch(bgs_plan* plan, hipStream_t stream);
+
+/* Frees the plan (NULL is accepted). */
+void bgs_plan_destroy(bgs_plan* plan);
 
 #ifdef __cplusplus
 }

@@ -46,9 +46,16 @@ class Frame(C.Structure):
                 ("conic_opacity", C.c_void_p), ("rgb", C.c_void_p), ("depth", C.c_void_p)]
 
 
+class ViewIO(C.Structure):
+    _fields_ = [("P", C.c_int64), ("out_color", C.c_void_p), ("out_alpha", C.c_void_p), ("out_depth", C.c_void_p),
+                ("final_T", C.c_void_p), ("n_contrib", C.c_void_p), ("dL_dcolor", C.c_void_p),
+                ("dL_dalpha", C.c_void_p), ("dL_ddepth", C.c_void_p), ("dL_dmeans2D", C.c_void_p),
+                ("dL_dconic_opacity", C.c_void_p), ("dL_drgb", C.c_void_p), ("dL_ddepths", C.c_void_p)]
+
+
 class RenderCfg(C.Structure):
     _fields_ = [("variant", C.c_int32), ("subtile", C.c_int32), ("order", C.c_int32), ("flags", C.c_int32),
-                ("bg", C.c_float * 3)]
+                ("bg", C.c_float * 3), ("wg_trace", C.c_void_p), ("wg_trace_cap", C.c_int64)]
 
 
 _LIB = None
@@ -80,6 +87,9 @@ def lib() -> C.CDLL:
             "bgs_render_bwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_autotune": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, C.c_char_p, _vp, _vp,
                               _vp, _vp, _vp], C.c_int),
+            "bgs_plan_create": ([_vp, _i32, _vp, _vp, _vp, _vp, _vp], C.c_int),
+            "bgs_plan_launch": ([_vp, _vp], C.c_int),
+            "bgs_plan_destroy": ([_vp], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -93,7 +103,8 @@ def exported_symbols():
     """Names the header declares (used by the load test)."""
     return ["bgs_last_error", "bgs_version", "bgs_project", "bgs_bin_workspace_bytes", "bgs_bin",
             "bgs_sort_workspace_bytes", "bgs_sort", "bgs_ranges", "bgs_tile_lists_workspace_bytes", "bgs_tile_lists",
-            "bgs_render_workspace_bytes", "bgs_queue_build", "bgs_autotune",
+            "bgs_render_workspace_bytes", "bgs_queue_build", "bgs_autotune", "bgs_plan_create", "bgs_plan_launch",
+            "bgs_plan_destroy",
             "bgs_render_fwd", "bgs_render_bwd"]
 
 
@@ -302,6 +313,37 @@ def bgs_autotune(frame: Frame, base: RenderCfg, out: dict, dL_dcolor, grads: Opt
         None if cache_path is None else cache_path.encode(), C.byref(bf), C.byref(bb), C.byref(fms), C.byref(bms),
         _stream(stream)))
     return bf, bb, float(fms.value), float(bms.value)
+
+
+def make_view_io(P, out: dict, dL_dcolor, grads: dict, dL_dalpha=None, dL_ddepth=None) -> ViewIO:
+    v = ViewIO()
+    v.P = int(P)
+    v.out_color, v.out_alpha, v.out_depth = _ptr(out["color"]), _ptr(out["alpha"]), _ptr(out["depth"])
+    v.final_T, v.n_contrib = _ptr(out["final_T"]), _ptr(out["n_contrib"])
+    v.dL_dcolor, v.dL_dalpha, v.dL_ddepth = _ptr(dL_dcolor), _ptr(dL_dalpha), _ptr(dL_ddepth)
+    v.dL_dmeans2D = _ptr(_nonempty(grads["means2D"]))
+    v.dL_dconic_opacity = _ptr(_nonempty(grads["conic_opacity"]))
+    v.dL_drgb = _ptr(_nonempty(grads["rgb"]))
+    v.dL_ddepths = None if grads.get("depth") is None else _ptr(_nonempty(grads["depth"]))
+    return v
+
+
+def bgs_plan_create(frames, ios, cfg: RenderCfg, cfg_bwd: RenderCfg = None, stream=None) -> C.c_void_p:
+    n = len(frames)
+    fa = (Frame * n)(*frames)
+    ia = (ViewIO * n)(*ios)
+    h = C.c_void_p()
+    _check("bgs_plan_create", lib().bgs_plan_create(C.byref(h), n, fa, ia, C.byref(cfg),
+                                                    None if cfg_bwd is None else C.byref(cfg_bwd), _stream(stream)))
+    return h
+
+
+def bgs_plan_launch(plan, stream=None):
+    _check("bgs_plan_launch", lib().bgs_plan_launch(plan, _stream(stream)))
+
+
+def bgs_plan_destroy(plan):
+    lib().bgs_plan_destroy(plan)
 
 
 def cfg_name(c: RenderCfg) -> str:

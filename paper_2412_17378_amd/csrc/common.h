@@ -69,21 +69,36 @@ __device__ inline bool tile_rect(float u, float v, int r, int TX, int TY, int& x
     return true;
 }
 
-// Gaussian as staged in LDS for the render loops.  The conic is pre-scaled so
-// that the exponent comes out in base 2:  power2 = log2(e) * power with
-// (a2, b2, c2) = (-log2e a / 2, -log2e b, -log2e c / 2).
-struct Splat {
-    float x, y, a2, b2, c2, o, r, g, b, d;
-};
+// Exponent of one (pixel, Gaussian) pair, base 2, from the conic staged in
+// pivoted form.  With r = b / a, q = (a c - b^2) / a and t = dx + r dy,
+//     a dx^2 + 2 b dx dy + c dy^2 = a t^2 + q dy^2,
+// two non-negative terms for a positive-definite conic, so the fp32 value has
+// no cancellation; the expanded form loses up to cond(conic) ulps at pixels
+// far along a needle-shaped Gaussian (measured: 2e-3 absolute in the
+// exponent at condition ~1e4, against 1e-5 here).  The staged numbers are
+// a2 = -log2(e) a / 2, r, q2 = -log2(e) q / 2, so the result is
+// log2(e) * power.  Written with explicit fma so that forward and backward
+// kernels evaluate bit-identical values (the backward re-takes the forward's
+// skip decisions).
+__device__ __forceinline__ float splat_power2(float dx, float dy, float a2, float r, float q2) {
+    const float t = __builtin_fmaf(r, dy, dx);
+    const float qdd = (q2 * dy) * dy;
+    return __builtin_fmaf(a2 * t, t, qdd);
+}
 
-// Exponent of one (pixel, Gaussian) pair, base 2.  Written with explicit fma
-// so that forward and backward kernels evaluate bit-identical values (the
-// backward re-takes the forward's skip decisions).
-__device__ __forceinline__ float splat_power2(float dx, float dy, float a2, float b2, float c2) {
-    float t = __builtin_fmaf(a2, dx, b2 * dy);
-    float cdy = c2 * dy;
-    float cdd = cdy * dy;
-    return __builtin_fmaf(dx, t, cdd);
+// (a2, r, q2) of splat_power2 from the conic (a, b, c).  a c - b^2 is formed
+// with an fma-compensated product, so its relative error stays a few ulps
+// when b^2 is close to a c.  A conic with a = 0 (not positive definite,
+// outside the render contract) is staged as (0, 0, c-term): its b dx dy term
+// is dropped.
+__device__ __forceinline__ float3 stage_conic(float a, float b, float c) {
+    constexpr float K = -0.5f * LOG2E;
+    if (!(a != 0.0f)) return make_float3(0.0f, 0.0f, K * c);
+    const float bb = b * b;
+    const float bb_err = __builtin_fmaf(b, b, -bb);  // b*b - bb, exact
+    const float det = __builtin_fmaf(a, c, -bb) - bb_err;
+    const float inv_a = 1.0f / a;
+    return make_float3(K * a, b * inv_a, (K * det) * inv_a);
 }
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -111,43 +126,59 @@ __device__ __forceinline__ float wave_sum(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
+// Lane exchanges of gfx950 that stay in the VALU (no LDS round trip):
+// permlane32_swap exchanges lanes 32..63 of x with lanes 0..31 of y, and
+// permlane16_swap exchanges the odd 16-lane rows of x with the even rows of
+// y.  For a butterfly stage that keeps x in the lower partner and y in the
+// upper one, (x' + y') is then the partner sum in every lane.
+__device__ __forceinline__ float swap_sum32(float x, float y) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                                    false, false);
+    return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+}
+
+__device__ __forceinline__ float swap_sum16(float x, float y) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                                    false, false);
+    return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+}
+
+// v from lane (lane xor 8) / (lane xor 4), as two DPP moves each:
+// row_mirror then row_half_mirror reads lane 8 - (i & 8) + (i & 7) of the row;
+// row_half_mirror then quad_perm [3,2,1,0] reads lane i xor 4.
+__device__ __forceinline__ float xor8(float v) { return dpp<0x141>(dpp<0x140>(v)); }
+__device__ __forceinline__ float xor4(float v) { return dpp<0x1B>(dpp<0x141>(v)); }
+
 // Transposed reduction of 10 per-lane values over the 64 lanes of a wave
 // (all lanes active).  Each butterfly stage halves the values a lane keeps
 // while it adds its partner's copy (xor 32: 10 -> 5, xor 16: 5 -> 3 (padded),
 // xor 8: 3 -> 2, xor 4: 2 -> 1), then xor 2 and xor 1 finish the sum, so 13
-// exchanges replace 10 full 64-lane reductions.  Value k's total ends in the
-// lanes whose bits (5,4,3,2) = (b5,b4,b3,b2) satisfy
-// k = 5 b5 + 3 b4 + 2 b3 + b2 (with 2 b3 + b2 < 3 and 3 b4 + 2 b3 + b2 < 5).
-// Returns k in the first lane of that quad (others: -1) and the total in out.
+// exchanges replace 10 full 64-lane reductions; all of them are VALU lane
+// swaps or DPP moves.  Value k's total ends in the lanes whose bits
+// (5,4,3,2) = (b5,b4,b3,b2) satisfy k = 5 b5 + 3 b4 + 2 b3 + b2 (with
+// 2 b3 + b2 < 3 and 3 b4 + 2 b3 + b2 < 5).  Returns k in the first lane of
+// that quad (others: -1) and the total in out.
 __device__ __forceinline__ int wave_reduce_scatter10(const float (&v)[10], int lane, float& out) {
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+    const bool b3 = lane & 8, b2 = lane & 4;
     float a[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        const float keep = b5 ? v[5 + i] : v[i];
-        const float send = b5 ? v[i] : v[5 + i];
-        a[i] = keep + __shfl_xor(send, 32, 64);
-    }
+    for (int i = 0; i < 5; ++i) a[i] = swap_sum32(v[i], v[5 + i]);  // b5 ? v[5+i] : v[i]
     float c[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const float hi = i < 2 ? a[3 + i] : 0.0f;
-        const float keep = b4 ? hi : a[i];
-        const float send = b4 ? a[i] : hi;
-        c[i] = keep + __shfl_xor(send, 16, 64);
-    }
+    for (int i = 0; i < 3; ++i) c[i] = swap_sum16(a[i], i < 2 ? a[3 + i] : 0.0f);  // b4 ? a[3+i] : a[i]
     float d[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const float hi = i == 0 ? c[2] : 0.0f;
         const float keep = b3 ? hi : c[i];
         const float send = b3 ? c[i] : hi;
-        d[i] = keep + __shfl_xor(send, 8, 64);
+        d[i] = keep + xor8(send);
     }
-    float e = (b2 ? d[1] : d[0]) + __shfl_xor(b2 ? d[0] : d[1], 4, 64);
-    e += __shfl_xor(e, 2, 64);
-    e += __shfl_xor(e, 1, 64);
+    float e = (b2 ? d[1] : d[0]) + xor4(b2 ? d[0] : d[1]);
+    e += dpp<0x4E>(e);  // quad_perm [2,3,0,1]: lane xor 2
+    e += dpp<0xB1>(e);  // quad_perm [1,0,3,2]: lane xor 1
     out = e;
+    const bool b5 = lane & 32, b4 = lane & 16;
     const int p3 = 2 * (int)b3 + (int)b2;
     const int p5 = 3 * (int)b4 + p3;
     const bool valid = p3 < 3 && p5 < 5 && (lane & 3) == 0;

@@ -22,12 +22,14 @@
 // All kernels are FP32-VALU bound (no dense contraction).  Per examined
 // (pixel, Gaussian) pair the forward spends ~22 VALU issues, the backward
 // ~45 plus the wave reduction.
+#include <algorithm>
+#include <string>
+#include <vector>
+
 #include "common.h"
 
 namespace bgs {
 
-constexpr float KA = -0.5f * LOG2E;  // a -> a2
-constexpr float KB = -LOG2E;         // b -> b2
 constexpr int NBUCKET = 136;         // cost buckets: 0 and quarter-octaves of 1 .. 2^33
 constexpr int HYBRID_SWITCH = 16;    // hybrid: Gaussian-wise once <= 16 of 64 pixels are active
 
@@ -40,6 +42,8 @@ struct FrameArgs {
     const float* __restrict__ rgb;
     const float* __restrict__ depth;
     float bg0, bg1, bg2;
+    uint64_t* trace;  // per-wave timing records (nullable), trace_cap of them
+    int64_t trace_cap;
 };
 
 struct FwdOut {
@@ -62,17 +66,52 @@ struct BwdIO {
     float* __restrict__ g_depth;
 };
 
+// One view of a batched plan: its frame, forward outputs and backward I/O.
+struct ViewDesc {
+    FrameArgs F;
+    FwdOut O;
+    BwdIO B;
+    int64_t P;
+};
+
+// Items carry their view in the top bits: item = view << 26 | tile << 2 | sub.
+constexpr int VIEW_SHIFT = 26;
+constexpr uint32_t LOCAL_MASK = (1u << VIEW_SHIFT) - 1u;
+constexpr int MAX_VIEWS = 64;
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Load one Gaussian of the list into registers in the staged (pre-scaled) form.
+// Optional per-wave timing records for load-balance measurements: record
+// w = (3 words) hardware location + 1 (XCC id << 8 | HW_ID bits 15:8, i.e.
+// shader engine, shader array and CU; 0 = no record), then the 100 MHz
+// real-time counter at the wave's start and end.  Off (one uniform branch)
+// when F.trace is null.
+__device__ __forceinline__ uint64_t trace_begin(const FrameArgs& F) {
+    return F.trace ? __builtin_amdgcn_s_memrealtime() : 0ull;
+}
+
+__device__ __forceinline__ void trace_end(const FrameArgs& F, uint64_t t0, int wave_index, int lane) {
+    if (F.trace && lane == 0 && wave_index < F.trace_cap) {
+        const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_ID
+        const uint32_t xcc = __builtin_amdgcn_s_getreg((31 << 11) | 20);  // XCC_ID
+        uint64_t* r = F.trace + 3 * (int64_t)wave_index;
+        r[0] = ((uint64_t)(xcc & 0xFF) << 8 | ((hw >> 8) & 0xFF)) + 1;
+        r[1] = t0;
+        r[2] = __builtin_amdgcn_s_memrealtime();
+    }
+}
+
+// Load one Gaussian of the list into registers in the staged form: co =
+// (a2, r, q2, opacity) of splat_power2, cd = (rgb, depth).
 __device__ __forceinline__ void load_splat(const FrameArgs& F, uint32_t g, float2& xy, float4& co, float4& cd) {
     xy = F.means2D[g];
     const float4 c = F.conic_opacity[g];
-    co = make_float4(c.x * KA, c.y * KB, c.z * KA, c.w);
+    const float3 s = stage_conic(c.x, c.y, c.z);
+    co = make_float4(s.x, s.y, s.z, c.w);
     cd = make_float4(F.rgb[3 * g], F.rgb[3 * g + 1], F.rgb[3 * g + 2], F.depth[g]);
 }
 
@@ -117,6 +156,7 @@ __device__ __forceinline__ void write_pixel(const FrameArgs& F, const FwdOut& O,
 
 // ------------------------------------------------------------------ static
 __global__ __launch_bounds__(256) void k_fwd_static(FrameArgs F, FwdOut O) {
+    const uint64_t t_begin = trace_begin(F);
     __shared__ float2 s_xy[256];
     __shared__ float4 s_co[256];
     __shared__ float4 s_cd[256];
@@ -146,6 +186,7 @@ __global__ __launch_bounds__(256) void k_fwd_static(FrameArgs F, FwdOut O) {
         }
     }
     if (inside) write_pixel(F, O, px, py, s);
+    trace_end(F, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // ------------------------------------------------------------- balanced fwd
@@ -225,9 +266,10 @@ __device__ __forceinline__ bool queue_next(WorkQueue& Q, int lane, uint32_t& ite
     }
 }
 
-template <bool PERSISTENT>
-__global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F, FwdOut O, const uint32_t* __restrict__ items,
-                                                   uint32_t* __restrict__ ctr) {
+template <bool PERSISTENT, bool MV = false>
+__global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F0, FwdOut O0, const ViewDesc* __restrict__ views,
+                                                   const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
+    const uint64_t t_begin = trace_begin(F0);
     __shared__ float2 s_xy[4][64];
     __shared__ float4 s_co[4][64];
     __shared__ float4 s_cd[4][64];
@@ -241,6 +283,9 @@ __global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F, FwdOut O, const 
         } else {
             item = blockIdx.x * 4 + wv;
         }
+        const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
+        const FwdOut O = MV ? views[item >> VIEW_SHIFT].O : O0;
+        item &= LOCAL_MASK;
         int tile, px, py;
         bool any_inside;
         item_pixel(F, item, lane, tile, px, py, any_inside);
@@ -279,6 +324,7 @@ __global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F, FwdOut O, const 
         }
         if (!PERSISTENT) break;
     }
+    trace_end(F0, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // --------------------------------------------------- Gaussian-wise / hybrid
@@ -354,6 +400,7 @@ __device__ __forceinline__ void gw_step(float fx, float fy, float2 xy, float4 co
 template <int SWITCH_AT>
 __global__ __launch_bounds__(256) void k_fwd_hybrid(FrameArgs F, FwdOut O, const uint32_t* __restrict__ items,
                                                     uint32_t* __restrict__ ctr) {
+    const uint64_t t_begin = trace_begin(F);
     __shared__ float2 s_xy[4][64];
     __shared__ float4 s_co[4][64];
     __shared__ float4 s_cd[4][64];
@@ -409,6 +456,7 @@ __global__ __launch_bounds__(256) void k_fwd_hybrid(FrameArgs F, FwdOut O, const
         }
         if (inside) write_pixel(F, O, px, py, s);
     }
+    trace_end(F, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // ------------------------------------------------- tile-granular persistent
@@ -417,6 +465,7 @@ __global__ __launch_bounds__(256) void k_fwd_hybrid(FrameArgs F, FwdOut O, const
 // render them like the static kernel (shared 256-Gaussian LDS batches).
 __global__ __launch_bounds__(256) void k_fwd_tile(FrameArgs F, FwdOut O, const uint32_t* __restrict__ items,
                                                   uint32_t* __restrict__ ctr) {
+    const uint64_t t_begin = trace_begin(F);
     __shared__ float2 s_xy[256];
     __shared__ float4 s_co[256];
     __shared__ float4 s_cd[256];
@@ -465,18 +514,19 @@ __global__ __launch_bounds__(256) void k_fwd_tile(FrameArgs F, FwdOut O, const u
         __syncthreads();  // LDS batch reads done before the next tile stages
         if (inside) write_pixel(F, O, px, py, s);
     }
+    trace_end(F, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // ------------------------------------------------------------------ backward
-template <bool PERSISTENT>
-__global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F, BwdIO B, const uint32_t* __restrict__ items,
-                                                   uint32_t* __restrict__ ctr) {
+template <bool PERSISTENT, bool MV = false>
+__global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const ViewDesc* __restrict__ views,
+                                                   const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
+    const uint64_t t_begin = trace_begin(F0);
     __shared__ float2 s_xy[4][64];
     __shared__ float4 s_co[4][64];
     __shared__ float4 s_cd[4][64];
     __shared__ float4 s_abc[4][64];  // raw conic a, b, c and the Gaussian id (bits)
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t HW = (int64_t)F.W * F.H;
     WorkQueue Q;
     if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
     for (;;) {
@@ -486,6 +536,10 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F, BwdIO B, const u
         } else {
             item = blockIdx.x * 4 + wv;
         }
+        const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
+        const BwdIO B = MV ? views[item >> VIEW_SHIFT].B : B0;
+        item &= LOCAL_MASK;
+        const int64_t HW = (int64_t)F.W * F.H;
         int tile, px, py;
         bool any_inside;
         item_pixel(F, item, lane, tile, px, py, any_inside);
@@ -579,6 +633,141 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F, BwdIO B, const u
         }
         if (!PERSISTENT) break;
     }
+    trace_end(F0, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
+}
+
+// Backward with one wave per 16x16 tile: lane l owns the four pixels
+// (l mod 16, l / 16 + 4q), q = 0..3, of the tile.  The per-entry work that
+// does not scale with pixels -- the LDS reads, the 10-value wave reduction
+// and the one multi-lane gradient atomic -- is paid once per 256 pixels
+// instead of once per 64, and dx (shared by a lane's four pixels) once per
+// entry.  Each pixel's arithmetic is the same as in k_bwd_pixel.
+constexpr int WQ = 4;  // pixels per lane
+
+template <bool MV = false>
+__global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const ViewDesc* __restrict__ views,
+                                                  const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
+    const uint64_t t_begin = trace_begin(F0);
+    __shared__ float2 s_xy[4][64];
+    __shared__ float4 s_co[4][64];
+    __shared__ float4 s_cd[4][64];
+    __shared__ float4 s_abc[4][64];  // raw conic a, b, c and the Gaussian id (bits)
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    WorkQueue Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
+    for (;;) {
+        uint32_t item;
+        if (!queue_next(Q, lane, item)) break;
+        const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
+        const BwdIO B = MV ? views[item >> VIEW_SHIFT].B : B0;
+        const int tile = (int)(item & LOCAL_MASK);
+        const int64_t HW = (int64_t)F.W * F.H;
+        const int tx = tile % F.TX, ty = tile / F.TX;
+        const int px = tx * TILE + (lane & 15);
+        const uint32_t start = F.ranges[2 * tile];
+        const int len = (int)(F.ranges[2 * tile + 1] - start);
+        float T[WQ], R0[WQ], R1[WQ], R2[WQ], Rd[WQ], gC0[WQ], gC1[WQ], gC2[WQ], gD[WQ], kc[WQ], fy[WQ];
+        int nc[WQ];
+        int my_max = 0;
+#pragma unroll
+        for (int q = 0; q < WQ; ++q) {
+            const int py = ty * TILE + (lane >> 4) + 4 * q;
+            const bool inside = px < F.W && py < F.H;
+            const int64_t p = inside ? (int64_t)py * F.W + px : 0;
+            const float TN = inside ? B.final_T[p] : 1.0f;
+            int n = inside ? B.n_contrib[p] : 0;
+            n = n < 0 ? 0 : (n > len ? len : n);  // stay inside the tile's list
+            nc[q] = n;
+            my_max = n > my_max ? n : my_max;
+            gC0[q] = inside ? B.dL_dcolor[p] : 0.f;
+            gC1[q] = inside ? B.dL_dcolor[HW + p] : 0.f;
+            gC2[q] = inside ? B.dL_dcolor[2 * HW + p] : 0.f;
+            const float ga = (inside && B.dL_dalpha) ? B.dL_dalpha[p] : 0.f;
+            gD[q] = (inside && B.dL_ddepth) ? B.dL_ddepth[p] : 0.f;
+            kc[q] = TN * (gC0[q] * F.bg0 + gC1[q] * F.bg1 + gC2[q] * F.bg2) - ga * TN;
+            T[q] = TN;
+            R0[q] = R1[q] = R2[q] = Rd[q] = 0.f;
+            fy[q] = (float)py;
+        }
+        const int max_n = wave_max(my_max);
+        const float fx = (float)px;
+        for (int hi = max_n; hi > 0; hi -= 64) {
+            const int lo = hi > 64 ? hi - 64 : 0;
+            if (lo + lane < hi) {
+                const uint32_t g = F.point_list[start + lo + lane];
+                float2 xy; float4 co, cd;
+                load_splat(F, g, xy, co, cd);
+                const float4 raw = F.conic_opacity[g];
+                s_xy[wv][lane] = xy;
+                s_co[wv][lane] = co;
+                s_cd[wv][lane] = cd;
+                s_abc[wv][lane] = make_float4(raw.x, raw.y, raw.z, __uint_as_float(g));
+            }
+            wave_sync();
+            for (int j = hi - 1; j >= lo; --j) {
+                const int jj = j - lo;
+                const float2 xy = s_xy[wv][jj];
+                const float4 co = s_co[wv][jj];
+                const float dx = fx - xy.x;
+                float dy[WQ], G[WQ], ga[WQ], alpha[WQ];
+                bool contrib[WQ];
+                bool anyc = false;
+#pragma unroll
+                for (int q = 0; q < WQ; ++q) {
+                    dy[q] = fy[q] - xy.y;
+                    const float p2 = splat_power2(dx, dy[q], co.x, co.y, co.z);
+                    G[q] = exp2_fast(p2);
+                    ga[q] = co.w * G[q];
+                    alpha[q] = fminf(ALPHA_MAX, ga[q]);
+                    contrib[q] = (j < nc[q]) && !(p2 > 0.0f || alpha[q] < ALPHA_MIN);
+                    anyc |= contrib[q];
+                }
+                if (ballot(anyc) == 0) continue;
+                const float4 cd = s_cd[wv][jj];
+                const float4 abc = s_abc[wv][jj];
+                float v[10];
+#pragma unroll
+                for (int i = 0; i < 10; ++i) v[i] = 0.f;
+#pragma unroll
+                for (int q = 0; q < WQ; ++q) {
+                    const float inv = __builtin_amdgcn_rcpf(1.0f - alpha[q]);
+                    const float Tb = T[q] * inv;
+                    const float w = contrib[q] ? alpha[q] * Tb : 0.0f;
+                    v[6] = __builtin_fmaf(w, gC0[q], v[6]);
+                    v[7] = __builtin_fmaf(w, gC1[q], v[7]);
+                    v[8] = __builtin_fmaf(w, gC2[q], v[8]);
+                    v[9] = __builtin_fmaf(w, gD[q], v[9]);
+                    const float dA = Tb * (gC0[q] * cd.x + gC1[q] * cd.y + gC2[q] * cd.z + gD[q] * cd.w) -
+                                     inv * (gC0[q] * R0[q] + gC1[q] * R1[q] + gC2[q] * R2[q] + gD[q] * Rd[q] + kc[q]);
+                    R0[q] = __builtin_fmaf(cd.x, w, R0[q]);
+                    R1[q] = __builtin_fmaf(cd.y, w, R1[q]);
+                    R2[q] = __builtin_fmaf(cd.z, w, R2[q]);
+                    Rd[q] = __builtin_fmaf(cd.w, w, Rd[q]);
+                    T[q] = contrib[q] ? Tb : T[q];
+                    const bool unclamped = contrib[q] && ga[q] <= ALPHA_MAX;
+                    const float dP = unclamped ? ga[q] * dA : 0.0f;  // dL/dpower
+                    v[5] += unclamped ? G[q] * dA : 0.0f;            // dL/dopacity
+                    v[2] += -0.5f * dx * dx * dP;
+                    v[3] += -dx * dy[q] * dP;
+                    v[4] += -0.5f * dy[q] * dy[q] * dP;
+                    v[0] += (abc.x * dx + abc.y * dy[q]) * dP;
+                    v[1] += (abc.y * dx + abc.z * dy[q]) * dP;
+                }
+                float tot;
+                const int slot = wave_reduce_scatter10(v, lane, tot);
+                if (slot >= 0) {
+                    const uint32_t g = __float_as_uint(abc.w);
+                    float* dst;
+                    if (slot < 2) dst = B.g_means2D + 2 * (size_t)g + slot;
+                    else if (slot < 6) dst = B.g_conic_opacity + 4 * (size_t)g + (slot - 2);
+                    else if (slot < 9) dst = B.g_rgb + 3 * (size_t)g + (slot - 6);
+                    else dst = B.g_depth ? B.g_depth + g : nullptr;
+                    if (dst) unsafeAtomicAdd(dst, tot);
+                }
+            }
+            wave_sync();
+        }
+    }
+    trace_end(F0, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------- task pool
@@ -609,22 +798,56 @@ __global__ __launch_bounds__(256) void k_tile_costs(FrameArgs F, const int* __re
     if (threadIdx.x == 0) cost[tile] = c;
 }
 
+// Batched views: global tile g (over all views, tile_off = per-view prefix of
+// tile counts) -> cost, as k_tile_costs for its view.
+__global__ __launch_bounds__(256) void k_tile_costs_mv(const ViewDesc* __restrict__ views,
+                                                       const uint32_t* __restrict__ tile_off, int n_views, int backward,
+                                                       uint32_t* __restrict__ cost) {
+    __shared__ int wmax[4];
+    const uint32_t g = blockIdx.x;
+    int v = 0;
+    while (v + 1 < n_views && tile_off[v + 1] <= g) ++v;
+    const FrameArgs F = views[v].F;
+    const int tile = (int)(g - tile_off[v]);
+    uint32_t c = 0;
+    if (backward) {
+        const int* nc_arr = views[v].B.n_contrib;
+        const int tx = tile % F.TX, ty = tile / F.TX;
+        const int px = tx * TILE + (threadIdx.x & 15), py = ty * TILE + (threadIdx.x >> 4);
+        const int nc = (px < F.W && py < F.H) ? nc_arr[(int64_t)py * F.W + px] : 0;
+        const int m = wave_max(nc);
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+        __syncthreads();
+        c = (uint32_t)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    } else {
+        c = F.ranges[2 * tile + 1] - F.ranges[2 * tile];
+    }
+    if (threadIdx.x == 0) cost[g] = c;
+}
+
 // Single workgroup: rank tiles (raster order, or by descending cost bucket)
 // and deal them.  Sub-tile items: tile of rank r goes to queue group r mod 16,
 // its sub-tile s to queue 4 (r mod 16) + s, at queue position r / 16.  Tile
 // items (per_tile): queue r mod 64, position r / 64.  Also resets the 64 fetch
 // counters and stores the item count.
 __global__ __launch_bounds__(1024) void k_queue(int n_tiles, const uint32_t* __restrict__ cost, int by_cost,
-                                                int per_tile, uint32_t* __restrict__ items,
-                                                uint32_t* __restrict__ ctr) {
+                                                int per_tile, const uint32_t* __restrict__ tile_off, int n_views,
+                                                uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
     __shared__ uint32_t hist[NBUCKET];
     auto deal = [&](uint32_t r, uint32_t tile) {
+        uint32_t vbits = 0;
+        if (tile_off) {  // batched views: global tile -> (view, tile of the view)
+            int v = 0;
+            while (v + 1 < n_views && tile_off[v + 1] <= tile) ++v;
+            tile -= tile_off[v];
+            vbits = (uint32_t)v << VIEW_SHIFT;
+        }
         if (per_tile) {  // tile of rank r: queue r mod 64, position r / 64, i.e. items[r]
-            items[r] = tile;
+            items[r] = vbits | tile;
             return;
         }
         const uint32_t grp = r % QGROUPS, pos = r / QGROUPS;
-        for (uint32_t sub = 0; sub < 4; ++sub) items[(size_t)pos * NQ + grp * 4 + sub] = tile * 4 + sub;
+        for (uint32_t sub = 0; sub < 4; ++sub) items[(size_t)pos * NQ + grp * 4 + sub] = vbits | (tile * 4 + sub);
     };
     if (!by_cost) {
         for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x) deal(t, t);
@@ -702,6 +925,8 @@ static bgs_status check_frame(const bgs_frame* f, const bgs_render_cfg* cfg, Fra
     A.bg0 = cfg->bg[0];
     A.bg1 = cfg->bg[1];
     A.bg2 = cfg->bg[2];
+    A.trace = cfg->wg_trace;
+    A.trace_cap = cfg->wg_trace ? cfg->wg_trace_cap : 0;
     return BGS_OK;
 }
 
@@ -714,8 +939,10 @@ static int persistent_blocks(K kernel, uint32_t n_items) {
     return (int)(want < cap ? want : (cap > 0 ? cap : 1));
 }
 
-static bool tile_items(const bgs_render_cfg* cfg, bool backward) {
-    return !backward && cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 16;
+// Whole 16x16 tiles as work items: the forward's tile-granular workgroups and
+// the backward's wave-per-tile kernel.
+static bool tile_items(const bgs_render_cfg* cfg) {
+    return cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 16;
 }
 
 static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, const int* n_contrib, char* ws,
@@ -728,8 +955,9 @@ static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, con
         hipLaunchKernelGGL(k_tile_costs, dim3(A.n_tiles), dim3(256), 0, stream, A, n_contrib, cost);
         BGS_HIP(hipGetLastError());
     }
-    const int per_tile = tile_items(cfg, n_contrib != nullptr) ? 1 : 0;
-    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, A.n_tiles, cost, by_cost, per_tile, items, ctr);
+    const int per_tile = tile_items(cfg) ? 1 : 0;
+    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, A.n_tiles, cost, by_cost, per_tile,
+                       (const uint32_t*)nullptr, 1, items, ctr);
     BGS_HIP(hipGetLastError());
     return BGS_OK;
 }
@@ -777,7 +1005,7 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
     }
     auto* ctr = reinterpret_cast<uint32_t*>(w + L.ctr);
     auto* items = reinterpret_cast<const uint32_t*>(w + L.items);
-    if (tile_items(cfg, false)) {
+    if (tile_items(cfg)) {
         const int blocks = persistent_blocks(k_fwd_tile, (uint32_t)A.n_tiles * 4u);
         hipLaunchKernelGGL(k_fwd_tile, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
     } else if (cfg->variant == BGS_BALANCED_GAUSS) {
@@ -788,7 +1016,8 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
         hipLaunchKernelGGL(k_fwd_hybrid<HYBRID_SWITCH>, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
     } else {
         const int blocks = persistent_blocks(k_fwd_pixel<true>, L.n_items);
-        hipLaunchKernelGGL(k_fwd_pixel<true>, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
+        hipLaunchKernelGGL(k_fwd_pixel<true>, dim3(blocks), dim3(256), 0, stream, A, O, (const ViewDesc*)nullptr,
+                           items, ctr);
     }
     BGS_HIP(hipGetLastError());
     return BGS_OK;
@@ -806,7 +1035,8 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
     BGS_REQUIRE(dL_dmeans2D && dL_dconic_opacity && dL_drgb, "bgs_render_bwd: null gradient output");
     BwdIO B{final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepths};
     if (cfg->variant == BGS_STATIC) {
-        hipLaunchKernelGGL(k_bwd_pixel<false>, dim3(A.n_tiles), dim3(256), 0, stream, A, B, nullptr, nullptr);
+        hipLaunchKernelGGL(k_bwd_pixel<false>, dim3(A.n_tiles), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
+                           (const uint32_t*)nullptr, (uint32_t*)nullptr);
         BGS_HIP(hipGetLastError());
         return BGS_OK;
     }
@@ -819,8 +1049,188 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
     }
     auto* ctr = reinterpret_cast<uint32_t*>(w + L.ctr);
     auto* items = reinterpret_cast<const uint32_t*>(w + L.items);
-    const int blocks = persistent_blocks(k_bwd_pixel<true>, L.n_items);
-    hipLaunchKernelGGL(k_bwd_pixel<true>, dim3(blocks), dim3(256), 0, stream, A, B, items, ctr);
+    if (tile_items(cfg)) {
+        const int blocks = persistent_blocks(k_bwd_wide<false>, (uint32_t)A.n_tiles);
+        hipLaunchKernelGGL(k_bwd_wide<false>, dim3(blocks), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
+                           items, ctr);
+    } else {
+        const int blocks = persistent_blocks(k_bwd_pixel<true>, L.n_items);
+        hipLaunchKernelGGL(k_bwd_pixel<true>, dim3(blocks), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
+                           items, ctr);
+    }
     BGS_HIP(hipGetLastError());
+    return BGS_OK;
+}
+
+// ======================================================================
+// Batched views in one graph: a cross-view queue (every sub-tile of every
+// view, ranked by cost across views) feeds one persistent forward and one
+// persistent backward launch; the gradient zero-fill, both cost passes and
+// both queue builds (which reset the fetch counters with a kernel, not a
+// memset) are captured with them into one hipGraph, so a training step over
+// all views is a single hipGraphLaunch.
+// ======================================================================
+namespace bgs {
+
+// zero the gradient outputs of every view (blockIdx.y = view)
+__global__ __launch_bounds__(256) void k_zero_grads(const ViewDesc* __restrict__ views) {
+    const ViewDesc& V = views[blockIdx.y];
+    const int64_t P = V.P;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += stride) {
+        reinterpret_cast<float2*>(V.B.g_means2D)[i] = make_float2(0.f, 0.f);
+        reinterpret_cast<float4*>(V.B.g_conic_opacity)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        V.B.g_rgb[3 * i] = 0.f;
+        V.B.g_rgb[3 * i + 1] = 0.f;
+        V.B.g_rgb[3 * i + 2] = 0.f;
+        if (V.B.g_depth) V.B.g_depth[i] = 0.f;
+    }
+}
+
+}  // namespace bgs
+
+struct bgs_plan {
+    int n_views = 0;
+    uint32_t total_tiles = 0;
+    bgs::ViewDesc* d_views = nullptr;
+    uint32_t* d_tile_off = nullptr;
+    uint32_t* d_items = nullptr;
+    uint32_t* d_cost = nullptr;
+    uint32_t* d_ctr = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" void bgs_plan_destroy(bgs_plan* plan) {
+    if (!plan) return;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    (void)hipFree(plan->d_views);
+    (void)hipFree(plan->d_tile_off);
+    (void)hipFree(plan->d_items);
+    (void)hipFree(plan->d_cost);
+    (void)hipFree(plan->d_ctr);
+    delete plan;
+}
+
+extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs_frame* frames,
+                                      const bgs_view_io* io, const bgs_render_cfg* cfg,
+                                      const bgs_render_cfg* cfg_bwd, hipStream_t stream) {
+    BGS_REQUIRE(out && frames && io && cfg, "bgs_plan_create: null argument");
+    *out = nullptr;
+    BGS_REQUIRE(n_views >= 1 && n_views <= MAX_VIEWS, "bgs_plan_create: 1..64 views");
+    if (!cfg_bwd) cfg_bwd = cfg;
+    if (cfg->variant != BGS_BALANCED_PIXEL || cfg->subtile != 8)
+        return fail(BGS_EUNSUPPORTED, "bgs_plan_create: the batched forward uses the balanced pixel-wise 8x8 variant");
+    if (cfg_bwd->variant != BGS_BALANCED_PIXEL || (cfg_bwd->subtile != 8 && cfg_bwd->subtile != 16))
+        return fail(BGS_EUNSUPPORTED, "bgs_plan_create: the batched backward uses the balanced pixel-wise variant");
+    if (cfg_bwd->order != BGS_ORDER_RASTER && cfg_bwd->order != BGS_ORDER_COST)
+        return fail(BGS_EINVAL, "bgs_plan_create: unknown backward order");
+    std::vector<ViewDesc> vd(n_views);
+    std::vector<uint32_t> off(n_views + 1, 0);
+    for (int v = 0; v < n_views; ++v) {
+        FrameArgs A;
+        bgs_status st = check_frame(&frames[v], cfg, A, "bgs_plan_create");
+        if (st != BGS_OK) return st;
+        const bgs_view_io& q = io[v];
+        BGS_REQUIRE(q.P >= 0, "bgs_plan_create: view P < 0");
+        BGS_REQUIRE(q.out_color && q.out_alpha && q.out_depth && q.final_T && q.n_contrib,
+                    "bgs_plan_create: null forward output");
+        BGS_REQUIRE(q.dL_dcolor && q.dL_dmeans2D && q.dL_dconic_opacity && q.dL_drgb,
+                    "bgs_plan_create: null upstream or gradient buffer");
+        BGS_REQUIRE((reinterpret_cast<uintptr_t>(q.dL_dconic_opacity) & 15) == 0 &&
+                        (reinterpret_cast<uintptr_t>(q.dL_dmeans2D) & 7) == 0,
+                    "bgs_plan_create: gradient buffers must be aligned like their inputs");
+        BGS_REQUIRE((uint64_t)A.n_tiles < (1u << (VIEW_SHIFT - 2)), "bgs_plan_create: too many tiles in a view");
+        vd[v].F = A;
+        vd[v].O = FwdOut{q.out_color, q.out_alpha, q.out_depth, q.final_T, q.n_contrib};
+        vd[v].B = BwdIO{q.final_T,     q.n_contrib,     q.dL_dcolor,       q.dL_dalpha, q.dL_ddepth,
+                        q.dL_dmeans2D, q.dL_dconic_opacity, q.dL_drgb,     q.dL_ddepths};
+        vd[v].P = q.P;
+        off[v + 1] = off[v] + (uint32_t)A.n_tiles;
+    }
+    bgs_plan* plan = new bgs_plan();
+    plan->n_views = n_views;
+    plan->total_tiles = off[n_views];
+    const size_t rounds = ((size_t)plan->total_tiles + QGROUPS - 1) / QGROUPS;
+    auto cleanup_fail = [&](const std::string& what, hipError_t e) {
+        bgs_plan_destroy(plan);
+        return fail(BGS_EHIP, what + ": " + hipGetErrorString(e));
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&plan->d_views, sizeof(ViewDesc) * n_views)) != hipSuccess) return cleanup_fail("hipMalloc", e);
+    if ((e = hipMalloc(&plan->d_tile_off, sizeof(uint32_t) * (n_views + 1))) != hipSuccess)
+        return cleanup_fail("hipMalloc", e);
+    if ((e = hipMalloc(&plan->d_items, sizeof(uint32_t) * (rounds * NQ > 0 ? rounds * NQ : 1))) != hipSuccess)
+        return cleanup_fail("hipMalloc", e);
+    if ((e = hipMalloc(&plan->d_cost, sizeof(uint32_t) * (plan->total_tiles ? plan->total_tiles : 1))) != hipSuccess)
+        return cleanup_fail("hipMalloc", e);
+    if ((e = hipMalloc(&plan->d_ctr, sizeof(uint32_t) * (NQ * QSTRIDE + QSTRIDE))) != hipSuccess)
+        return cleanup_fail("hipMalloc", e);
+    if ((e = hipMemcpyAsync(plan->d_views, vd.data(), sizeof(ViewDesc) * n_views, hipMemcpyHostToDevice, stream)) !=
+        hipSuccess)
+        return cleanup_fail("hipMemcpyAsync", e);
+    if ((e = hipMemcpyAsync(plan->d_tile_off, off.data(), sizeof(uint32_t) * (n_views + 1), hipMemcpyHostToDevice,
+                            stream)) != hipSuccess)
+        return cleanup_fail("hipMemcpyAsync", e);
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return cleanup_fail("hipStreamSynchronize", e);
+
+    int64_t maxP = 1;
+    for (int v = 0; v < n_views; ++v) maxP = std::max<int64_t>(maxP, io[v].P);
+    const unsigned zero_blocks = (unsigned)std::min<int64_t>((maxP + 255) / 256, 1024);
+    const uint32_t n_items = plan->total_tiles * 4u;
+    const int fblocks = persistent_blocks(k_fwd_pixel<true, true>, n_items);
+    const bool bwd_wide = tile_items(cfg_bwd);
+    const int bblocks = bwd_wide ? persistent_blocks(k_bwd_wide<true>, plan->total_tiles)
+                                 : persistent_blocks(k_bwd_pixel<true, true>, n_items);
+    const int by_cost = cfg->order == BGS_ORDER_COST;
+    const int bwd_by_cost = cfg_bwd->order == BGS_ORDER_COST;
+    const FrameArgs F0{};
+    const FwdOut O0{};
+    const BwdIO B0{};
+
+    // record on a private stream (the legacy default stream cannot capture);
+    // the graph is launched later on the caller's stream
+    hipStream_t cap = nullptr;
+    if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
+        return cleanup_fail("hipStreamCreateWithFlags", e);
+    if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed)) != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return cleanup_fail("hipStreamBeginCapture", e);
+    }
+    stream = cap;
+    hipLaunchKernelGGL(k_zero_grads, dim3(zero_blocks, n_views), dim3(256), 0, stream, plan->d_views);
+    if (by_cost)
+        hipLaunchKernelGGL(k_tile_costs_mv, dim3(plan->total_tiles), dim3(256), 0, stream, plan->d_views,
+                           plan->d_tile_off, n_views, 0, plan->d_cost);
+    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, (int)plan->total_tiles, plan->d_cost, by_cost, 0,
+                       plan->d_tile_off, n_views, plan->d_items, plan->d_ctr);
+    hipLaunchKernelGGL((k_fwd_pixel<true, true>), dim3(fblocks), dim3(256), 0, stream, F0, O0, plan->d_views,
+                       plan->d_items, plan->d_ctr);
+    if (bwd_by_cost)
+        hipLaunchKernelGGL(k_tile_costs_mv, dim3(plan->total_tiles), dim3(256), 0, stream, plan->d_views,
+                           plan->d_tile_off, n_views, 1, plan->d_cost);
+    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, (int)plan->total_tiles, plan->d_cost, bwd_by_cost,
+                       bwd_wide ? 1 : 0, plan->d_tile_off, n_views, plan->d_items, plan->d_ctr);
+    if (bwd_wide)
+        hipLaunchKernelGGL((k_bwd_wide<true>), dim3(bblocks), dim3(256), 0, stream, F0, B0, plan->d_views,
+                           plan->d_items, plan->d_ctr);
+    else
+        hipLaunchKernelGGL((k_bwd_pixel<true, true>), dim3(bblocks), dim3(256), 0, stream, F0, B0, plan->d_views,
+                           plan->d_items, plan->d_ctr);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cap, &graph);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return cleanup_fail("hipStreamEndCapture", e);
+    plan->graph = graph;
+    if ((e = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+        return cleanup_fail("hipGraphInstantiate", e);
+    *out = plan;
+    return BGS_OK;
+}
+
+extern "C" bgs_status bgs_plan_launch(bgs_plan* plan, hipStream_t stream) {
+    BGS_REQUIRE(plan && plan->exec, "bgs_plan_launch: null plan");
+    BGS_HIP(hipGraphLaunch(plan->exec, stream));
     return BGS_OK;
 }

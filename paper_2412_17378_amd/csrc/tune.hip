@@ -3,8 +3,9 @@
 // shared-memory static kernel on the current data and keeps the faster.  Here
 // every forward candidate (static, pixel-wise 8x8 raster / cost-ordered,
 // tile-granular persistent, hybrid, Gaussian-wise) and every backward
-// candidate (static, balanced raster / cost-ordered) is run on the caller's
-// frame and timed with HIP events; the winners are returned and cached in a
+// candidate (static, balanced 8x8 raster / cost-ordered, wave per 16x16
+// tile) is run on the caller's frame and timed with HIP events; the winners
+// are returned and cached in a
 // text file keyed by a workload signature (image size and log2 buckets of the
 // pair count and of the 50th / 99th / 100th percentile tile-list lengths), so
 // a later call on a similar workload skips the timing.
@@ -119,7 +120,8 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
                                 {BGS_BALANCED_HYBRID, 8, BGS_ORDER_COST},  {BGS_BALANCED_GAUSS, 8, BGS_ORDER_COST}};
     const int bwd_cands[][3] = {{BGS_STATIC, 16, BGS_ORDER_RASTER},
                                 {BGS_BALANCED_PIXEL, 8, BGS_ORDER_RASTER},
-                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST}};
+                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST},
+                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST}};
     hipEvent_t e0, e1;
     BGS_HIP(hipEventCreate(&e0));
     BGS_HIP(hipEventCreate(&e1));

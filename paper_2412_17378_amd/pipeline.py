@@ -198,6 +198,45 @@ class Rasterizer:
         return B.bgs_autotune(f, base, out, dL_dcolor, grads, ws, cache_path)
 
 
+class BatchedPlan:
+    """Forward + backward over several prepared views in one hipGraph launch
+    (bgs_plan_*): one cross-view work queue, one persistent launch each way.
+    Owns the per-view outputs (`outs[v]`) and gradients (`grads[v]`), which
+    every launch overwrites."""
+
+    def __init__(self, rast: Rasterizer, preps, upstream, cfg: B.RenderCfg, cfg_bwd: B.RenderCfg = None):
+        self.preps = list(preps)
+        self.upstream = [u.contiguous() for u in upstream]
+        dev = rast.device
+        self.outs, self.grads, frames, ios = [], [], [], []
+        for prep, g in zip(self.preps, self.upstream):
+            H, W, P = prep.height, prep.width, prep.P
+            out = dict(color=torch.empty(3, H, W, device=dev), alpha=torch.empty(H, W, device=dev),
+                       depth=torch.empty(H, W, device=dev), final_T=torch.empty(H, W, device=dev),
+                       n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
+            grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
+                         rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
+            self.outs.append(out)
+            self.grads.append(grads)
+            frames.append(prep.frame())
+            ios.append(B.make_view_io(P, out, g, grads))
+        self.handle = B.bgs_plan_create(frames, ios, cfg, cfg_bwd)
+
+    def launch(self):
+        B.bgs_plan_launch(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            B.bgs_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class AdaptiveSelector:
     """The training-time selection policy of Sec. 4.4: start from the given
     configuration and, every `interval` calls, re-measure the candidates on

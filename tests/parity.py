@@ -35,16 +35,16 @@ def check_close(x, y, s_floor, name, rtol=RTOL, mask=None):
     assert x.shape == y.shape, (name, x.shape, y.shape)
     tol = rtol * np.maximum(np.abs(y), s_floor)
     ratio = np.abs(x - y) / tol
-    if mask is not None:
-        ratio = ratio[np.broadcast_to(mask, ratio.shape)]
-    if ratio.size == 0:
+    keep = np.ones(ratio.shape, bool) if mask is None else np.broadcast_to(mask, ratio.shape)
+    if not keep.any():
         return 0.0, 0.0
-    worst = float(ratio.max())
+    full = np.where(keep, ratio, 0.0)
+    worst = float(full.max()) if np.isfinite(full).all() else float("inf")
     if not worst <= 1.0:
-        idx = int(np.argmax(ratio))
-        raise AssertionError(f"{name}: max |x-y|/tol = {worst:.3g} at flat index {idx} "
-                             f"(x={x.reshape(-1)[idx] if mask is None else 'masked'})")
-    return worst, float(np.quantile(ratio, 0.999))
+        idx = np.unravel_index(int(np.argmax(np.where(np.isfinite(full), full, np.inf))), full.shape)
+        raise AssertionError(f"{name}: max |x-y|/tol = {worst:.3g} at index {tuple(int(i) for i in idx)} "
+                             f"(x={x[idx]!r}, y={y[idx]!r}; {int((full > 1).sum())} elements over)")
+    return worst, float(np.quantile(ratio[keep], 0.999))
 
 
 def rms(y):

@@ -102,7 +102,11 @@ def test_full_backward_cropped(full):
         m = orc["margin"][y0:y1, x0:x1] < MARGIN
         flagged_total += int(m.sum())
         gC[:, y0:y1, x0:x1][:, m] = 0.0
-    grads = rast.render_bwd(prep, cfg, fwd, torch.from_numpy(gC).cuda())
+    from paper_2412_17378_amd import make_cfg
+    runs = []
+    for c in (cfg, make_cfg("pixel", 16, "cost"), make_cfg("static")):
+        print(f"[full-bwd] cfg variant={c.variant} sub={c.subtile}", flush=True)
+        runs.append((c, rast.render_bwd(prep, c, fwd, torch.from_numpy(gC).cuda())))
     torch.cuda.synchronize()
     acc = None
     for w in wins:
@@ -112,4 +116,5 @@ def test_full_backward_cropped(full):
         else:
             for k in ("means2D", "conic", "opacity", "rgb", "depth"):
                 acc[k] = acc[k] + o[k]
-    compare_grads(grads, acc, name="full bwd")
+    for c, grads in runs:
+        compare_grads(grads, acc, name=f"full bwd variant={c.variant} sub={c.subtile}")

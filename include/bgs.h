@@ -99,9 +99,8 @@ typedef struct bgs_render_cfg {
     int32_t variant;          /* bgs_variant */
     int32_t subtile;          /* balanced variants: work-item edge.  8: one wave per
                                  8x8 sub-tile (one pixel per lane).  16 (BGS_BALANCED_PIXEL
-                                 only): whole 16x16 tiles -- the forward gives each to a
-                                 256-lane workgroup, the backward to one wave with four
-                                 pixels per lane */
+                                 only): one wave per whole 16x16 tile, four pixels per
+                                 lane, forward and backward */
     int32_t order;            /* bgs_order */
     int32_t flags;            /* BGS_FLAG_* */
     float bg[3];              /* background colour */
@@ -113,6 +112,12 @@ typedef struct bgs_render_cfg {
        Records of waves not launched are left untouched (zero the buffer). */
     uint64_t* wg_trace;
     int64_t wg_trace_cap;
+    /* Optional work count (DEVICE [H][W], nullable; bgs_render_fwd only):
+       per pixel the number of list entries the sequential loop examines,
+       skipped entries and the stopping entry included (the list length when
+       the pixel never stops).  Written by BGS_BALANCED_PIXEL with subtile
+       16; other variants return BGS_EUNSUPPORTED when it is set. */
+    int32_t* n_examined;
 } bgs_render_cfg;
 
 /* Thread-local text for the last non-OK status of this thread. */
@@ -259,7 +264,7 @@ bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cfg* cfg, con
 /*
  * Variant selection by measurement (the self-adaptive kernel selection of
  * Sec. 4.4, generalized): runs every forward candidate (static; pixel-wise 8x8
- * raster and cost-ordered; tile-granular persistent; hybrid; Gaussian-wise) on
+ * raster and cost-ordered; one wave per 16x16 tile; hybrid; Gaussian-wise) on
  * `frame` with base's background, times each with HIP events (one warm-up,
  * two timed runs) and returns the fastest in *best_fwd; then renders once with
  * it and, if dL_dcolor and the gradient buffers are given, times the backward
@@ -307,9 +312,9 @@ typedef struct bgs_plan bgs_plan;
  * backward over all views.  frames / io are HOST arrays of n_views (1..64)
  * entries; the device buffers they point to must stay valid (their contents
  * may change between launches, e.g. per-tile lists rebuilt in place).
- * cfg_fwd must select BGS_BALANCED_PIXEL with subtile 8; cfg_bwd (nullable:
- * same as cfg_fwd) BGS_BALANCED_PIXEL with subtile 8 or 16; each gives its
- * pass's queue order, cfg_fwd the background.  Other variants return
+ * cfg_fwd and cfg_bwd (nullable: same as cfg_fwd) must select
+ * BGS_BALANCED_PIXEL with subtile 8 or 16; each gives its pass's queue order,
+ * cfg_fwd the background.  Other variants return
  * BGS_EUNSUPPORTED.  The plan owns its queue memory and graph
  * (allocated here, freed by bgs_plan_destroy).  The graph is recorded on a
  * private stream; `stream` only receives the descriptor uploads and is

@@ -55,7 +55,8 @@ class ViewIO(C.Structure):
 
 class RenderCfg(C.Structure):
     _fields_ = [("variant", C.c_int32), ("subtile", C.c_int32), ("order", C.c_int32), ("flags", C.c_int32),
-                ("bg", C.c_float * 3), ("wg_trace", C.c_void_p), ("wg_trace_cap", C.c_int64)]
+                ("bg", C.c_float * 3), ("wg_trace", C.c_void_p), ("wg_trace_cap", C.c_int64),
+                ("n_examined", C.c_void_p)]
 
 
 _LIB = None

@@ -10,8 +10,6 @@
 // the same list a (tile, depth, id) sort gives.
 #include <cstring>
 
-#include <rocprim/block/block_radix_sort.hpp>
-#include <rocprim/block/block_scan.hpp>
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
@@ -404,109 +402,50 @@ __global__ __launch_bounds__(256) void k_chunk_base(int C, int nt, const uint32_
     }
 }
 
-// One 256-lane workgroup per chunk (CHUNK = 256 Gaussians, in depth order)
-// writes the chunk's (group, Gaussian) pairs into the coarse lists, each
-// group's run contiguously at the chunk's base slot of the group.  The
-// chunk's pairs are enumerated Gaussian-major (entry e of Gaussian i at
-// off[i] + its row-major index in i's group rectangle) and handled in windows
-// of EMIT_WIN entries: every entry becomes the unique key (group << 8 | i),
-// a block radix sort orders the window by (group, depth rank), and sorted
-// position p goes to nextpos[group] + (p - first position of its group);
-// nextpos then advances by the run length.  Consecutive lanes thus store
-// consecutive slots of one group instead of one slot in each of 64 groups.
-constexpr int EMIT_IPT = 8;
-constexpr int EMIT_WIN = 256 * EMIT_IPT;
-
-__global__ __launch_bounds__(256) void k_chunk_emit(int64_t P, int GX, int GY, int key_bits,
-                                                    const uint32_t* __restrict__ order,
-                                                    const uint2* __restrict__ rect, const uint32_t* __restrict__ base,
-                                                    uint32_t* __restrict__ coarse) {
-    using Sort = rocprim::block_radix_sort<uint32_t, 256, EMIT_IPT>;
-    using Scan = rocprim::block_scan<uint32_t, 256>;
-    __shared__ typename Sort::storage_type s_sort;
-    __shared__ typename Scan::storage_type s_scan;
-    __shared__ uint32_t s_off[257];
-    __shared__ uint32_t s_id[256];
-    __shared__ int s_gx0[256], s_gy0[256], s_w[256];
-    __shared__ float s_invw[256];
-    __shared__ uint32_t s_key[EMIT_WIN];
+// One wave per chunk: drop the chunk's (group, Gaussian) pairs, Gaussians in
+// depth order, at the chunk's base slot of each group plus a running count
+// kept in LDS.
+__global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, const uint32_t* __restrict__ order,
+                                                   const uint2* __restrict__ rect, const uint32_t* __restrict__ base,
+                                                   uint32_t* __restrict__ coarse) {
     extern __shared__ uint32_t nextpos[];  // ng running slots
     const int ng = GX * GY;
-    const int tid = threadIdx.x, c = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int c = blockIdx.x;
     const uint32_t* bc = base + (int64_t)c * ng;
-    for (int t = tid; t < ng; t += 256) nextpos[t] = bc[t];
-    const int64_t k = (int64_t)c * CHUNK + tid;
-    uint32_t n = 0;
-    int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
-    uint32_t g = 0;
-    if (k < P) {
-        g = order[k];
-        if (group_rect(rect[g], x0, y0, x1, y1)) n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
-    }
-    s_id[tid] = g;
-    s_gx0[tid] = x0;
-    s_gy0[tid] = y0;
-    s_w[tid] = n ? x1 - x0 + 1 : 1;
-    s_invw[tid] = 1.0f / (float)(n ? x1 - x0 + 1 : 1);
-    uint32_t off = 0, total = 0;
-    Scan().exclusive_scan(n, off, 0u, total, s_scan);
-    s_off[tid] = off;
-    if (tid == 0) s_off[256] = total;
-    __syncthreads();
-    const uint32_t E = s_off[256];
-    for (uint32_t w0 = 0; w0 < E; w0 += EMIT_WIN) {
-        uint32_t keys[EMIT_IPT];
-#pragma unroll
-        for (int j = 0; j < EMIT_IPT; ++j) {
-            const uint32_t e = w0 + (uint32_t)(tid * EMIT_IPT + j);
-            keys[j] = 0xFFFFFFFFu;
-            if (e < E) {
-                int lo = 0, hi = 256;  // s_off[lo] <= e < s_off[hi]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_off[mid] <= e) lo = mid;
-                    else hi = mid;
-                }
-                const int l = (int)(e - s_off[lo]), w = s_w[lo];
-                int q = (int)((float)l * s_invw[lo]);
-                int r = l - q * w;
-                if (r >= w) { ++q; r -= w; }
-                if (r < 0) { --q; r += w; }
-                const uint32_t grp = (uint32_t)((s_gy0[lo] + q) * GX + s_gx0[lo] + r);
-                keys[j] = grp << 8 | (uint32_t)lo;
+    for (int t = lane; t < ng; t += 64) nextpos[t] = bc[t];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int m = 0; m < CHUNK / 64; ++m) {
+        const int64_t k0 = (int64_t)c * CHUNK + m * 64;
+        if (k0 >= P) break;
+        const int64_t k = k0 + lane;
+        uint32_t g = 0, n = 0;
+        int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+        if (k < P) {
+            g = order[k];
+            if (group_rect(rect[g], x0, y0, x1, y1)) n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+        }
+        const int cntk = (int)((P - k0) < 64 ? (P - k0) : 64);
+        for (int i = 0; i < cntk; ++i) {
+            const uint32_t ni = __builtin_amdgcn_readlane(n, i);
+            if (ni == 0) continue;
+            const uint32_t gi = __builtin_amdgcn_readlane(g, i);
+            const int xi = __builtin_amdgcn_readlane(x0, i), yi = __builtin_amdgcn_readlane(y0, i);
+            const int wi = __builtin_amdgcn_readlane(x1, i) - xi + 1;
+            const float inv_w = 1.0f / (float)wi;
+            for (uint32_t j = lane; j < ni; j += 64) {
+                int q = (int)((float)j * inv_w);
+                int r = (int)j - q * wi;
+                if (r >= wi) { ++q; r -= wi; }
+                if (r < 0) { --q; r += wi; }
+                const int t = (yi + q) * GX + xi + r;
+                const uint32_t pos = nextpos[t];
+                nextpos[t] = pos + 1;
+                coarse[pos] = gi;
             }
         }
-        Sort().sort_to_striped(keys, s_sort, 0, (unsigned)key_bits + 8u);
-        const uint32_t cnt = min(E - w0, (uint32_t)EMIT_WIN);
-#pragma unroll
-        for (int j = 0; j < EMIT_IPT; ++j) s_key[j * 256 + tid] = keys[j];
-        __syncthreads();
-        uint32_t adv_grp[EMIT_IPT], adv_to[EMIT_IPT];
-#pragma unroll
-        for (int j = 0; j < EMIT_IPT; ++j) {
-            const uint32_t p = (uint32_t)(j * 256 + tid);
-            adv_grp[j] = 0xFFFFFFFFu;
-            if (p < cnt) {
-                const uint32_t grp = keys[j] >> 8;
-                uint32_t lo = 0, hi = p;  // first position of the group's run
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if ((s_key[mid] >> 8) < grp) lo = mid + 1;
-                    else hi = mid;
-                }
-                const uint32_t slot = nextpos[grp] + (p - lo);
-                coarse[slot] = s_id[keys[j] & 255u];
-                if (p + 1 == cnt || (s_key[p + 1] >> 8) != grp) {
-                    adv_grp[j] = grp;
-                    adv_to[j] = slot + 1;
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < EMIT_IPT; ++j)
-            if (adv_grp[j] != 0xFFFFFFFFu) nextpos[adv_grp[j]] = adv_to[j];
-        __syncthreads();
     }
 }
 
@@ -530,11 +469,18 @@ __global__ __launch_bounds__(256) void k_seg_map(int ng, const uint32_t* __restr
     for (uint32_t q = 0; q < n; ++q) segmap[b + q] = make_uint2((uint32_t)g, q);
 }
 
-// One workgroup per segment; wave w owns the group's tiles 4w .. 4w+3 (local
-// (i % 4, i / 4)) and walks the segment's entries in order.
-// COUNT: segcnt[seg][i] = entries whose rectangle contains local tile i.
-// WRITE: append each such entry at segcnt[seg][i] (by then the slot where
-// this segment's run of tile i starts) + running count.
+// One workgroup per segment; wave w walks the contiguous quarter
+// [e0 + w SEG/4, e0 + (w+1) SEG/4) of it, 64 entries at a time, and for each
+// of the group's 16 tiles (local index i = (x mod 4) + 4 (y mod 4)) takes
+// the ballot of the entries whose rectangle contains the tile.  Counts are
+// kept per (segment, wave) unit, so the write pass knows every wave's start
+// slots and needs no exchange between waves.
+// COUNT: segcnt[seg][i][w] = entries of wave w's quarter whose rectangle
+// contains tile i.
+// WRITE: append each such entry at segcnt[seg][i][w] (by then the slot where
+// that quarter's run of tile i starts) + the earlier entries of that run.
+constexpr int SUBSEG = SEG / 4;
+
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_seg_split(int TX, int TY, int GX, const uint64_t* __restrict__ n_segs,
                                                    const uint2* __restrict__ segmap,
@@ -547,59 +493,52 @@ __global__ __launch_bounds__(256) void k_seg_split(int TX, int TY, int GX, const
     if (sidx >= n_segs[0]) return;
     const uint2 gs = segmap[sidx];
     const int grp = (int)gs.x;
-    const int gx = grp % GX, gy = grp / GX;
+    const int gx0 = (grp % GX) * GTILES, gy0 = (grp / GX) * GTILES;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int tx[4], ty[4];
-    bool ok[4];
-    uint32_t run[4];
+    // counts of (segment, tile i, wave w) at segcnt[(segment * 16 + i) * 4 + w]
+    // tile columns / rows of the group inside the image
+    const uint32_t colv = (1u << min(GTILES, TX - gx0)) - 1u, rowv = (1u << min(GTILES, TY - gy0)) - 1u;
+    uint32_t run[16];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int li = wv * 4 + u;
-        tx[u] = gx * GTILES + (li % GTILES);
-        ty[u] = gy * GTILES + (li / GTILES);
-        ok[u] = tx[u] < TX && ty[u] < TY;
-        run[u] = WRITE ? segcnt[(size_t)sidx * 16 + li] : 0u;
-    }
+    for (int i = 0; i < 16; ++i) run[i] = WRITE ? segcnt[((size_t)sidx * 16 + i) * 4 + wv] : 0u;
     const uint32_t gt = gtotal[grp];
-    const uint32_t e0 = gs.y * SEG;
-    const uint32_t e1 = min(gt, e0 + SEG);
+    const uint32_t e0 = min(gt, gs.y * SEG + wv * SUBSEG);
+    const uint32_t e1 = min(gt, gs.y * SEG + (wv + 1) * SUBSEG);
     const uint32_t b0 = gstart[grp];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // SB rounds of 64 entries per memory round trip: all ids first, then all
-    // (dependent) rectangle gathers, then the ordered appends
-    constexpr int SB = 8;
-    for (uint32_t k0 = e0; k0 < e1; k0 += 64 * SB) {
-        uint32_t gb[SB];
-        uint2 rb[SB];
+    for (uint32_t k0 = e0; k0 < e1; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        uint32_t g = 0, tmask = 0;
+        if (k < e1) {
+            g = coarse[b0 + k];
+            const uint2 r = rect[g];
+            const int x0 = (int)(r.x & 0xFFFF) - gx0, y0 = (int)(r.x >> 16) - gy0;
+            const int x1 = (int)(r.y & 0xFFFF) - gx0, y1 = (int)(r.y >> 16) - gy0;
+            // covered local columns / rows as bit ranges [lo, hi)
+            const int cl = min(max(x0, 0), GTILES), ch = min(max(x1 + 1, 0), GTILES);
+            const int rl = min(max(y0, 0), GTILES), rh = min(max(y1 + 1, 0), GTILES);
+            const uint32_t cols = colv & (((1u << ch) - 1u) & ~((1u << cl) - 1u));
+            const uint32_t rows = rowv & (((1u << rh) - 1u) & ~((1u << rl) - 1u));
 #pragma unroll
-        for (int b = 0; b < SB; ++b) {
-            const uint32_t k = k0 + b * 64 + lane;
-            gb[b] = k < e1 ? coarse[b0 + k] : 0u;
+            for (int y = 0; y < GTILES; ++y)
+                if (rows & (1u << y)) tmask |= cols << (GTILES * y);
         }
 #pragma unroll
-        for (int b = 0; b < SB; ++b) {
-            const uint32_t k = k0 + b * 64 + lane;
-            rb[b] = k < e1 ? rect[gb[b]] : make_uint2(1u, 0u);  // (1, 0): empty
-        }
-#pragma unroll
-        for (int b = 0; b < SB; ++b) {
-            const int x0 = (int)(rb[b].x & 0xFFFF), y0 = (int)(rb[b].x >> 16);
-            const int x1 = (int)(rb[b].y & 0xFFFF), y1 = (int)(rb[b].y >> 16);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool in = ok[u] && x0 <= tx[u] && tx[u] <= x1 && y0 <= ty[u] && ty[u] <= y1;
-                const uint64_t m = ballot(in);
-                if (WRITE && in) {
-                    const uint64_t pos = (uint64_t)run[u] + __builtin_popcountll(m & lt);
-                    if (pos < capacity) point_list[pos] = gb[b];
-                }
-                run[u] += (uint32_t)__builtin_popcountll(m);
+        for (int i = 0; i < 16; ++i) {
+            const bool in = (tmask >> i) & 1u;
+            const uint64_t m = ballot(in);
+            if (WRITE && in) {
+                const uint64_t pos = (uint64_t)run[i] + __builtin_popcountll(m & lt);
+                if (pos < capacity) point_list[pos] = g;
             }
+            run[i] += (uint32_t)__builtin_popcountll(m);
         }
     }
-    if (!WRITE && lane == 0) {
+    if (!WRITE && lane < 16) {
+        uint32_t c = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) segcnt[(size_t)sidx * 16 + wv * 4 + u] = run[u];
+        for (int i = 0; i < 16; ++i) c = lane == i ? run[i] : c;
+        segcnt[((size_t)sidx * 16 + lane) * 4 + wv] = c;
     }
 }
 
@@ -619,10 +558,10 @@ __global__ __launch_bounds__(256) void k_seg_scan(int TX, int TY, int GX, int ng
     const uint32_t n = nseg[grp], b = segstart[grp];
     uint32_t run = OFFSETS ? tstart[tile] : 0u;
     for (uint32_t q = 0; q < n; ++q) {
-        uint32_t& c = segcnt[(size_t)(b + q) * 16 + li];
-        const uint32_t v = c;
-        if (OFFSETS) c = run;
-        run += v;
+        uint4& c = reinterpret_cast<uint4*>(segcnt)[(size_t)(b + q) * 16 + li];  // the segment's 4 waves
+        const uint4 v = c;
+        if (OFFSETS) c = make_uint4(run, run + v.x, run + v.x + v.y, run + v.x + v.y + v.z);
+        run += v.x + v.y + v.z + v.w;
     }
     if (!OFFSETS) ttotal[tile] = run;
 }
@@ -674,7 +613,7 @@ static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P, size_t
     // segments: at most coarse_cap / SEG + ng of them
     L.max_segs = coarse_cap / SEG + (size_t)L.ng + 1;
     L.segmap = take(8 * L.max_segs);
-    L.segcnt = take(4 * 16 * L.max_segs);
+    L.segcnt = take(4 * 64 * L.max_segs);  // 16 counts per (segment, wave)
     L.temp_bytes = sort_bytes;
     L.temp = take(sort_bytes);
     L.bytes = off;
@@ -757,10 +696,8 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
                                        std::to_string(capacity));
     hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(nbg)), dim3(256), 0, stream, L.C, L.ng, gstart, part, h);
     BGS_HIP(hipGetLastError());
-    int gbits = 0;  // group ids < 2^gbits - 1, so no real key equals the window padding
-    while ((1 << gbits) - 1 <= L.ng) ++gbits;
-    hipLaunchKernelGGL(k_chunk_emit, dim3(L.C), dim3(256), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX, L.GY,
-                       gbits, order, rect, h, coarse);
+    hipLaunchKernelGGL(k_chunk_emit, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX, L.GY,
+                       order, rect, h, coarse);
     BGS_HIP(hipGetLastError());
     // fine (tile) lists, on segments of the coarse lists
     auto* nseg = reinterpret_cast<uint32_t*>(w + L.nseg);

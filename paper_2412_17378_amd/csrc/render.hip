@@ -32,6 +32,7 @@ namespace bgs {
 
 constexpr int NBUCKET = 136;         // cost buckets: 0 and quarter-octaves of 1 .. 2^33
 constexpr int HYBRID_SWITCH = 16;    // hybrid: Gaussian-wise once <= 16 of 64 pixels are active
+constexpr int WQ = 4;                // pixels per lane of the wave-per-tile kernels
 
 struct FrameArgs {
     int W, H, TX, TY, n_tiles;
@@ -44,6 +45,7 @@ struct FrameArgs {
     float bg0, bg1, bg2;
     uint64_t* trace;  // per-wave timing records (nullable), trace_cap of them
     int64_t trace_cap;
+    int* n_examined;  // optional per-pixel count of examined list entries (forward)
 };
 
 struct FwdOut {
@@ -123,6 +125,7 @@ struct Pix {
 
 // One list entry at list position pos (0-based) for one pixel.  Branch-free:
 // a skipped or stopping entry blends with weight 0 and leaves T unchanged.
+// Callers stop calling once s.done is set.
 __device__ __forceinline__ void blend(float fx, float fy, float2 xy, float4 co, float4 cd, int pos, Pix& s) {
     const float dx = fx - xy.x, dy = fy - xy.y;
     const float p2 = splat_power2(dx, dy, co.x, co.y, co.z);
@@ -460,61 +463,99 @@ __global__ __launch_bounds__(256) void k_fwd_hybrid(FrameArgs F, FwdOut O, const
 }
 
 // ------------------------------------------------- tile-granular persistent
-// Inter-block dynamic distribution at tile granularity (Sec. 4.1, Alg. 1):
-// persistent 256-lane workgroups take whole 16x16 tiles from the queue and
-// render them like the static kernel (shared 256-Gaussian LDS batches).
-__global__ __launch_bounds__(256) void k_fwd_tile(FrameArgs F, FwdOut O, const uint32_t* __restrict__ items,
-                                                  uint32_t* __restrict__ ctr) {
-    const uint64_t t_begin = trace_begin(F);
-    __shared__ float2 s_xy[256];
-    __shared__ float4 s_co[256];
-    __shared__ float4 s_cd[256];
-    __shared__ uint32_t s_item;
-    __shared__ int s_ok;
+// Persistent waves take whole 16x16 tiles from the queue (the inter-block
+// dynamic distribution of Sec. 4.1, Alg. 1, with a wave as the worker):
+// lane l owns the four pixels (l mod 16, l / 16 + 4q), q = 0..3.  One wave
+// per tile loads the tile's list once (a 256-lane workgroup per tile would
+// load it once too but synchronizes its four waves per batch; four 8x8
+// waves load it four times), and each staged entry is read from LDS once
+// for four pixels.  Pixel q of every lane forms a 16x4 block that is skipped
+// as soon as all its pixels have stopped; a lane leaves the entry loop once
+// its four pixels have, the wave once all 256 have.  Per pixel the arithmetic is that of
+// blend(), so the result equals the other variants bit for bit.
+// COUNT: also write F.n_examined[p] = list entries the sequential loop
+// examines for pixel p (the stopping entry included).
+template <bool MV = false, bool COUNT = false>
+__global__ __launch_bounds__(256) void k_fwd_wide(FrameArgs F0, FwdOut O0, const ViewDesc* __restrict__ views,
+                                                  const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
+    const uint64_t t_begin = trace_begin(F0);
+    __shared__ float2 s_xy[4][64];
+    __shared__ float4 s_co[4][64];
+    __shared__ float4 s_cd[4][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    WorkQueue Q = make_queue(ctr, items, blockIdx.x);
+    WorkQueue Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
     for (;;) {
-        if (wv == 0) {
-            uint32_t it = 0;
-            const bool ok = queue_next(Q, lane, it);
-            if (lane == 0) {
-                s_item = it;
-                s_ok = ok;
-            }
-        }
-        __syncthreads();
-        const bool ok = s_ok;
-        const int tile = (int)s_item;
-        __syncthreads();
-        if (!ok) break;
+        uint32_t item;
+        if (!queue_next(Q, lane, item)) break;
+        const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
+        const FwdOut O = MV ? views[item >> VIEW_SHIFT].O : O0;
+        const int tile = (int)(item & LOCAL_MASK);
         const int tx = tile % F.TX, ty = tile / F.TX;
-        const int px = tx * TILE + (threadIdx.x & 15), py = ty * TILE + (threadIdx.x >> 4);
-        const bool inside = px < F.W && py < F.H;
+        const int px = tx * TILE + (lane & 15);
+        const float fx = (float)px;
+        Pix s[WQ];
+        float fy[WQ];
+        int stop_at[WQ];
+#pragma unroll
+        for (int q = 0; q < WQ; ++q) {
+            const int py = ty * TILE + (lane >> 4) + 4 * q;
+            fy[q] = (float)py;
+            s[q] = Pix{1.0f, 0.f, 0.f, 0.f, 0.f, 0, !(px < F.W && py < F.H)};
+            stop_at[q] = -1;
+        }
         const uint32_t start = F.ranges[2 * tile], end = F.ranges[2 * tile + 1];
-        Pix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
-        const float fx = (float)px, fy = (float)py;
-        for (uint32_t base = start; base < end; base += 256) {
-            if (__syncthreads_count(s.done) == 256) break;
-            const uint32_t k = base + threadIdx.x;
-            if (k < end) {
-                float2 xy; float4 co, cd;
-                load_splat(F, F.point_list[k], xy, co, cd);
-                s_xy[threadIdx.x] = xy;
-                s_co[threadIdx.x] = co;
-                s_cd[threadIdx.x] = cd;
-            }
-            __syncthreads();
-            const int cnt = (int)min(256u, end - base);
+        // two-stage prefetch: ids two chunks ahead, splat data one chunk ahead
+        SplatRegs cur{}, nxt{};
+        {
+            const uint32_t k0 = start + lane;
+            gather_splat(F, k0 < end, k0 < end ? F.point_list[k0] : 0u, cur);
+        }
+        uint32_t k1 = start + 64 + lane;
+        uint32_t id1 = k1 < end ? F.point_list[k1] : 0u;
+        for (uint32_t base = start; base < end; base += 64) {
+            bool all_done = true;
+#pragma unroll
+            for (int q = 0; q < WQ; ++q) all_done &= s[q].done;
+            if (ballot(!all_done) == 0) break;
+            s_xy[wv][lane] = cur.xy;
+            s_co[wv][lane] = cur.co;
+            s_cd[wv][lane] = cur.cd;
+            wave_sync();
+            gather_splat(F, k1 < end, id1, nxt);
+            k1 += 64;
+            id1 = k1 < end ? F.point_list[k1] : 0u;
+            const int cnt = (int)min(64u, end - base);
             const int pos0 = (int)(base - start);
             for (int j = 0; j < cnt; ++j) {
-                if (s.done) break;
-                blend(fx, fy, s_xy[j], s_co[j], s_cd[j], pos0 + j, s);
+                if (all_done) break;
+                const float2 xy = s_xy[wv][j];
+                const float4 co = s_co[wv][j];
+                const float4 cd = s_cd[wv][j];
+                all_done = true;
+#pragma unroll
+                for (int q = 0; q < WQ; ++q) {
+                    // skipped by the whole wave once the 16x4 block q has stopped
+                    if (!s[q].done) {
+                        blend(fx, fy[q], xy, co, cd, pos0 + j, s[q]);
+                        if (COUNT && s[q].done) stop_at[q] = pos0 + j + 1;
+                    }
+                    all_done &= s[q].done;
+                }
+            }
+            wave_sync();
+            cur = nxt;
+        }
+#pragma unroll
+        for (int q = 0; q < WQ; ++q) {
+            const int py = ty * TILE + (lane >> 4) + 4 * q;
+            if (px < F.W && py < F.H) {
+                write_pixel(F, O, px, py, s[q]);
+                if (COUNT)
+                    F.n_examined[(int64_t)py * F.W + px] = stop_at[q] >= 0 ? stop_at[q] : (int)(end - start);
             }
         }
-        __syncthreads();  // LDS batch reads done before the next tile stages
-        if (inside) write_pixel(F, O, px, py, s);
     }
-    trace_end(F, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
+    trace_end(F0, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // ------------------------------------------------------------------ backward
@@ -642,7 +683,6 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
 // and the one multi-lane gradient atomic -- is paid once per 256 pixels
 // instead of once per 64, and dx (shared by a lane's four pixels) once per
 // entry.  Each pixel's arithmetic is the same as in k_bwd_pixel.
-constexpr int WQ = 4;  // pixels per lane
 
 template <bool MV = false>
 __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const ViewDesc* __restrict__ views,
@@ -927,6 +967,7 @@ static bgs_status check_frame(const bgs_frame* f, const bgs_render_cfg* cfg, Fra
     A.bg2 = cfg->bg[2];
     A.trace = cfg->wg_trace;
     A.trace_cap = cfg->wg_trace ? cfg->wg_trace_cap : 0;
+    A.n_examined = cfg->n_examined;
     return BGS_OK;
 }
 
@@ -939,8 +980,8 @@ static int persistent_blocks(K kernel, uint32_t n_items) {
     return (int)(want < cap ? want : (cap > 0 ? cap : 1));
 }
 
-// Whole 16x16 tiles as work items: the forward's tile-granular workgroups and
-// the backward's wave-per-tile kernel.
+// Whole 16x16 tiles as work items: the forward's and the backward's
+// wave-per-tile kernels.
 static bool tile_items(const bgs_render_cfg* cfg) {
     return cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 16;
 }
@@ -990,6 +1031,8 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
     bgs_status st = check_frame(frame, cfg, A, "bgs_render_fwd");
     if (st != BGS_OK) return st;
     BGS_REQUIRE(out_color && out_alpha && out_depth && final_T && n_contrib, "bgs_render_fwd: null output");
+    if (cfg->n_examined && !tile_items(cfg))
+        return fail(BGS_EUNSUPPORTED, "bgs_render_fwd: n_examined is written by the pixel-wise subtile-16 variant");
     FwdOut O{out_color, out_alpha, out_depth, final_T, n_contrib};
     if (cfg->variant == BGS_STATIC) {
         hipLaunchKernelGGL(k_fwd_static, dim3(A.n_tiles), dim3(256), 0, stream, A, O);
@@ -1005,9 +1048,14 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
     }
     auto* ctr = reinterpret_cast<uint32_t*>(w + L.ctr);
     auto* items = reinterpret_cast<const uint32_t*>(w + L.items);
-    if (tile_items(cfg)) {
-        const int blocks = persistent_blocks(k_fwd_tile, (uint32_t)A.n_tiles * 4u);
-        hipLaunchKernelGGL(k_fwd_tile, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
+    if (tile_items(cfg) && A.n_examined) {
+        const int blocks = persistent_blocks(k_fwd_wide<false, true>, (uint32_t)A.n_tiles);
+        hipLaunchKernelGGL((k_fwd_wide<false, true>), dim3(blocks), dim3(256), 0, stream, A, O,
+                           (const ViewDesc*)nullptr, items, ctr);
+    } else if (tile_items(cfg)) {
+        const int blocks = persistent_blocks(k_fwd_wide<false>, (uint32_t)A.n_tiles);
+        hipLaunchKernelGGL(k_fwd_wide<false>, dim3(blocks), dim3(256), 0, stream, A, O, (const ViewDesc*)nullptr,
+                           items, ctr);
     } else if (cfg->variant == BGS_BALANCED_GAUSS) {
         const int blocks = persistent_blocks(k_fwd_hybrid<64>, L.n_items);
         hipLaunchKernelGGL(k_fwd_hybrid<64>, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
@@ -1120,8 +1168,8 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
     *out = nullptr;
     BGS_REQUIRE(n_views >= 1 && n_views <= MAX_VIEWS, "bgs_plan_create: 1..64 views");
     if (!cfg_bwd) cfg_bwd = cfg;
-    if (cfg->variant != BGS_BALANCED_PIXEL || cfg->subtile != 8)
-        return fail(BGS_EUNSUPPORTED, "bgs_plan_create: the batched forward uses the balanced pixel-wise 8x8 variant");
+    if (cfg->variant != BGS_BALANCED_PIXEL || (cfg->subtile != 8 && cfg->subtile != 16))
+        return fail(BGS_EUNSUPPORTED, "bgs_plan_create: the batched forward uses the balanced pixel-wise variant");
     if (cfg_bwd->variant != BGS_BALANCED_PIXEL || (cfg_bwd->subtile != 8 && cfg_bwd->subtile != 16))
         return fail(BGS_EUNSUPPORTED, "bgs_plan_create: the batched backward uses the balanced pixel-wise variant");
     if (cfg_bwd->order != BGS_ORDER_RASTER && cfg_bwd->order != BGS_ORDER_COST)
@@ -1179,7 +1227,9 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
     for (int v = 0; v < n_views; ++v) maxP = std::max<int64_t>(maxP, io[v].P);
     const unsigned zero_blocks = (unsigned)std::min<int64_t>((maxP + 255) / 256, 1024);
     const uint32_t n_items = plan->total_tiles * 4u;
-    const int fblocks = persistent_blocks(k_fwd_pixel<true, true>, n_items);
+    const bool fwd_wide = tile_items(cfg);
+    const int fblocks = fwd_wide ? persistent_blocks(k_fwd_wide<true>, plan->total_tiles)
+                                 : persistent_blocks(k_fwd_pixel<true, true>, n_items);
     const bool bwd_wide = tile_items(cfg_bwd);
     const int bblocks = bwd_wide ? persistent_blocks(k_bwd_wide<true>, plan->total_tiles)
                                  : persistent_blocks(k_bwd_pixel<true, true>, n_items);
@@ -1203,10 +1253,14 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
     if (by_cost)
         hipLaunchKernelGGL(k_tile_costs_mv, dim3(plan->total_tiles), dim3(256), 0, stream, plan->d_views,
                            plan->d_tile_off, n_views, 0, plan->d_cost);
-    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, (int)plan->total_tiles, plan->d_cost, by_cost, 0,
-                       plan->d_tile_off, n_views, plan->d_items, plan->d_ctr);
-    hipLaunchKernelGGL((k_fwd_pixel<true, true>), dim3(fblocks), dim3(256), 0, stream, F0, O0, plan->d_views,
-                       plan->d_items, plan->d_ctr);
+    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, (int)plan->total_tiles, plan->d_cost, by_cost,
+                       fwd_wide ? 1 : 0, plan->d_tile_off, n_views, plan->d_items, plan->d_ctr);
+    if (fwd_wide)
+        hipLaunchKernelGGL((k_fwd_wide<true>), dim3(fblocks), dim3(256), 0, stream, F0, O0, plan->d_views,
+                           plan->d_items, plan->d_ctr);
+    else
+        hipLaunchKernelGGL((k_fwd_pixel<true, true>), dim3(fblocks), dim3(256), 0, stream, F0, O0, plan->d_views,
+                           plan->d_items, plan->d_ctr);
     if (bwd_by_cost)
         hipLaunchKernelGGL(k_tile_costs_mv, dim3(plan->total_tiles), dim3(256), 0, stream, plan->d_views,
                            plan->d_tile_off, n_views, 1, plan->d_cost);

@@ -2,7 +2,7 @@
 // self-adaptive kernel selection (Sec. 4.4), which times the balanced and the
 // shared-memory static kernel on the current data and keeps the faster.  Here
 // every forward candidate (static, pixel-wise 8x8 raster / cost-ordered,
-// tile-granular persistent, hybrid, Gaussian-wise) and every backward
+// wave per 16x16 tile, hybrid, Gaussian-wise) and every backward
 // candidate (static, balanced 8x8 raster / cost-ordered, wave per 16x16
 // tile) is run on the caller's frame and timed with HIP events; the winners
 // are returned and cached in a
@@ -96,6 +96,13 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
                                    float* bwd_ms_out, hipStream_t stream) {
     BGS_REQUIRE(frame && base && best_fwd && best_bwd, "bgs_autotune: null argument");
     std::lock_guard<std::mutex> lock(g_tune_mu);
+    // candidates and results carry the base's background and order fields,
+    // not its instrumentation outputs
+    bgs_render_cfg plain = *base;
+    plain.wg_trace = nullptr;
+    plain.wg_trace_cap = 0;
+    plain.n_examined = nullptr;
+    base = &plain;
     std::string key;
     bgs_status st = workload_key(frame, stream, key);
     if (st != BGS_OK) return st;

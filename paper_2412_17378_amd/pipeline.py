@@ -167,6 +167,17 @@ class Rasterizer:
         B.bgs_render_fwd(f, cfg, out["color"], out["alpha"], out["depth"], out["final_T"], out["n_contrib"], ws)
         return out
 
+    def count_examined(self, prep: Prepared, bg=(0.0, 0.0, 0.0)) -> torch.Tensor:
+        """Per-pixel number of list entries the sequential forward loop
+        examines (the forward's algorithmic work), int32 [H, W], from one
+        forward with the wave-per-tile kernel."""
+        H, W = prep.height, prep.width
+        n = torch.empty(H, W, dtype=torch.int32, device=self.device)
+        cfg = B.make_cfg("pixel", 16, "cost", bg)
+        cfg.n_examined = n.data_ptr()
+        self.render_fwd(prep, cfg)
+        return n
+
     def render_bwd(self, prep: Prepared, cfg: B.RenderCfg, fwd: dict, dL_dcolor, dL_dalpha=None, dL_ddepth=None,
                    grads: Optional[dict] = None, want_depth: bool = True) -> dict:
         P = prep.P

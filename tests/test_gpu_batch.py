@@ -65,18 +65,22 @@ def test_plan_replays_match_eager(batch):
         plan.close()
 
 
-def test_plan_wide_backward(batch):
-    """The plan with the wave-per-tile backward gives the eager gradients."""
+def test_plan_wide(batch):
+    """The plan with the wave-per-tile kernels (forward and backward) gives the
+    eager results: forward bit for bit, gradients up to summation order."""
     from paper_2412_17378_amd import make_cfg
     from paper_2412_17378_amd.pipeline import BatchedPlan
     s, rast, preps, ups, cfg, eager = batch
-    plan = BatchedPlan(rast, preps, ups, cfg, make_cfg("pixel", 16, "cost"))
+    wide = make_cfg("pixel", 16, "cost")
+    plan = BatchedPlan(rast, preps, ups, wide, wide)
     try:
         for rep in range(2):
             print(f"[batch-wide] replay {rep}", flush=True)
             plan.launch()
             torch.cuda.synchronize()
             for v in range(len(preps)):
+                for k in ("color", "alpha", "depth", "final_T", "n_contrib"):
+                    assert torch.equal(plan.outs[v][k], eager[v][0][k]), (rep, v, k)
                 for k in ("means2D", "conic_opacity", "rgb", "depth"):
                     ref = eager[v][1][k]
                     scale = float(ref.abs().max()) + 1e-30

@@ -83,9 +83,11 @@ def test_full_static_equals_balanced(full):
     from paper_2412_17378_amd import make_cfg
     s, rast, prep, cfg, fwd, wins = full
     st = rast.render_fwd(prep, make_cfg("static"))
+    wide = rast.render_fwd(prep, make_cfg("pixel", 16, "cost"))
     torch.cuda.synchronize()
     for k in fwd:
         assert torch.equal(st[k], fwd[k]), k
+        assert torch.equal(wide[k], fwd[k]), ("wide", k)
 
 
 def test_full_backward_cropped(full):

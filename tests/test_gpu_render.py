@@ -92,6 +92,18 @@ def test_backward_parity(rast, name, variant, sub, order):
     compare_grads(grads, orc, name=f"{name}/{variant}/{sub}/{order}")
 
 
+@pytest.mark.parametrize("name", ["tiny-60", "ragged", "0", "sh3"])
+def test_examined_count(rast, name):
+    """The forward's optional work count equals the oracle's examined count."""
+    s = _scene(name)
+    print(f"[examined] case={name}", flush=True)
+    prep = rast.prepare_scene(s)
+    n = to_np(rast.count_examined(prep))
+    orc = oracle_render_from_gpu(prep)
+    ok = orc["margin"] >= MARGIN
+    np.testing.assert_array_equal(n[ok], orc["n_examined"][ok])
+
+
 def test_autograd_function(rast):
     """RenderFn gives the same gradients as calling render_bwd directly."""
     from paper_2412_17378_amd import make_cfg, render

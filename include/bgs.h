@@ -195,13 +195,13 @@ size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P, 
  * Gaussians are put in depth order; a stable counting sort over groups of
  * 4x4 tiles (per-chunk group histograms from 2D difference arrays, a column
  * scan over chunks, in-order placement) builds coarse per-group lists, and
- * one workgroup per group splits its list into its 16 tile lists with
- * ordered ballot compaction.
+ * the coarse lists are split into the 16 tile lists of each group by ordered
+ * ballot compaction, one workgroup per segment of 2048 coarse entries.
  *   point_list [capacity] Gaussian ids, ranges [n_tiles][2] (empty: (0, 0)),
  *   n_pairs_dev (DEVICE, uint64[1]) receives M.
  * Synchronizes the stream once (to size the coarse lists).  When M exceeds
- * capacity, no entry beyond capacity is written and the caller must grow
- * point_list (and the workspace) and call again before rendering; when the
+ * capacity, point_list is not written and the caller must grow point_list
+ * (and the workspace) and call again before rendering; when the
  * overflow is already visible at the coarse level the call returns
  * BGS_ECAPACITY with a lower bound of M in n_pairs_dev.  Tile grids of more
  * than 8192 groups return BGS_EUNSUPPORTED (use the three separate calls).

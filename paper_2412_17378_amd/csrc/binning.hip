@@ -10,6 +10,7 @@
 // the same list a (tile, depth, id) sort gives.
 #include <cstring>
 
+#include <rocprim/block/block_scan.hpp>
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
@@ -259,8 +260,8 @@ extern "C" bgs_status bgs_ranges(const uint32_t* sorted_keys, int64_t n, int32_t
 // ======================================================================
 namespace bgs {
 
-constexpr int CHUNK = 256;       // Gaussians per chunk of the coarse sort
-constexpr int PART = 64;         // chunks per column-scan block
+constexpr int CHUNK = 64;        // Gaussians per chunk of the coarse sort (one wave emits a chunk)
+constexpr int PART = 32;         // chunks per column-scan block
 constexpr int GSHIFT = 2;        // group = 4x4 tiles
 constexpr int GTILES = 1 << GSHIFT;
 constexpr int MAX_GROUPS = 8192;
@@ -332,49 +333,51 @@ __global__ __launch_bounds__(256) void k_part_sums(int C, int nt, const uint32_t
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)nb * nt) return;
     const int b = (int)(i / nt), t = (int)(i % nt);
-    const int c1 = min(C, (b + 1) * PART);
+    const int c0 = b * PART, n = min(C - c0, PART);
     uint32_t s = 0;
-    for (int c = b * PART; c < c1; ++c) s += h[(int64_t)c * nt + t];
+#pragma unroll
+    for (int c = 0; c < PART; ++c)
+        if (c < n) s += h[(int64_t)(c0 + c) * nt + t];
     part[i] = s;
 }
 
-// exclusive scan of part[.][t] over blocks; total[t] = column sum
+// exclusive scan of part[.][t] over the nb blocks, one wave per column t;
+// total[t] = column sum
 __global__ __launch_bounds__(256) void k_part_scan(int nb, int nt, uint32_t* __restrict__ part,
                                                    uint32_t* __restrict__ total) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (t >= nt) return;
-    uint32_t run = 0;
-    for (int b = 0; b < nb; ++b) {
-        const uint32_t v = part[(int64_t)b * nt + t];
-        part[(int64_t)b * nt + t] = run;
-        run += v;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 64) {
+        const int b = b0 + lane;
+        const uint32_t v = b < nb ? part[(int64_t)b * nt + t] : 0u;
+        uint32_t x = v;  // inclusive scan over the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (b < nb) part[(int64_t)b * nt + t] = carry + x - v;
+        carry += __shfl(x, 63, 64);
     }
-    total[t] = run;
+    if (lane == 0) total[t] = carry;
 }
 
 // Single workgroup: exclusive scan of total -> start; ranges (empty: (0, 0));
-// the grand total in n_pairs[0].
+// the grand total in n_pairs[0].  Thread i owns the contiguous run
+// [i per, (i+1) per); the per-thread sums are scanned with a block scan.
 __global__ __launch_bounds__(1024) void k_tile_scan(int nt, const uint32_t* __restrict__ total,
                                                     uint32_t* __restrict__ start, uint32_t* __restrict__ ranges,
                                                     uint64_t* __restrict__ n_pairs) {
-    __shared__ uint64_t sums[1024];
+    using Scan = rocprim::block_scan<uint64_t, 1024>;
+    __shared__ typename Scan::storage_type s_scan;
     const int per = (nt + 1023) / 1024;
-    const int t0 = threadIdx.x * per, t1 = min(nt, t0 + per);
+    const int t0 = min(nt, (int)threadIdx.x * per), t1 = min(nt, t0 + per);
     uint64_t s = 0;
     for (int t = t0; t < t1; ++t) s += total[t];
-    sums[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t run = 0;
-        for (int i = 0; i < 1024; ++i) {
-            const uint64_t v = sums[i];
-            sums[i] = run;
-            run += v;
-        }
-        n_pairs[0] = run;
-    }
-    __syncthreads();
-    uint64_t run = sums[threadIdx.x];
+    uint64_t run = 0, grand = 0;
+    Scan().exclusive_scan(s, run, (uint64_t)0, grand, s_scan);
+    if (threadIdx.x == 0) n_pairs[0] = grand;
     for (int t = t0; t < t1; ++t) {
         const uint32_t n = total[t];
         start[t] = (uint32_t)run;
@@ -393,21 +396,30 @@ __global__ __launch_bounds__(256) void k_chunk_base(int C, int nt, const uint32_
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)nb * nt) return;
     const int b = (int)(i / nt), t = (int)(i % nt);
-    const int c1 = min(C, (b + 1) * PART);
+    const int c0 = b * PART, n = min(C - c0, PART);
+    uint32_t v[PART];
+#pragma unroll
+    for (int c = 0; c < PART; ++c) v[c] = c < n ? h[(int64_t)(c0 + c) * nt + t] : 0u;  // all loads first
     uint32_t run = start[t] + part[i];
-    for (int c = b * PART; c < c1; ++c) {
-        const uint32_t v = h[(int64_t)c * nt + t];
-        h[(int64_t)c * nt + t] = run;
-        run += v;
+#pragma unroll
+    for (int c = 0; c < PART; ++c) {
+        if (c < n) h[(int64_t)(c0 + c) * nt + t] = run;
+        run += v[c];
     }
 }
 
 // One wave per chunk: drop the chunk's (group, Gaussian) pairs, Gaussians in
 // depth order, at the chunk's base slot of each group plus a running count
-// kept in LDS.
+// kept in LDS.  An entry is (Gaussian id, mask of the group's 16 tiles the
+// Gaussian's tile rectangle covers, bit (x mod 4) + 4 (y mod 4)), so the
+// split into tile lists streams the coarse lists without a gather.
+__device__ __forceinline__ uint32_t spread_rows(uint32_t rows) {  // bit y -> bit 4y
+    return (rows & 1u) | ((rows & 2u) << 3) | ((rows & 4u) << 6) | ((rows & 8u) << 9);
+}
+
 __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, const uint32_t* __restrict__ order,
                                                    const uint2* __restrict__ rect, const uint32_t* __restrict__ base,
-                                                   uint32_t* __restrict__ coarse) {
+                                                   uint2* __restrict__ coarse) {
     extern __shared__ uint32_t nextpos[];  // ng running slots
     const int ng = GX * GY;
     const int lane = threadIdx.x;
@@ -422,10 +434,12 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
         if (k0 >= P) break;
         const int64_t k = k0 + lane;
         uint32_t g = 0, n = 0;
+        uint2 rr = make_uint2(1u, 0u);
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
         if (k < P) {
             g = order[k];
-            if (group_rect(rect[g], x0, y0, x1, y1)) n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+            rr = rect[g];
+            if (group_rect(rr, x0, y0, x1, y1)) n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
         }
         const int cntk = (int)((P - k0) < 64 ? (P - k0) : 64);
         for (int i = 0; i < cntk; ++i) {
@@ -434,16 +448,26 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
             const uint32_t gi = __builtin_amdgcn_readlane(g, i);
             const int xi = __builtin_amdgcn_readlane(x0, i), yi = __builtin_amdgcn_readlane(y0, i);
             const int wi = __builtin_amdgcn_readlane(x1, i) - xi + 1;
+            const uint32_t ra = __builtin_amdgcn_readlane(rr.x, i), rb = __builtin_amdgcn_readlane(rr.y, i);
+            const int tx0 = (int)(ra & 0xFFFF), ty0 = (int)(ra >> 16), tx1 = (int)(rb & 0xFFFF), ty1 = (int)(rb >> 16);
             const float inv_w = 1.0f / (float)wi;
             for (uint32_t j = lane; j < ni; j += 64) {
                 int q = (int)((float)j * inv_w);
                 int r = (int)j - q * wi;
                 if (r >= wi) { ++q; r -= wi; }
                 if (r < 0) { --q; r += wi; }
-                const int t = (yi + q) * GX + xi + r;
+                const int gx = xi + r, gy = yi + q;
+                const int t = gy * GX + gx;
+                // the tile rectangle is clamped to the image, so the mask
+                // only holds tiles inside it
+                const int bx = gx * GTILES, by = gy * GTILES;
+                const int cl = max(tx0 - bx, 0), ch = min(tx1 - bx + 1, GTILES);
+                const int rl = max(ty0 - by, 0), rh = min(ty1 - by + 1, GTILES);
+                const uint32_t cols = ((1u << ch) - 1u) & ~((1u << cl) - 1u);
+                const uint32_t rows = ((1u << rh) - 1u) & ~((1u << rl) - 1u);
                 const uint32_t pos = nextpos[t];
                 nextpos[t] = pos + 1;
-                coarse[pos] = gi;
+                coarse[pos] = make_uint2(gi, cols * spread_rows(rows));
             }
         }
     }
@@ -472,7 +496,7 @@ __global__ __launch_bounds__(256) void k_seg_map(int ng, const uint32_t* __restr
 // One workgroup per segment; wave w walks the contiguous quarter
 // [e0 + w SEG/4, e0 + (w+1) SEG/4) of it, 64 entries at a time, and for each
 // of the group's 16 tiles (local index i = (x mod 4) + 4 (y mod 4)) takes
-// the ballot of the entries whose rectangle contains the tile.  Counts are
+// the ballot of the entries whose tile mask holds the tile.  Counts are
 // kept per (segment, wave) unit, so the write pass knows every wave's start
 // slots and needs no exchange between waves.
 // COUNT: segcnt[seg][i][w] = entries of wave w's quarter whose rectangle
@@ -482,22 +506,21 @@ __global__ __launch_bounds__(256) void k_seg_map(int ng, const uint32_t* __restr
 constexpr int SUBSEG = SEG / 4;
 
 template <bool WRITE>
-__global__ __launch_bounds__(256) void k_seg_split(int TX, int TY, int GX, const uint64_t* __restrict__ n_segs,
-                                                   const uint2* __restrict__ segmap,
-                                                   const uint32_t* __restrict__ coarse,
+__global__ __launch_bounds__(256) void k_seg_split(const uint64_t* __restrict__ n_segs, const uint2* __restrict__ segmap,
+                                                   const uint2* __restrict__ coarse,
                                                    const uint32_t* __restrict__ gstart,
-                                                   const uint32_t* __restrict__ gtotal,
-                                                   const uint2* __restrict__ rect, uint32_t* __restrict__ segcnt,
-                                                   uint32_t* __restrict__ point_list, uint64_t capacity) {
+                                                   const uint32_t* __restrict__ gtotal, uint32_t* __restrict__ segcnt,
+                                                   uint32_t* __restrict__ point_list, const uint64_t* __restrict__ n_pairs,
+                                                   uint64_t capacity) {
     const uint32_t sidx = blockIdx.x;
     if (sidx >= n_segs[0]) return;
+    // the pair count is final here; a list that does not fit is not written
+    // at all (the caller grows the buffer and builds again)
+    if (WRITE && n_pairs[0] > capacity) return;
     const uint2 gs = segmap[sidx];
     const int grp = (int)gs.x;
-    const int gx0 = (grp % GX) * GTILES, gy0 = (grp / GX) * GTILES;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // counts of (segment, tile i, wave w) at segcnt[(segment * 16 + i) * 4 + w]
-    // tile columns / rows of the group inside the image
-    const uint32_t colv = (1u << min(GTILES, TX - gx0)) - 1u, rowv = (1u << min(GTILES, TY - gy0)) - 1u;
     uint32_t run[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) run[i] = WRITE ? segcnt[((size_t)sidx * 16 + i) * 4 + wv] : 0u;
@@ -510,27 +533,15 @@ __global__ __launch_bounds__(256) void k_seg_split(int TX, int TY, int GX, const
         const uint32_t k = k0 + lane;
         uint32_t g = 0, tmask = 0;
         if (k < e1) {
-            g = coarse[b0 + k];
-            const uint2 r = rect[g];
-            const int x0 = (int)(r.x & 0xFFFF) - gx0, y0 = (int)(r.x >> 16) - gy0;
-            const int x1 = (int)(r.y & 0xFFFF) - gx0, y1 = (int)(r.y >> 16) - gy0;
-            // covered local columns / rows as bit ranges [lo, hi)
-            const int cl = min(max(x0, 0), GTILES), ch = min(max(x1 + 1, 0), GTILES);
-            const int rl = min(max(y0, 0), GTILES), rh = min(max(y1 + 1, 0), GTILES);
-            const uint32_t cols = colv & (((1u << ch) - 1u) & ~((1u << cl) - 1u));
-            const uint32_t rows = rowv & (((1u << rh) - 1u) & ~((1u << rl) - 1u));
-#pragma unroll
-            for (int y = 0; y < GTILES; ++y)
-                if (rows & (1u << y)) tmask |= cols << (GTILES * y);
+            const uint2 e = coarse[b0 + k];
+            g = e.x;
+            tmask = e.y;
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const bool in = (tmask >> i) & 1u;
             const uint64_t m = ballot(in);
-            if (WRITE && in) {
-                const uint64_t pos = (uint64_t)run[i] + __builtin_popcountll(m & lt);
-                if (pos < capacity) point_list[pos] = g;
-            }
+            if (WRITE && in) point_list[run[i] + (uint32_t)__builtin_popcountll(m & lt)] = g;
             run[i] += (uint32_t)__builtin_popcountll(m);
         }
     }
@@ -609,7 +620,7 @@ static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P, size_t
     L.ttotal = take(4 * (size_t)L.nt);
     L.tstart = take(4 * (size_t)L.nt);
     L.coarse_cap = coarse_cap;
-    L.coarse = take(4 * (coarse_cap > 0 ? coarse_cap : 1));
+    L.coarse = take(8 * (coarse_cap > 0 ? coarse_cap : 1));  // (id, tile mask) pairs
     // segments: at most coarse_cap / SEG + ng of them
     L.max_segs = coarse_cap / SEG + (size_t)L.ng + 1;
     L.segmap = take(8 * L.max_segs);
@@ -657,7 +668,7 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
     auto* gstart = reinterpret_cast<uint32_t*>(w + L.gstart);
     auto* ttotal = reinterpret_cast<uint32_t*>(w + L.ttotal);
     auto* tstart = reinterpret_cast<uint32_t*>(w + L.tstart);
-    auto* coarse = reinterpret_cast<uint32_t*>(w + L.coarse);
+    auto* coarse = reinterpret_cast<uint2*>(w + L.coarse);
     if (P == 0) {
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * (int64_t)L.nt)), dim3(256), 0, stream, ranges,
                            2 * (int64_t)L.nt, 0u);
@@ -675,13 +686,13 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
                        rect);
     BGS_HIP(hipGetLastError());
     // coarse (group) lists
-    hipLaunchKernelGGL(k_chunk_hist, dim3(L.C), dim3(256), sizeof(int) * (size_t)(L.GX + 1) * (L.GY + 1), stream, P,
+    hipLaunchKernelGGL(k_chunk_hist, dim3(L.C), dim3(CHUNK), sizeof(int) * (size_t)(L.GX + 1) * (L.GY + 1), stream, P,
                        L.GX, L.GY, order, rect, h);
     BGS_HIP(hipGetLastError());
     const int64_t nbg = (int64_t)L.nb * L.ng;
     hipLaunchKernelGGL(k_part_sums, dim3(blocks_for(nbg)), dim3(256), 0, stream, L.C, L.ng, h, part);
     BGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_part_scan, dim3(blocks_for(L.ng)), dim3(256), 0, stream, L.nb, L.ng, part, gtotal);
+    hipLaunchKernelGGL(k_part_scan, dim3((unsigned)((L.ng + 3) / 4)), dim3(256), 0, stream, L.nb, L.ng, part, gtotal);
     BGS_HIP(hipGetLastError());
     // the group scan reuses n_pairs_dev[0] for the coarse total; it is
     // overwritten by the tile scan below
@@ -714,8 +725,9 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
     hipLaunchKernelGGL(k_seg_map, dim3(blocks_for(L.ng)), dim3(256), 0, stream, L.ng, nseg, segstart, segmap);
     BGS_HIP(hipGetLastError());
     if (grid_segs > 0) {
-        hipLaunchKernelGGL(k_seg_split<false>, dim3((unsigned)grid_segs), dim3(256), 0, stream, TX, TY, L.GX, nsegs,
-                           segmap, coarse, gstart, gtotal, rect, segcnt, (uint32_t*)nullptr, (uint64_t)0);
+        hipLaunchKernelGGL(k_seg_split<false>, dim3((unsigned)grid_segs), dim3(256), 0, stream, nsegs, segmap,
+                           coarse,
+                           gstart, gtotal, segcnt, (uint32_t*)nullptr, (const uint64_t*)nullptr, (uint64_t)0);
         BGS_HIP(hipGetLastError());
     }
     const int n_gt = L.ng * 16;
@@ -728,8 +740,9 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
         hipLaunchKernelGGL(k_seg_scan<true>, dim3(blocks_for(n_gt)), dim3(256), 0, stream, TX, TY, L.GX, L.ng, nseg,
                            segstart, segcnt, tstart, (uint32_t*)nullptr);
         BGS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_seg_split<true>, dim3((unsigned)grid_segs), dim3(256), 0, stream, TX, TY, L.GX, nsegs,
-                           segmap, coarse, gstart, gtotal, rect, segcnt, point_list, (uint64_t)capacity);
+        hipLaunchKernelGGL(k_seg_split<true>, dim3((unsigned)grid_segs), dim3(256), 0, stream, nsegs, segmap,
+                           coarse,
+                           gstart, gtotal, segcnt, point_list, n_pairs_dev, (uint64_t)capacity);
         BGS_HIP(hipGetLastError());
     }
     return BGS_OK;

@@ -158,6 +158,14 @@ __device__ __forceinline__ float xor4(float v) { return dpp<0x1B>(dpp<0x141>(v))
 // (5,4,3,2) = (b5,b4,b3,b2) satisfy k = 5 b5 + 3 b4 + 2 b3 + b2 (with
 // 2 b3 + b2 < 3 and 3 b4 + 2 b3 + b2 < 5).  Returns k in the first lane of
 // that quad (others: -1) and the total in out.
+__device__ __forceinline__ int scatter10_slot(int lane) {
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+    const int p3 = 2 * (int)b3 + (int)b2;
+    const int p5 = 3 * (int)b4 + p3;
+    const bool valid = p3 < 3 && p5 < 5 && (lane & 3) == 0;
+    return valid ? 5 * (int)b5 + p5 : -1;
+}
+
 __device__ __forceinline__ int wave_reduce_scatter10(const float (&v)[10], int lane, float& out) {
     const bool b3 = lane & 8, b2 = lane & 4;
     float a[5];
@@ -178,11 +186,7 @@ __device__ __forceinline__ int wave_reduce_scatter10(const float (&v)[10], int l
     e += dpp<0x4E>(e);  // quad_perm [2,3,0,1]: lane xor 2
     e += dpp<0xB1>(e);  // quad_perm [1,0,3,2]: lane xor 1
     out = e;
-    const bool b5 = lane & 32, b4 = lane & 16;
-    const int p3 = 2 * (int)b3 + (int)b2;
-    const int p5 = 3 * (int)b4 + p3;
-    const bool valid = p3 < 3 && p5 < 5 && (lane & 3) == 0;
-    return valid ? 5 * (int)b5 + p5 : -1;
+    return scatter10_slot(lane);
 }
 
 __device__ __forceinline__ int wave_max(int v) {

@@ -145,6 +145,46 @@ __device__ __forceinline__ void blend(float fx, float fy, float2 xy, float4 co, 
     s.done = s.done | stop;
 }
 
+// blend() for an entry of an unrolled group: a pixel that stopped earlier in
+// the group is left as it is.
+__device__ __forceinline__ void blend_masked(float fx, float fy, float2 xy, float4 co, float4 cd, int pos, Pix& s) {
+    const float dx = fx - xy.x, dy = fy - xy.y;
+    const float p2 = splat_power2(dx, dy, co.x, co.y, co.z);
+    const float alpha = fminf(ALPHA_MAX, co.w * exp2_fast(p2));
+    const bool skip = (p2 > 0.0f) | (alpha < ALPHA_MIN) | s.done;
+    const float w = alpha * s.T;
+    const float Tn = s.T - w;
+    const bool stop = !skip & (Tn < T_MIN);
+    const bool take = !skip & !stop;
+    const float we = take ? w : 0.0f;
+    s.C0 = __builtin_fmaf(cd.x, we, s.C0);
+    s.C1 = __builtin_fmaf(cd.y, we, s.C1);
+    s.C2 = __builtin_fmaf(cd.z, we, s.C2);
+    s.D = __builtin_fmaf(cd.w, we, s.D);
+    s.T = take ? Tn : s.T;
+    s.last = take ? pos + 1 : s.last;
+    s.done = s.done | stop;
+}
+
+// One pixel over cnt LDS-staged entries (list positions pos0 ..), in groups of
+// four so that the LDS reads of a group share one address register; the
+// pixel leaves at the first group boundary after it stops.  Same arithmetic
+// per entry as blend(), so the result is bit-identical.
+__device__ __forceinline__ void blend_batch(float fx, float fy, const float2* __restrict__ xy,
+                                            const float4* __restrict__ co, const float4* __restrict__ cd, int cnt,
+                                            int pos0, Pix& s) {
+    int j = 0;
+    for (; j + 4 <= cnt; j += 4) {
+        if (s.done) return;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) blend_masked(fx, fy, xy[j + u], co[j + u], cd[j + u], pos0 + j + u, s);
+    }
+    for (; j < cnt; ++j) {
+        if (s.done) return;
+        blend(fx, fy, xy[j], co[j], cd[j], pos0 + j, s);
+    }
+}
+
 __device__ __forceinline__ void write_pixel(const FrameArgs& F, const FwdOut& O, int px, int py, const Pix& s) {
     const int64_t HW = (int64_t)F.W * F.H;
     const int64_t p = (int64_t)py * F.W + px;
@@ -183,10 +223,7 @@ __global__ __launch_bounds__(256) void k_fwd_static(FrameArgs F, FwdOut O) {
         __syncthreads();
         const int cnt = (int)min(256u, end - base);
         const int pos0 = (int)(base - start);
-        for (int j = 0; j < cnt; ++j) {
-            if (s.done) break;
-            blend(fx, fy, s_xy[j], s_co[j], s_cd[j], pos0 + j, s);
-        }
+        blend_batch(fx, fy, s_xy, s_co, s_cd, cnt, pos0, s);
     }
     if (inside) write_pixel(F, O, px, py, s);
     trace_end(F, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
@@ -316,10 +353,7 @@ __global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F0, FwdOut O0, cons
                 id1 = k1 < end ? F.point_list[k1] : 0u;
                 const int cnt = (int)min(64u, end - base);
                 const int pos0 = (int)(base - start);
-                for (int j = 0; j < cnt; ++j) {
-                    if (s.done) break;
-                    blend(fx, fy, s_xy[wv][j], s_co[wv][j], s_cd[wv][j], pos0 + j, s);
-                }
+                blend_batch(fx, fy, s_xy[wv], s_co[wv], s_cd[wv], cnt, pos0, s);
                 wave_sync();
                 cur = nxt;
             }
@@ -436,10 +470,7 @@ __global__ __launch_bounds__(256) void k_fwd_hybrid(FrameArgs F, FwdOut O, const
             wave_sync();
             const int cnt = (int)min(64u, end - base);
             const int pos0 = (int)(base - start);
-            for (int j = 0; j < cnt; ++j) {
-                if (s.done) break;
-                blend(fx, fy, s_xy[wv][j], s_co[wv][j], s_cd[wv][j], pos0 + j, s);
-            }
+            blend_batch(fx, fy, s_xy[wv], s_co[wv], s_cd[wv], cnt, pos0, s);
             wave_sync();
         }
         uint64_t act = ballot(!s.done);
@@ -559,6 +590,22 @@ __global__ __launch_bounds__(256) void k_fwd_wide(FrameArgs F0, FwdOut O0, const
 }
 
 // ------------------------------------------------------------------ backward
+// The gradient slot a lane adds after wave_reduce_scatter10 depends only on
+// the lane; its target array, stride and offset are resolved once per item.
+struct GradLane {
+    float* base;  // the lane's component of Gaussian 0; null: the lane adds nothing
+    uint32_t stride;
+};
+
+__device__ __forceinline__ GradLane grad_lane(const BwdIO& B, int slot) {
+    if (slot < 0) return GradLane{nullptr, 0u};
+    if (slot < 2) return GradLane{B.g_means2D + slot, 2u};
+    if (slot < 6) return GradLane{B.g_conic_opacity + (slot - 2), 4u};
+    if (slot < 9) return GradLane{B.g_rgb + (slot - 6), 3u};
+    return GradLane{B.g_depth, 1u};
+}
+
+
 template <bool PERSISTENT, bool MV = false>
 __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const ViewDesc* __restrict__ views,
                                                    const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
@@ -585,6 +632,7 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
         bool any_inside;
         item_pixel(F, item, lane, tile, px, py, any_inside);
         if (any_inside) {
+            const GradLane GL = grad_lane(B, scatter10_slot(lane));
             const bool inside = px < F.W && py < F.H;
             const int64_t p = inside ? (int64_t)py * F.W + px : 0;
             const float TN = inside ? B.final_T[p] : 1.0f;
@@ -658,15 +706,10 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
                     }
                     const float vals[10] = {v0, v1, v2, v3, v4, v5, v6, v7, v8, v9};
                     float tot;
-                    const int slot = wave_reduce_scatter10(vals, lane, tot);
-                    if (slot >= 0) {
+                    wave_reduce_scatter10(vals, lane, tot);
+                    if (GL.base) {
                         const uint32_t g = __float_as_uint(s_abc[wv][jj].w);
-                        float* dst;
-                        if (slot < 2) dst = B.g_means2D + 2 * (size_t)g + slot;
-                        else if (slot < 6) dst = B.g_conic_opacity + 4 * (size_t)g + (slot - 2);
-                        else if (slot < 9) dst = B.g_rgb + 3 * (size_t)g + (slot - 6);
-                        else dst = B.g_depth ? B.g_depth + g : nullptr;
-                        if (dst) unsafeAtomicAdd(dst, tot);
+                        unsafeAtomicAdd(GL.base + (size_t)g * GL.stride, tot);
                     }
                 }
                 wave_sync();
@@ -705,6 +748,7 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
         const int px = tx * TILE + (lane & 15);
         const uint32_t start = F.ranges[2 * tile];
         const int len = (int)(F.ranges[2 * tile + 1] - start);
+        const GradLane GL = grad_lane(B, scatter10_slot(lane));
         float T[WQ], R0[WQ], R1[WQ], R2[WQ], Rd[WQ], gC0[WQ], gC1[WQ], gC2[WQ], gD[WQ], kc[WQ], fy[WQ];
         int nc[WQ];
         int my_max = 0;
@@ -793,16 +837,8 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
                     v[1] += (abc.y * dx + abc.z * dy[q]) * dP;
                 }
                 float tot;
-                const int slot = wave_reduce_scatter10(v, lane, tot);
-                if (slot >= 0) {
-                    const uint32_t g = __float_as_uint(abc.w);
-                    float* dst;
-                    if (slot < 2) dst = B.g_means2D + 2 * (size_t)g + slot;
-                    else if (slot < 6) dst = B.g_conic_opacity + 4 * (size_t)g + (slot - 2);
-                    else if (slot < 9) dst = B.g_rgb + 3 * (size_t)g + (slot - 6);
-                    else dst = B.g_depth ? B.g_depth + g : nullptr;
-                    if (dst) unsafeAtomicAdd(dst, tot);
-                }
+                wave_reduce_scatter10(v, lane, tot);
+                if (GL.base) unsafeAtomicAdd(GL.base + (size_t)__float_as_uint(abc.w) * GL.stride, tot);
             }
             wave_sync();
         }

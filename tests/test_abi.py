@@ -60,6 +60,17 @@ def test_invalid_arguments_are_status_codes():
     st = L.bgs_sort(None, None, None, None, 10, 0, None, 0, None)
     assert st == B.BGS_EINVAL
     assert L.bgs_render_workspace_bytes(ctypes.byref(f), ctypes.byref(cfg)) > 0
+    # the work counter is only written by the wave-per-tile forward
+    cfg.n_examined = 1
+    st = L.bgs_render_fwd(ctypes.byref(f), ctypes.byref(cfg), None, None, None, None, None, None, 0, None)
+    assert st == B.BGS_EINVAL  # (null frame arrays are checked first)
+    st = L.bgs_autotune(None, None, None, None, None, None, None, None, None, None, None, None, 0, None, None, None,
+                        None, None, None)
+    assert st == B.BGS_EINVAL
+    plan = ctypes.c_void_p()
+    st = L.bgs_plan_create(ctypes.byref(plan), 0, None, None, None, None, None)
+    assert st == B.BGS_EINVAL
+    L.bgs_plan_destroy(None)  # accepted
 
 
 def test_version():

@@ -54,7 +54,7 @@ def lib():
         L.orc_ranges.restype = C.c_int
         L.orc_render_fwd.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_render_fwd.restype = i64
-        L.orc_render_bwd.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_render_bwd.argtypes = [i32, i32, i32] + [vp] * 21
         L.orc_render_bwd.restype = i64
         L.orc_sh_basis.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double]
         L.orc_sh_basis.restype = C.c_double
@@ -183,7 +183,9 @@ def render_bwd(width, height, ranges_, point_list, means2D, conic_opacity, rgb, 
                dL_dalpha=None, dL_ddepth=None, bg=(0, 0, 0), tile: int = TILE,
                window: Optional[Sequence[int]] = None) -> dict:
     """Exact derivative of :func:`render_fwd` (decisions frozen) for
-    L = <dL_dcolor, color> + <dL_dalpha, alpha> + <dL_ddepth, depth>."""
+    L = <dL_dcolor, color> + <dL_dalpha, alpha> + <dL_ddepth, depth>.
+    ``mag`` holds, per gradient element, the sum of the absolute values of
+    its per-pixel terms."""
     H, W = int(height), int(width)
     rg, pl = _i32(ranges_), _i32(point_list)
     m2, co, cl, dp, b = _f64(means2D), _f64(conic_opacity), _f64(rgb), _f64(depth), _f64(bg)
@@ -194,8 +196,11 @@ def render_bwd(width, height, ranges_, point_list, means2D, conic_opacity, rgb, 
     win = None if window is None else _i32(window)
     out = dict(means2D=np.zeros((P, 2)), conic=np.zeros((P, 3)), opacity=np.zeros(P), rgb=np.zeros((P, 3)),
                depth=np.zeros(P))
+    mag = {k: np.zeros_like(v) for k, v in out.items()}
     tot = lib().orc_render_bwd(W, H, tile, _p(rg), _p(pl), _p(m2), _p(co), _p(cl), _p(dp), _p(b), _p(win),
                                _p(gC), _p(gA), _p(gD), _p(out["means2D"]), _p(out["conic"]), _p(out["opacity"]),
-                               _p(out["rgb"]), _p(out["depth"]))
+                               _p(out["rgb"]), _p(out["depth"]), _p(mag["means2D"]), _p(mag["conic"]),
+                               _p(mag["opacity"]), _p(mag["rgb"]), _p(mag["depth"]))
     out["blends"] = int(tot)
+    out["mag"] = mag
     return out

@@ -471,6 +471,15 @@ static void atomic_add(double *p, double v)
     *p += v;
 }
 
+/* p[i] += v and, when the magnitude array m is given, m[i] += |v|: the sum
+ * of absolute per-pixel contributions, the natural scale of a gradient that
+ * is a sum of terms of both signs. */
+static void grad_add(double *p, double *m, int64_t i, double v)
+{
+    atomic_add(&p[i], v);
+    if (m) atomic_add(&m[i], fabs(v));
+}
+
 /*
  * Backward of orc_render_fwd for the loss L = sum g_C . out_color
  * + g_A . out_alpha + g_D . out_depth (g_A, g_D nullable).  Per pixel the
@@ -486,15 +495,17 @@ static void atomic_add(double *p, double v)
  *   dL/d o += G dL/dalpha;  dL/dpower = o G dL/dalpha
  *   dL/d (a, b, c) += (-dx^2 / 2, -dx dy, -dy^2 / 2) dL/dpower
  *   dL/d (u, v)    += (a dx + b dy, b dx + c dy) dL/dpower
- * Gradients are added (+=) into the caller's buffers.  Returns the number of
- * contributors walked (the backward "blend" count).
+ * Gradients are added (+=) into the caller's buffers; the mag_* arrays
+ * (nullable, same layouts) receive the sums of the absolute per-pixel terms.
+ * Returns the number of contributors walked (the backward "blend" count).
  */
 int64_t orc_render_bwd(int32_t width, int32_t height, int32_t tile, const int32_t *ranges,
                        const int32_t *point_list, const double *means2D, const double *conic_opacity,
                        const double *rgb, const double *depth, const double *bg, const int32_t *window,
                        const double *dL_dcolor, const double *dL_dalpha, const double *dL_ddepth,
                        double *dL_dmeans2D, double *dL_dconic, double *dL_dopacity, double *dL_drgb,
-                       double *dL_ddepths)
+                       double *dL_ddepths, double *mag_means2D, double *mag_conic, double *mag_opacity,
+                       double *mag_rgb, double *mag_depths)
 {
     int32_t win[4];
     window_or_full(window, width, height, win);
@@ -552,12 +563,12 @@ int64_t orc_render_bwd(int32_t width, int32_t height, int32_t tile, const int32_
                     const double dk = depth[g];
                     double dA = 0;
                     for (int c = 0; c < 3; ++c) {
-                        atomic_add(&dL_drgb[3 * g + c], w * gC[c]);
+                        grad_add(dL_drgb, mag_rgb, 3 * g + c, w * gC[c]);
                         dA += gC[c] * (col[c] * Tb - (R[c] + TN * bg[c]) / (1.0 - a));
                     }
                     dA += gA * TN / (1.0 - a);
                     dA += gD * (dk * Tb - Rd / (1.0 - a));
-                    if (dL_ddepths) atomic_add(&dL_ddepths[g], w * gD);
+                    if (dL_ddepths) grad_add(dL_ddepths, mag_depths, g, w * gD);
                     for (int c = 0; c < 3; ++c) R[c] += col[c] * w;
                     Rd += dk * w;
                     if (cg[q] <= amax) {
@@ -565,12 +576,12 @@ int64_t orc_render_bwd(int32_t width, int32_t height, int32_t tile, const int32_
                         const double G = cg[q] / co[3];
                         const double dx = px - means2D[2 * g], dy = py - means2D[2 * g + 1];
                         const double dP = cg[q] * dA;
-                        atomic_add(&dL_dopacity[g], G * dA);
-                        atomic_add(&dL_dconic[3 * g + 0], -0.5 * dx * dx * dP);
-                        atomic_add(&dL_dconic[3 * g + 1], -dx * dy * dP);
-                        atomic_add(&dL_dconic[3 * g + 2], -0.5 * dy * dy * dP);
-                        atomic_add(&dL_dmeans2D[2 * g + 0], (co[0] * dx + co[1] * dy) * dP);
-                        atomic_add(&dL_dmeans2D[2 * g + 1], (co[1] * dx + co[2] * dy) * dP);
+                        grad_add(dL_dopacity, mag_opacity, g, G * dA);
+                        grad_add(dL_dconic, mag_conic, 3 * g + 0, -0.5 * dx * dx * dP);
+                        grad_add(dL_dconic, mag_conic, 3 * g + 1, -dx * dy * dP);
+                        grad_add(dL_dconic, mag_conic, 3 * g + 2, -0.5 * dy * dy * dP);
+                        grad_add(dL_dmeans2D, mag_means2D, 2 * g + 0, (co[0] * dx + co[1] * dy) * dP);
+                        grad_add(dL_dmeans2D, mag_means2D, 2 * g + 1, (co[1] * dx + co[2] * dy) * dP);
                     }
                 }
                 total += N > 0 ? (ck[N - 1] - s + 1) : 0;

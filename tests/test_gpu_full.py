@@ -117,6 +117,7 @@ def test_full_backward_cropped(full):
             acc = o
         else:
             for k in ("means2D", "conic", "opacity", "rgb", "depth"):
+                acc["mag"][k] = acc["mag"][k] + o["mag"][k]
                 acc[k] = acc[k] + o[k]
     for c, grads in runs:
         compare_grads(grads, acc, name=f"full bwd variant={c.variant} sub={c.subtile}")

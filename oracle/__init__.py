@@ -46,6 +46,8 @@ def lib():
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.orc_project.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_project.restype = C.c_int
+        L.orc_project_bwd.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_project_bwd.restype = C.c_int
         L.orc_bin.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, vp]
         L.orc_bin.restype = i64
         L.orc_sort.argtypes = [i64, vp, vp, vp]
@@ -112,6 +114,27 @@ def project(cam, means3D, log_scales, quats, opacity, colors, sh_degree: int) ->
                            _p(out["radius"]), _p(out["extent"]), _p(out["cov2d"]))
     if rc != 0:
         raise ValueError("orc_project failed")
+    return out
+
+
+def project_bwd(cam, means3D, log_scales, quats, opacity, colors, sh_degree: int, dL_dmeans2D,
+                dL_dconic_opacity, dL_drgb, dL_ddepth=None) -> dict:
+    """Derivative of :func:`project`: from the gradients of its outputs
+    (means2D, conic_opacity, rgb, depth) to those of its inputs.  Returns
+    means3D [P,3], log_scales [P,3], quats [P,4], opacity [P], colors (shape
+    of the colour input); zeros for culled Gaussians."""
+    P = int(np.asarray(means3D).shape[0])
+    m3, ls, q, op, col = _f32(means3D), _f32(log_scales), _f32(quats), _f32(opacity), _f32(colors)
+    gm, gco, gr = _f64(dL_dmeans2D), _f64(dL_dconic_opacity), _f64(dL_drgb)
+    gd = None if dL_ddepth is None else _f64(dL_ddepth)
+    out = dict(means3D=np.zeros((P, 3)), log_scales=np.zeros((P, 3)), quats=np.zeros((P, 4)),
+               opacity=np.zeros(P), colors=np.zeros(col.shape))
+    cc = _camera(cam)
+    rc = lib().orc_project_bwd(C.byref(cc), P, _p(m3), _p(ls), _p(q), _p(op), _p(col), int(sh_degree), _p(gm),
+                               _p(gco), _p(gr), _p(gd), _p(out["means3D"]), _p(out["log_scales"]),
+                               _p(out["quats"]), _p(out["opacity"]), _p(out["colors"]))
+    if rc != 0:
+        raise ValueError("orc_project_bwd failed")
     return out
 
 

@@ -26,6 +26,8 @@
  *                    to 0.99.
  *   orc_render_bwd   the exact derivative of orc_render_fwd with every skip /
  *                    stop decision held fixed, summed over pixels.
+ *   orc_project_bwd  the derivative of orc_project (3D means, log-scales,
+ *                    quaternions, opacity, colour coefficients).
  *
  * All arithmetic is double precision.  The three thresholds are the FP32
  * constants (1/255, 1e-4, 0.99 as floats) promoted to double.
@@ -248,6 +250,240 @@ int orc_project(const orc_camera *cam, int64_t P, const float *means3D, const fl
                         s += (double)col[3 * (l * l + l + m) + c] * orc_sh_basis(l, m, d[0], d[1], d[2]);
                 rgb[3 * i + c] = s > 0 ? s : 0;
             }
+        }
+    }
+    return 0;
+}
+
+/*
+ * Gradient of a real spherical harmonic (as orc_sh_basis defines it, a
+ * polynomial in x, y, z) at (x, y, z):  with A = (x + iy)^m, dA/dx =
+ * m (x + iy)^(m-1), dA/dy = i m (x + iy)^(m-1), and d/dz P_l^(m) = P_l^(m+1).
+ */
+static void sh_basis_grad(int l, int m, double x, double y, double z, double g[3])
+{
+    int am = m < 0 ? -m : m;
+    double K = sqrt((2.0 * l + 1.0) / (4.0 * ORC_PI) * factorial(l - am) / factorial(l + am));
+    double re = 1.0, im = 0.0, re1 = 0.0, im1 = 0.0; /* (x+iy)^am and (x+iy)^(am-1) */
+    for (int k = 0; k < am; ++k) {
+        re1 = re;
+        im1 = im;
+        double r2 = re * x - im * y;
+        double i2 = re * y + im * x;
+        re = r2;
+        im = i2;
+    }
+    double d = legendre_deriv(l, am, z), dz = legendre_deriv(l, am + 1, z);
+    if (m == 0) {
+        g[0] = 0.0;
+        g[1] = 0.0;
+        g[2] = K * dz;
+        return;
+    }
+    const double c = sqrt(2.0) * K;
+    /* dA/dx = am (re1 + i im1), dA/dy = i am (re1 + i im1) = am (-im1 + i re1) */
+    if (m > 0) {
+        g[0] = c * am * re1 * d;
+        g[1] = c * am * (-im1) * d;
+        g[2] = c * re * dz;
+    } else {
+        g[0] = c * am * im1 * d;
+        g[1] = c * am * re1 * d;
+        g[2] = c * im * dz;
+    }
+}
+
+/*
+ * Derivative of orc_project for a loss L of its outputs: given dL/dmeans2D
+ * [P][2], dL/dconic_opacity [P][4] (a, b, c, opacity), dL/drgb [P][3] and
+ * dL/ddepth [P] (nullable), writes (=) dL/dmeans3D [P][3], dL/dlog_scales
+ * [P][3], dL/dquats [P][4] (w, x, y, z, through the normalization),
+ * dL/dopacity [P] and dL/dcolors [P][K][3] (K SH coefficients, or the RGB).
+ * Culled Gaussians get zeros.  Every step is the derivative of the forward's
+ * step, taken in reverse order:
+ *   conic (a, b, c) = (s11, -s01, s00) / det,  det = s00 s11 - s01^2;
+ *   Sigma'_2x2 = T Sigma T^T (+0.3 I),  T = J R;  Sigma = M M^T, M = Rq S;
+ *   J depends on p through z and the clamped x/z, y/z (derivative 0 where
+ *   clamped);  (u, v) = (fx x / z, fy y / z) + const;  depth = z;
+ *   p = R mu + t;  colour = max(0, 1/2 + sum_lm k_lm Y_lm(d)), d the unit ray
+ *   (derivative 0 where clamped at 0).
+ */
+int orc_project_bwd(const orc_camera *cam, int64_t P, const float *means3D, const float *log_scales,
+                    const float *quats, const float *opacity, const float *colors, int32_t sh_degree,
+                    const double *g_means2D, const double *g_conic_opacity, const double *g_rgb,
+                    const double *g_depth, double *d_means3D, double *d_log_scales, double *d_quats,
+                    double *d_opacity, double *d_colors)
+{
+    (void)opacity;
+    if (sh_degree > 3) return -1;
+    const double *R = cam->R;
+    double campos[3];
+    for (int i = 0; i < 3; ++i)
+        campos[i] = -(R[0 * 3 + i] * cam->t[0] + R[1 * 3 + i] * cam->t[1] + R[2 * 3 + i] * cam->t[2]);
+    const double limx = 1.3 * (0.5 * cam->width) / cam->fx;
+    const double limy = 1.3 * (0.5 * cam->height) / cam->fy;
+    const int nsh = sh_degree < 0 ? 1 : (sh_degree + 1) * (sh_degree + 1);
+    const double fx = cam->fx, fy = cam->fy;
+
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < P; ++i) {
+        const float *mu = means3D + 3 * i;
+        double *dmu = d_means3D + 3 * i, *ds = d_log_scales + 3 * i, *dq = d_quats + 4 * i;
+        double *dc = d_colors + (int64_t)3 * nsh * i;
+        for (int k = 0; k < 3; ++k) dmu[k] = ds[k] = 0;
+        for (int k = 0; k < 4; ++k) dq[k] = 0;
+        for (int k = 0; k < 3 * nsh; ++k) dc[k] = 0;
+        d_opacity[i] = 0;
+
+        /* ---- recompute the forward */
+        double p[3];
+        for (int r = 0; r < 3; ++r)
+            p[r] = R[r * 3 + 0] * mu[0] + R[r * 3 + 1] * mu[1] + R[r * 3 + 2] * mu[2] + cam->t[r];
+        if (p[2] <= cam->znear) continue;
+        const float *qf = quats + 4 * i;
+        double qn = sqrt((double)qf[0] * qf[0] + (double)qf[1] * qf[1] + (double)qf[2] * qf[2] + (double)qf[3] * qf[3]);
+        double qh[4] = {qf[0] / qn, qf[1] / qn, qf[2] / qn, qf[3] / qn};
+        double Rq[9], Sd[3], M[9], Sig[9];
+        quat_to_rot(qf, Rq);
+        for (int k = 0; k < 3; ++k) Sd[k] = exp((double)log_scales[3 * i + k]);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) M[a * 3 + b] = Rq[a * 3 + b] * Sd[b];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double acc = 0;
+                for (int k = 0; k < 3; ++k) acc += M[a * 3 + k] * M[b * 3 + k];
+                Sig[a * 3 + b] = acc;
+            }
+        const double z = p[2];
+        double xz = p[0] / z, yz = p[1] / z;
+        const int cx_ = xz < -limx || xz > limx, cy_ = yz < -limy || yz > limy;
+        if (xz < -limx) xz = -limx;
+        if (xz > limx) xz = limx;
+        if (yz < -limy) yz = -limy;
+        if (yz > limy) yz = limy;
+        double J[6] = {fx / z, 0, -fx * xz / z, 0, fy / z, -fy * yz / z}; /* 2x3 */
+        double T[6];                                                      /* J R */
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b) T[a * 3 + b] = J[a * 3 + 0] * R[0 * 3 + b] + J[a * 3 + 1] * R[1 * 3 + b] + J[a * 3 + 2] * R[2 * 3 + b];
+        double TS[6];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b) TS[a * 3 + b] = T[a * 3 + 0] * Sig[0 * 3 + b] + T[a * 3 + 1] * Sig[1 * 3 + b] + T[a * 3 + 2] * Sig[2 * 3 + b];
+        double C2[4];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) C2[a * 2 + b] = TS[a * 3 + 0] * T[b * 3 + 0] + TS[a * 3 + 1] * T[b * 3 + 1] + TS[a * 3 + 2] * T[b * 3 + 2];
+        const double s00 = C2[0] + 0.3, s01 = C2[1], s11 = C2[3] + 0.3;
+        const double det = s00 * s11 - s01 * s01;
+        if (!(det > 0)) continue;
+        double mid = 0.5 * (s00 + s11), disc = mid * mid - det;
+        if (disc < 0) disc = 0;
+        if ((int32_t)ceil(3.0 * sqrt(mid + sqrt(disc))) <= 0) continue;
+
+        /* ---- conic -> Sigma'  */
+        const double ga = g_conic_opacity[4 * i + 0], gb = g_conic_opacity[4 * i + 1], gc = g_conic_opacity[4 * i + 2];
+        d_opacity[i] = g_conic_opacity[4 * i + 3];
+        const double Kd = -(ga * s11 - gb * s01 + gc * s00) / (det * det);
+        const double g00 = gc / det + Kd * s11;
+        const double g11 = ga / det + Kd * s00;
+        const double g01 = -gb / det + Kd * (-2.0 * s01);
+        const double Gm[4] = {g00, 0.5 * g01, 0.5 * g01, g11}; /* symmetric dL/dC2 */
+
+        /* ---- C2 = T Sig T^T:  dL/dSig = T^T Gm T,  dL/dT = 2 Gm T Sig */
+        double GT[6]; /* Gm T (2x3) */
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b) GT[a * 3 + b] = Gm[a * 2 + 0] * T[0 * 3 + b] + Gm[a * 2 + 1] * T[1 * 3 + b];
+        double dSig[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) dSig[a * 3 + b] = T[0 * 3 + a] * GT[0 * 3 + b] + T[1 * 3 + a] * GT[1 * 3 + b];
+        double dT[6];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b)
+                dT[a * 3 + b] = 2.0 * (GT[a * 3 + 0] * Sig[0 * 3 + b] + GT[a * 3 + 1] * Sig[1 * 3 + b] + GT[a * 3 + 2] * Sig[2 * 3 + b]);
+        /* T = J R:  dL/dJ = dL/dT R^T */
+        double dJ[6];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b)
+                dJ[a * 3 + b] = dT[a * 3 + 0] * R[b * 3 + 0] + dT[a * 3 + 1] * R[b * 3 + 1] + dT[a * 3 + 2] * R[b * 3 + 2];
+
+        /* ---- J(p) and the screen position, depth */
+        double dp[3] = {0, 0, 0};
+        const double z2 = z * z;
+        dp[2] += dJ[0] * (-fx / z2) + dJ[4] * (-fy / z2);
+        if (cx_) {
+            dp[2] += dJ[2] * (fx * xz / z2);
+        } else {
+            dp[0] += dJ[2] * (-fx / z2);
+            dp[2] += dJ[2] * (2.0 * fx * p[0] / (z2 * z));
+        }
+        if (cy_) {
+            dp[2] += dJ[5] * (fy * yz / z2);
+        } else {
+            dp[1] += dJ[5] * (-fy / z2);
+            dp[2] += dJ[5] * (2.0 * fy * p[1] / (z2 * z));
+        }
+        const double gu = g_means2D[2 * i], gv = g_means2D[2 * i + 1];
+        dp[0] += gu * fx / z;
+        dp[1] += gv * fy / z;
+        dp[2] += -gu * fx * p[0] / z2 - gv * fy * p[1] / z2;
+        if (g_depth) dp[2] += g_depth[i];
+        /* p = R mu + t */
+        for (int k = 0; k < 3; ++k) dmu[k] = R[0 * 3 + k] * dp[0] + R[1 * 3 + k] * dp[1] + R[2 * 3 + k] * dp[2];
+
+        /* ---- Sigma = M M^T, M = Rq diag(e^s):  dL/dM = 2 dSig M */
+        double dM[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                dM[a * 3 + b] = 2.0 * (dSig[a * 3 + 0] * M[0 * 3 + b] + dSig[a * 3 + 1] * M[1 * 3 + b] + dSig[a * 3 + 2] * M[2 * 3 + b]);
+        double gR[9];
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int a = 0; a < 3; ++a) {
+                acc += dM[a * 3 + b] * Rq[a * 3 + b];
+                gR[a * 3 + b] = dM[a * 3 + b] * Sd[b];
+            }
+            ds[b] = acc * Sd[b]; /* d e^s / ds = e^s */
+        }
+        /* rotation of the unit quaternion (w, x, y, z) */
+        const double w = qh[0], x = qh[1], y = qh[2], zq = qh[3];
+        double gq[4];
+        gq[0] = 2.0 * (-zq * gR[1] + y * gR[2] + zq * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+        gq[1] = 2.0 * (y * gR[1] + zq * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] + zq * gR[6] + w * gR[7] -
+                       2.0 * x * gR[8]);
+        gq[2] = 2.0 * (-2.0 * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + zq * gR[5] - w * gR[6] + zq * gR[7] -
+                       2.0 * y * gR[8]);
+        gq[3] = 2.0 * (-2.0 * zq * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * zq * gR[4] + y * gR[5] +
+                       x * gR[6] + y * gR[7]);
+        /* q_hat = q / |q|:  dL/dq = (g - q_hat (q_hat . g)) / |q| */
+        const double dot = qh[0] * gq[0] + qh[1] * gq[1] + qh[2] * gq[2] + qh[3] * gq[3];
+        for (int k = 0; k < 4; ++k) dq[k] = (gq[k] - qh[k] * dot) / qn;
+
+        /* ---- colour */
+        const float *col = colors + (int64_t)3 * nsh * i;
+        const double *gr = g_rgb + 3 * i;
+        if (sh_degree < 0) {
+            for (int c = 0; c < 3; ++c) dc[c] = gr[c];
+        } else {
+            double dv[3] = {mu[0] - campos[0], mu[1] - campos[1], mu[2] - campos[2]};
+            const double n = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+            for (int k = 0; k < 3; ++k) dv[k] /= n;
+            double gd[3] = {0, 0, 0}; /* dL/d(unit ray) */
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.5;
+                for (int l = 0; l <= sh_degree; ++l)
+                    for (int m = -l; m <= l; ++m)
+                        s += (double)col[3 * (l * l + l + m) + c] * orc_sh_basis(l, m, dv[0], dv[1], dv[2]);
+                if (!(s > 0)) continue; /* clamped at 0 */
+                for (int l = 0; l <= sh_degree; ++l)
+                    for (int m = -l; m <= l; ++m) {
+                        const int idx = l * l + l + m;
+                        dc[3 * idx + c] = gr[c] * orc_sh_basis(l, m, dv[0], dv[1], dv[2]);
+                        double gy[3];
+                        sh_basis_grad(l, m, dv[0], dv[1], dv[2], gy);
+                        for (int k = 0; k < 3; ++k) gd[k] += gr[c] * (double)col[3 * idx + c] * gy[k];
+                    }
+            }
+            /* d = v / |v|:  dL/dv = (gd - d (d . gd)) / |v| */
+            const double dd = dv[0] * gd[0] + dv[1] * gd[1] + dv[2] * gd[2];
+            for (int k = 0; k < 3; ++k) dmu[k] += (gd[k] - dv[k] * dd) / n;
         }
     }
     return 0;

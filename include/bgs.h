@@ -147,6 +147,26 @@ bgs_status bgs_project(const bgs_camera* cam, int64_t P, const float* means3D, c
                        int32_t tile, float* means2D, float* conic_opacity, float* rgb, float* depth,
                        int32_t* radius, uint32_t* tiles_touched, hipStream_t stream);
 
+/*
+ * Derivative of bgs_project (the preprocessing step before the render; it
+ * closes a training step through the 3D parameters): from the gradients of
+ * the projection outputs -- dL_dmeans2D [P][2], dL_dconic_opacity [P][4]
+ * (a, b, c, opacity; 16-byte aligned, the layout bgs_render_bwd writes),
+ * dL_drgb [P][3], dL_ddepth [P] (nullable) -- to those of its inputs, WRITTEN
+ * (=), not accumulated: dL_dmeans3D [P][3], dL_dlog_scales [P][3],
+ * dL_dquats [P][4] (16-byte aligned; through the quaternion's
+ * normalization), dL_dopacity [P], dL_dcolors (the layout of `colors`: RGB
+ * [P][3], or SH coefficients [P][(d+1)^2][3]).  Same camera, inputs and
+ * sh_degree as the forward call.  The derivative through the 1.3x field-of-
+ * view clamp of the Jacobian and through the colour's clamp at 0 is 0;
+ * culled Gaussians get zeros.  Asynchronous on `stream`.
+ */
+bgs_status bgs_project_bwd(const bgs_camera* cam, int64_t P, const float* means3D, const float* log_scales,
+                           const float* quats, const float* colors, int32_t sh_degree, const float* dL_dmeans2D,
+                           const float* dL_dconic_opacity, const float* dL_drgb, const float* dL_ddepth,
+                           float* dL_dmeans3D, float* dL_dlog_scales, float* dL_dquats, float* dL_dopacity,
+                           float* dL_dcolors, hipStream_t stream);
+
 /* Workspace bytes for bgs_bin with P Gaussians. */
 size_t bgs_bin_workspace_bytes(int64_t P);
 

@@ -74,6 +74,8 @@ def lib() -> C.CDLL:
             "bgs_version": ([], C.c_char_p),
             "bgs_project": ([_vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
                             C.c_int),
+            "bgs_project_bwd": ([_vp, _i64, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                 _vp], C.c_int),
             "bgs_bin_workspace_bytes": ([_i64], _sz),
             "bgs_bin": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_sort_workspace_bytes": ([_i64], _sz),
@@ -102,7 +104,7 @@ def lib() -> C.CDLL:
 
 def exported_symbols():
     """Names the header declares (used by the load test)."""
-    return ["bgs_last_error", "bgs_version", "bgs_project", "bgs_bin_workspace_bytes", "bgs_bin",
+    return ["bgs_last_error", "bgs_version", "bgs_project", "bgs_project_bwd", "bgs_bin_workspace_bytes", "bgs_bin",
             "bgs_sort_workspace_bytes", "bgs_sort", "bgs_ranges", "bgs_tile_lists_workspace_bytes", "bgs_tile_lists",
             "bgs_render_workspace_bytes", "bgs_queue_build", "bgs_autotune", "bgs_plan_create", "bgs_plan_launch",
             "bgs_plan_destroy",
@@ -223,6 +225,26 @@ def bgs_project(cam, means3D, log_scales, quats, opacity, colors, sh_degree: int
                                             _ptr(opacity), _ptr(colors), int(sh_degree), TILE, _ptr(means2D),
                                             _ptr(conic_opacity), _ptr(rgb), _ptr(depth), _ptr(radius),
                                             _ptr(tiles_touched), _stream(stream)))
+
+
+def bgs_project_bwd(cam, means3D, log_scales, quats, colors, sh_degree: int, dL_dmeans2D, dL_dconic_opacity,
+                    dL_drgb, dL_ddepth, out: dict, stream=None):
+    """Writes out["means3D"|"log_scales"|"quats"|"opacity"|"colors"] (the
+    gradients of the projection inputs)."""
+    P = means3D.shape[0]
+    _expect(dL_dmeans2D, (P, 2), torch.float32, "dL_dmeans2D")
+    _expect(dL_dconic_opacity, (P, 4), torch.float32, "dL_dconic_opacity")
+    _expect(dL_drgb, (P, 3), torch.float32, "dL_drgb")
+    if dL_ddepth is not None:
+        _expect(dL_ddepth, (P,), torch.float32, "dL_ddepth")
+    _expect(out["quats"], (P, 4), torch.float32, "dL_dquats")
+    if out["colors"].numel() != colors.numel():
+        raise ValueError("dL_dcolors: wrong size")
+    c = make_camera(cam) if not isinstance(cam, Camera) else cam
+    _check("bgs_project_bwd", lib().bgs_project_bwd(
+        C.byref(c), P, _ptr(means3D), _ptr(log_scales), _ptr(quats), _ptr(colors), int(sh_degree),
+        _ptr(dL_dmeans2D), _ptr(dL_dconic_opacity), _ptr(dL_drgb), _ptr(dL_ddepth), _ptr(out["means3D"]),
+        _ptr(out["log_scales"]), _ptr(out["quats"]), _ptr(out["opacity"]), _ptr(out["colors"]), _stream(stream)))
 
 
 def bgs_bin_workspace_bytes(P: int) -> int:

@@ -20,10 +20,11 @@ struct ProjParams {
     int TX, TY;
 };
 
-// Real spherical harmonics (no Condon-Shortley phase), index l*l + l + m.
-// Amplitudes: C0 = 1/(2 sqrt(pi)), C1 = sqrt(3/(4 pi)), and for l = 2, 3 the
-// closed forms written beside each constant.
-__device__ inline void sh_colour(const float* __restrict__ k, int degree, float x, float y, float z, float out[3]) {
+// Real spherical harmonics (no Condon-Shortley phase), index l*l + l + m,
+// at the unit vector (x, y, z), for l <= degree.  Amplitudes: C0 = 1/(2
+// sqrt(pi)), C1 = sqrt(3/(4 pi)), and for l = 2, 3 the closed forms written
+// beside each constant.
+__device__ inline void sh_basis(int degree, float x, float y, float z, float Y[16]) {
     const float C0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
     const float C1 = 0.4886025119029199f;    // sqrt(3/(4 pi))
     const float C2a = 1.0925484305920792f;   // sqrt(15/pi)/2
@@ -34,7 +35,6 @@ __device__ inline void sh_colour(const float* __restrict__ k, int degree, float 
     const float C3c = 0.4570457994644658f;   // sqrt(21/(2 pi))/4
     const float C3d = 0.3731763325901154f;   // sqrt(7/pi)/4
     const float C3e = 1.445305721320277f;    // sqrt(105/pi)/4
-    float Y[16];
     Y[0] = C0;
     if (degree >= 1) {
         Y[1] = C1 * y;
@@ -58,6 +58,12 @@ __device__ inline void sh_colour(const float* __restrict__ k, int degree, float 
             Y[15] = C3a * x * (xx - 3.0f * yy);
         }
     }
+}
+
+// colour = max(0, 1/2 + sum_i k_i Y_i) per channel; coefficients k[i][3].
+__device__ inline void sh_colour(const float* __restrict__ k, int degree, float x, float y, float z, float out[3]) {
+    float Y[16];
+    sh_basis(degree, x, y, z, Y);
     const int n = (degree + 1) * (degree + 1);
     for (int c = 0; c < 3; ++c) {
         float s = 0.5f;
@@ -91,16 +97,6 @@ __global__ __launch_bounds__(256) void k_project(ProjParams pp, int64_t P, const
         const float Rq[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
                              2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
                              2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
-        const float e0 = __expf(2.f * log_scales[3 * i]), e1 = __expf(2.f * log_scales[3 * i + 1]),
-                    e2 = __expf(2.f * log_scales[3 * i + 2]);
-        float S[6];  // 00 01 02 11 12 22
-        {
-            int idx = 0;
-            for (int a = 0; a < 3; ++a)
-                for (int b = a; b < 3; ++b)
-                    S[idx++] = Rq[3 * a] * e0 * Rq[3 * b] + Rq[3 * a + 1] * e1 * Rq[3 * b + 1] +
-                               Rq[3 * a + 2] * e2 * Rq[3 * b + 2];
-        }
         // Jacobian of the pinhole map at the (clamped) ray, times the view rotation
         const float iz = 1.0f / pz;
         const float xz = fminf(fmaxf(px * iz, -pp.limx), pp.limx);
@@ -112,15 +108,34 @@ __global__ __launch_bounds__(256) void k_project(ProjParams pp, int64_t P, const
             T0[c] = j00 * R[c] + j02 * R[6 + c];
             T1[c] = j11 * R[3 + c] + j12 * R[6 + c];
         }
-        // Sigma' = T Sigma T^T
-        const float SigT0[3] = {S[0] * T0[0] + S[1] * T0[1] + S[2] * T0[2], S[1] * T0[0] + S[3] * T0[1] + S[4] * T0[2],
-                                S[2] * T0[0] + S[4] * T0[1] + S[5] * T0[2]};
-        const float SigT1[3] = {S[0] * T1[0] + S[1] * T1[1] + S[2] * T1[2], S[1] * T1[0] + S[3] * T1[1] + S[4] * T1[2],
-                                S[2] * T1[0] + S[4] * T1[1] + S[5] * T1[2]};
-        s00 = T0[0] * SigT0[0] + T0[1] * SigT0[1] + T0[2] * SigT0[2] + 0.3f;
-        s01 = T0[0] * SigT1[0] + T0[1] * SigT1[1] + T0[2] * SigT1[2];
-        s11 = T1[0] * SigT1[0] + T1[1] * SigT1[1] + T1[2] * SigT1[2] + 0.3f;
-        det = s00 * s11 - s01 * s01;
+        // Sigma = sum_b e_b^2 r_b r_b^T (r_b the columns of Rq, e_b^2 = exp(2 s_b)),
+        // so Sigma' = sum_b e_b^2 u_b u_b^T + 0.3 I with u_b = T r_b the screen
+        // images of the axes.  Its determinant (Cauchy-Binet)
+        //   det = sum_{b<c} e_b^2 e_c^2 (u_b x u_c)^2 + 0.3 sum_b e_b^2 |u_b|^2 + 0.09
+        // is a sum of non-negative terms: no cancellation, where the expanded
+        // s00 s11 - s01^2 of a needle-shaped Gaussian loses ~cond ulps.
+        float u[3][2], e2[3];
+        for (int b = 0; b < 3; ++b) {
+            e2[b] = __expf(2.f * log_scales[3 * i + b]);
+            u[b][0] = T0[0] * Rq[b] + T0[1] * Rq[3 + b] + T0[2] * Rq[6 + b];
+            u[b][1] = T1[0] * Rq[b] + T1[1] * Rq[3 + b] + T1[2] * Rq[6 + b];
+        }
+        s00 = 0.3f;
+        s01 = 0.f;
+        s11 = 0.3f;
+        float tr = 0.f;
+        for (int b = 0; b < 3; ++b) {
+            s00 += e2[b] * u[b][0] * u[b][0];
+            s01 += e2[b] * u[b][0] * u[b][1];
+            s11 += e2[b] * u[b][1] * u[b][1];
+            tr += e2[b] * (u[b][0] * u[b][0] + u[b][1] * u[b][1]);
+        }
+        det = 0.3f * tr + 0.09f;
+        for (int b = 0; b < 3; ++b)
+            for (int c = b + 1; c < 3; ++c) {
+                const float x = u[b][0] * u[c][1] - u[b][1] * u[c][0];
+                det += e2[b] * e2[c] * x * x;
+            }
         keep = det > 0.0f;
     }
     int r = 0;
@@ -170,9 +185,245 @@ __global__ __launch_bounds__(256) void k_project(ProjParams pp, int64_t P, const
     }
 }
 
+// ---------------------------------------------------------------- backward
+// Gradients of the real spherical harmonics above with respect to the
+// (unnormalized) direction components, the derivatives of the same
+// polynomials.
+__device__ inline void sh_grad(int degree, float x, float y, float z, float g[16][3]) {
+    const float C1 = 0.4886025119029199f;
+    const float C2a = 1.0925484305920792f, C2b = 0.31539156525252005f, C2c = 0.5462742152960396f;
+    const float C3a = 0.5900435899266435f, C3b = 2.890611442640554f, C3c = 0.4570457994644658f;
+    const float C3d = 0.3731763325901154f, C3e = 1.445305721320277f;
+    for (int i = 0; i < 16; ++i) g[i][0] = g[i][1] = g[i][2] = 0.f;
+    if (degree >= 1) {
+        g[1][1] = C1;
+        g[2][2] = C1;
+        g[3][0] = C1;
+    }
+    if (degree >= 2) {
+        g[4][0] = C2a * y; g[4][1] = C2a * x;
+        g[5][1] = C2a * z; g[5][2] = C2a * y;
+        g[6][2] = 6.0f * C2b * z;
+        g[7][0] = C2a * z; g[7][2] = C2a * x;
+        g[8][0] = 2.0f * C2c * x; g[8][1] = -2.0f * C2c * y;
+    }
+    if (degree >= 3) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        g[9][0] = 6.0f * C3a * x * y; g[9][1] = 3.0f * C3a * (xx - yy);
+        g[10][0] = C3b * y * z; g[10][1] = C3b * x * z; g[10][2] = C3b * x * y;
+        g[11][1] = C3c * (5.0f * zz - 1.0f); g[11][2] = 10.0f * C3c * y * z;
+        g[12][2] = C3d * (15.0f * zz - 3.0f);
+        g[13][0] = C3c * (5.0f * zz - 1.0f); g[13][2] = 10.0f * C3c * x * z;
+        g[14][0] = 2.0f * C3e * x * z; g[14][1] = -2.0f * C3e * y * z; g[14][2] = C3e * (xx - yy);
+        g[15][0] = 3.0f * C3a * (xx - yy); g[15][1] = -6.0f * C3a * x * y;
+    }
+}
+
+// One thread per Gaussian: the forward is recomputed and every step is
+// differentiated in reverse order (conic inverse; Sigma' = T Sigma T^T with
+// T = J R; J of the clamped ray, whose derivative through the clamp is 0;
+// the pinhole map and depth; Sigma = M M^T, M = Rq diag(e^s); the rotation
+// of the normalized quaternion; the SH colour along the view ray and its 0
+// clamp).  Gradients are written (=); culled Gaussians get zeros.
+__global__ __launch_bounds__(256) void k_project_bwd(ProjParams pp, int64_t P, const float* __restrict__ means3D,
+                                                     const float* __restrict__ log_scales,
+                                                     const float* __restrict__ quats,
+                                                     const float* __restrict__ colors, int sh_degree,
+                                                     const float* __restrict__ g_means2D,
+                                                     const float* __restrict__ g_conic_opacity,
+                                                     const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
+                                                     float* __restrict__ d_means3D, float* __restrict__ d_log_scales,
+                                                     float* __restrict__ d_quats, float* __restrict__ d_opacity,
+                                                     float* __restrict__ d_colors) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const int nsh = sh_degree < 0 ? 1 : (sh_degree + 1) * (sh_degree + 1);
+    float* dc = d_colors + (int64_t)3 * nsh * i;
+    const float mx = means3D[3 * i], my = means3D[3 * i + 1], mz = means3D[3 * i + 2];
+    const float* R = pp.R;
+    const float p[3] = {R[0] * mx + R[1] * my + R[2] * mz + pp.t[0], R[3] * mx + R[4] * my + R[5] * mz + pp.t[1],
+                        R[6] * mx + R[7] * my + R[8] * mz + pp.t[2]};
+    auto zero = [&]() {
+        for (int k = 0; k < 3; ++k) d_means3D[3 * i + k] = d_log_scales[3 * i + k] = 0.f;
+        reinterpret_cast<float4*>(d_quats)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        d_opacity[i] = 0.f;
+        for (int k = 0; k < 3 * nsh; ++k) dc[k] = 0.f;
+    };
+    if (!(p[2] > pp.znear)) {
+        zero();
+        return;
+    }
+    // ---- forward recomputation
+    const float q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
+    const float qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3), iqn = 1.0f / qn;
+    const float w = q0 * iqn, x = q1 * iqn, y = q2 * iqn, z = q3 * iqn;
+    const float Rq[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+                         2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+                         2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
+    const float e[3] = {__expf(log_scales[3 * i]), __expf(log_scales[3 * i + 1]), __expf(log_scales[3 * i + 2])};
+    const float iz = 1.0f / p[2];
+    const float rx = p[0] * iz, ry = p[1] * iz;
+    const bool clx = rx < -pp.limx || rx > pp.limx, cly = ry < -pp.limy || ry > pp.limy;
+    const float xz = fminf(fmaxf(rx, -pp.limx), pp.limx), yz = fminf(fmaxf(ry, -pp.limy), pp.limy);
+    const float J[6] = {pp.fx * iz, 0.f, -pp.fx * xz * iz, 0.f, pp.fy * iz, -pp.fy * yz * iz};
+    float T[6];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) T[3 * a + b] = J[3 * a] * R[b] + J[3 * a + 1] * R[3 + b] + J[3 * a + 2] * R[6 + b];
+    // Sigma' = S = sum_b e_b^2 u_b u_b^T + 0.3 I with u_b = T r_b (r_b the
+    // columns of Rq), as in the forward.  With C = S^-1 (the conic) and
+    // Gamma = dL/dC (symmetric; b enters C twice), dL/dS = -C Gamma C, so
+    //   dL/ds_b  = 2 e_b^2 u_b^T (dL/dS) u_b = -2 e_b^2 v_b^T Gamma v_b,  v_b = C u_b
+    //   dL/dr_b  = 2 e_b^2 T^T (dL/dS) u_b   = -2 e_b^2 T^T z_b,         z_b = C Gamma v_b
+    //   dL/dT    = -2 sum_b e_b^2 z_b r_b^T.
+    // C w = adj(S) w / det with adj(S) w = sum_c e_c^2 (u_c x w) u_c_perp + 0.3 w
+    // (u_perp = (-u_y, u_x)) and det by Cauchy-Binet: for w = u_b the c = b
+    // term vanishes exactly, so v_b of a needle's long axis -- tiny, and
+    // formed by cancellation in the expanded adj(S) u_b -- keeps its relative
+    // accuracy.
+    float u[3][2], e2[3];
+    for (int b = 0; b < 3; ++b) {
+        e2[b] = e[b] * e[b];
+        for (int a = 0; a < 2; ++a) u[b][a] = T[3 * a] * Rq[b] + T[3 * a + 1] * Rq[3 + b] + T[3 * a + 2] * Rq[6 + b];
+    }
+    float tr = 0.f, det = 0.09f;
+    for (int b = 0; b < 3; ++b) {
+        tr += e2[b] * (u[b][0] * u[b][0] + u[b][1] * u[b][1]);
+        for (int c = b + 1; c < 3; ++c) {
+            const float x = u[b][0] * u[c][1] - u[b][1] * u[c][0];
+            det += e2[b] * e2[c] * x * x;
+        }
+    }
+    det += 0.3f * tr;
+    const float idet = 1.0f / det;
+    // C w for a 2-vector w; `skip` names an axis whose term is known to be 0
+    auto conic_apply = [&](float w0, float w1, int skip, float& o0, float& o1) {
+        o0 = 0.3f * w0;
+        o1 = 0.3f * w1;
+        for (int c = 0; c < 3; ++c) {
+            if (c == skip) continue;
+            const float k = e2[c] * (u[c][0] * w1 - u[c][1] * w0);
+            o0 -= k * u[c][1];
+            o1 += k * u[c][0];
+        }
+        o0 *= idet;
+        o1 *= idet;
+    };
+    const float4 gco = reinterpret_cast<const float4*>(g_conic_opacity)[i];
+    const float G00 = gco.x, G01 = 0.5f * gco.y, G11 = gco.z;  // Gamma
+    float gR[9], dT[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < 3; ++b) {
+        float v0, v1, z0, z1;
+        conic_apply(u[b][0], u[b][1], b, v0, v1);
+        const float h0 = G00 * v0 + G01 * v1, h1 = G01 * v0 + G11 * v1;  // Gamma v_b
+        conic_apply(h0, h1, -1, z0, z1);
+        const float k2 = -2.0f * e2[b];
+        d_log_scales[3 * i + b] = k2 * (v0 * h0 + v1 * h1);
+        for (int k = 0; k < 3; ++k) {
+            gR[3 * k + b] = k2 * (T[k] * z0 + T[3 + k] * z1);
+            dT[k] += k2 * z0 * Rq[3 * k + b];
+            dT[3 + k] += k2 * z1 * Rq[3 * k + b];
+        }
+    }
+    float dJ[6];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b)
+            dJ[3 * a + b] = dT[3 * a] * R[3 * b] + dT[3 * a + 1] * R[3 * b + 1] + dT[3 * a + 2] * R[3 * b + 2];
+    // ---- J(p), pinhole map, depth
+    const float iz2 = iz * iz;
+    float dp[3] = {0.f, 0.f, 0.f};
+    dp[2] -= (dJ[0] * pp.fx + dJ[4] * pp.fy) * iz2;
+    if (clx) {
+        dp[2] += dJ[2] * pp.fx * xz * iz2;
+    } else {
+        dp[0] -= dJ[2] * pp.fx * iz2;
+        dp[2] += dJ[2] * 2.0f * pp.fx * p[0] * iz2 * iz;
+    }
+    if (cly) {
+        dp[2] += dJ[5] * pp.fy * yz * iz2;
+    } else {
+        dp[1] -= dJ[5] * pp.fy * iz2;
+        dp[2] += dJ[5] * 2.0f * pp.fy * p[1] * iz2 * iz;
+    }
+    const float gu = g_means2D[2 * i], gv = g_means2D[2 * i + 1];
+    dp[0] += gu * pp.fx * iz;
+    dp[1] += gv * pp.fy * iz;
+    dp[2] -= (gu * pp.fx * p[0] + gv * pp.fy * p[1]) * iz2;
+    if (g_depth) dp[2] += g_depth[i];
+    float dmu[3];
+    for (int k = 0; k < 3; ++k) dmu[k] = R[k] * dp[0] + R[3 + k] * dp[1] + R[6 + k] * dp[2];
+    // rotation: a world-frame turn by dtheta moves each axis r_b by dtheta x r_b,
+    // so the torque is omega = sum_b r_b x dL/dr_b, and the unit quaternion
+    // moves by (0, dtheta) (x) q_hat / 2; the gradient in the tangent space of
+    // the unit sphere is 2 (0, omega) (x) q_hat, divided by |q| for the
+    // normalization.  (Forming the 4-vector gradient of the rotation formula
+    // and then removing its radial part cancels when that part dominates.)
+    float om[3] = {0.f, 0.f, 0.f};
+    for (int b = 0; b < 3; ++b) {
+        const float r0 = Rq[b], r1 = Rq[3 + b], r2 = Rq[6 + b];
+        const float g0 = gR[b], g1 = gR[3 + b], g2 = gR[6 + b];
+        om[0] += r1 * g2 - r2 * g1;
+        om[1] += r2 * g0 - r0 * g2;
+        om[2] += r0 * g1 - r1 * g0;
+    }
+    const float k2q = 2.0f * iqn;
+    reinterpret_cast<float4*>(d_quats)[i] =
+        make_float4(-k2q * (om[0] * x + om[1] * y + om[2] * z), k2q * (w * om[0] + om[1] * z - om[2] * y),
+                    k2q * (w * om[1] + om[2] * x - om[0] * z), k2q * (w * om[2] + om[0] * y - om[1] * x));
+    d_opacity[i] = gco.w;
+    // ---- colour
+    const float* gr = g_rgb + 3 * i;
+    if (sh_degree < 0) {
+        dc[0] = gr[0];
+        dc[1] = gr[1];
+        dc[2] = gr[2];
+    } else {
+        float v[3] = {mx - pp.campos[0], my - pp.campos[1], mz - pp.campos[2]};
+        const float vn = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]), ivn = 1.0f / vn;
+        const float d[3] = {v[0] * ivn, v[1] * ivn, v[2] * ivn};
+        const float* k = colors + (int64_t)3 * nsh * i;
+        float Y[16], G[16][3];
+        sh_basis(sh_degree, d[0], d[1], d[2], Y);
+        sh_grad(sh_degree, d[0], d[1], d[2], G);
+        float c[3];  // the colour before its clamp at 0
+        for (int ch = 0; ch < 3; ++ch) {
+            c[ch] = 0.5f;
+            for (int j = 0; j < nsh; ++j) c[ch] += k[3 * j + ch] * Y[j];
+        }
+        float gd[3] = {0.f, 0.f, 0.f};
+        for (int ch = 0; ch < 3; ++ch) {
+            const bool live = c[ch] > 0.0f;
+            for (int j = 0; j < nsh; ++j) {
+                dc[3 * j + ch] = live ? gr[ch] * Y[j] : 0.0f;
+                if (live)
+                    for (int a = 0; a < 3; ++a) gd[a] += gr[ch] * k[3 * j + ch] * G[j][a];
+            }
+        }
+        const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+        for (int a = 0; a < 3; ++a) dmu[a] += (gd[a] - d[a] * dd) * ivn;
+    }
+    for (int k = 0; k < 3; ++k) d_means3D[3 * i + k] = dmu[k];
+}
+
 }  // namespace bgs
 
 using namespace bgs;
+
+static ProjParams proj_params(const bgs_camera* cam) {
+    ProjParams pp;
+    pp.fx = cam->fx; pp.fy = cam->fy; pp.cx = cam->cx; pp.cy = cam->cy;
+    for (int k = 0; k < 9; ++k) pp.R[k] = cam->R[k];
+    for (int k = 0; k < 3; ++k) pp.t[k] = cam->t[k];
+    // camera centre -R^T t, in double on the host
+    for (int c = 0; c < 3; ++c)
+        pp.campos[c] = (float)(-((double)cam->R[c] * cam->t[0] + (double)cam->R[3 + c] * cam->t[1] +
+                                 (double)cam->R[6 + c] * cam->t[2]));
+    pp.znear = cam->znear;
+    pp.limx = (float)(1.3 * (0.5 * cam->width) / cam->fx);
+    pp.limy = (float)(1.3 * (0.5 * cam->height) / cam->fy);
+    pp.TX = (cam->width + TILE - 1) / TILE;
+    pp.TY = (cam->height + TILE - 1) / TILE;
+    return pp;
+}
 
 extern "C" bgs_status bgs_project(const bgs_camera* cam, int64_t P, const float* means3D, const float* log_scales,
                                   const float* quats, const float* opacity, const float* colors, int32_t sh_degree,
@@ -188,24 +439,39 @@ extern "C" bgs_status bgs_project(const bgs_camera* cam, int64_t P, const float*
                     radius && tiles_touched,
                 "bgs_project: null array");
     BGS_REQUIRE((reinterpret_cast<uintptr_t>(conic_opacity) & 15) == 0, "bgs_project: conic_opacity must be 16-byte aligned");
-    ProjParams pp;
-    pp.fx = cam->fx; pp.fy = cam->fy; pp.cx = cam->cx; pp.cy = cam->cy;
-    for (int k = 0; k < 9; ++k) pp.R[k] = cam->R[k];
-    for (int k = 0; k < 3; ++k) pp.t[k] = cam->t[k];
-    // camera centre -R^T t, in double on the host
-    for (int c = 0; c < 3; ++c)
-        pp.campos[c] = (float)(-((double)cam->R[c] * cam->t[0] + (double)cam->R[3 + c] * cam->t[1] +
-                                 (double)cam->R[6 + c] * cam->t[2]));
-    pp.znear = cam->znear;
-    pp.limx = (float)(1.3 * (0.5 * cam->width) / cam->fx);
-    pp.limy = (float)(1.3 * (0.5 * cam->height) / cam->fy);
-    pp.TX = (cam->width + TILE - 1) / TILE;
-    pp.TY = (cam->height + TILE - 1) / TILE;
+    const ProjParams pp = proj_params(cam);
     const int threads = 256;
     const int64_t blocks = (P + threads - 1) / threads;
     BGS_REQUIRE(blocks < (int64_t)1 << 31, "bgs_project: P too large");
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(threads), 0, stream, pp, P, means3D, log_scales, quats,
                        opacity, colors, (int)sh_degree, means2D, conic_opacity, rgb, depth, radius, tiles_touched);
+    BGS_HIP(hipGetLastError());
+    return BGS_OK;
+}
+
+extern "C" bgs_status bgs_project_bwd(const bgs_camera* cam, int64_t P, const float* means3D, const float* log_scales,
+                                      const float* quats, const float* colors, int32_t sh_degree,
+                                      const float* dL_dmeans2D, const float* dL_dconic_opacity, const float* dL_drgb,
+                                      const float* dL_ddepth, float* dL_dmeans3D, float* dL_dlog_scales,
+                                      float* dL_dquats, float* dL_dopacity, float* dL_dcolors, hipStream_t stream) {
+    BGS_REQUIRE(cam != nullptr, "bgs_project_bwd: camera is null");
+    BGS_REQUIRE(P >= 0, "bgs_project_bwd: P < 0");
+    BGS_REQUIRE(cam->width > 0 && cam->height > 0, "bgs_project_bwd: image size must be positive");
+    BGS_REQUIRE(sh_degree >= -1 && sh_degree <= 3, "bgs_project_bwd: sh_degree must be in -1..3");
+    if (P == 0) return BGS_OK;
+    BGS_REQUIRE(means3D && log_scales && quats && colors && dL_dmeans2D && dL_dconic_opacity && dL_drgb &&
+                    dL_dmeans3D && dL_dlog_scales && dL_dquats && dL_dopacity && dL_dcolors,
+                "bgs_project_bwd: null array");
+    BGS_REQUIRE((reinterpret_cast<uintptr_t>(dL_dconic_opacity) & 15) == 0 &&
+                    (reinterpret_cast<uintptr_t>(dL_dquats) & 15) == 0,
+                "bgs_project_bwd: dL_dconic_opacity and dL_dquats must be 16-byte aligned");
+    const ProjParams pp = proj_params(cam);
+    const int threads = 256;
+    const int64_t blocks = (P + threads - 1) / threads;
+    BGS_REQUIRE(blocks < (int64_t)1 << 31, "bgs_project_bwd: P too large");
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(threads), 0, stream, pp, P, means3D, log_scales,
+                       quats, colors, (int)sh_degree, dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepth, dL_dmeans3D,
+                       dL_dlog_scales, dL_dquats, dL_dopacity, dL_dcolors);
     BGS_HIP(hipGetLastError());
     return BGS_OK;
 }

@@ -90,6 +90,20 @@ class Rasterizer:
                       out["conic_opacity"], out["rgb"], out["depth"], out["radius"], out["tiles_touched"])
         return out
 
+    def project_bwd(self, cam, means3D, log_scales, quats, colors, sh_degree: int, dL_dmeans2D, dL_dconic_opacity,
+                    dL_drgb, dL_ddepth=None) -> dict:
+        """Gradients of the projection inputs (bgs_project_bwd)."""
+        means3D, log_scales, quats, colors = self._t(means3D), self._t(log_scales), self._t(quats), self._t(colors)
+        P = means3D.shape[0]
+        dev = self.device
+        out = dict(means3D=torch.empty(P, 3, device=dev), log_scales=torch.empty(P, 3, device=dev),
+                   quats=torch.empty(P, 4, device=dev), opacity=torch.empty(P, device=dev),
+                   colors=torch.empty_like(colors))
+        B.bgs_project_bwd(cam, means3D, log_scales, quats, colors, sh_degree, dL_dmeans2D.contiguous(),
+                          dL_dconic_opacity.contiguous(), dL_drgb.contiguous(),
+                          None if dL_ddepth is None else dL_ddepth.contiguous(), out)
+        return out
+
     def bin_sort_ranges(self, width: int, height: int, pr: dict, method: Optional[str] = None) -> Prepared:
         """Per-tile depth-ordered lists.  method "fused" = bgs_tile_lists (one
         counting pass), "sort" = bgs_bin + bgs_sort + bgs_ranges; default: fused
@@ -296,3 +310,41 @@ class RenderFn(torch.autograd.Function):
 
 def render(means2D, conic_opacity, rgb, depth, prep: Prepared, cfg: B.RenderCfg, rast: Rasterizer):
     return RenderFn.apply(means2D, conic_opacity, rgb, depth, prep, cfg, rast)
+
+
+class Render3DFn(torch.autograd.Function):
+    """Differentiable render from the 3D Gaussian parameters: projection, tile
+    lists and the forward render, with the backward render followed by the
+    projection's derivative (bgs_project_bwd).  Inputs means3D [P,3],
+    log_scales [P,3], quats [P,4], opacity [P], colors (RGB [P,3] or SH
+    [P,K,3]); outputs color [3,H,W], alpha [H,W], depth [H,W]."""
+
+    @staticmethod
+    def forward(ctx, means3D, log_scales, quats, opacity, colors, cam, sh_degree, fwd_cfg, bwd_cfg, rast):
+        args = [t.detach().contiguous() for t in (means3D, log_scales, quats, opacity, colors)]
+        prep = rast.prepare(cam, *args, sh_degree)
+        out = rast.render_fwd(prep, fwd_cfg)
+        ctx.save_for_backward(*args)
+        ctx.prep, ctx.out, ctx.cam, ctx.sh_degree, ctx.bwd_cfg, ctx.rast = prep, out, cam, sh_degree, bwd_cfg, rast
+        return out["color"], out["alpha"], out["depth"]
+
+    @staticmethod
+    def backward(ctx, g_color, g_alpha, g_depth):
+        means3D, log_scales, quats, opacity, colors = ctx.saved_tensors
+        rast = ctx.rast
+        g2 = rast.render_bwd(ctx.prep, ctx.bwd_cfg, ctx.out, g_color.contiguous(),
+                             None if g_alpha is None else g_alpha.contiguous(),
+                             None if g_depth is None else g_depth.contiguous())
+        g3 = rast.project_bwd(ctx.cam, means3D, log_scales, quats, colors, ctx.sh_degree, g2["means2D"],
+                              g2["conic_opacity"], g2["rgb"], g2["depth"])
+        return (g3["means3D"], g3["log_scales"], g3["quats"], g3["opacity"], g3["colors"].view_as(colors),
+                None, None, None, None, None)
+
+
+def render_gaussians(means3D, log_scales, quats, opacity, colors, cam, sh_degree: int, rast: Rasterizer,
+                     fwd_cfg: Optional[B.RenderCfg] = None, bwd_cfg: Optional[B.RenderCfg] = None):
+    """color, alpha, depth of the 3D Gaussians seen by `cam`, differentiable in
+    all five parameter tensors."""
+    fwd_cfg = fwd_cfg or B.make_cfg("pixel", 16, "cost")
+    bwd_cfg = bwd_cfg or fwd_cfg
+    return Render3DFn.apply(means3D, log_scales, quats, opacity, colors, cam, sh_degree, fwd_cfg, bwd_cfg, rast)

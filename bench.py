@@ -262,6 +262,29 @@ def main():
         print(f"[bench] static: {ms_s:.3f} ms/step, fwd {st_s['render_fwd']:.3f} ms, bwd {st_s['render_bwd']:.3f} ms",
               flush=True)
 
+    # supplementary: the projection's derivative on the same frame (the step before the hot path in a
+    # training step; not part of ms_per_step)
+    def project_bwd_ms():
+        P = scene.P
+        out = dict(means3D=torch.empty(P, 3, device=dev), log_scales=torch.empty(P, 3, device=dev),
+                   quats=torch.empty(P, 4, device=dev), opacity=torch.empty(P, device=dev),
+                   colors=torch.empty_like(g_in["colors"]))
+        run1 = lambda: B.bgs_project_bwd(cam, g_in["means3D"], g_in["log_scales"], g_in["quats"], g_in["colors"],
+                                         scene.sh_degree, grads["means2D"], grads["conic_opacity"], grads["rgb"],
+                                         grads["depth"], out)
+        run1()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            run1()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 10
+
+    pbwd_ms = project_bwd_ms()
+    print(f"[bench] project_bwd (supplementary): {pbwd_ms:.3f} ms", flush=True)
+
     # per-CU load balance of the render kernels: one traced run of each (untimed)
     def cu_balance(fcfg_, bcfg_):
         frame, rws = state["frame"], state["rws"]
@@ -370,6 +393,7 @@ def main():
         "stage_roofline": stage_roofs,
         "static": static,
         "cu_balance": {"tuned": balance, "static": balance_static},
+        "project_bwd_ms": pbwd_ms,
         "batched_views": batched,
         "speedup_vs_static": (None if static is None else
                               {"render_fwd": static["render_fwd_ms"] / stages["render_fwd"],

@@ -320,9 +320,11 @@ class Render3DFn(torch.autograd.Function):
     [P,K,3]); outputs color [3,H,W], alpha [H,W], depth [H,W]."""
 
     @staticmethod
-    def forward(ctx, means3D, log_scales, quats, opacity, colors, cam, sh_degree, fwd_cfg, bwd_cfg, rast):
+    def forward(ctx, means3D, log_scales, quats, opacity, colors, cam, sh_degree, fwd_cfg, bwd_cfg, rast,
+                prep=None):
         args = [t.detach().contiguous() for t in (means3D, log_scales, quats, opacity, colors)]
-        prep = rast.prepare(cam, *args, sh_degree)
+        if prep is None:  # else: prepared by the caller from these same parameters
+            prep = rast.prepare(cam, *args, sh_degree)
         out = rast.render_fwd(prep, fwd_cfg)
         ctx.save_for_backward(*args)
         ctx.prep, ctx.out, ctx.cam, ctx.sh_degree, ctx.bwd_cfg, ctx.rast = prep, out, cam, sh_degree, bwd_cfg, rast
@@ -338,7 +340,7 @@ class Render3DFn(torch.autograd.Function):
         g3 = rast.project_bwd(ctx.cam, means3D, log_scales, quats, colors, ctx.sh_degree, g2["means2D"],
                               g2["conic_opacity"], g2["rgb"], g2["depth"])
         return (g3["means3D"], g3["log_scales"], g3["quats"], g3["opacity"], g3["colors"].view_as(colors),
-                None, None, None, None, None)
+                None, None, None, None, None, None)
 
 
 def render_gaussians(means3D, log_scales, quats, opacity, colors, cam, sh_degree: int, rast: Rasterizer,
@@ -348,3 +350,33 @@ def render_gaussians(means3D, log_scales, quats, opacity, colors, cam, sh_degree
     fwd_cfg = fwd_cfg or B.make_cfg("pixel", 16, "cost")
     bwd_cfg = bwd_cfg or fwd_cfg
     return Render3DFn.apply(means3D, log_scales, quats, opacity, colors, cam, sh_degree, fwd_cfg, bwd_cfg, rast)
+
+
+def fit(params: dict, cameras, targets, sh_degree: int, rast: Rasterizer, iters: int, lr: float = 1e-2,
+        selector: Optional[AdaptiveSelector] = None, cfg: Optional[B.RenderCfg] = None):
+    """A plain training loop over the 3D Gaussian parameters (the setting of
+    the paper's self-adaptive kernel selection, Sec. 4.4): views are visited
+    in turn, the image loss is the mean squared error against `targets`, Adam
+    updates means3D / log_scales / quats / opacity / colors (opacity kept in
+    (0, 1)).  When a selector is given, it chooses the forward and backward
+    kernels from measurements every `selector.interval` iterations.  Returns
+    the per-iteration losses."""
+    keys = ("means3D", "log_scales", "quats", "opacity", "colors")
+    opt = torch.optim.Adam([params[k] for k in keys], lr=lr)
+    cfg = cfg or B.make_cfg("pixel", 16, "cost")
+    losses = []
+    for it in range(iters):
+        v = it % len(cameras)
+        cam = cameras[v]
+        with torch.no_grad():
+            prep = rast.prepare(cam, *[params[k].detach() for k in keys], sh_degree)
+        fcfg, bcfg = selector.select(prep) if selector is not None else (cfg, cfg)
+        color, _, _ = Render3DFn.apply(*[params[k] for k in keys], cam, sh_degree, fcfg, bcfg, rast, prep)
+        loss = torch.mean((color - targets[v]) ** 2)
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            params["opacity"].clamp_(1e-3, 0.999)
+        losses.append(float(loss.detach()))
+    return losses

@@ -140,12 +140,12 @@ def main():
                 B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], pl, ranges,
                                  n_dev, lws)
                 mark(2)
-                M = int(n_dev.item())  # the host needs M to size the frame (one sync, as in bgs_bin)
-                if M > rast.pair_capacity:
-                    raise RuntimeError("pair capacity exceeded")
                 mark(3)
                 mark(4)
-                plist = pl[:M]
+                # no host sync: the ranges address [0, M) of the whole buffer (all empty
+                # on overflow), and M is read once the steps are done
+                M = None
+                plist = pl
             else:
                 ws = rast.ws.get("bin", B.bgs_bin_workspace_bytes(P))
                 cap = rast.pair_capacity
@@ -176,6 +176,7 @@ def main():
                              grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], rws)
             mark(8)
             state["M"] = M
+            state["n_dev"] = n_dev
             state["frame_bufs"] = (ranges, plist)
             state["frame"] = frame
             state["rws"] = rws
@@ -209,10 +210,17 @@ def main():
             step(evs[k])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        names = ["project", "lists" if args.lists == "fused" else "bin", "host_sync" if args.lists == "fused" else "sort",
-                 "ranges", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"]
+        if state["M"] is None:  # the fused lists' pair count, checked after the steps
+            M = int(state["n_dev"].item())
+            if M > rast.pair_capacity:
+                raise RuntimeError("pair capacity exceeded")
+            state["M"] = M
+            state["frame_bufs"] = (state["frame_bufs"][0], state["frame_bufs"][1][:M])
+        names = ["project", "lists", "_", "_", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"] \
+            if args.lists == "fused" else \
+            ["project", "bin", "sort", "ranges", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"]
         stages = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
-                  for i, n in enumerate(names)}
+                  for i, n in enumerate(names) if n != "_"}
         return (t1 - t0) * 1e3 / steps, stages, state, pr, fwd, grads
 
     bg = tuple(scene.bg)

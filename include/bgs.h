@@ -219,12 +219,15 @@ size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P, 
  * ballot compaction, one workgroup per segment of 2048 coarse entries.
  *   point_list [capacity] Gaussian ids, ranges [n_tiles][2] (empty: (0, 0)),
  *   n_pairs_dev (DEVICE, uint64[1]) receives M.
- * Synchronizes the stream once (to size the coarse lists).  When M exceeds
- * capacity, point_list is not written and the caller must grow point_list
- * (and the workspace) and call again before rendering; when the
- * overflow is already visible at the coarse level the call returns
- * BGS_ECAPACITY with a lower bound of M in n_pairs_dev.  Tile grids of more
- * than 8192 groups return BGS_EUNSUPPORTED (use the three separate calls).
+ * Never synchronizes: every size the kernels need stays on the device and
+ * the grids are fixed by P and the image size.  When M exceeds capacity,
+ * point_list is not written, every range is written empty (0, 0), so a render
+ * of the frame reads nothing from point_list, and n_pairs_dev receives M, or
+ * a lower bound of M above capacity when the overflow shows already in the
+ * coarse lists (sized by the same capacity); the caller reads n_pairs_dev when
+ * convenient, grows point_list (and the workspace) and calls again.
+ * capacity must be < 2^32.  Tile grids of more than 8192 groups return
+ * BGS_EUNSUPPORTED (use the three separate calls).
  */
 bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
                           const int32_t* radius, const float* depth, const uint32_t* tiles_touched,

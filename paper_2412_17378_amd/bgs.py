@@ -288,9 +288,10 @@ def bgs_tile_lists_workspace_bytes(width: int, height: int, P: int, capacity: in
 
 def bgs_tile_lists(width, height, means2D, radius, depth, tiles_touched, point_list, ranges, n_pairs_dev, ws,
                    stream=None) -> bool:
-    """n_pairs_dev (int64 [>=1] device tensor) receives M (or a lower bound).
-    Returns False when the capacity was visibly too small (BGS_ECAPACITY);
-    the caller then compares n_pairs_dev with the capacity and grows."""
+    """Asynchronous: n_pairs_dev (int64 [>=1] device tensor) receives M, or a
+    lower bound of M above the capacity (point_list.numel()) on overflow, in
+    which case every range is empty; the caller compares n_pairs_dev with the
+    capacity when convenient and grows.  Returns False on BGS_ECAPACITY."""
     cap = 0 if point_list is None else point_list.numel()
     _expect(ranges, (n_tiles(width, height), 2), torch.int32, "ranges")
     st = lib().bgs_tile_lists(int(width), int(height), TILE, means2D.shape[0], _ptr(means2D), _ptr(radius),

@@ -8,6 +8,7 @@
 // Gaussians, P << M), so the M pairs only need a stable sort by tile id:
 // ceil(log2(n_tiles)) key bits (13 at 1080p) instead of 45.  The result is
 // the same list a (tile, depth, id) sort gives.
+#include <algorithm>
 #include <cstring>
 
 #include <rocprim/block/block_scan.hpp>
@@ -18,15 +19,208 @@
 
 namespace bgs {
 
-// depth keys of the Gaussians: positive fp32 depths order like their bit
-// patterns; Gaussians with no pairs go last.
-__global__ __launch_bounds__(256) void k_depth_keys(int64_t P, const float* __restrict__ depth,
-                                                    const uint32_t* __restrict__ tiles_touched,
-                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ ids) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    keys[i] = tiles_touched[i] ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
-    ids[i] = (uint32_t)i;
+// ----------------------------------------------------------------------
+// Depth order of the Gaussians: a stable sort of 32-bit keys (positive fp32
+// depths order like their bit patterns; Gaussians with no pairs get the
+// largest key and go last), so equal depths keep id order.  LSD radix sort,
+// four passes of 8 bits, over blocks of DS_TILE consecutive items (1024
+// threads; wave w of the block owns items [256 w, 256 w + 256), 64 at a
+// time).  Per pass: every block's digit histogram (the first one fused into
+// the key generation), an exclusive scan of each digit's counts over the
+// blocks, and a scatter in which each block ranks its items stably in LDS
+// (ballots over the 8 digit bits find the lanes with the same digit) and
+// writes them out as per-digit runs.  Grids depend on P alone and nothing is
+// cleared with a memset, so the sort can be captured into a graph.
+// ----------------------------------------------------------------------
+constexpr int DS_THREADS = 1024;
+constexpr int DS_WAVES = DS_THREADS / 64;
+constexpr int DS_TILE = DS_THREADS * 4;
+constexpr int DS_RADIX = 256;
+
+static inline int ds_blocks(int64_t P) { return (int)((P + DS_TILE - 1) / DS_TILE); }
+
+__device__ __forceinline__ int64_t ds_item(int j) {  // item j (0..3) of this lane, block-relative
+    return (int64_t)(threadIdx.x >> 6) * 256 + j * 64 + (threadIdx.x & 63);
+}
+
+// cnt[d * nb + b] = number of block b's items with digit d
+__device__ __forceinline__ void ds_hist_store(uint32_t* s_hist, uint32_t* __restrict__ cnt, int nb) {
+    __syncthreads();
+    if (threadIdx.x < DS_RADIX) cnt[(size_t)threadIdx.x * nb + blockIdx.x] = s_hist[threadIdx.x];
+}
+
+__global__ __launch_bounds__(DS_THREADS) void k_ds_keys(int64_t P, const float* __restrict__ depth,
+                                                        const uint32_t* __restrict__ tiles_touched,
+                                                        uint32_t* __restrict__ keys, uint32_t* __restrict__ ids,
+                                                        uint32_t* __restrict__ cnt, int nb) {
+    __shared__ uint32_t s_hist[DS_RADIX];
+    if (threadIdx.x < DS_RADIX) s_hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * DS_TILE;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = b0 + ds_item(j);
+        if (i < P) {
+            const uint32_t k = tiles_touched[i] ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
+            keys[i] = k;
+            ids[i] = (uint32_t)i;
+            atomicAdd(&s_hist[k & 0xFFu], 1u);
+        }
+    }
+    ds_hist_store(s_hist, cnt, nb);
+}
+
+__global__ __launch_bounds__(DS_THREADS) void k_ds_hist(int64_t P, const uint32_t* __restrict__ keys, int shift,
+                                                        uint32_t* __restrict__ cnt, int nb) {
+    __shared__ uint32_t s_hist[DS_RADIX];
+    if (threadIdx.x < DS_RADIX) s_hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * DS_TILE;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = b0 + ds_item(j);
+        if (i < P) atomicAdd(&s_hist[(keys[i] >> shift) & 0xFFu], 1u);
+    }
+    ds_hist_store(s_hist, cnt, nb);
+}
+
+// One workgroup per digit d: exclusive scan of cnt[d][0..nb) in place,
+// tot[d] = the digit's total.
+__global__ __launch_bounds__(256) void k_ds_colscan(int nb, uint32_t* __restrict__ cnt, uint32_t* __restrict__ tot) {
+    using Scan = rocprim::block_scan<uint32_t, 256>;
+    __shared__ typename Scan::storage_type s_scan;
+    uint32_t* c = cnt + (size_t)blockIdx.x * nb;
+    const int per = (nb + 255) / 256;
+    const int t0 = min(nb, (int)threadIdx.x * per), t1 = min(nb, t0 + per);
+    uint32_t sum = 0;
+    for (int t = t0; t < t1; ++t) sum += c[t];
+    uint32_t run = 0, total = 0;
+    Scan().exclusive_scan(sum, run, 0u, total, s_scan);
+    for (int t = t0; t < t1; ++t) {
+        const uint32_t v = c[t];
+        c[t] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
+// Block b's items go to keys_out / vals_out at base[d] + (rank among the
+// block's items of digit d), base[d] = (items with a smaller digit) + (items
+// of digit d in earlier blocks).  KEYS = false skips the key output (the last
+// pass only needs the values).
+template <bool KEYS>
+__global__ __launch_bounds__(DS_THREADS) void k_ds_scatter(int64_t P, const uint32_t* __restrict__ keys_in,
+                                                           const uint32_t* __restrict__ vals_in,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ vals_out, int shift,
+                                                           const uint32_t* __restrict__ cnt,
+                                                           const uint32_t* __restrict__ tot, int nb) {
+    using Scan = rocprim::block_scan<uint32_t, DS_THREADS>;
+    __shared__ typename Scan::storage_type s_scan;
+    __shared__ uint32_t s_wcnt[DS_WAVES][DS_RADIX];  // per-wave digit counts, then their offsets
+    __shared__ uint32_t s_keys[DS_TILE], s_vals[DS_TILE];
+    __shared__ uint32_t s_lstart[DS_RADIX], s_base[DS_RADIX];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < DS_WAVES * DS_RADIX; i += DS_THREADS) (&s_wcnt[0][0])[i] = 0u;
+    const int64_t b0 = (int64_t)blockIdx.x * DS_TILE;
+    const int n_valid = (int)min((int64_t)DS_TILE, P - b0);
+    uint32_t k[4], v[4], d[4], r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = b0 + ds_item(j);
+        k[j] = i < P ? keys_in[i] : 0u;
+        v[j] = i < P ? vals_in[i] : 0u;
+        d[j] = (k[j] >> shift) & 0xFFu;
+    }
+    __syncthreads();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool valid = ds_item(j) < n_valid;
+        uint64_t peers = ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (d[j] >> bit) & 1u;
+            const uint64_t bal = ballot(set);
+            peers &= set ? bal : ~bal;
+        }
+        // the wave's items so far with this digit, then this batch's earlier lanes
+        const uint32_t prior = valid ? s_wcnt[w][d[j]] : 0u;
+        r[j] = prior + (uint32_t)__builtin_popcountll(peers & lt);
+        if (valid && (peers & lt) == 0ull) s_wcnt[w][d[j]] = prior + (uint32_t)__builtin_popcountll(peers);
+    }
+    __syncthreads();
+    uint32_t nd = 0;  // the block's count of digit tid (tid < 256)
+    if (tid < DS_RADIX) {
+#pragma unroll
+        for (int ww = 0; ww < DS_WAVES; ++ww) {
+            const uint32_t c = s_wcnt[ww][tid];
+            s_wcnt[ww][tid] = nd;
+            nd += c;
+        }
+    }
+    uint32_t lstart = 0, dbase = 0, agg = 0;
+    Scan().exclusive_scan(nd, lstart, 0u, agg, s_scan);
+    __syncthreads();
+    Scan().exclusive_scan(tid < DS_RADIX ? tot[tid] : 0u, dbase, 0u, agg, s_scan);
+    if (tid < DS_RADIX) {
+        s_lstart[tid] = lstart;
+        s_base[tid] = dbase + cnt[(size_t)tid * nb + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (ds_item(j) < n_valid) {
+            const uint32_t pos = s_lstart[d[j]] + s_wcnt[w][d[j]] + r[j];
+            s_keys[pos] = k[j];
+            s_vals[pos] = v[j];
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < n_valid; i += DS_THREADS) {
+        const uint32_t kk = s_keys[i];
+        const uint32_t dd = (kk >> shift) & 0xFFu;
+        const uint32_t dest = s_base[dd] + (uint32_t)i - s_lstart[dd];
+        if (KEYS) keys_out[dest] = kk;
+        vals_out[dest] = s_vals[i];
+    }
+}
+
+// Sorted Gaussian ids into order[P]; keys / keys2 / ids2 [P] are scratch,
+// cnt [256 ds_blocks(P)] and tot [256] the histograms.
+static bgs_status depth_order(int64_t P, const float* depth, const uint32_t* tiles_touched, uint32_t* keys,
+                              uint32_t* order, uint32_t* keys2, uint32_t* ids2, uint32_t* cnt, uint32_t* tot,
+                              hipStream_t stream) {
+    if (P == 0) return BGS_OK;
+    const int nb = ds_blocks(P);
+    hipLaunchKernelGGL(k_ds_keys, dim3(nb), dim3(DS_THREADS), 0, stream, P, depth, tiles_touched, keys, order, cnt,
+                       nb);
+    BGS_HIP(hipGetLastError());
+    // (keys, order) -> (keys2, ids2) -> (keys, order) -> ... : four passes end in order
+    uint32_t* kin = keys;
+    uint32_t* vin = order;
+    uint32_t* kout = keys2;
+    uint32_t* vout = ids2;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        if (pass > 0) {
+            hipLaunchKernelGGL(k_ds_hist, dim3(nb), dim3(DS_THREADS), 0, stream, P, (const uint32_t*)kin, shift, cnt,
+                               nb);
+            BGS_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_ds_colscan, dim3(DS_RADIX), dim3(256), 0, stream, nb, cnt, tot);
+        BGS_HIP(hipGetLastError());
+        if (pass < 3)
+            hipLaunchKernelGGL(k_ds_scatter<true>, dim3(nb), dim3(DS_THREADS), 0, stream, P, (const uint32_t*)kin,
+                               (const uint32_t*)vin, kout, vout, shift, (const uint32_t*)cnt, (const uint32_t*)tot, nb);
+        else
+            hipLaunchKernelGGL(k_ds_scatter<false>, dim3(nb), dim3(DS_THREADS), 0, stream, P, (const uint32_t*)kin,
+                               (const uint32_t*)vin, kout, vout, shift, (const uint32_t*)cnt, (const uint32_t*)tot, nb);
+        BGS_HIP(hipGetLastError());
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    return BGS_OK;
 }
 
 __global__ __launch_bounds__(256) void k_gather_counts(int64_t P, const uint32_t* __restrict__ order,
@@ -111,15 +305,13 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
 static unsigned blocks_for(int64_t n, int threads = 256) { return (unsigned)((n + threads - 1) / threads); }
 
 struct BinLayout {
-    size_t keys, ids, keys2, order, counts, offsets, total, temp, temp_bytes, bytes;
+    size_t keys, ids, keys2, order, dcnt, dtot, counts, offsets, total, temp, temp_bytes, bytes;
 };
 
 static BinLayout bin_layout(int64_t P) {
     BinLayout L{};
     const size_t n = (size_t)(P > 0 ? P : 1);
-    size_t sort_bytes = 0, scan_bytes = 0;
-    (void)rocprim::radix_sort_pairs((void*)nullptr, sort_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                              (uint32_t*)nullptr, n, 0, 32);
+    size_t scan_bytes = 0;
     (void)rocprim::exclusive_scan((void*)nullptr, scan_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr, (uint64_t)0, n,
                             rocprim::plus<uint64_t>());
     size_t off = 0;
@@ -135,7 +327,9 @@ static BinLayout bin_layout(int64_t P) {
     L.counts = take(8 * n);
     L.offsets = take(8 * n);
     L.total = take(8);
-    L.temp_bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
+    L.dcnt = take(4 * (size_t)DS_RADIX * ds_blocks((int64_t)n));
+    L.dtot = take(4 * (size_t)DS_RADIX);
+    L.temp_bytes = scan_bytes;
     L.temp = take(L.temp_bytes);
     L.bytes = off;
     return L;
@@ -173,12 +367,14 @@ extern "C" bgs_status bgs_bin(int32_t width, int32_t height, int32_t tile, int64
     size_t temp_bytes = L.temp_bytes;
 
     const int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
-    hipLaunchKernelGGL(k_depth_keys, dim3(blocks_for(P)), dim3(256), 0, stream, P, depth, tiles_touched, dkeys, ids);
-    BGS_HIP(hipGetLastError());
-    BGS_HIP(rocprim::radix_sort_pairs(temp, temp_bytes, dkeys, dkeys2, ids, order, (size_t)P, 0, 32, stream));
+    {
+        const bgs_status st = depth_order(P, depth, tiles_touched, dkeys, order, dkeys2, ids,
+                                          reinterpret_cast<uint32_t*>(w + L.dcnt),
+                                          reinterpret_cast<uint32_t*>(w + L.dtot), stream);
+        if (st != BGS_OK) return st;
+    }
     hipLaunchKernelGGL(k_gather_counts, dim3(blocks_for(P)), dim3(256), 0, stream, P, order, tiles_touched, counts);
     BGS_HIP(hipGetLastError());
-    temp_bytes = L.temp_bytes;
     BGS_HIP(rocprim::exclusive_scan(temp, temp_bytes, counts, offsets, (uint64_t)0, (size_t)P,
                                     rocprim::plus<uint64_t>(), stream));
     hipLaunchKernelGGL(k_total, dim3(1), dim3(64), 0, stream, P, offsets, order, tiles_touched, total);
@@ -366,9 +562,14 @@ __global__ __launch_bounds__(256) void k_part_scan(int nb, int nt, uint32_t* __r
 // Single workgroup: exclusive scan of total -> start; ranges (empty: (0, 0));
 // the grand total in n_pairs[0].  Thread i owns the contiguous run
 // [i per, (i+1) per); the per-thread sums are scanned with a block scan.
+// Overflow: when coarse_n (nullable) exceeds coarse_cap, n_pairs[0] receives
+// coarse_n (a lower bound of the pair count); then, or when the total
+// exceeds cap, every range is written empty, so that nothing reads the
+// unwritten point list.
 __global__ __launch_bounds__(1024) void k_tile_scan(int nt, const uint32_t* __restrict__ total,
                                                     uint32_t* __restrict__ start, uint32_t* __restrict__ ranges,
-                                                    uint64_t* __restrict__ n_pairs) {
+                                                    uint64_t* __restrict__ n_pairs, const uint64_t* __restrict__ coarse_n,
+                                                    uint64_t coarse_cap, uint64_t cap) {
     using Scan = rocprim::block_scan<uint64_t, 1024>;
     __shared__ typename Scan::storage_type s_scan;
     const int per = (nt + 1023) / 1024;
@@ -377,13 +578,15 @@ __global__ __launch_bounds__(1024) void k_tile_scan(int nt, const uint32_t* __re
     for (int t = t0; t < t1; ++t) s += total[t];
     uint64_t run = 0, grand = 0;
     Scan().exclusive_scan(s, run, (uint64_t)0, grand, s_scan);
-    if (threadIdx.x == 0) n_pairs[0] = grand;
+    const bool coarse_over = coarse_n != nullptr && coarse_n[0] > coarse_cap;
+    if (threadIdx.x == 0) n_pairs[0] = coarse_over ? coarse_n[0] : grand;
+    const bool keep = !coarse_over && grand <= cap;
     for (int t = t0; t < t1; ++t) {
         const uint32_t n = total[t];
         start[t] = (uint32_t)run;
         if (ranges) {
-            ranges[2 * t] = n ? (uint32_t)run : 0u;
-            ranges[2 * t + 1] = n ? (uint32_t)(run + n) : 0u;
+            ranges[2 * t] = n && keep ? (uint32_t)run : 0u;
+            ranges[2 * t + 1] = n && keep ? (uint32_t)(run + n) : 0u;
         }
         run += n;
     }
@@ -419,8 +622,10 @@ __device__ __forceinline__ uint32_t spread_rows(uint32_t rows) {  // bit y -> bi
 
 __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, const uint32_t* __restrict__ order,
                                                    const uint2* __restrict__ rect, const uint32_t* __restrict__ base,
-                                                   uint2* __restrict__ coarse) {
+                                                   uint2* __restrict__ coarse, const uint64_t* __restrict__ coarse_n,
+                                                   uint64_t coarse_cap) {
     extern __shared__ uint32_t nextpos[];  // ng running slots
+    if (coarse_n[0] > coarse_cap) return;  // the coarse lists do not fit: nothing is written
     const int ng = GX * GY;
     const int lane = threadIdx.x;
     const int c = blockIdx.x;
@@ -484,16 +689,20 @@ __global__ __launch_bounds__(256) void k_seg_count(int ng, const uint32_t* __res
     if (g < ng) nseg[g] = (gtotal[g] + SEG - 1) / SEG;
 }
 
-// segmap[segstart[g] + s] = (g, s)
+// segmap[segstart[g] + s] = (g, s); nothing when the coarse lists overflowed
+// (the segment table is sized for coarse lists that fit)
 __global__ __launch_bounds__(256) void k_seg_map(int ng, const uint32_t* __restrict__ nseg,
-                                                 const uint32_t* __restrict__ segstart, uint2* __restrict__ segmap) {
+                                                 const uint32_t* __restrict__ segstart, uint2* __restrict__ segmap,
+                                                 const uint64_t* __restrict__ coarse_n, uint64_t coarse_cap,
+                                                 uint32_t max_segs) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ng) return;
+    if (g >= ng || coarse_n[0] > coarse_cap) return;
     const uint32_t n = nseg[g], b = segstart[g];
-    for (uint32_t q = 0; q < n; ++q) segmap[b + q] = make_uint2((uint32_t)g, q);
+    for (uint32_t q = 0; q < n && b + q < max_segs; ++q) segmap[b + q] = make_uint2((uint32_t)g, q);
 }
 
-// One workgroup per segment; wave w walks the contiguous quarter
+// A fixed grid of workgroups strides over the segments (the segment count
+// stays on the device); per segment, wave w walks the contiguous quarter
 // [e0 + w SEG/4, e0 + (w+1) SEG/4) of it, 64 entries at a time, and for each
 // of the group's 16 tiles (local index i = (x mod 4) + 4 (y mod 4)) takes
 // the ballot of the entries whose tile mask holds the tile.  Counts are
@@ -504,19 +713,13 @@ __global__ __launch_bounds__(256) void k_seg_map(int ng, const uint32_t* __restr
 // WRITE: append each such entry at segcnt[seg][i][w] (by then the slot where
 // that quarter's run of tile i starts) + the earlier entries of that run.
 constexpr int SUBSEG = SEG / 4;
+constexpr size_t SPLIT_GRID = 2048;  // workgroups of the split passes: 8 per CU
 
 template <bool WRITE>
-__global__ __launch_bounds__(256) void k_seg_split(const uint64_t* __restrict__ n_segs, const uint2* __restrict__ segmap,
-                                                   const uint2* __restrict__ coarse,
-                                                   const uint32_t* __restrict__ gstart,
-                                                   const uint32_t* __restrict__ gtotal, uint32_t* __restrict__ segcnt,
-                                                   uint32_t* __restrict__ point_list, const uint64_t* __restrict__ n_pairs,
-                                                   uint64_t capacity) {
-    const uint32_t sidx = blockIdx.x;
-    if (sidx >= n_segs[0]) return;
-    // the pair count is final here; a list that does not fit is not written
-    // at all (the caller grows the buffer and builds again)
-    if (WRITE && n_pairs[0] > capacity) return;
+__device__ __forceinline__ void split_segment(uint32_t sidx, const uint2* __restrict__ segmap,
+                                              const uint2* __restrict__ coarse, const uint32_t* __restrict__ gstart,
+                                              const uint32_t* __restrict__ gtotal, uint32_t* __restrict__ segcnt,
+                                              uint32_t* __restrict__ point_list) {
     const uint2 gs = segmap[sidx];
     const int grp = (int)gs.x;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -553,19 +756,42 @@ __global__ __launch_bounds__(256) void k_seg_split(const uint64_t* __restrict__ 
     }
 }
 
+template <bool WRITE>
+__global__ __launch_bounds__(256) void k_seg_split(const uint64_t* __restrict__ n_segs, const uint2* __restrict__ segmap,
+                                                   const uint2* __restrict__ coarse,
+                                                   const uint32_t* __restrict__ gstart,
+                                                   const uint32_t* __restrict__ gtotal, uint32_t* __restrict__ segcnt,
+                                                   uint32_t* __restrict__ point_list, const uint64_t* __restrict__ n_pairs,
+                                                   uint64_t capacity, const uint64_t* __restrict__ coarse_n,
+                                                   uint64_t coarse_cap, uint32_t max_segs) {
+    if (coarse_n[0] > coarse_cap) return;  // no coarse lists to split
+    // the pair count is final here; a list that does not fit is not written
+    // at all (the caller grows the buffer and builds again)
+    if (WRITE && n_pairs[0] > capacity) return;
+    const uint32_t nsg = (uint32_t)min(n_segs[0], (uint64_t)max_segs);
+    for (uint32_t sidx = blockIdx.x; sidx < nsg; sidx += gridDim.x) split_segment<WRITE>(sidx, segmap, coarse, gstart,
+                                                                                        gtotal, segcnt, point_list);
+}
+
 // One thread per (group, local tile i).  OFFSETS = false: ttotal[tile] = sum
 // of the tile's segment counts.  OFFSETS = true: the counts become the
-// tile's slot at the start of each segment's run (from tstart).
+// tile's slot at the start of each segment's run (from tstart).  After a
+// coarse overflow there are no segments: every tile total is zero.
 template <bool OFFSETS>
 __global__ __launch_bounds__(256) void k_seg_scan(int TX, int TY, int GX, int ng, const uint32_t* __restrict__ nseg,
                                                   const uint32_t* __restrict__ segstart, uint32_t* __restrict__ segcnt,
-                                                  const uint32_t* __restrict__ tstart, uint32_t* __restrict__ ttotal) {
+                                                  const uint32_t* __restrict__ tstart, uint32_t* __restrict__ ttotal,
+                                                  const uint64_t* __restrict__ coarse_n, uint64_t coarse_cap) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= ng * 16) return;
     const int grp = idx >> 4, li = idx & 15;
     const int tx = (grp % GX) * GTILES + (li % GTILES), ty = (grp / GX) * GTILES + (li / GTILES);
     if (tx >= TX || ty >= TY) return;
     const int tile = ty * TX + tx;
+    if (coarse_n[0] > coarse_cap) {
+        if (!OFFSETS) ttotal[tile] = 0u;
+        return;
+    }
     const uint32_t n = nseg[grp], b = segstart[grp];
     uint32_t run = OFFSETS ? tstart[tile] : 0u;
     for (uint32_t q = 0; q < n; ++q) {
@@ -578,8 +804,8 @@ __global__ __launch_bounds__(256) void k_seg_scan(int TX, int TY, int GX, int ng
 }
 
 struct ListsLayout {
-    size_t dkeys, ids, dkeys2, order, rect, h, part, gtotal, gstart, nseg, segstart, nsegs, coarse_cap, coarse, ttotal,
-        tstart, temp, temp_bytes, bytes;
+    size_t dkeys, ids, dkeys2, order, rect, h, part, gtotal, gstart, nseg, segstart, nsegs, mg, coarse_cap, coarse, ttotal,
+        tstart, dcnt, dtot, bytes;
     size_t max_segs, segmap, segcnt;
     int C, nb, GX, GY, ng, nt;
 };
@@ -596,9 +822,6 @@ static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P, size_t
     L.ng = L.GX * L.GY;
     L.C = (int)((n + CHUNK - 1) / CHUNK);
     L.nb = (L.C + PART - 1) / PART;
-    size_t sort_bytes = 0;
-    (void)rocprim::radix_sort_pairs((void*)nullptr, sort_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                    (uint32_t*)nullptr, (uint32_t*)nullptr, n, 0, 32);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -617,6 +840,7 @@ static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P, size_t
     L.nseg = take(4 * (size_t)L.ng);
     L.segstart = take(4 * (size_t)L.ng);
     L.nsegs = take(8);
+    L.mg = take(8);
     L.ttotal = take(4 * (size_t)L.nt);
     L.tstart = take(4 * (size_t)L.nt);
     L.coarse_cap = coarse_cap;
@@ -625,8 +849,8 @@ static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P, size_t
     L.max_segs = coarse_cap / SEG + (size_t)L.ng + 1;
     L.segmap = take(8 * L.max_segs);
     L.segcnt = take(4 * 64 * L.max_segs);  // 16 counts per (segment, wave)
-    L.temp_bytes = sort_bytes;
-    L.temp = take(sort_bytes);
+    L.dcnt = take(4 * (size_t)DS_RADIX * ds_blocks((int64_t)n));
+    L.dtot = take(4 * (size_t)DS_RADIX);
     L.bytes = off;
     return L;
 }
@@ -649,6 +873,7 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
     if (tile != TILE) return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: only 16x16 tiles are supported");
     BGS_REQUIRE(ranges && n_pairs_dev, "bgs_tile_lists: null ranges or n_pairs");
     BGS_REQUIRE(P < ((int64_t)1 << 31), "bgs_tile_lists: P must be < 2^31");
+    BGS_REQUIRE(capacity < ((int64_t)1 << 32), "bgs_tile_lists: capacity must be < 2^32 (32-bit list offsets)");
     const int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
     const ListsLayout L = lists_layout(width, height, P, (size_t)capacity);
     if (L.ng > MAX_GROUPS || (size_t)(L.GX + 1) * (L.GY + 1) * sizeof(int) > 65536 || TX > 65535 || TY > 65535)
@@ -678,10 +903,12 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
         BGS_HIP(hipGetLastError());
         return BGS_OK;
     }
-    size_t temp_bytes = L.temp_bytes;
-    hipLaunchKernelGGL(k_depth_keys, dim3(blocks_for(P)), dim3(256), 0, stream, P, depth, tiles_touched, dkeys, ids);
-    BGS_HIP(hipGetLastError());
-    BGS_HIP(rocprim::radix_sort_pairs(w + L.temp, temp_bytes, dkeys, dkeys2, ids, order, (size_t)P, 0, 32, stream));
+    {
+        const bgs_status st = depth_order(P, depth, tiles_touched, dkeys, order, dkeys2, ids,
+                                          reinterpret_cast<uint32_t*>(w + L.dcnt),
+                                          reinterpret_cast<uint32_t*>(w + L.dtot), stream);
+        if (st != BGS_OK) return st;
+    }
     hipLaunchKernelGGL(k_rects, dim3(blocks_for(P)), dim3(256), 0, stream, P, TX, TY, means2D, radius, tiles_touched,
                        rect);
     BGS_HIP(hipGetLastError());
@@ -694,21 +921,18 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_part_scan, dim3((unsigned)((L.ng + 3) / 4)), dim3(256), 0, stream, L.nb, L.ng, part, gtotal);
     BGS_HIP(hipGetLastError());
-    // the group scan reuses n_pairs_dev[0] for the coarse total; it is
-    // overwritten by the tile scan below
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.ng, gtotal, gstart, (uint32_t*)nullptr,
-                       n_pairs_dev);
+    // the coarse total Mg stays on the device; every later kernel checks it
+    // against the coarse capacity, so the call never waits for the GPU
+    auto* mg = reinterpret_cast<uint64_t*>(w + L.mg);
+    const uint64_t ccap = (uint64_t)L.coarse_cap, pcap = (uint64_t)capacity;
+    const uint64_t no_cap = ~(uint64_t)0;
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.ng, gtotal, gstart, (uint32_t*)nullptr, mg,
+                       (const uint64_t*)nullptr, no_cap, no_cap);
     BGS_HIP(hipGetLastError());
-    uint64_t Mg = 0;
-    BGS_HIP(hipMemcpyAsync(&Mg, n_pairs_dev, sizeof(Mg), hipMemcpyDeviceToHost, stream));
-    BGS_HIP(hipStreamSynchronize(stream));
-    if (Mg > L.coarse_cap)  // then M >= Mg > capacity as well; n_pairs_dev holds the lower bound Mg
-        return fail(BGS_ECAPACITY, "bgs_tile_lists: at least " + std::to_string(Mg) + " pairs exceed capacity " +
-                                       std::to_string(capacity));
     hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(nbg)), dim3(256), 0, stream, L.C, L.ng, gstart, part, h);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_chunk_emit, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX, L.GY,
-                       order, rect, h, coarse);
+                       order, rect, h, coarse, (const uint64_t*)mg, ccap);
     BGS_HIP(hipGetLastError());
     // fine (tile) lists, on segments of the coarse lists
     auto* nseg = reinterpret_cast<uint32_t*>(w + L.nseg);
@@ -716,33 +940,34 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
     auto* nsegs = reinterpret_cast<uint64_t*>(w + L.nsegs);
     auto* segmap = reinterpret_cast<uint2*>(w + L.segmap);
     auto* segcnt = reinterpret_cast<uint32_t*>(w + L.segcnt);
-    const size_t grid_segs = (size_t)(Mg / SEG) + (size_t)L.ng;  // >= the real segment count
-    if (grid_segs > L.max_segs) return fail(BGS_EINTERNAL, "bgs_tile_lists: segment table overflow");
+    const uint32_t max_segs = (uint32_t)L.max_segs;
+    const unsigned grid_split = (unsigned)std::min<size_t>(L.max_segs, SPLIT_GRID);
     hipLaunchKernelGGL(k_seg_count, dim3(blocks_for(L.ng)), dim3(256), 0, stream, L.ng, gtotal, nseg);
     BGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.ng, nseg, segstart, (uint32_t*)nullptr, nsegs);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.ng, nseg, segstart, (uint32_t*)nullptr, nsegs,
+                       (const uint64_t*)nullptr, no_cap, no_cap);
     BGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_seg_map, dim3(blocks_for(L.ng)), dim3(256), 0, stream, L.ng, nseg, segstart, segmap);
+    hipLaunchKernelGGL(k_seg_map, dim3(blocks_for(L.ng)), dim3(256), 0, stream, L.ng, nseg, segstart, segmap,
+                       (const uint64_t*)mg, ccap, max_segs);
     BGS_HIP(hipGetLastError());
-    if (grid_segs > 0) {
-        hipLaunchKernelGGL(k_seg_split<false>, dim3((unsigned)grid_segs), dim3(256), 0, stream, nsegs, segmap,
-                           coarse,
-                           gstart, gtotal, segcnt, (uint32_t*)nullptr, (const uint64_t*)nullptr, (uint64_t)0);
-        BGS_HIP(hipGetLastError());
-    }
+    hipLaunchKernelGGL(k_seg_split<false>, dim3(grid_split), dim3(256), 0, stream, nsegs, segmap, coarse, gstart,
+                       gtotal, segcnt, (uint32_t*)nullptr, (const uint64_t*)nullptr, (uint64_t)0, (const uint64_t*)mg,
+                       ccap, max_segs);
+    BGS_HIP(hipGetLastError());
     const int n_gt = L.ng * 16;
     hipLaunchKernelGGL(k_seg_scan<false>, dim3(blocks_for(n_gt)), dim3(256), 0, stream, TX, TY, L.GX, L.ng, nseg,
-                       segstart, segcnt, (const uint32_t*)nullptr, ttotal);
+                       segstart, segcnt, (const uint32_t*)nullptr, ttotal, (const uint64_t*)mg, ccap);
     BGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.nt, ttotal, tstart, ranges, n_pairs_dev);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.nt, ttotal, tstart, ranges, n_pairs_dev,
+                       (const uint64_t*)mg, ccap, pcap);
     BGS_HIP(hipGetLastError());
-    if (capacity > 0 && grid_segs > 0) {
+    if (capacity > 0) {
         hipLaunchKernelGGL(k_seg_scan<true>, dim3(blocks_for(n_gt)), dim3(256), 0, stream, TX, TY, L.GX, L.ng, nseg,
-                           segstart, segcnt, tstart, (uint32_t*)nullptr);
+                           segstart, segcnt, tstart, (uint32_t*)nullptr, (const uint64_t*)mg, ccap);
         BGS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_seg_split<true>, dim3((unsigned)grid_segs), dim3(256), 0, stream, nsegs, segmap,
-                           coarse,
-                           gstart, gtotal, segcnt, point_list, n_pairs_dev, (uint64_t)capacity);
+        hipLaunchKernelGGL(k_seg_split<true>, dim3(grid_split), dim3(256), 0, stream, nsegs, segmap, coarse, gstart,
+                           gtotal, segcnt, point_list, (const uint64_t*)n_pairs_dev, pcap, (const uint64_t*)mg, ccap,
+                           max_segs);
         BGS_HIP(hipGetLastError());
     }
     return BGS_OK;

@@ -117,3 +117,41 @@ def test_lists_end_to_end(rast, name):
                 mism |= {x for x, y in zip(a, b) if x != y}
     unexplained = [m for m in mism if not flag[m]]
     assert not unexplained, unexplained[:10]
+
+
+@pytest.mark.parametrize("name", ["0", "tiny-300"])
+def test_fused_lists_overflow(rast, name):
+    """A capacity below M: the call returns without waiting, writes nothing to
+    the point list, writes every range empty and puts M (overflow of the tile
+    lists) or a lower bound of M above the capacity (overflow already of the
+    coarse lists) in n_pairs; the same buffers with capacity M then hold the
+    oracle's lists."""
+    from paper_2412_17378_amd import bgs as B
+    s = _scene(name)
+    cam = s.cameras[0]
+    W, H = cam.width, cam.height
+    pr = rast.project(cam, s.means3D, s.log_scales, s.quats, s.opacity, s.colors, s.sh_degree)
+    torch.cuda.synchronize()
+    ob = oracle.bin_sort_ranges(W, H, to_np(pr["means2D"]), to_np(pr["radius"]), to_np(pr["depth"]))
+    M = int(ob["n_pairs"])
+    assert M > 8
+    dev = torch.device("cuda")
+    n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+    ranges = torch.full((B.n_tiles(W, H), 2), 7, dtype=torch.int32, device=dev)
+    for cap in (M - 1, M // 8, 1, M):
+        print(f"[lists-overflow] case={name} M={M} capacity={cap}", flush=True)
+        pl = torch.full((cap,), -5, dtype=torch.int32, device=dev)
+        ws = torch.empty(B.bgs_tile_lists_workspace_bytes(W, H, s.P, cap), dtype=torch.uint8, device=dev)
+        B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], pl, ranges, n_dev, ws)
+        torch.cuda.synchronize()
+        n = int(n_dev.item())
+        if cap < M:
+            assert cap < n <= M, (cap, n, M)
+            if cap == M - 1:
+                assert n == M
+            assert bool(torch.all(pl == -5))
+            assert bool(torch.all(ranges == 0))
+        else:
+            assert n == M
+            np.testing.assert_array_equal(to_np(pl), ob["point_list"])
+            np.testing.assert_array_equal(to_np(ranges), ob["ranges"])

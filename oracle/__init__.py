@@ -50,6 +50,12 @@ def lib():
         L.orc_project_bwd.restype = C.c_int
         L.orc_bin.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, vp]
         L.orc_bin.restype = i64
+        L.orc_bin_exact.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, vp, vp]
+        L.orc_bin_exact.restype = i64
+        L.orc_rect_min_q.argtypes = [C.c_double] * 7
+        L.orc_rect_min_q.restype = C.c_double
+        L.orc_bin_q_limit.argtypes = [C.c_double]
+        L.orc_bin_q_limit.restype = C.c_double
         L.orc_sort.argtypes = [i64, vp, vp, vp]
         L.orc_sort.restype = C.c_int
         L.orc_ranges.argtypes = [i64, vp, i32, vp]
@@ -147,17 +153,38 @@ def n_tiles(width: int, height: int, tile: int = TILE) -> int:
     return ((width + tile - 1) // tile) * ((height + tile - 1) // tile)
 
 
-def bin_pairs(width, height, means2D, radius, tile: int = TILE, window: Optional[Sequence[int]] = None):
-    """(tile id, Gaussian id) pairs in input order, unsorted."""
+def bin_pairs(width, height, means2D, radius, tile: int = TILE, window: Optional[Sequence[int]] = None,
+              conic_opacity=None):
+    """(tile id, Gaussian id) pairs in input order, unsorted.  With
+    conic_opacity [P,4] the exact ellipse-tile rule filters the square rule's
+    pairs (orc_bin_exact)."""
     m2, r = _f64(means2D), _i32(radius)
     P = int(r.shape[0])
     win = None if window is None else _i32(window)
-    M = lib().orc_bin(width, height, tile, P, _p(m2), _p(r), _p(win), None, None)
+    if conic_opacity is None:
+        def run(t, g):
+            return lib().orc_bin(width, height, tile, P, _p(m2), _p(r), _p(win), t, g)
+    else:
+        co = _f64(conic_opacity)
+
+        def run(t, g):
+            return lib().orc_bin_exact(width, height, tile, P, _p(m2), _p(r), _p(co), _p(win), t, g)
+    M = run(None, None)
     tid = np.zeros(max(M, 1), np.int32)
     gid = np.zeros(max(M, 1), np.int32)
-    M2 = lib().orc_bin(width, height, tile, P, _p(m2), _p(r), _p(win), _p(tid), _p(gid))
+    M2 = run(_p(tid), _p(gid))
     assert M == M2
     return tid[:M].copy(), gid[:M].copy()
+
+
+def rect_min_q(a, b, c, lx, hx, ly, hy) -> float:
+    """min of a x^2 + 2 b x y + c y^2 over [lx, hx] x [ly, hy]."""
+    return float(lib().orc_rect_min_q(a, b, c, lx, hx, ly, hy))
+
+
+def bin_q_limit(opacity) -> float:
+    """Upper bound on q of the exact binning rule (negative: never blends)."""
+    return float(lib().orc_bin_q_limit(float(opacity)))
 
 
 def sort_pairs(tile_ids, gauss_ids, depth):
@@ -176,8 +203,8 @@ def ranges(sorted_tile_ids, n_tiles_: int):
     return out
 
 
-def bin_sort_ranges(width, height, means2D, radius, depth, tile: int = TILE, window=None) -> dict:
-    tid, gid = bin_pairs(width, height, means2D, radius, tile, window)
+def bin_sort_ranges(width, height, means2D, radius, depth, tile: int = TILE, window=None, conic_opacity=None) -> dict:
+    tid, gid = bin_pairs(width, height, means2D, radius, tile, window, conic_opacity)
     tid, gid = sort_pairs(tid, gid, depth)
     return dict(tile_ids=tid, point_list=gid, ranges=ranges(tid, n_tiles(width, height, tile)),
                 n_pairs=int(tid.shape[0]))

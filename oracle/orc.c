@@ -15,6 +15,12 @@
  *   orc_bin          the (tile, Gaussian) pairs: a Gaussian is listed in every
  *                    16x16 tile that its screen square [u-r, u+r] x [v-r, v+r]
  *                    meets.
+ *   orc_bin_exact    the same pairs, keeping a tile only when its pixel-centre
+ *                    rectangle meets the ellipse inside which the Gaussian's
+ *                    alpha can reach 1/255 (exact ellipse-tile binning, the
+ *                    list-shrinking refinement of the tile rule that the paper
+ *                    lists among related work); all other pairs are skipped by
+ *                    Eq. (4)'s rules at every pixel of their tile.
  *   orc_sort         order the pairs by (tile, view depth); equal depths keep
  *                    the input order (Eq. (4) blends "N-sorted" Gaussians).
  *   orc_ranges       per-tile [start, end) into the sorted list.
@@ -531,6 +537,86 @@ int64_t orc_bin(int32_t width, int32_t height, int32_t tile, int64_t P, const do
             for (int tx = rc[0]; tx <= rc[2]; ++tx) {
                 if (window && (tx < window[0] || ty < window[1] || tx >= window[2] || ty >= window[3]))
                     continue;
+                if (tile_ids) {
+                    tile_ids[m] = ty * TX + tx;
+                    gauss_ids[m] = (int32_t)i;
+                }
+                ++m;
+            }
+    }
+    return m;
+}
+
+/*
+ * Minimum of q(x, y) = a x^2 + 2 b x y + c y^2 (a > 0, a c - b^2 > 0) over the
+ * rectangle [lx, hx] x [ly, hy].  q is convex with its minimum 0 at the
+ * origin, so the value is 0 when the rectangle holds the origin and
+ * otherwise the least of the four edge minima; along an edge q is a convex
+ * quadratic in one variable, minimised at its stationary point clamped to the
+ * edge.
+ */
+static double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+double orc_rect_min_q(double a, double b, double c, double lx, double hx, double ly, double hy)
+{
+    if (lx <= 0.0 && hx >= 0.0 && ly <= 0.0 && hy >= 0.0) return 0.0;
+    double best = INFINITY;
+    const double xs[2] = {lx, hx}, ys[2] = {ly, hy};
+    for (int k = 0; k < 2; ++k) {
+        const double x = xs[k], y = clampd(-b * x / c, ly, hy);      /* edge x = const */
+        const double qx = a * x * x + 2.0 * b * x * y + c * y * y;
+        const double y2 = ys[k], x2 = clampd(-b * y2 / a, lx, hx);  /* edge y = const */
+        const double qy = a * x2 * x2 + 2.0 * b * x2 * y2 + c * y2 * y2;
+        if (qx < best) best = qx;
+        if (qy < best) best = qy;
+    }
+    return best;
+}
+
+/*
+ * The exact binning rule.  A pixel at offset d from the mean is blended only
+ * when o exp(-q(d)/2) >= 1/255 (alpha below 1/255 is skipped), i.e. when
+ * q(d) <= 2 ln(255 o).  The rule keeps a tile when q <= that bound plus
+ * 2^-10 (relative and absolute) somewhere on the tile's rectangle of pixel
+ * centres widened by 2^-6 px on every side; the widenings only add tiles.
+ */
+static const double BIN_Q_SLACK = 1.0 / 1024.0;
+static const double BIN_PX_SLACK = 1.0 / 64.0;
+
+double orc_bin_q_limit(double opacity)
+{
+    if (!(opacity > 0.0)) return -1.0;
+    const double tau = 2.0 * log(opacity / thr_alpha_min());
+    return tau * (1.0 + BIN_Q_SLACK) + BIN_Q_SLACK;
+}
+
+static int exact_keep(double u, double v, const double *co, int tx, int ty, int32_t tile)
+{
+    const double a = co[0], b = co[1], c = co[2];
+    const double lim = orc_bin_q_limit(co[3]);
+    if (lim < 0.0) return 0;
+    if (!(a > 0.0 && c > 0.0 && a * c - b * b > 0.0)) return 1; /* not an ellipse: keep the square rule */
+    const double lx = (double)tx * tile - BIN_PX_SLACK - u, hx = (double)tx * tile + (tile - 1) + BIN_PX_SLACK - u;
+    const double ly = (double)ty * tile - BIN_PX_SLACK - v, hy = (double)ty * tile + (tile - 1) + BIN_PX_SLACK - v;
+    return orc_rect_min_q(a, b, c, lx, hx, ly, hy) <= lim;
+}
+
+/* orc_bin restricted by the exact rule; conic_opacity [P][4] = (a, b, c, o). */
+int64_t orc_bin_exact(int32_t width, int32_t height, int32_t tile, int64_t P, const double *means2D,
+                      const int32_t *radius, const double *conic_opacity, const int32_t *window,
+                      int32_t *tile_ids, int32_t *gauss_ids)
+{
+    int TX = tiles_x(width, tile), TY = tiles_y(height, tile);
+    int64_t m = 0;
+    for (int64_t i = 0; i < P; ++i) {
+        int rc[4];
+        const double u = means2D[2 * i], v = means2D[2 * i + 1];
+        if (!tile_rect(u, v, radius[i], TX, TY, tile, rc)) continue;
+        for (int ty = rc[1]; ty <= rc[3]; ++ty)
+            for (int tx = rc[0]; tx <= rc[2]; ++tx) {
+                if (window && (tx < window[0] || ty < window[1] || tx >= window[2] || ty >= window[3]))
+                    continue;
+                if (!exact_keep(u, v, conic_opacity + 4 * i, tx, ty, tile)) continue;
                 if (tile_ids) {
                     tile_ids[m] = ty * TX + tx;
                     gauss_ids[m] = (int32_t)i;

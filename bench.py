@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--lists", default="fused", choices=["fused", "sort"],
                     help="tile lists by the fused counting pass or by bin + radix sort + ranges")
     ap.add_argument("--no-static", action="store_true", help="skip the static-kernel comparison")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the run with exact ellipse-tile binning (bgs_tile_lists_exact)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", default="720,360,1200,600",
                     help="pixel window x0,y0,x1,y1 of the oracle's CPU sample")
@@ -103,11 +105,13 @@ def main():
     g_in = {k: torch.from_numpy(getattr(scene, k)).to(dev).contiguous()
             for k in ("means3D", "log_scales", "quats", "opacity", "colors")}
     dL_dcolor = torch.from_numpy(scene.upstream()["dL_dcolor"]).to(dev).contiguous()
-    rast = Rasterizer(dev, reuse_pairs=True)
+    # one rasterizer (own list buffers) per tile rule
+    rasts = {"square": Rasterizer(dev, reuse_pairs=True), "ellipse": Rasterizer(dev, reuse_pairs=True)}
     stream = torch.cuda.current_stream()
 
-    def make_step(fcfg, bcfg):
+    def make_step(fcfg, bcfg, binning="square"):
         cfg, bcfg_ = fcfg, bcfg
+        rast = rasts[binning]
         cfg_ready = B.make_cfg(fcfg.variant, fcfg.subtile, fcfg.order, tuple(scene.bg), flags=B.FLAG_QUEUE_READY)
         bcfg_ready = B.make_cfg(bcfg.variant, bcfg.subtile, bcfg.order, tuple(scene.bg), flags=B.FLAG_QUEUE_READY)
         nt = B.n_tiles(W, H)
@@ -123,7 +127,10 @@ def main():
                      rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
         ranges = torch.empty(nt, 2, dtype=torch.int32, device=dev)
         n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
-        state = {}
+        conic = pr["conic_opacity"] if binning == "ellipse" else None
+        if conic is not None and args.lists != "fused":
+            raise SystemExit("exact ellipse-tile binning needs --lists fused")
+        state = {"rast": rast}
 
         def step(ev=None):
             def mark(i):
@@ -138,7 +145,7 @@ def main():
                 lws = rast.ws.get("lists", B.bgs_tile_lists_workspace_bytes(W, H, P, rast.pair_capacity))
                 pl = rast.ws.get("svals", 4 * rast.pair_capacity).view(torch.int32)[:rast.pair_capacity]
                 B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], pl, ranges,
-                                 n_dev, lws)
+                                 n_dev, lws, conic_opacity=conic)
                 mark(2)
                 mark(3)
                 mark(4)
@@ -191,15 +198,15 @@ def main():
             lws0 = rast.ws.get("lists", B.bgs_tile_lists_workspace_bytes(W, H, P, cap))
             pl0 = rast.ws.get("svals", 4 * cap).view(torch.int32)[:cap]
             B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
-                             pl0 if cap else None, ranges, n_dev, lws0)
+                             pl0 if cap else None, ranges, n_dev, lws0, conic_opacity=conic)
             need = int(n_dev.item())
             if need <= cap:
                 break
             rast.pair_capacity = need
         return step, state, pr, fwd, grads
 
-    def run(fcfg, bcfg, steps, warmup):
-        step, state, pr, fwd, grads = make_step(fcfg, bcfg)
+    def run(fcfg, bcfg, steps, warmup, binning="square"):
+        step, state, pr, fwd, grads = make_step(fcfg, bcfg, binning)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -212,7 +219,7 @@ def main():
         t1 = time.perf_counter()
         if state["M"] is None:  # the fused lists' pair count, checked after the steps
             M = int(state["n_dev"].item())
-            if M > rast.pair_capacity:
+            if M > state["rast"].pair_capacity:
                 raise RuntimeError("pair capacity exceeded")
             state["M"] = M
             state["frame_bufs"] = (state["frame_bufs"][0], state["frame_bufs"][1][:M])
@@ -269,6 +276,28 @@ def main():
         static = dict(ms_per_step=ms_s, render_fwd_ms=st_s["render_fwd"], render_bwd_ms=st_s["render_bwd"])
         print(f"[bench] static: {ms_s:.3f} ms/step, fwd {st_s['render_fwd']:.3f} ms, bwd {st_s['render_bwd']:.3f} ms",
               flush=True)
+
+    # the same step with exact ellipse-tile binning: identical images from shorter lists.  Its blends
+    # are the entries its own pixel loops examine (fewer: the removed entries were all skipped), so
+    # its value is not the headline's (which counts on the square rule's lists).
+    exact = None
+    if not args.no_exact and args.lists == "fused":
+        print("[bench] exact ellipse-tile binning run", flush=True)
+        ms_e, st_e, state_e, _, fwd_e, _ = run(fcfg, bcfg, args.steps, args.warmup, binning="ellipse")
+        rg_e, pl_e = state_e["frame_bufs"][0].cpu().numpy(), state_e["frame_bufs"][1].cpu().numpy()
+        of_e = oracle.render_fwd(W, H, rg_e, pl_e, m2, co, rgb, dep, bg=scene.bg)
+        fb_e, bb_e = int(of_e["blends"]), int(of_e["n_contrib"].astype(np.int64).sum())
+        agree_e = float(np.mean(fwd_e["n_contrib"].cpu().numpy() == of_e["n_contrib"]))
+        del of_e
+        same = all(torch.equal(fwd[k], fwd_e[k]) for k in ("color", "alpha", "depth", "final_T"))
+        diff = max(float((fwd[k] - fwd_e[k]).abs().max()) for k in ("color", "alpha", "depth", "final_T"))
+        exact = {"n_pairs": state_e["M"], "ms_per_step": ms_e, "stages_ms": st_e,
+                 "blends": {"fwd": fb_e, "bwd": bb_e}, "value": (fb_e + bb_e) / (ms_e * 1e-3),
+                 "unit": "examined blends/s", "images_equal_square_rule": same, "max_abs_image_diff": diff,
+                 "n_contrib_agreement_oracle": agree_e, "step_speedup_vs_square_rule": ms_step / ms_e}
+        print(f"[bench] exact binning: {ms_e:.3f} ms/step ({ms_step / ms_e:.2f}x), M={state_e['M']}, stages " +
+              ", ".join(f"{k}={v:.3f}" for k, v in st_e.items()) +
+              f"; blends fwd={fb_e} bwd={bb_e}; images equal: {same}", flush=True)
 
     # supplementary: the projection's derivative on the same frame (the step before the hot path in a
     # training step; not part of ms_per_step)
@@ -400,6 +429,7 @@ def main():
         "render_roofline": render_roofs,
         "stage_roofline": stage_roofs,
         "static": static,
+        "exact_binning": exact,
         "cu_balance": {"tuned": balance, "static": balance_static},
         "project_bwd_ms": pbwd_ms,
         "batched_views": batched,

@@ -234,6 +234,30 @@ bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P
                           uint32_t* point_list, int64_t capacity, uint32_t* ranges, uint64_t* n_pairs_dev, void* ws,
                           size_t ws_bytes, hipStream_t stream);
 
+/*
+ * bgs_tile_lists with exact ellipse-tile binning (the list-shrinking binning
+ * refinement the paper names among related work, Sec. 2): a pair (tile, g)
+ * of the square rule is kept only when the tile's rectangle of pixel centres,
+ * widened by 2^-6 px, meets the ellipse q(d) <= 2 ln(255 o) (1 + 2^-10) +
+ * 2^-10, q(d) = a dx^2 + 2 b dx dy + c dy^2 with (a, b, c, o) =
+ * conic_opacity[g] -- outside it g's alpha stays below 1/255 and Eq. (4)
+ * skips g.  So the forward and backward rendered from these lists equal
+ * those from bgs_tile_lists (the removed entries are skipped at every pixel
+ * of their tile); n_contrib counts positions in the shorter lists.  The GPU
+ * evaluates the rule in fp32 on a slightly larger ellipse (2^-12 per axis,
+ * row intervals padded by 2^-11 of the half extent), so rounding can add
+ * pairs next to the boundary but never removes one.  A Gaussian whose conic
+ * is not positive definite keeps the square rule; one with opacity below
+ * 1/255 gets no pair.
+ *   conic_opacity [P][4] (DEVICE, 16-byte aligned), everything else, the
+ *   workspace size and the overflow behaviour as for bgs_tile_lists.
+ */
+bgs_status bgs_tile_lists_exact(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
+                                const float* conic_opacity, const int32_t* radius, const float* depth,
+                                const uint32_t* tiles_touched, uint32_t* point_list, int64_t capacity,
+                                uint32_t* ranges, uint64_t* n_pairs_dev, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
+
 /* Workspace bytes for bgs_queue_build / bgs_render_fwd / bgs_render_bwd. */
 size_t bgs_render_workspace_bytes(const bgs_frame* frame, const bgs_render_cfg* cfg);
 

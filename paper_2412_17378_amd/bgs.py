@@ -84,6 +84,8 @@ def lib() -> C.CDLL:
             "bgs_tile_lists_workspace_bytes": ([_i32, _i32, _i64, _i64], _sz),
             "bgs_tile_lists": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp],
                                C.c_int),
+            "bgs_tile_lists_exact": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz,
+                                      _vp], C.c_int),
             "bgs_render_workspace_bytes": ([_vp, _vp], _sz),
             "bgs_queue_build": ([_vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_render_fwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
@@ -106,7 +108,7 @@ def exported_symbols():
     """Names the header declares (used by the load test)."""
     return ["bgs_last_error", "bgs_version", "bgs_project", "bgs_project_bwd", "bgs_bin_workspace_bytes", "bgs_bin",
             "bgs_sort_workspace_bytes", "bgs_sort", "bgs_ranges", "bgs_tile_lists_workspace_bytes", "bgs_tile_lists",
-            "bgs_render_workspace_bytes", "bgs_queue_build", "bgs_autotune", "bgs_plan_create", "bgs_plan_launch",
+            "bgs_tile_lists_exact", "bgs_render_workspace_bytes", "bgs_queue_build", "bgs_autotune", "bgs_plan_create", "bgs_plan_launch",
             "bgs_plan_destroy",
             "bgs_render_fwd", "bgs_render_bwd"]
 
@@ -287,16 +289,26 @@ def bgs_tile_lists_workspace_bytes(width: int, height: int, P: int, capacity: in
 
 
 def bgs_tile_lists(width, height, means2D, radius, depth, tiles_touched, point_list, ranges, n_pairs_dev, ws,
-                   stream=None) -> bool:
+                   stream=None, conic_opacity=None) -> bool:
     """Asynchronous: n_pairs_dev (int64 [>=1] device tensor) receives M, or a
     lower bound of M above the capacity (point_list.numel()) on overflow, in
     which case every range is empty; the caller compares n_pairs_dev with the
-    capacity when convenient and grows.  Returns False on BGS_ECAPACITY."""
+    capacity when convenient and grows.  Returns False on BGS_ECAPACITY.
+    With conic_opacity ([P,4] float32) the lists use exact ellipse-tile
+    binning (bgs_tile_lists_exact)."""
     cap = 0 if point_list is None else point_list.numel()
     _expect(ranges, (n_tiles(width, height), 2), torch.int32, "ranges")
-    st = lib().bgs_tile_lists(int(width), int(height), TILE, means2D.shape[0], _ptr(means2D), _ptr(radius),
-                              _ptr(depth), _ptr(tiles_touched), _ptr(point_list) if cap else None, cap, _ptr(ranges),
-                              _ptr(n_pairs_dev), _ptr(ws), ws.numel(), _stream(stream))
+    P = means2D.shape[0]
+    if conic_opacity is None:
+        st = lib().bgs_tile_lists(int(width), int(height), TILE, P, _ptr(means2D), _ptr(radius), _ptr(depth),
+                                  _ptr(tiles_touched), _ptr(point_list) if cap else None, cap, _ptr(ranges),
+                                  _ptr(n_pairs_dev), _ptr(ws), ws.numel(), _stream(stream))
+    else:
+        _expect(conic_opacity, (P, 4), torch.float32, "conic_opacity")
+        st = lib().bgs_tile_lists_exact(int(width), int(height), TILE, P, _ptr(means2D), _ptr(conic_opacity),
+                                        _ptr(radius), _ptr(depth), _ptr(tiles_touched),
+                                        _ptr(point_list) if cap else None, cap, _ptr(ranges), _ptr(n_pairs_dev),
+                                        _ptr(ws), ws.numel(), _stream(stream))
     if st == BGS_ECAPACITY:
         return False
     _check("bgs_tile_lists", st)

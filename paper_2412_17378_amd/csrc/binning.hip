@@ -462,16 +462,111 @@ constexpr int GSHIFT = 2;        // group = 4x4 tiles
 constexpr int GTILES = 1 << GSHIFT;
 constexpr int MAX_GROUPS = 8192;
 
+// ----------------------------------------------------------------------
+// Exact ellipse-tile binning (optional).  Eq. (4) blends Gaussian g at pixel
+// offset d only when o exp(-q(d)/2) reaches 1/255, q(d) = a dx^2 + 2 b dx dy
+// + c dy^2 with (a, b, c) the conic: inside the ellipse q <= 2 ln(255 o).  A
+// tile of the square rule is kept only when its rectangle of pixel centres
+// meets that ellipse, so every removed pair is one the forward would skip at
+// each pixel of its tile.  The bound is widened by 2^-10 (relative and
+// absolute) and the tile rectangles by 2^-6 px, as in the rule's fp64
+// definition; on top, the fp32 evaluation below uses an ellipse 2^-12 larger
+// per axis and widens each row interval by 2^-11 of the half extent, so
+// rounding only ever adds tiles.
+// Per tile row, the tiles met form one run of columns: the x-range of the
+// ellipse within the row's slab of pixel centres, whose ends lie at the
+// ellipse's right- and leftmost points clamped into the slab.
+// ----------------------------------------------------------------------
+constexpr float BIN_PX_SLACK = 1.0f / 64.0f;
+
+struct Ellipse {
+    float b, inv_a, det;  // conic b, 1/a, a c - b^2
+    float xe, ye;         // half extents of the (enlarged) ellipse
+    float yr;             // y of its rightmost point (the leftmost is at -yr)
+    float mx, my;
+    bool blends;          // false: alpha never reaches 1/255, no tile
+    bool proper;          // false: not an ellipse, the square rule stands
+};
+
+__device__ __forceinline__ Ellipse make_ellipse(float4 co, float mx, float my) {
+    Ellipse e;
+    e.mx = mx;
+    e.my = my;
+    const float a = co.x, b = co.y, c = co.z, o = co.w;
+    const float bb = b * b;
+    e.det = __builtin_fmaf(a, c, -bb) - __builtin_fmaf(b, b, -bb);
+    e.b = b;
+    e.inv_a = 1.0f / a;
+    const float t255 = 1.0f / 255.0f;
+    e.blends = o > 0.0f;
+    float lim = e.blends ? 2.0f * logf(o / t255) : -1.0f;
+    lim = lim * (1.0f + 1.0f / 1024.0f) + 1.0f / 1024.0f;
+    e.blends = e.blends && lim >= 0.0f;
+    e.proper = a > 0.0f && c > 0.0f && e.det > 0.0f;
+    const float grow = 1.0f + 1.0f / 4096.0f;
+    e.xe = grow * sqrtf(lim * c / e.det);
+    e.ye = grow * sqrtf(lim * a / e.det);
+    e.yr = -b * e.xe / c;
+    e.proper = e.proper && e.blends && e.xe < 1.0e7f && e.ye < 1.0e7f;
+    return e;
+}
+
+// x of the ellipse boundary at height y (right or left end of its chord)
+__device__ __forceinline__ float chord_end(const Ellipse& e, float y, float sign) {
+    const float ay = fabsf(y);
+    const float D = fmaxf(0.0f, e.det * (e.ye - ay) * (e.ye + ay));  // = a lim' - det y^2
+    return (-e.b * y + sign * sqrtf(D)) * e.inv_a;
+}
+
+// The run of tile columns of tile row ty that the ellipse meets, clamped to
+// [tx0, tx1]: packed lo | (hi + 1) << 16 (empty: lo >= hi + 1).
+__device__ __forceinline__ uint32_t row_interval(const Ellipse& e, int ty, int tx0, int tx1) {
+    const float y0 = (float)(TILE * ty) - BIN_PX_SLACK - e.my, y1 = (float)(TILE * ty + TILE - 1) + BIN_PX_SLACK - e.my;
+    const float lo = fmaxf(y0, -e.ye), hi = fminf(y1, e.ye);
+    if (!(lo <= hi)) return (uint32_t)(tx1 + 1) | ((uint32_t)tx0 << 16);
+    const float pad = BIN_PX_SLACK + e.xe * (1.0f / 2048.0f);
+    const float xr = chord_end(e, fminf(fmaxf(e.yr, lo), hi), 1.0f) + pad;
+    const float xl = chord_end(e, fminf(fmaxf(-e.yr, lo), hi), -1.0f) - pad;
+    // tile tx (pixel centres 16 tx .. 16 tx + 15, widened) meets [xl, xr]
+    const float flo = ceilf((xl + e.mx - BIN_PX_SLACK - (float)(TILE - 1)) * (1.0f / TILE));
+    const float fhi = floorf((xr + e.mx + BIN_PX_SLACK) * (1.0f / TILE));
+    const int c0 = (int)fminf(fmaxf(flo, (float)tx0), (float)(tx1 + 1));
+    const int c1 = (int)fmaxf(fminf(fhi, (float)tx1), (float)(tx0 - 1));
+    return (uint32_t)c0 | ((uint32_t)(c1 + 1) << 16);
+}
+
 // rect[g] = (x0 | y0 << 16, x1 | y1 << 16) of Gaussian g's tile rectangle;
-// an empty one has x0 > x1.
+// an empty one has x0 > x1.  EXACT: cut to the tiles that the ellipse's
+// bounding box meets.
+template <bool EXACT>
 __global__ __launch_bounds__(256) void k_rects(int64_t P, int TX, int TY, const float* __restrict__ means2D,
                                                const int* __restrict__ radius,
-                                               const uint32_t* __restrict__ tiles_touched, uint2* __restrict__ rect) {
+                                               const uint32_t* __restrict__ tiles_touched,
+                                               const float4* __restrict__ conic_opacity, uint2* __restrict__ rect) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= P) return;
     int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
-    if (tiles_touched[g] == 0 || !tile_rect(means2D[2 * g], means2D[2 * g + 1], radius[g], TX, TY, x0, y0, x1, y1)) {
+    const float mx = means2D[2 * g], my = means2D[2 * g + 1];
+    if (tiles_touched[g] == 0 || !tile_rect(mx, my, radius[g], TX, TY, x0, y0, x1, y1)) {
         x0 = 1; y0 = 0; x1 = 0; y1 = 0;
+    } else if (EXACT) {
+        const Ellipse e = make_ellipse(conic_opacity[g], mx, my);
+        if (!e.blends) {
+            x0 = 1; y0 = 0; x1 = 0; y1 = 0;
+        } else if (e.proper) {
+            // tiles whose widened pixel-centre range meets [m - extent, m + extent];
+            // the float bounds are clamped into the rectangle before conversion
+            const float ph = BIN_PX_SLACK + (float)(TILE - 1);
+            const float fx0 = ceilf((mx - e.xe - ph) / TILE), fx1 = floorf((mx + e.xe + BIN_PX_SLACK) / TILE);
+            const float fy0 = ceilf((my - e.ye - ph) / TILE), fy1 = floorf((my + e.ye + BIN_PX_SLACK) / TILE);
+            x0 = max(x0, (int)fminf(fmaxf(fx0, (float)x0), (float)x1 + 1.0f));
+            x1 = min(x1, (int)fmaxf(fminf(fx1, (float)x1), (float)x0 - 1.0f));
+            y0 = max(y0, (int)fminf(fmaxf(fy0, (float)y0), (float)y1 + 1.0f));
+            y1 = min(y1, (int)fmaxf(fminf(fy1, (float)y1), (float)y0 - 1.0f));
+            if (x0 > x1 || y0 > y1) {
+                x0 = 1; y0 = 0; x1 = 0; y1 = 0;
+            }
+        }
     }
     rect[g] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
 }
@@ -620,13 +715,16 @@ __device__ __forceinline__ uint32_t spread_rows(uint32_t rows) {  // bit y -> bi
     return (rows & 1u) | ((rows & 2u) << 3) | ((rows & 4u) << 6) | ((rows & 8u) << 9);
 }
 
+template <bool EXACT>
 __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, const uint32_t* __restrict__ order,
                                                    const uint2* __restrict__ rect, const uint32_t* __restrict__ base,
                                                    uint2* __restrict__ coarse, const uint64_t* __restrict__ coarse_n,
-                                                   uint64_t coarse_cap) {
-    extern __shared__ uint32_t nextpos[];  // ng running slots
+                                                   uint64_t coarse_cap, const float* __restrict__ means2D,
+                                                   const float4* __restrict__ conic_opacity) {
+    extern __shared__ uint32_t nextpos[];  // ng running slots, then (EXACT) one column run per tile row
     if (coarse_n[0] > coarse_cap) return;  // the coarse lists do not fit: nothing is written
     const int ng = GX * GY;
+    uint32_t* rowiv = nextpos + ng;
     const int lane = threadIdx.x;
     const int c = blockIdx.x;
     const uint32_t* bc = base + (int64_t)c * ng;
@@ -641,10 +739,12 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
         uint32_t g = 0, n = 0;
         uint2 rr = make_uint2(1u, 0u);
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+        Ellipse el{};
         if (k < P) {
             g = order[k];
             rr = rect[g];
             if (group_rect(rr, x0, y0, x1, y1)) n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+            if (EXACT && n) el = make_ellipse(conic_opacity[g], means2D[2 * g], means2D[2 * g + 1]);
         }
         const int cntk = (int)((P - k0) < 64 ? (P - k0) : 64);
         for (int i = 0; i < cntk; ++i) {
@@ -655,6 +755,24 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
             const int wi = __builtin_amdgcn_readlane(x1, i) - xi + 1;
             const uint32_t ra = __builtin_amdgcn_readlane(rr.x, i), rb = __builtin_amdgcn_readlane(rr.y, i);
             const int tx0 = (int)(ra & 0xFFFF), ty0 = (int)(ra >> 16), tx1 = (int)(rb & 0xFFFF), ty1 = (int)(rb >> 16);
+            bool exact_i = false;
+            if (EXACT && __builtin_amdgcn_readlane((int)el.proper, i) != 0) {
+                // the column run of each of Gaussian i's tile rows, one row per lane
+                exact_i = true;
+                Ellipse ei{};
+                ei.b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.b), i));
+                ei.inv_a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.inv_a), i));
+                ei.det = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.det), i));
+                ei.xe = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.xe), i));
+                ei.ye = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.ye), i));
+                ei.yr = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.yr), i));
+                ei.mx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.mx), i));
+                ei.my = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.my), i));
+                for (int j = lane; j <= ty1 - ty0; j += 64) rowiv[j] = row_interval(ei, ty0 + j, tx0, tx1);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
             const float inv_w = 1.0f / (float)wi;
             for (uint32_t j = lane; j < ni; j += 64) {
                 int q = (int)((float)j * inv_w);
@@ -670,9 +788,18 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
                 const int rl = max(ty0 - by, 0), rh = min(ty1 - by + 1, GTILES);
                 const uint32_t cols = ((1u << ch) - 1u) & ~((1u << cl) - 1u);
                 const uint32_t rows = ((1u << rh) - 1u) & ~((1u << rl) - 1u);
+                uint32_t mask = cols * spread_rows(rows);
+                if (EXACT && exact_i) {
+                    mask = 0u;
+                    for (int r = rl; r < rh; ++r) {
+                        const uint32_t iv = rowiv[by + r - ty0];
+                        const int c0 = max((int)(iv & 0xFFFFu) - bx, 0), c1 = min((int)(iv >> 16) - bx, GTILES);
+                        if (c0 < c1) mask |= (((1u << c1) - 1u) & ~((1u << c0) - 1u)) << (GTILES * r);
+                    }
+                }
                 const uint32_t pos = nextpos[t];
                 nextpos[t] = pos + 1;
-                coarse[pos] = make_uint2(gi, cols * spread_rows(rows));
+                coarse[pos] = make_uint2(gi, mask);
             }
         }
     }
@@ -864,10 +991,12 @@ extern "C" size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, 
     return lists_layout(width, height, P, (size_t)capacity).bytes;
 }
 
-extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
-                                     const int32_t* radius, const float* depth, const uint32_t* tiles_touched,
-                                     uint32_t* point_list, int64_t capacity, uint32_t* ranges, uint64_t* n_pairs_dev,
-                                     void* ws, size_t ws_bytes, hipStream_t stream) {
+// conic_opacity == nullptr: the square tile rule; else exact ellipse-tile
+// binning
+static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
+                             const float* conic_opacity, const int32_t* radius, const float* depth,
+                             const uint32_t* tiles_touched, uint32_t* point_list, int64_t capacity, uint32_t* ranges,
+                             uint64_t* n_pairs_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
     BGS_REQUIRE(width > 0 && height > 0, "bgs_tile_lists: image size must be positive");
     BGS_REQUIRE(P >= 0 && capacity >= 0, "bgs_tile_lists: negative size");
     if (tile != TILE) return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: only 16x16 tiles are supported");
@@ -879,6 +1008,8 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
     if (L.ng > MAX_GROUPS || (size_t)(L.GX + 1) * (L.GY + 1) * sizeof(int) > 65536 || TX > 65535 || TY > 65535)
         return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: tile grid too large (over 8192 groups of 4x4 tiles); use "
                                       "bgs_bin + bgs_sort + bgs_ranges");
+    if (conic_opacity && sizeof(uint32_t) * ((size_t)L.ng + TY) > 65536)
+        return fail(BGS_EUNSUPPORTED, "bgs_tile_lists_exact: tile grid too large for the exact rule");
     BGS_REQUIRE(ws && ws_bytes >= L.bytes, "bgs_tile_lists: workspace too small");
     BGS_REQUIRE(capacity == 0 || point_list != nullptr, "bgs_tile_lists: null point_list");
     char* w = static_cast<char*>(ws);
@@ -909,8 +1040,13 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
                                           reinterpret_cast<uint32_t*>(w + L.dtot), stream);
         if (st != BGS_OK) return st;
     }
-    hipLaunchKernelGGL(k_rects, dim3(blocks_for(P)), dim3(256), 0, stream, P, TX, TY, means2D, radius, tiles_touched,
-                       rect);
+    const auto* co4 = reinterpret_cast<const float4*>(conic_opacity);
+    if (conic_opacity)
+        hipLaunchKernelGGL(k_rects<true>, dim3(blocks_for(P)), dim3(256), 0, stream, P, TX, TY, means2D, radius,
+                           tiles_touched, co4, rect);
+    else
+        hipLaunchKernelGGL(k_rects<false>, dim3(blocks_for(P)), dim3(256), 0, stream, P, TX, TY, means2D, radius,
+                           tiles_touched, co4, rect);
     BGS_HIP(hipGetLastError());
     // coarse (group) lists
     hipLaunchKernelGGL(k_chunk_hist, dim3(L.C), dim3(CHUNK), sizeof(int) * (size_t)(L.GX + 1) * (L.GY + 1), stream, P,
@@ -931,8 +1067,12 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(nbg)), dim3(256), 0, stream, L.C, L.ng, gstart, part, h);
     BGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_chunk_emit, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX, L.GY,
-                       order, rect, h, coarse, (const uint64_t*)mg, ccap);
+    if (conic_opacity)
+        hipLaunchKernelGGL(k_chunk_emit<true>, dim3(L.C), dim3(64), sizeof(uint32_t) * ((size_t)L.ng + TY), stream, P,
+                           L.GX, L.GY, order, rect, h, coarse, (const uint64_t*)mg, ccap, means2D, co4);
+    else
+        hipLaunchKernelGGL(k_chunk_emit<false>, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX,
+                           L.GY, order, rect, h, coarse, (const uint64_t*)mg, ccap, means2D, co4);
     BGS_HIP(hipGetLastError());
     // fine (tile) lists, on segments of the coarse lists
     auto* nseg = reinterpret_cast<uint32_t*>(w + L.nseg);
@@ -971,4 +1111,23 @@ extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile
         BGS_HIP(hipGetLastError());
     }
     return BGS_OK;
+}
+
+extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
+                                     const int32_t* radius, const float* depth, const uint32_t* tiles_touched,
+                                     uint32_t* point_list, int64_t capacity, uint32_t* ranges, uint64_t* n_pairs_dev,
+                                     void* ws, size_t ws_bytes, hipStream_t stream) {
+    return tile_lists(width, height, tile, P, means2D, nullptr, radius, depth, tiles_touched, point_list, capacity,
+                      ranges, n_pairs_dev, ws, ws_bytes, stream);
+}
+
+extern "C" bgs_status bgs_tile_lists_exact(int32_t width, int32_t height, int32_t tile, int64_t P,
+                                           const float* means2D, const float* conic_opacity, const int32_t* radius,
+                                           const float* depth, const uint32_t* tiles_touched, uint32_t* point_list,
+                                           int64_t capacity, uint32_t* ranges, uint64_t* n_pairs_dev, void* ws,
+                                           size_t ws_bytes, hipStream_t stream) {
+    BGS_REQUIRE(P == 0 || conic_opacity != nullptr, "bgs_tile_lists_exact: conic_opacity is null");
+    BGS_REQUIRE(((uintptr_t)conic_opacity & 15u) == 0, "bgs_tile_lists_exact: conic_opacity must be 16-byte aligned");
+    return tile_lists(width, height, tile, P, means2D, P ? conic_opacity : nullptr, radius, depth, tiles_touched,
+                      point_list, capacity, ranges, n_pairs_dev, ws, ws_bytes, stream);
 }

@@ -61,16 +61,23 @@ def key_bits_for(n_tiles: int) -> int:
 
 
 class Rasterizer:
-    def __init__(self, device: str = "cuda", reuse_pairs: bool = False, lists_method: str = "fused"):
+    def __init__(self, device: str = "cuda", reuse_pairs: bool = False, lists_method: str = "fused",
+                 binning: str = "square"):
         """reuse_pairs: the sorted lists of a prepared frame live in buffers
         that the next prepare() overwrites (no per-frame allocation); off by
-        default so that several prepared frames can coexist."""
+        default so that several prepared frames can coexist.  binning:
+        "square" (the 3-sigma square tile rule) or "ellipse" (exact
+        ellipse-tile binning: shorter lists, the same renders; fused lists
+        only)."""
+        if binning not in ("square", "ellipse"):
+            raise ValueError(f"unknown binning {binning!r}")
         B.lib()
         self.device = torch.device(device)
         self.ws = Workspace(self.device)
         self.pair_capacity = 0
         self.reuse_pairs = reuse_pairs
         self.lists_method = lists_method
+        self.binning = binning
 
     def _t(self, a, dtype=torch.float32):
         if isinstance(a, torch.Tensor):
@@ -114,6 +121,8 @@ class Rasterizer:
         method = method or self.lists_method
         if method == "fused" and not B.tile_lists_supported(width, height):
             method = "sort"
+        if self.binning == "ellipse" and method != "fused":
+            raise ValueError("ellipse binning needs the fused list builder (bgs_tile_lists_exact)")
         ranges = torch.empty(nt, 2, dtype=torch.int32, device=dev)
 
         def pair_bufs(cap):
@@ -126,7 +135,8 @@ class Rasterizer:
                 ws = self.ws.get("lists", B.bgs_tile_lists_workspace_bytes(width, height, P, cap))
                 pl = self.ws.get("svals", 4 * cap).view(torch.int32)[:cap]
                 B.bgs_tile_lists(width, height, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
-                                 pl if cap else None, ranges, n_dev, ws)
+                                 pl if cap else None, ranges, n_dev, ws,
+                                 conic_opacity=pr["conic_opacity"] if self.binning == "ellipse" else None)
                 M = int(n_dev.item())
                 if M <= cap:
                     break

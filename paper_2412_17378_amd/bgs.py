@@ -172,7 +172,7 @@ def n_tiles(width: int, height: int) -> int:
 def tile_lists_supported(width: int, height: int) -> bool:
     """Whether bgs_tile_lists handles this tile grid (see include/bgs.h)."""
     tx, ty = (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
-    gx, gy = (tx + 3) // 4, (ty + 3) // 4
+    gx, gy = (tx + 7) // 8, (ty + 7) // 8  # groups of 8x8 tiles
     return gx * gy <= 8192 and (gx + 1) * (gy + 1) * 4 <= 65536 and tx <= 65535 and ty <= 65535
 
 

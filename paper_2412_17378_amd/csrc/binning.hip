@@ -438,19 +438,20 @@ extern "C" bgs_status bgs_ranges(const uint32_t* sorted_keys, int64_t n, int32_t
 //
 // 1. The Gaussians are put in depth order (a P-element sort) and each one's
 //    tile rectangle is computed once.
-// 2. Coarse lists per group of 4x4 tiles (64x64 px): a stable counting sort of
+// 2. Coarse lists per group of 8x8 tiles (128x128 px): a stable counting sort of
 //    the (group, Gaussian) pairs.  The depth order is cut into chunks of
 //    CHUNK Gaussians; per chunk a group histogram (2D difference array in LDS,
 //    four updates per Gaussian, then a 2D prefix sum), a column scan over
 //    chunks and a scan over groups give every (chunk, group) its base slot,
 //    and one wave per chunk drops the chunk's pairs, in depth order, at base +
-//    running count.  With 510 groups at 1080p the runs a chunk writes per
-//    group are long enough for the stores to combine in L2.
-// 3. Fine lists: one workgroup per group reads its coarse list (in depth
-//    order) and splits it into its 16 tile lists; each wave owns 4 tiles and
-//    appends, with a ballot and a prefix count, the Gaussians whose rectangle
-//    contains the tile -- coalesced sequential appends, first counting (to
-//    size the tiles), then writing.
+//    running count.  Each coarse entry is one aligned 16-byte store: the
+//    scattered coarse writes cost one memory sector each, and 8x8 groups
+//    keep their number low (135 groups at 1080p).
+// 3. Fine lists: one workgroup per segment of a group's coarse list (in
+//    depth order) splits it into the group's 64 tile lists; wave w owns tiles
+//    16 w .. 16 w + 15 and appends, with a ballot and a prefix count, the
+//    Gaussians whose tile mask holds the tile -- coalesced sequential
+//    appends, first counting (to size the tiles), then writing.
 // The result is exactly the list a stable sort of the depth-ordered
 // (tile, Gaussian) pairs by tile gives.
 // ======================================================================
@@ -458,7 +459,7 @@ namespace bgs {
 
 constexpr int CHUNK = 64;        // Gaussians per chunk of the coarse sort (one wave emits a chunk)
 constexpr int PART = 32;         // chunks per column-scan block
-constexpr int GSHIFT = 2;        // group = 4x4 tiles
+constexpr int GSHIFT = 3;        // group = 8x8 tiles
 constexpr int GTILES = 1 << GSHIFT;
 constexpr int MAX_GROUPS = 8192;
 
@@ -708,17 +709,20 @@ __global__ __launch_bounds__(256) void k_chunk_base(int C, int nt, const uint32_
 
 // One wave per chunk: drop the chunk's (group, Gaussian) pairs, Gaussians in
 // depth order, at the chunk's base slot of each group plus a running count
-// kept in LDS.  An entry is (Gaussian id, mask of the group's 16 tiles the
-// Gaussian's tile rectangle covers, bit (x mod 4) + 4 (y mod 4)), so the
-// split into tile lists streams the coarse lists without a gather.
-__device__ __forceinline__ uint32_t spread_rows(uint32_t rows) {  // bit y -> bit 4y
-    return (rows & 1u) | ((rows & 2u) << 3) | ((rows & 4u) << 6) | ((rows & 8u) << 9);
+// kept in LDS.  An entry is (Gaussian id, 64-bit mask of the group's tiles
+// the Gaussian covers, bit (x mod 8) + 8 (y mod 8), 0), so the split into
+// tile lists streams the coarse lists without a gather.
+__device__ __forceinline__ uint64_t spread_rows(uint32_t rows) {  // bit y -> bit 8y
+    uint64_t m = 0;
+#pragma unroll
+    for (int y = 0; y < GTILES; ++y) m |= (uint64_t)((rows >> y) & 1u) << (GTILES * y);
+    return m;
 }
 
 template <bool EXACT>
 __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, const uint32_t* __restrict__ order,
                                                    const uint2* __restrict__ rect, const uint32_t* __restrict__ base,
-                                                   uint2* __restrict__ coarse, const uint64_t* __restrict__ coarse_n,
+                                                   uint4* __restrict__ coarse, const uint64_t* __restrict__ coarse_n,
                                                    uint64_t coarse_cap, const float* __restrict__ means2D,
                                                    const float4* __restrict__ conic_opacity) {
     extern __shared__ uint32_t nextpos[];  // ng running slots, then (EXACT) one column run per tile row
@@ -788,18 +792,18 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
                 const int rl = max(ty0 - by, 0), rh = min(ty1 - by + 1, GTILES);
                 const uint32_t cols = ((1u << ch) - 1u) & ~((1u << cl) - 1u);
                 const uint32_t rows = ((1u << rh) - 1u) & ~((1u << rl) - 1u);
-                uint32_t mask = cols * spread_rows(rows);
+                uint64_t mask = (uint64_t)cols * spread_rows(rows);
                 if (EXACT && exact_i) {
                     mask = 0u;
                     for (int r = rl; r < rh; ++r) {
                         const uint32_t iv = rowiv[by + r - ty0];
                         const int c0 = max((int)(iv & 0xFFFFu) - bx, 0), c1 = min((int)(iv >> 16) - bx, GTILES);
-                        if (c0 < c1) mask |= (((1u << c1) - 1u) & ~((1u << c0) - 1u)) << (GTILES * r);
+                        if (c0 < c1) mask |= (uint64_t)(((1u << c1) - 1u) & ~((1u << c0) - 1u)) << (GTILES * r);
                     }
                 }
                 const uint32_t pos = nextpos[t];
                 nextpos[t] = pos + 1;
-                coarse[pos] = make_uint2(gi, mask);
+                coarse[pos] = make_uint4(gi, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
             }
         }
     }
@@ -808,7 +812,7 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
 // The fine split runs on segments of SEG consecutive coarse entries of one
 // group, so that a heavily covered group does not serialize on one
 // workgroup.  nseg[g] = ceil(gtotal[g] / SEG).
-constexpr int SEG = 2048;
+constexpr int SEG = 1024;
 
 __global__ __launch_bounds__(256) void k_seg_count(int ng, const uint32_t* __restrict__ gtotal,
                                                    uint32_t* __restrict__ nseg) {
@@ -816,118 +820,157 @@ __global__ __launch_bounds__(256) void k_seg_count(int ng, const uint32_t* __res
     if (g < ng) nseg[g] = (gtotal[g] + SEG - 1) / SEG;
 }
 
-// segmap[segstart[g] + s] = (g, s); nothing when the coarse lists overflowed
-// (the segment table is sized for coarse lists that fit)
+// segmap[segstart[g] + s] = (g, s), one wave per group; nothing when the
+// coarse lists overflowed (the segment table is sized for lists that fit)
 __global__ __launch_bounds__(256) void k_seg_map(int ng, const uint32_t* __restrict__ nseg,
                                                  const uint32_t* __restrict__ segstart, uint2* __restrict__ segmap,
                                                  const uint64_t* __restrict__ coarse_n, uint64_t coarse_cap,
                                                  uint32_t max_segs) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (g >= ng || coarse_n[0] > coarse_cap) return;
     const uint32_t n = nseg[g], b = segstart[g];
-    for (uint32_t q = 0; q < n && b + q < max_segs; ++q) segmap[b + q] = make_uint2((uint32_t)g, q);
+    for (uint32_t q = lane; q < n && b + q < max_segs; q += 64) segmap[b + q] = make_uint2((uint32_t)g, q);
 }
 
 // A fixed grid of workgroups strides over the segments (the segment count
-// stays on the device); per segment, wave w walks the contiguous quarter
-// [e0 + w SEG/4, e0 + (w+1) SEG/4) of it, 64 entries at a time, and for each
-// of the group's 16 tiles (local index i = (x mod 4) + 4 (y mod 4)) takes
-// the ballot of the entries whose tile mask holds the tile.  Counts are
-// kept per (segment, wave) unit, so the write pass knows every wave's start
-// slots and needs no exchange between waves.
-// COUNT: segcnt[seg][i][w] = entries of wave w's quarter whose rectangle
-// contains tile i.
-// WRITE: append each such entry at segcnt[seg][i][w] (by then the slot where
-// that quarter's run of tile i starts) + the earlier entries of that run.
-constexpr int SUBSEG = SEG / 4;
+// stays on the device); per segment, wave w walks all of its entries, 64 at a
+// time, and for each of its 16 tiles (local index i = (x mod 8) + 8 (y mod 8)
+// in [16 w, 16 w + 16)) takes the ballot of the entries whose mask holds the
+// tile.
+// COUNT: segcnt[seg][i] = the segment's entries whose mask holds tile i.
+// WRITE: the k-th such entry goes to segcnt[seg][i] (by then the slot where
+// the segment's run of tile i starts) + k.  The entries are compacted into a
+// 128-slot LDS ring per tile and leave it 64 at a time, one full-wave store
+// of 64 consecutive slots, so the point list is written by few, contiguous
+// stores.
 constexpr size_t SPLIT_GRID = 2048;  // workgroups of the split passes: 8 per CU
+constexpr int RING = 128;
 
 template <bool WRITE>
 __device__ __forceinline__ void split_segment(uint32_t sidx, const uint2* __restrict__ segmap,
-                                              const uint2* __restrict__ coarse, const uint32_t* __restrict__ gstart,
+                                              const uint4* __restrict__ coarse, const uint32_t* __restrict__ gstart,
                                               const uint32_t* __restrict__ gtotal, uint32_t* __restrict__ segcnt,
-                                              uint32_t* __restrict__ point_list) {
+                                              uint32_t* __restrict__ point_list, uint32_t* ring) {
     const uint2 gs = segmap[sidx];
     const int grp = (int)gs.x;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // counts of (segment, tile i, wave w) at segcnt[(segment * 16 + i) * 4 + w]
-    uint32_t run[16];
+    uint32_t base[16], staged[16], flushed[16];  // WRITE: run start, entries staged so far, entries stored
 #pragma unroll
-    for (int i = 0; i < 16; ++i) run[i] = WRITE ? segcnt[((size_t)sidx * 16 + i) * 4 + wv] : 0u;
+    for (int i = 0; i < 16; ++i) {
+        base[i] = WRITE ? segcnt[(size_t)sidx * 64 + wv * 16 + i] : 0u;
+        staged[i] = 0u;
+        flushed[i] = 0u;
+    }
     const uint32_t gt = gtotal[grp];
-    const uint32_t e0 = min(gt, gs.y * SEG + wv * SUBSEG);
-    const uint32_t e1 = min(gt, gs.y * SEG + (wv + 1) * SUBSEG);
+    const uint32_t e0 = min(gt, gs.y * SEG), e1 = min(gt, (gs.y + 1) * SEG);
     const uint32_t b0 = gstart[grp];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (uint32_t k0 = e0; k0 < e1; k0 += 64) {
         const uint32_t k = k0 + lane;
         uint32_t g = 0, tmask = 0;
         if (k < e1) {
-            const uint2 e = coarse[b0 + k];
+            const uint4 e = coarse[b0 + k];
             g = e.x;
-            tmask = e.y;
+            tmask = ((wv < 2 ? e.y : e.z) >> (16 * (wv & 1))) & 0xFFFFu;
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const bool in = (tmask >> i) & 1u;
             const uint64_t m = ballot(in);
-            if (WRITE && in) point_list[run[i] + (uint32_t)__builtin_popcountll(m & lt)] = g;
-            run[i] += (uint32_t)__builtin_popcountll(m);
+            if (WRITE) {
+                if (in) ring[i * RING + ((staged[i] + (uint32_t)__builtin_popcountll(m & lt)) & (RING - 1))] = g;
+                staged[i] += (uint32_t)__builtin_popcountll(m);
+                if (staged[i] - flushed[i] >= 64u) {  // uniform
+                    point_list[base[i] + flushed[i] + lane] = ring[i * RING + ((flushed[i] + lane) & (RING - 1))];
+                    flushed[i] += 64u;
+                }
+            } else {
+                staged[i] += (uint32_t)__builtin_popcountll(m);
+            }
         }
     }
-    if (!WRITE && lane < 16) {
+    if (WRITE) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if ((uint32_t)lane < staged[i] - flushed[i])
+                point_list[base[i] + flushed[i] + lane] = ring[i * RING + ((flushed[i] + lane) & (RING - 1))];
+    } else if (lane < 16) {
         uint32_t c = 0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) c = lane == i ? run[i] : c;
-        segcnt[((size_t)sidx * 16 + lane) * 4 + wv] = c;
+        for (int i = 0; i < 16; ++i) c = lane == i ? staged[i] : c;
+        segcnt[(size_t)sidx * 64 + wv * 16 + lane] = c;
     }
 }
 
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_seg_split(const uint64_t* __restrict__ n_segs, const uint2* __restrict__ segmap,
-                                                   const uint2* __restrict__ coarse,
+                                                   const uint4* __restrict__ coarse,
                                                    const uint32_t* __restrict__ gstart,
                                                    const uint32_t* __restrict__ gtotal, uint32_t* __restrict__ segcnt,
                                                    uint32_t* __restrict__ point_list, const uint64_t* __restrict__ n_pairs,
                                                    uint64_t capacity, const uint64_t* __restrict__ coarse_n,
                                                    uint64_t coarse_cap, uint32_t max_segs) {
+    __shared__ uint32_t s_ring[WRITE ? 4 * 16 * RING : 1];  // per wave: 16 tiles x RING slots
     if (coarse_n[0] > coarse_cap) return;  // no coarse lists to split
     // the pair count is final here; a list that does not fit is not written
     // at all (the caller grows the buffer and builds again)
     if (WRITE && n_pairs[0] > capacity) return;
     const uint32_t nsg = (uint32_t)min(n_segs[0], (uint64_t)max_segs);
-    for (uint32_t sidx = blockIdx.x; sidx < nsg; sidx += gridDim.x) split_segment<WRITE>(sidx, segmap, coarse, gstart,
-                                                                                        gtotal, segcnt, point_list);
+    uint32_t* ring = s_ring + (WRITE ? (threadIdx.x >> 6) * 16 * RING : 0);
+    for (uint32_t sidx = blockIdx.x; sidx < nsg; sidx += gridDim.x)
+        split_segment<WRITE>(sidx, segmap, coarse, gstart, gtotal, segcnt, point_list, ring);
 }
 
-// One thread per (group, local tile i).  OFFSETS = false: ttotal[tile] = sum
-// of the tile's segment counts.  OFFSETS = true: the counts become the
+// One workgroup per group, thread (part p, local tile i): p takes a
+// contiguous sixteenth of the group's segments.  OFFSETS = false: ttotal[tile]
+// = sum of the tile's segment counts.  OFFSETS = true: the counts become the
 // tile's slot at the start of each segment's run (from tstart).  After a
 // coarse overflow there are no segments: every tile total is zero.
+constexpr int SCAN_PARTS = 16;
+
 template <bool OFFSETS>
-__global__ __launch_bounds__(256) void k_seg_scan(int TX, int TY, int GX, int ng, const uint32_t* __restrict__ nseg,
-                                                  const uint32_t* __restrict__ segstart, uint32_t* __restrict__ segcnt,
-                                                  const uint32_t* __restrict__ tstart, uint32_t* __restrict__ ttotal,
-                                                  const uint64_t* __restrict__ coarse_n, uint64_t coarse_cap) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ng * 16) return;
-    const int grp = idx >> 4, li = idx & 15;
+__global__ __launch_bounds__(SCAN_PARTS * 64) void k_seg_scan(int TX, int TY, int GX, int ng,
+                                                               const uint32_t* __restrict__ nseg,
+                                                               const uint32_t* __restrict__ segstart,
+                                                               uint32_t* __restrict__ segcnt,
+                                                               const uint32_t* __restrict__ tstart,
+                                                               uint32_t* __restrict__ ttotal,
+                                                               const uint64_t* __restrict__ coarse_n,
+                                                               uint64_t coarse_cap) {
+    __shared__ uint32_t s_part[SCAN_PARTS][64];
+    const int grp = blockIdx.x, li = threadIdx.x & 63, p = threadIdx.x >> 6;
     const int tx = (grp % GX) * GTILES + (li % GTILES), ty = (grp / GX) * GTILES + (li / GTILES);
-    if (tx >= TX || ty >= TY) return;
+    const bool valid = tx < TX && ty < TY;
     const int tile = ty * TX + tx;
     if (coarse_n[0] > coarse_cap) {
-        if (!OFFSETS) ttotal[tile] = 0u;
+        if (!OFFSETS && valid && p == 0) ttotal[tile] = 0u;
         return;
     }
     const uint32_t n = nseg[grp], b = segstart[grp];
-    uint32_t run = OFFSETS ? tstart[tile] : 0u;
-    for (uint32_t q = 0; q < n; ++q) {
-        uint4& c = reinterpret_cast<uint4*>(segcnt)[(size_t)(b + q) * 16 + li];  // the segment's 4 waves
-        const uint4 v = c;
-        if (OFFSETS) c = make_uint4(run, run + v.x, run + v.x + v.y, run + v.x + v.y + v.z);
-        run += v.x + v.y + v.z + v.w;
+    const uint32_t q0 = (uint32_t)(((uint64_t)n * p) / SCAN_PARTS), q1 = (uint32_t)(((uint64_t)n * (p + 1)) / SCAN_PARTS);
+    uint32_t sum = 0;
+    for (uint32_t q = q0; q < q1; ++q) sum += segcnt[(size_t)(b + q) * 64 + li];
+    s_part[p][li] = sum;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int pp = 0; pp < SCAN_PARTS; ++pp) {
+        const uint32_t v = s_part[pp][li];
+        before += pp < p ? v : 0u;
+        total += v;
     }
-    if (!OFFSETS) ttotal[tile] = run;
+    if (!valid) return;
+    if (!OFFSETS) {
+        if (p == 0) ttotal[tile] = total;
+        return;
+    }
+    uint32_t run = tstart[tile] + before;
+    for (uint32_t q = q0; q < q1; ++q) {
+        uint32_t& c = segcnt[(size_t)(b + q) * 64 + li];
+        const uint32_t v = c;
+        c = run;
+        run += v;
+    }
 }
 
 struct ListsLayout {
@@ -971,11 +1014,11 @@ static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P, size_t
     L.ttotal = take(4 * (size_t)L.nt);
     L.tstart = take(4 * (size_t)L.nt);
     L.coarse_cap = coarse_cap;
-    L.coarse = take(8 * (coarse_cap > 0 ? coarse_cap : 1));  // (id, tile mask) pairs
+    L.coarse = take(16 * (coarse_cap > 0 ? coarse_cap : 1));  // (id, 64-bit tile mask, 0) entries
     // segments: at most coarse_cap / SEG + ng of them
     L.max_segs = coarse_cap / SEG + (size_t)L.ng + 1;
     L.segmap = take(8 * L.max_segs);
-    L.segcnt = take(4 * 64 * L.max_segs);  // 16 counts per (segment, wave)
+    L.segcnt = take(4 * 64 * L.max_segs);  // one count per (segment, tile of the group)
     L.dcnt = take(4 * (size_t)DS_RADIX * ds_blocks((int64_t)n));
     L.dtot = take(4 * (size_t)DS_RADIX);
     L.bytes = off;
@@ -1006,7 +1049,7 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
     const int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
     const ListsLayout L = lists_layout(width, height, P, (size_t)capacity);
     if (L.ng > MAX_GROUPS || (size_t)(L.GX + 1) * (L.GY + 1) * sizeof(int) > 65536 || TX > 65535 || TY > 65535)
-        return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: tile grid too large (over 8192 groups of 4x4 tiles); use "
+        return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: tile grid too large (over 8192 groups of 8x8 tiles); use "
                                       "bgs_bin + bgs_sort + bgs_ranges");
     if (conic_opacity && sizeof(uint32_t) * ((size_t)L.ng + TY) > 65536)
         return fail(BGS_EUNSUPPORTED, "bgs_tile_lists_exact: tile grid too large for the exact rule");
@@ -1024,7 +1067,7 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
     auto* gstart = reinterpret_cast<uint32_t*>(w + L.gstart);
     auto* ttotal = reinterpret_cast<uint32_t*>(w + L.ttotal);
     auto* tstart = reinterpret_cast<uint32_t*>(w + L.tstart);
-    auto* coarse = reinterpret_cast<uint2*>(w + L.coarse);
+    auto* coarse = reinterpret_cast<uint4*>(w + L.coarse);
     if (P == 0) {
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * (int64_t)L.nt)), dim3(256), 0, stream, ranges,
                            2 * (int64_t)L.nt, 0u);
@@ -1087,22 +1130,21 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.ng, nseg, segstart, (uint32_t*)nullptr, nsegs,
                        (const uint64_t*)nullptr, no_cap, no_cap);
     BGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_seg_map, dim3(blocks_for(L.ng)), dim3(256), 0, stream, L.ng, nseg, segstart, segmap,
+    hipLaunchKernelGGL(k_seg_map, dim3((unsigned)((L.ng + 3) / 4)), dim3(256), 0, stream, L.ng, nseg, segstart, segmap,
                        (const uint64_t*)mg, ccap, max_segs);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_seg_split<false>, dim3(grid_split), dim3(256), 0, stream, nsegs, segmap, coarse, gstart,
                        gtotal, segcnt, (uint32_t*)nullptr, (const uint64_t*)nullptr, (uint64_t)0, (const uint64_t*)mg,
                        ccap, max_segs);
     BGS_HIP(hipGetLastError());
-    const int n_gt = L.ng * 16;
-    hipLaunchKernelGGL(k_seg_scan<false>, dim3(blocks_for(n_gt)), dim3(256), 0, stream, TX, TY, L.GX, L.ng, nseg,
+    hipLaunchKernelGGL(k_seg_scan<false>, dim3(L.ng), dim3(SCAN_PARTS * 64), 0, stream, TX, TY, L.GX, L.ng, nseg,
                        segstart, segcnt, (const uint32_t*)nullptr, ttotal, (const uint64_t*)mg, ccap);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.nt, ttotal, tstart, ranges, n_pairs_dev,
                        (const uint64_t*)mg, ccap, pcap);
     BGS_HIP(hipGetLastError());
     if (capacity > 0) {
-        hipLaunchKernelGGL(k_seg_scan<true>, dim3(blocks_for(n_gt)), dim3(256), 0, stream, TX, TY, L.GX, L.ng, nseg,
+        hipLaunchKernelGGL(k_seg_scan<true>, dim3(L.ng), dim3(SCAN_PARTS * 64), 0, stream, TX, TY, L.GX, L.ng, nseg,
                            segstart, segcnt, tstart, (uint32_t*)nullptr, (const uint64_t*)mg, ccap);
         BGS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_seg_split<true>, dim3(grid_split), dim3(256), 0, stream, nsegs, segmap, coarse, gstart,

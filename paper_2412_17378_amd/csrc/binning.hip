@@ -833,72 +833,57 @@ __global__ __launch_bounds__(256) void k_seg_map(int ng, const uint32_t* __restr
 }
 
 // A fixed grid of workgroups strides over the segments (the segment count
-// stays on the device); per segment, wave w walks all of its entries, 64 at a
-// time, and for each of its 16 tiles (local index i = (x mod 8) + 8 (y mod 8)
-// in [16 w, 16 w + 16)) takes the ballot of the entries whose mask holds the
-// tile.
+// stays on the device); per segment, wave w takes its 16 tiles (local index
+// i = (x mod 8) + 8 (y mod 8) in [16 w, 16 w + 16)) in turn and, 64 entries
+// at a time, the ballot of the entries whose mask holds the tile.
 // COUNT: segcnt[seg][i] = the segment's entries whose mask holds tile i.
 // WRITE: the k-th such entry goes to segcnt[seg][i] (by then the slot where
-// the segment's run of tile i starts) + k.  The entries are compacted into a
-// 128-slot LDS ring per tile and leave it 64 at a time, one full-wave store
-// of 64 consecutive slots, so the point list is written by few, contiguous
-// stores.
+// the segment's run of tile i starts) + k.  Each lane keeps its 16 entries of
+// the segment in registers and the wave takes its tiles one after another,
+// so a (tile, 64 entries) step is a bit test, a ballot, the lane's rank
+// (mbcnt) and one store of the compacted run at a wave-uniform base.
 constexpr size_t SPLIT_GRID = 2048;  // workgroups of the split passes: 8 per CU
-constexpr int RING = 128;
 
 template <bool WRITE>
 __device__ __forceinline__ void split_segment(uint32_t sidx, const uint2* __restrict__ segmap,
                                               const uint4* __restrict__ coarse, const uint32_t* __restrict__ gstart,
                                               const uint32_t* __restrict__ gtotal, uint32_t* __restrict__ segcnt,
-                                              uint32_t* __restrict__ point_list, uint32_t* ring) {
+                                              uint32_t* __restrict__ point_list) {
     const uint2 gs = segmap[sidx];
     const int grp = (int)gs.x;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t base[16], staged[16], flushed[16];  // WRITE: run start, entries staged so far, entries stored
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        base[i] = WRITE ? segcnt[(size_t)sidx * 64 + wv * 16 + i] : 0u;
-        staged[i] = 0u;
-        flushed[i] = 0u;
-    }
     const uint32_t gt = gtotal[grp];
     const uint32_t e0 = min(gt, gs.y * SEG), e1 = min(gt, (gs.y + 1) * SEG);
     const uint32_t b0 = gstart[grp];
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (uint32_t k0 = e0; k0 < e1; k0 += 64) {
-        const uint32_t k = k0 + lane;
-        uint32_t g = 0, tmask = 0;
+    // the segment's entries in registers: entry e0 + 64 b + lane in slot b
+    constexpr int NB = SEG / 64;
+    uint32_t ids[NB], bits[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const uint32_t k = e0 + 64 * b + lane;
+        ids[b] = 0u;
+        bits[b] = 0u;
         if (k < e1) {
             const uint4 e = coarse[b0 + k];
-            g = e.x;
-            tmask = ((wv < 2 ? e.y : e.z) >> (16 * (wv & 1))) & 0xFFFFu;
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const bool in = (tmask >> i) & 1u;
-            const uint64_t m = ballot(in);
-            if (WRITE) {
-                if (in) ring[i * RING + ((staged[i] + (uint32_t)__builtin_popcountll(m & lt)) & (RING - 1))] = g;
-                staged[i] += (uint32_t)__builtin_popcountll(m);
-                if (staged[i] - flushed[i] >= 64u) {  // uniform
-                    point_list[base[i] + flushed[i] + lane] = ring[i * RING + ((flushed[i] + lane) & (RING - 1))];
-                    flushed[i] += 64u;
-                }
-            } else {
-                staged[i] += (uint32_t)__builtin_popcountll(m);
-            }
+            ids[b] = e.x;
+            bits[b] = ((wv < 2 ? e.y : e.z) >> (16 * (wv & 1))) & 0xFFFFu;
         }
     }
-    if (WRITE) {
+    for (int i = 0; i < 16; ++i) {
+        uint32_t run = __builtin_amdgcn_readfirstlane(WRITE ? segcnt[(size_t)sidx * 64 + wv * 16 + i] : 0u);
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if ((uint32_t)lane < staged[i] - flushed[i])
-                point_list[base[i] + flushed[i] + lane] = ring[i * RING + ((flushed[i] + lane) & (RING - 1))];
-    } else if (lane < 16) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) c = lane == i ? staged[i] : c;
-        segcnt[(size_t)sidx * 64 + wv * 16 + lane] = c;
+        for (int b = 0; b < NB; ++b) {
+            const bool in = (bits[b] >> i) & 1u;
+            const uint64_t m = ballot(in);
+            if (WRITE) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                uint32_t* dst = point_list + run;
+                if (in) dst[rank] = ids[b];
+            }
+            run = __builtin_amdgcn_readfirstlane(run + (uint32_t)__builtin_popcountll(m));
+        }
+        if (!WRITE && lane == 0) segcnt[(size_t)sidx * 64 + wv * 16 + i] = run;
     }
 }
 
@@ -910,15 +895,13 @@ __global__ __launch_bounds__(256) void k_seg_split(const uint64_t* __restrict__ 
                                                    uint32_t* __restrict__ point_list, const uint64_t* __restrict__ n_pairs,
                                                    uint64_t capacity, const uint64_t* __restrict__ coarse_n,
                                                    uint64_t coarse_cap, uint32_t max_segs) {
-    __shared__ uint32_t s_ring[WRITE ? 4 * 16 * RING : 1];  // per wave: 16 tiles x RING slots
     if (coarse_n[0] > coarse_cap) return;  // no coarse lists to split
     // the pair count is final here; a list that does not fit is not written
     // at all (the caller grows the buffer and builds again)
     if (WRITE && n_pairs[0] > capacity) return;
     const uint32_t nsg = (uint32_t)min(n_segs[0], (uint64_t)max_segs);
-    uint32_t* ring = s_ring + (WRITE ? (threadIdx.x >> 6) * 16 * RING : 0);
     for (uint32_t sidx = blockIdx.x; sidx < nsg; sidx += gridDim.x)
-        split_segment<WRITE>(sidx, segmap, coarse, gstart, gtotal, segcnt, point_list, ring);
+        split_segment<WRITE>(sidx, segmap, coarse, gstart, gtotal, segcnt, point_list);
 }
 
 // One workgroup per group, thread (part p, local tile i): p takes a

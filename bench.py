@@ -2,8 +2,11 @@
 """Benchmark of the balanced 3DGS rasterizer path on one MI355X.
 
 One step = the whole path on one synthetic frame, inputs resident in HBM:
-    project -> bin -> sort -> ranges -> queue -> render_fwd -> queue -> render_bwd
-(gradient buffers zeroed each step).  The workload is the imbalanced 1080p
+    project -> tile lists (bin + sort + ranges) -> queue -> render_fwd -> queue -> render_bwd
+(gradient buffers zeroed each step), issued without host synchronization
+(pipeline.FrameStep).  The timed steps replay the step captured once as a
+hipGraph; the same step launched eagerly, call by call, is timed too and
+gives the per-stage times, and the replays must reproduce its outputs.  The workload is the imbalanced 1080p
 scene: 1920x1080, 500k Gaussians (30% clustered in 5% of the screen, 1%
 large), 16x16 tiles, random upstream dL/dcolor ~ N(0,1).
 
@@ -59,8 +62,6 @@ def parse():
                          "variant: static | pixel | gauss | hybrid")
     ap.add_argument("--subtile", type=int, default=8)
     ap.add_argument("--order", default="cost")
-    ap.add_argument("--lists", default="fused", choices=["fused", "sort"],
-                    help="tile lists by the fused counting pass or by bin + radix sort + ranges")
     ap.add_argument("--no-static", action="store_true", help="skip the static-kernel comparison")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the run with exact ellipse-tile binning (bgs_tile_lists_exact)")
@@ -88,7 +89,7 @@ def main():
     import torch
 
     from paper_2412_17378_amd import bgs as B
-    from paper_2412_17378_amd.pipeline import Rasterizer, key_bits_for
+    from paper_2412_17378_amd.pipeline import FrameStep
     from workloads import scenes
 
     if not torch.cuda.is_available():
@@ -105,130 +106,60 @@ def main():
     g_in = {k: torch.from_numpy(getattr(scene, k)).to(dev).contiguous()
             for k in ("means3D", "log_scales", "quats", "opacity", "colors")}
     dL_dcolor = torch.from_numpy(scene.upstream()["dL_dcolor"]).to(dev).contiguous()
-    # one rasterizer (own list buffers) per tile rule
-    rasts = {"square": Rasterizer(dev, reuse_pairs=True), "ellipse": Rasterizer(dev, reuse_pairs=True)}
     stream = torch.cuda.current_stream()
 
     def make_step(fcfg, bcfg, binning="square"):
-        cfg, bcfg_ = fcfg, bcfg
-        rast = rasts[binning]
-        cfg_ready = B.make_cfg(fcfg.variant, fcfg.subtile, fcfg.order, tuple(scene.bg), flags=B.FLAG_QUEUE_READY)
-        bcfg_ready = B.make_cfg(bcfg.variant, bcfg.subtile, bcfg.order, tuple(scene.bg), flags=B.FLAG_QUEUE_READY)
-        nt = B.n_tiles(W, H)
-        P = scene.P
-        pr = dict(means2D=torch.empty(P, 2, device=dev), conic_opacity=torch.empty(P, 4, device=dev),
-                  rgb=torch.empty(P, 3, device=dev), depth=torch.empty(P, device=dev),
-                  radius=torch.empty(P, dtype=torch.int32, device=dev),
-                  tiles_touched=torch.empty(P, dtype=torch.int32, device=dev))
-        fwd = dict(color=torch.empty(3, H, W, device=dev), alpha=torch.empty(H, W, device=dev),
-                   depth=torch.empty(H, W, device=dev), final_T=torch.empty(H, W, device=dev),
-                   n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
-        grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
-                     rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
-        ranges = torch.empty(nt, 2, dtype=torch.int32, device=dev)
-        n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
-        conic = pr["conic_opacity"] if binning == "ellipse" else None
-        if conic is not None and args.lists != "fused":
-            raise SystemExit("exact ellipse-tile binning needs --lists fused")
-        state = {"rast": rast}
+        """A FrameStep (every buffer up front, no host sync inside a step) and the
+        state the rest of the benchmark reads."""
+        st = FrameStep(cam, g_in, scene.sh_degree, dL_dcolor, fcfg, bcfg, binning=binning)
+        state = {"step": st, "frame": st.frame, "rws": st.rws}
+        return st, state, st.pr, st.fwd, st.grads
 
-        def step(ev=None):
-            def mark(i):
-                if ev is not None:
-                    ev[i].record(stream)
-            mark(0)
-            B.bgs_project(cam, g_in["means3D"], g_in["log_scales"], g_in["quats"], g_in["opacity"], g_in["colors"],
-                          scene.sh_degree, pr["means2D"], pr["conic_opacity"], pr["rgb"], pr["depth"], pr["radius"],
-                          pr["tiles_touched"])
-            mark(1)
-            if args.lists == "fused":
-                lws = rast.ws.get("lists", B.bgs_tile_lists_workspace_bytes(W, H, P, rast.pair_capacity))
-                pl = rast.ws.get("svals", 4 * rast.pair_capacity).view(torch.int32)[:rast.pair_capacity]
-                B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], pl, ranges,
-                                 n_dev, lws, conic_opacity=conic)
-                mark(2)
-                mark(3)
-                mark(4)
-                # no host sync: the ranges address [0, M) of the whole buffer (all empty
-                # on overflow), and M is read once the steps are done
-                M = None
-                plist = pl
-            else:
-                ws = rast.ws.get("bin", B.bgs_bin_workspace_bytes(P))
-                cap = rast.pair_capacity
-                bufs = [rast.ws.get(r, 4 * cap).view(torch.int32)[:cap] for r in ("keys", "vals", "skeys", "svals")]
-                M = B.bgs_bin(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], bufs[0], bufs[1],
-                              ws)
-                mark(2)
-                sws = rast.ws.get("sort", B.bgs_sort_workspace_bytes(M))
-                B.bgs_sort(bufs[0], bufs[1], bufs[2], bufs[3], M, key_bits_for(nt), sws)
-                mark(3)
-                B.bgs_ranges(bufs[2], M, nt, ranges)
-                mark(4)
-                plist = bufs[3][:M]
-            frame = B.make_frame(W, H, ranges, plist, pr["means2D"], pr["conic_opacity"], pr["rgb"], pr["depth"])
-            rws = rast.ws.get("render", B.bgs_render_workspace_bytes(frame, cfg))
-            if cfg.variant != B.STATIC:
-                B.bgs_queue_build(frame, cfg, None, rws)
-            mark(5)
-            B.bgs_render_fwd(frame, cfg_ready, fwd["color"], fwd["alpha"], fwd["depth"], fwd["final_T"],
-                             fwd["n_contrib"], rws)
-            mark(6)
-            for g in grads.values():
-                g.zero_()
-            if bcfg_.variant != B.STATIC:
-                B.bgs_queue_build(frame, bcfg_, fwd["n_contrib"], rws)
-            mark(7)
-            B.bgs_render_bwd(frame, bcfg_ready, fwd["final_T"], fwd["n_contrib"], dL_dcolor, None, None,
-                             grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], rws)
-            mark(8)
-            state["M"] = M
-            state["n_dev"] = n_dev
-            state["frame_bufs"] = (ranges, plist)
-            state["frame"] = frame
-            state["rws"] = rws
-            return M
-
-        # size the pair buffers once, outside any timed region
-        B.bgs_project(cam, g_in["means3D"], g_in["log_scales"], g_in["quats"], g_in["opacity"], g_in["colors"],
-                      scene.sh_degree, pr["means2D"], pr["conic_opacity"], pr["rgb"], pr["depth"], pr["radius"],
-                      pr["tiles_touched"])
-        while True:
-            cap = rast.pair_capacity
-            lws0 = rast.ws.get("lists", B.bgs_tile_lists_workspace_bytes(W, H, P, cap))
-            pl0 = rast.ws.get("svals", 4 * cap).view(torch.int32)[:cap]
-            B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
-                             pl0 if cap else None, ranges, n_dev, lws0, conic_opacity=conic)
-            need = int(n_dev.item())
-            if need <= cap:
-                break
-            rast.pair_capacity = need
-        return step, state, pr, fwd, grads
-
-    def run(fcfg, bcfg, steps, warmup, binning="square"):
-        step, state, pr, fwd, grads = make_step(fcfg, bcfg, binning)
+    def run(fcfg, bcfg, steps, warmup, binning="square", graph=True):
+        """Eager steps with HIP events at the stage boundaries, then (graph) the
+        same step captured once and replayed: ms per step of both, and a check
+        that the replays reproduce the eager step's outputs."""
+        st, state, pr, fwd, grads = make_step(fcfg, bcfg, binning)
         for _ in range(warmup):
-            step()
+            st.run()
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(9)] for _ in range(steps)]
-        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(steps)]
         t0 = time.perf_counter()
         for k in range(steps):
-            step(evs[k])
+            st.run(lambda i, e=evs[k]: e[i].record(stream))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        if state["M"] is None:  # the fused lists' pair count, checked after the steps
-            M = int(state["n_dev"].item())
-            if M > state["rast"].pair_capacity:
-                raise RuntimeError("pair capacity exceeded")
-            state["M"] = M
-            state["frame_bufs"] = (state["frame_bufs"][0], state["frame_bufs"][1][:M])
-        names = ["project", "lists", "_", "_", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"] \
-            if args.lists == "fused" else \
-            ["project", "bin", "sort", "ranges", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"]
+        M = st.n_pairs()  # read once the steps are done
+        if M > st.capacity:
+            raise RuntimeError("pair capacity exceeded")
+        state["M"] = M
+        state["frame_bufs"] = (st.ranges, st.point_list[:M])
+        names = ["project", "lists", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"]
         stages = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
-                  for i, n in enumerate(names) if n != "_"}
-        return (t1 - t0) * 1e3 / steps, stages, state, pr, fwd, grads
+                  for i, n in enumerate(names)}
+        ms_eager = (t1 - t0) * 1e3 / steps
+        state["eager_ms"] = ms_eager
+        if graph:
+            ref_f = {k: v.clone() for k, v in fwd.items()}
+            ref_g = {k: v.clone() for k, v in grads.items()}
+            g = st.capture()
+            for _ in range(warmup):
+                g.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                g.replay()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            same_f = all(torch.equal(ref_f[k], fwd[k]) for k in fwd)
+            gerr = max(float((ref_g[k] - grads[k]).abs().max()) / (float(ref_g[k].abs().max()) + 1e-30)
+                       for k in grads)
+            state["graph_ms"] = (t1 - t0) * 1e3 / steps
+            state["graph_check"] = {"images_equal_eager": same_f, "max_rel_grad_diff_eager": gerr}
+            if not same_f or gerr > 1e-5:
+                raise RuntimeError(f"graph replay differs from the eager step: {state['graph_check']}")
+            del g
+        return ms_eager, stages, state, pr, fwd, grads
 
     bg = tuple(scene.bg)
     tuned = None
@@ -236,7 +167,7 @@ def main():
         # one step with a default configuration builds the frame, then the autotuner picks
         default = B.make_cfg("pixel", 8, "cost", bg)
         step0, st0, _, fwd0, grads0 = make_step(default, default)
-        step0()
+        step0.run()
         torch.cuda.synchronize()
         fcfg, bcfg, fms, bms = B.bgs_autotune(st0["frame"], default, fwd0, dL_dcolor, grads0, st0["rws"])
         tuned = {"forward": B.cfg_name(fcfg), "backward": B.cfg_name(bcfg), "forward_ms": fms, "backward_ms": bms}
@@ -246,10 +177,12 @@ def main():
         fcfg = bcfg = B.make_cfg(args.variant, args.subtile, args.order, bg)
     print(f"[bench] timed run: forward {B.cfg_name(fcfg)} backward {B.cfg_name(bcfg)} warmup={args.warmup} "
           f"steps={args.steps}", flush=True)
-    ms_step, stages, state, pr, fwd, grads = run(fcfg, bcfg, args.steps, args.warmup)
+    ms_eager, stages, state, pr, fwd, grads = run(fcfg, bcfg, args.steps, args.warmup)
+    ms_step = state["graph_ms"]  # the step as one hipGraph launch; eager (launch by launch) reported beside it
+    graph_check = state["graph_check"]
     M = state["M"]
-    print(f"[bench] balanced: {ms_step:.3f} ms/step, M={M}, stages " +
-          ", ".join(f"{k}={v:.3f}" for k, v in stages.items()), flush=True)
+    print(f"[bench] balanced: {ms_step:.3f} ms/step as one graph launch ({ms_eager:.3f} launched eagerly), M={M}, "
+          f"eager stages " + ", ".join(f"{k}={v:.3f}" for k, v in stages.items()), flush=True)
 
     # algorithmic blend counts: the oracle over the GPU's own lists (untimed)
     import oracle
@@ -272,18 +205,21 @@ def main():
     if not args.no_static:
         print("[bench] static run", flush=True)
         scfg = B.make_cfg("static", 16, "raster", bg)
-        ms_s, st_s, _, _, _, _ = run(scfg, scfg, max(3, args.steps // 2), 2)
-        static = dict(ms_per_step=ms_s, render_fwd_ms=st_s["render_fwd"], render_bwd_ms=st_s["render_bwd"])
-        print(f"[bench] static: {ms_s:.3f} ms/step, fwd {st_s['render_fwd']:.3f} ms, bwd {st_s['render_bwd']:.3f} ms",
-              flush=True)
+        ms_se, st_s, state_s, _, _, _ = run(scfg, scfg, max(3, args.steps // 2), 2)
+        ms_s = state_s["graph_ms"]
+        static = dict(ms_per_step=ms_s, eager_ms_per_step=ms_se, render_fwd_ms=st_s["render_fwd"],
+                      render_bwd_ms=st_s["render_bwd"])
+        print(f"[bench] static: {ms_s:.3f} ms/step as one graph launch ({ms_se:.3f} eagerly), "
+              f"fwd {st_s['render_fwd']:.3f} ms, bwd {st_s['render_bwd']:.3f} ms", flush=True)
 
     # the same step with exact ellipse-tile binning: identical images from shorter lists.  Its blends
     # are the entries its own pixel loops examine (fewer: the removed entries were all skipped), so
     # its value is not the headline's (which counts on the square rule's lists).
     exact = None
-    if not args.no_exact and args.lists == "fused":
+    if not args.no_exact:
         print("[bench] exact ellipse-tile binning run", flush=True)
-        ms_e, st_e, state_e, _, fwd_e, _ = run(fcfg, bcfg, args.steps, args.warmup, binning="ellipse")
+        ms_ee, st_e, state_e, _, fwd_e, _ = run(fcfg, bcfg, args.steps, args.warmup, binning="ellipse")
+        ms_e = state_e["graph_ms"]
         rg_e, pl_e = state_e["frame_bufs"][0].cpu().numpy(), state_e["frame_bufs"][1].cpu().numpy()
         of_e = oracle.render_fwd(W, H, rg_e, pl_e, m2, co, rgb, dep, bg=scene.bg)
         fb_e, bb_e = int(of_e["blends"]), int(of_e["n_contrib"].astype(np.int64).sum())
@@ -291,7 +227,7 @@ def main():
         del of_e
         same = all(torch.equal(fwd[k], fwd_e[k]) for k in ("color", "alpha", "depth", "final_T"))
         diff = max(float((fwd[k] - fwd_e[k]).abs().max()) for k in ("color", "alpha", "depth", "final_T"))
-        exact = {"n_pairs": state_e["M"], "ms_per_step": ms_e, "stages_ms": st_e,
+        exact = {"n_pairs": state_e["M"], "ms_per_step": ms_e, "eager_ms_per_step": ms_ee, "stages_ms": st_e,
                  "blends": {"fwd": fb_e, "bwd": bb_e}, "value": (fb_e + bb_e) / (ms_e * 1e-3),
                  "unit": "examined blends/s", "images_equal_square_rule": same, "max_abs_image_diff": diff,
                  "n_contrib_agreement_oracle": agree_e, "step_speedup_vs_square_rule": ms_step / ms_e}
@@ -412,6 +348,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "execution": {"timed": "the step captured once as a hipGraph, one replay per step",
+                      "eager_ms_per_step": ms_eager, **graph_check},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -419,7 +357,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_NAME, "scene": scene.name, "seed": scene.seed, "P": scene.P,
                    "width": W, "height": H, "n_pairs": M, "forward": B.cfg_name(fcfg),
-                   "backward": B.cfg_name(bcfg), "lists": args.lists},
+                   "backward": B.cfg_name(bcfg), "lists": "fused"},
         "autotune": tuned,
         "workload_stats": wstats,
         "blends": {"fwd": fwd_blends, "bwd": bwd_blends},

@@ -272,6 +272,125 @@ class BatchedPlan:
             pass
 
 
+class FrameStep:
+    """One training-shaped step on one view with every buffer allocated up
+    front and no host synchronization: project -> tile lists (bgs_tile_lists,
+    or bgs_tile_lists_exact with binning="ellipse") -> queue -> render_fwd ->
+    gradients zeroed -> queue -> render_bwd, on the current stream.  The pair
+    capacity is sized once by a synchronous build (headroom for later steps);
+    should a later step need more, its lists come out empty and n_pairs()
+    (a host read) exceeds capacity.  Because nothing in the step waits for
+    the GPU or allocates, capture() can record it once as a hipGraph that
+    replays the whole step with a single launch.
+
+    params: means3D [P,3], log_scales [P,3], quats [P,4], opacity [P],
+    colors [P,3] or [P,K,3] (device tensors, read each step, so they may be
+    updated in place between steps).  Outputs: self.pr (projection),
+    self.fwd (images), self.grads (gradients of the 2D splats)."""
+
+    def __init__(self, cam, params: dict, sh_degree: int, dL_dcolor, fcfg: B.RenderCfg, bcfg: B.RenderCfg,
+                 binning: str = "square", headroom: float = 1.25):
+        if binning not in ("square", "ellipse"):
+            raise ValueError(f"unknown binning {binning!r}")
+        W, H = int(cam.width), int(cam.height)
+        if not B.tile_lists_supported(W, H):
+            raise ValueError("FrameStep needs the fused list builder (tile grid too large)")
+        self.cam, self.params, self.sh_degree = cam, params, int(sh_degree)
+        self.W, self.H, self.binning = W, H, binning
+        self.dL_dcolor = dL_dcolor.contiguous()
+        dev = self.dL_dcolor.device
+        P = params["means3D"].shape[0]
+        self.P = P
+        self.fcfg, self.bcfg = fcfg, bcfg
+        self.fcfg_ready = B.make_cfg(fcfg.variant, fcfg.subtile, fcfg.order, tuple(fcfg.bg), flags=B.FLAG_QUEUE_READY)
+        self.bcfg_ready = B.make_cfg(bcfg.variant, bcfg.subtile, bcfg.order, tuple(bcfg.bg), flags=B.FLAG_QUEUE_READY)
+        self.pr = dict(means2D=torch.empty(P, 2, device=dev), conic_opacity=torch.empty(P, 4, device=dev),
+                       rgb=torch.empty(P, 3, device=dev), depth=torch.empty(P, device=dev),
+                       radius=torch.empty(P, dtype=torch.int32, device=dev),
+                       tiles_touched=torch.empty(P, dtype=torch.int32, device=dev))
+        self.fwd = dict(color=torch.empty(3, H, W, device=dev), alpha=torch.empty(H, W, device=dev),
+                        depth=torch.empty(H, W, device=dev), final_T=torch.empty(H, W, device=dev),
+                        n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
+        self.grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
+                          rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
+        self.ranges = torch.empty(B.n_tiles(W, H), 2, dtype=torch.int32, device=dev)
+        self.n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+        # size the pair buffers: build the lists until the capacity holds M
+        self._project()
+        cap = 0
+        while True:
+            self._alloc_lists(cap)
+            self._lists()
+            M = int(self.n_dev.item())
+            if M <= cap:
+                break
+            cap = int(M * headroom) + 1024
+        self.capacity = cap
+        self.frame = B.make_frame(W, H, self.ranges, self.point_list, self.pr["means2D"], self.pr["conic_opacity"],
+                                  self.pr["rgb"], self.pr["depth"])
+        rb = max(B.bgs_render_workspace_bytes(self.frame, fcfg), B.bgs_render_workspace_bytes(self.frame, bcfg))
+        self.rws = torch.empty(rb, dtype=torch.uint8, device=dev)
+
+    def _alloc_lists(self, cap):
+        dev = self.dL_dcolor.device
+        self.point_list = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)[:cap]
+        self.lws = torch.empty(B.bgs_tile_lists_workspace_bytes(self.W, self.H, self.P, cap), dtype=torch.uint8,
+                               device=dev)
+
+    def _project(self):
+        p, pr = self.params, self.pr
+        B.bgs_project(self.cam, p["means3D"], p["log_scales"], p["quats"], p["opacity"], p["colors"], self.sh_degree,
+                      pr["means2D"], pr["conic_opacity"], pr["rgb"], pr["depth"], pr["radius"], pr["tiles_touched"])
+
+    def _lists(self):
+        pr = self.pr
+        B.bgs_tile_lists(self.W, self.H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
+                         self.point_list if self.point_list.numel() else None, self.ranges, self.n_dev, self.lws,
+                         conic_opacity=pr["conic_opacity"] if self.binning == "ellipse" else None)
+
+    def run(self, mark=None):
+        """Issue one step; mark(i) (optional) is called at the stage
+        boundaries 0..6: before project, after project, after the lists,
+        after the forward queue, after the forward, after the backward queue
+        (gradients zeroed), after the backward."""
+        mark = mark or (lambda i: None)
+        mark(0)
+        self._project()
+        mark(1)
+        self._lists()
+        mark(2)
+        if self.fcfg.variant != B.STATIC:
+            B.bgs_queue_build(self.frame, self.fcfg, None, self.rws)
+        mark(3)
+        f = self.fwd
+        B.bgs_render_fwd(self.frame, self.fcfg_ready, f["color"], f["alpha"], f["depth"], f["final_T"],
+                         f["n_contrib"], self.rws)
+        mark(4)
+        for g in self.grads.values():
+            g.zero_()
+        if self.bcfg.variant != B.STATIC:
+            B.bgs_queue_build(self.frame, self.bcfg, f["n_contrib"], self.rws)
+        mark(5)
+        g = self.grads
+        B.bgs_render_bwd(self.frame, self.bcfg_ready, f["final_T"], f["n_contrib"], self.dL_dcolor, None, None,
+                         g["means2D"], g["conic_opacity"], g["rgb"], g["depth"], self.rws)
+        mark(6)
+
+    def n_pairs(self) -> int:
+        """M of the last step (reads the device; synchronizes)."""
+        return int(self.n_dev.item())
+
+    def capture(self) -> "torch.cuda.CUDAGraph":
+        """Record one step as a hipGraph; graph.replay() then runs the whole
+        step.  The step is run once first, outside the capture."""
+        self.run()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.run()
+        return graph
+
+
 class AdaptiveSelector:
     """The training-time selection policy of Sec. 4.4: start from the given
     configuration and, every `interval` calls, re-measure the candidates on

@@ -725,7 +725,10 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
                                                    uint4* __restrict__ coarse, const uint64_t* __restrict__ coarse_n,
                                                    uint64_t coarse_cap, const float* __restrict__ means2D,
                                                    const float4* __restrict__ conic_opacity) {
-    extern __shared__ uint32_t nextpos[];  // ng running slots, then (EXACT) one column run per tile row
+    extern __shared__ uint32_t nextpos[];  // ng running slots, then (EXACT) the row runs of 16 Gaussians
+    __shared__ uint32_t s_roff[EXACT ? 16 : 1];
+    __shared__ uint2 s_rect[EXACT ? 16 : 1];
+    __shared__ Ellipse s_ell[EXACT ? 16 : 1];
     if (coarse_n[0] > coarse_cap) return;  // the coarse lists do not fit: nothing is written
     const int ng = GX * GY;
     uint32_t* rowiv = nextpos + ng;
@@ -751,7 +754,43 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
             if (EXACT && n) el = make_ellipse(conic_opacity[g], means2D[2 * g], means2D[2 * g + 1]);
         }
         const int cntk = (int)((P - k0) < 64 ? (P - k0) : 64);
+        uint32_t roff = 0;  // EXACT: where this lane's Gaussian's row runs start in rowiv
         for (int i = 0; i < cntk; ++i) {
+            if (EXACT && (i & 15) == 0) {
+                // the column run of every tile row of Gaussians i .. i + 15, one
+                // (Gaussian, row) pair per lane, into rowiv
+                const bool mine = lane >= i && lane < i + 16 && el.proper;
+                const uint32_t nr = mine ? (rr.y >> 16) - (rr.x >> 16) + 1u : 0u;
+                uint32_t incl = nr;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t y = __shfl_up(incl, off, 64);
+                    if (lane >= off) incl += y;
+                }
+                const uint32_t nrows = __builtin_amdgcn_readlane(incl, 63);
+                roff = incl - nr;
+                if (lane >= i && lane < i + 16) {
+                    const int kk = lane - i;
+                    s_roff[kk] = roff;  // lanes past the Gaussians have nr = 0: offset nrows
+                    s_rect[kk] = rr;
+                    s_ell[kk] = el;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (uint32_t pr = lane; pr < nrows; pr += 64) {
+                    int kk = 0;  // the last of the 16 whose rows start at or before pr (s_roff[0] = 0)
+#pragma unroll
+                    for (int step = 8; step > 0; step >>= 1)
+                        if (s_roff[kk + step] <= pr) kk += step;  // kk + step <= 15
+                    const uint2 rk = s_rect[kk];
+                    const int row = (int)(rk.x >> 16) + (int)(pr - s_roff[kk]);
+                    rowiv[pr] = row_interval(s_ell[kk], row, (int)(rk.x & 0xFFFFu), (int)(rk.y & 0xFFFFu));
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
             const uint32_t ni = __builtin_amdgcn_readlane(n, i);
             if (ni == 0) continue;
             const uint32_t gi = __builtin_amdgcn_readlane(g, i);
@@ -759,24 +798,8 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
             const int wi = __builtin_amdgcn_readlane(x1, i) - xi + 1;
             const uint32_t ra = __builtin_amdgcn_readlane(rr.x, i), rb = __builtin_amdgcn_readlane(rr.y, i);
             const int tx0 = (int)(ra & 0xFFFF), ty0 = (int)(ra >> 16), tx1 = (int)(rb & 0xFFFF), ty1 = (int)(rb >> 16);
-            bool exact_i = false;
-            if (EXACT && __builtin_amdgcn_readlane((int)el.proper, i) != 0) {
-                // the column run of each of Gaussian i's tile rows, one row per lane
-                exact_i = true;
-                Ellipse ei{};
-                ei.b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.b), i));
-                ei.inv_a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.inv_a), i));
-                ei.det = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.det), i));
-                ei.xe = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.xe), i));
-                ei.ye = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.ye), i));
-                ei.yr = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.yr), i));
-                ei.mx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.mx), i));
-                ei.my = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, el.my), i));
-                for (int j = lane; j <= ty1 - ty0; j += 64) rowiv[j] = row_interval(ei, ty0 + j, tx0, tx1);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
+            const bool exact_i = EXACT && __builtin_amdgcn_readlane((int)el.proper, i) != 0;
+            const uint32_t roff_i = EXACT ? __builtin_amdgcn_readlane(roff, i) : 0u;  // row ty0's run in rowiv
             const float inv_w = 1.0f / (float)wi;
             for (uint32_t j = lane; j < ni; j += 64) {
                 int q = (int)((float)j * inv_w);
@@ -796,7 +819,7 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
                 if (EXACT && exact_i) {
                     mask = 0u;
                     for (int r = rl; r < rh; ++r) {
-                        const uint32_t iv = rowiv[by + r - ty0];
+                        const uint32_t iv = rowiv[roff_i + (uint32_t)(by + r - ty0)];
                         const int c0 = max((int)(iv & 0xFFFFu) - bx, 0), c1 = min((int)(iv >> 16) - bx, GTILES);
                         if (c0 < c1) mask |= (uint64_t)(((1u << c1) - 1u) & ~((1u << c0) - 1u)) << (GTILES * r);
                     }
@@ -1034,7 +1057,7 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
     if (L.ng > MAX_GROUPS || (size_t)(L.GX + 1) * (L.GY + 1) * sizeof(int) > 65536 || TX > 65535 || TY > 65535)
         return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: tile grid too large (over 8192 groups of 8x8 tiles); use "
                                       "bgs_bin + bgs_sort + bgs_ranges");
-    if (conic_opacity && sizeof(uint32_t) * ((size_t)L.ng + TY) > 65536)
+    if (conic_opacity && sizeof(uint32_t) * ((size_t)L.ng + 16 * (size_t)TY) > 60000)
         return fail(BGS_EUNSUPPORTED, "bgs_tile_lists_exact: tile grid too large for the exact rule");
     BGS_REQUIRE(ws && ws_bytes >= L.bytes, "bgs_tile_lists: workspace too small");
     BGS_REQUIRE(capacity == 0 || point_list != nullptr, "bgs_tile_lists: null point_list");
@@ -1094,7 +1117,7 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
     hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(nbg)), dim3(256), 0, stream, L.C, L.ng, gstart, part, h);
     BGS_HIP(hipGetLastError());
     if (conic_opacity)
-        hipLaunchKernelGGL(k_chunk_emit<true>, dim3(L.C), dim3(64), sizeof(uint32_t) * ((size_t)L.ng + TY), stream, P,
+        hipLaunchKernelGGL(k_chunk_emit<true>, dim3(L.C), dim3(64), sizeof(uint32_t) * ((size_t)L.ng + 16 * TY), stream, P,
                            L.GX, L.GY, order, rect, h, coarse, (const uint64_t*)mg, ccap, means2D, co4);
     else
         hipLaunchKernelGGL(k_chunk_emit<false>, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX,

@@ -23,16 +23,16 @@ namespace bgs {
 // Depth order of the Gaussians: a stable sort of 32-bit keys (positive fp32
 // depths order like their bit patterns; Gaussians with no pairs get the
 // largest key and go last), so equal depths keep id order.  LSD radix sort,
-// four passes of 8 bits, over blocks of DS_TILE consecutive items (1024
-// threads; wave w of the block owns items [256 w, 256 w + 256), 64 at a
-// time).  Per pass: every block's digit histogram (the first one fused into
+// four passes of 8 bits, over blocks of DS_TILE = 2048 consecutive items
+// (512 threads; wave w of the block owns items [256 w, 256 w + 256), 64 at a
+// time: 245 blocks at P = 500 k, so every pass spreads over the CUs).  Per pass: every block's digit histogram (the first one fused into
 // the key generation), an exclusive scan of each digit's counts over the
 // blocks, and a scatter in which each block ranks its items stably in LDS
 // (ballots over the 8 digit bits find the lanes with the same digit) and
 // writes them out as per-digit runs.  Grids depend on P alone and nothing is
 // cleared with a memset, so the sort can be captured into a graph.
 // ----------------------------------------------------------------------
-constexpr int DS_THREADS = 1024;
+constexpr int DS_THREADS = 512;
 constexpr int DS_WAVES = DS_THREADS / 64;
 constexpr int DS_TILE = DS_THREADS * 4;
 constexpr int DS_RADIX = 256;

@@ -216,7 +216,7 @@ size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P, 
  * 8x8 tiles (per-chunk group histograms from 2D difference arrays, a column
  * scan over chunks, in-order placement) builds coarse per-group lists, and
  * the coarse lists are split into the 64 tile lists of each group by ordered
- * ballot compaction, one workgroup per segment of 1024 coarse entries.
+ * ballot compaction, one workgroup per segment of 2048 coarse entries.
  *   point_list [capacity] Gaussian ids, ranges [n_tiles][2] (empty: (0, 0)),
  *   n_pairs_dev (DEVICE, uint64[1]) receives M.
  * Never synchronizes: every size the kernels need stays on the device and

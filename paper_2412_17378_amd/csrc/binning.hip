@@ -835,7 +835,7 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
 // The fine split runs on segments of SEG consecutive coarse entries of one
 // group, so that a heavily covered group does not serialize on one
 // workgroup.  nseg[g] = ceil(gtotal[g] / SEG).
-constexpr int SEG = 1024;
+constexpr int SEG = 2048;
 
 __global__ __launch_bounds__(256) void k_seg_count(int ng, const uint32_t* __restrict__ gtotal,
                                                    uint32_t* __restrict__ nseg) {
@@ -861,7 +861,7 @@ __global__ __launch_bounds__(256) void k_seg_map(int ng, const uint32_t* __restr
 // at a time, the ballot of the entries whose mask holds the tile.
 // COUNT: segcnt[seg][i] = the segment's entries whose mask holds tile i.
 // WRITE: the k-th such entry goes to segcnt[seg][i] (by then the slot where
-// the segment's run of tile i starts) + k.  Each lane keeps its 16 entries of
+// the segment's run of tile i starts) + k.  Each lane keeps its 32 entries of
 // the segment in registers and the wave takes its tiles one after another,
 // so a (tile, 64 entries) step is a bit test, a ballot, the lane's rank
 // (mbcnt) and one store of the compacted run at a wave-uniform base.

@@ -311,11 +311,12 @@ class FrameStep:
         self.fwd = dict(color=torch.empty(3, H, W, device=dev), alpha=torch.empty(H, W, device=dev),
                         depth=torch.empty(H, W, device=dev), final_T=torch.empty(H, W, device=dev),
                         n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
-        # the four gradient buffers are views of one allocation: one fill zeroes them
-        self._grad_buf = torch.zeros(P * 10, device=dev)
-        gb = self._grad_buf
-        self.grads = dict(means2D=gb[4 * P:6 * P].view(P, 2), conic_opacity=gb[:4 * P].view(P, 4),
-                          rgb=gb[6 * P:9 * P].view(P, 3), depth=gb[9 * P:])  # conic first: 16-byte aligned
+        # separate allocations (the backward's atomics spread better over the
+        # memory channels than with the four in one buffer), zeroed by one
+        # multi-tensor fill
+        self.grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
+                          rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
+        self._grad_list = list(self.grads.values())
         self.ranges = torch.empty(B.n_tiles(W, H), 2, dtype=torch.int32, device=dev)
         self.n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         # size the pair buffers: build the lists until the capacity holds M
@@ -369,7 +370,7 @@ class FrameStep:
         B.bgs_render_fwd(self.frame, self.fcfg_ready, f["color"], f["alpha"], f["depth"], f["final_T"],
                          f["n_contrib"], self.rws)
         mark(4)
-        self._grad_buf.zero_()
+        torch._foreach_zero_(self._grad_list)
         if self.bcfg.variant != B.STATIC:
             B.bgs_queue_build(self.frame, self.bcfg, f["n_contrib"], self.rws)
         mark(5)

@@ -258,6 +258,45 @@ def main():
     pbwd_ms = project_bwd_ms()
     print(f"[bench] project_bwd (supplementary): {pbwd_ms:.3f} ms", flush=True)
 
+    # supplementary: the deterministic-order backward on the same frame (one host sync per call, included)
+    def det_bwd():
+        st = state["step"]
+        dcfg = B.make_cfg("pixel", 16, "cost", bg)
+        P = scene.P
+        f = st.fwd
+        gd = [torch.zeros(P, n, device=dev) for n in (2, 4, 3)] + [torch.zeros(P, device=dev)]
+        cap = 1 << 20
+        for _ in range(2):
+            ws = torch.empty(B.bgs_render_bwd_det_workspace_bytes(st.frame, P, cap), dtype=torch.uint8, device=dev)
+            try:
+                B.bgs_render_bwd_det(st.frame, dcfg, P, f["final_T"], f["n_contrib"], dL_dcolor, None, None, *gd, cap,
+                                     ws)
+                break
+            except B.BgsError as e:
+                if e.status != B.BGS_ECAPACITY:
+                    raise
+                cap = int(e.n_occ * 1.25) + 1024
+        runs, snaps = 10, []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(runs):
+            for g in gd:
+                g.zero_()
+            K = B.bgs_render_bwd_det(st.frame, dcfg, P, f["final_T"], f["n_contrib"], dL_dcolor, None, None, *gd,
+                                     cap, ws)
+            if r < 2:
+                torch.cuda.synchronize()
+                snaps.append([g.clone() for g in gd])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / runs
+        same = all(torch.equal(a, b) for a, b in zip(*snaps))
+        return {"ms": ms, "walked_entries": K, "repeatable_bit_for_bit": same, "config": B.cfg_name(dcfg),
+                "note": "includes the gradient zeroing and the call's one host synchronization"}
+
+    det = det_bwd()
+    print(f"[bench] deterministic backward (supplementary): {det['ms']:.3f} ms, {det['walked_entries']} walked "
+          f"entries, repeatable: {det['repeatable_bit_for_bit']}", flush=True)
+
     # per-CU load balance of the render kernels: one traced run of each (untimed)
     def cu_balance(fcfg_, bcfg_):
         frame, rws = state["frame"], state["rws"]
@@ -370,6 +409,7 @@ def main():
         "exact_binning": exact,
         "cu_balance": {"tuned": balance, "static": balance_static},
         "project_bwd_ms": pbwd_ms,
+        "deterministic_backward": det,
         "batched_views": batched,
         "speedup_vs_static": (None if static is None else
                               {"render_fwd": static["render_fwd_ms"] / stages["render_fwd"],

@@ -308,6 +308,31 @@ bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cfg* cfg, con
                           const float* dL_ddepth, float* dL_dmeans2D, float* dL_dconic_opacity, float* dL_drgb,
                           float* dL_ddepths, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Workspace bytes of bgs_render_bwd_det for P Gaussians and up to max_occ
+ * walked (tile, list entry) pairs. */
+size_t bgs_render_bwd_det_workspace_bytes(const bgs_frame* frame, int64_t P, int64_t max_occ);
+
+/*
+ * Deterministic-order backward: the derivative bgs_render_bwd computes (same
+ * arguments and += semantics; P = number of Gaussians, every id in the lists
+ * below P), with gradients that are identical from run to run.  One wave per
+ * 16x16 tile (cfg: BGS_BALANCED_PIXEL with subtile 16, else
+ * BGS_EUNSUPPORTED) reduces each walked list entry's ten values over the
+ * tile's pixels in a fixed order and stores them in the entry's own slot
+ * instead of adding them with atomics (the wave-level pre-reduction of
+ * backward atomics the paper cites, Sec. 3, kept, and the summation order
+ * fixed); the (Gaussian, slot) pairs are sorted stably by Gaussian and one
+ * wave per Gaussian sums its slots in (tile, list position) order.
+ * SYNCHRONIZES the stream once, to read K = the number of walked (tile,
+ * entry) pairs (sum over tiles of the largest n_contrib of the tile) into
+ * *n_occ_host; K > max_occ returns BGS_ECAPACITY with nothing written.
+ */
+bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_render_cfg* cfg, int64_t P, const float* final_T,
+                              const int32_t* n_contrib, const float* dL_dcolor, const float* dL_dalpha,
+                              const float* dL_ddepth, float* dL_dmeans2D, float* dL_dconic_opacity, float* dL_drgb,
+                              float* dL_ddepths, int64_t max_occ, int64_t* n_occ_host, void* ws, size_t ws_bytes,
+                              hipStream_t stream);
+
 /*
  * Variant selection by measurement (the self-adaptive kernel selection of
  * Sec. 4.4, generalized): runs every forward candidate (static; pixel-wise 8x8

@@ -90,6 +90,9 @@ def lib() -> C.CDLL:
             "bgs_queue_build": ([_vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_render_fwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_render_bwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
+            "bgs_render_bwd_det_workspace_bytes": ([_vp, _i64, _i64], _sz),
+            "bgs_render_bwd_det": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _sz,
+                                    _vp], C.c_int),
             "bgs_autotune": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, C.c_char_p, _vp, _vp,
                               _vp, _vp, _vp], C.c_int),
             "bgs_plan_create": ([_vp, _i32, _vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -110,7 +113,7 @@ def exported_symbols():
             "bgs_sort_workspace_bytes", "bgs_sort", "bgs_ranges", "bgs_tile_lists_workspace_bytes", "bgs_tile_lists",
             "bgs_tile_lists_exact", "bgs_render_workspace_bytes", "bgs_queue_build", "bgs_autotune", "bgs_plan_create", "bgs_plan_launch",
             "bgs_plan_destroy",
-            "bgs_render_fwd", "bgs_render_bwd"]
+            "bgs_render_fwd", "bgs_render_bwd", "bgs_render_bwd_det_workspace_bytes", "bgs_render_bwd_det"]
 
 
 def _check(fn: str, st: int):
@@ -385,6 +388,34 @@ def bgs_plan_destroy(plan):
 def cfg_name(c: RenderCfg) -> str:
     names = {v: k for k, v in VARIANTS.items()}
     return f"{names.get(c.variant, c.variant)}{c.subtile}/{'cost' if c.order == ORDER_COST else 'raster'}"
+
+
+def bgs_render_bwd_det_workspace_bytes(frame: Frame, P: int, max_occ: int) -> int:
+    return int(lib().bgs_render_bwd_det_workspace_bytes(C.byref(frame), int(P), int(max_occ)))
+
+
+def bgs_render_bwd_det(frame: Frame, cfg: RenderCfg, P: int, final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth,
+                       dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepths, max_occ: int, ws, stream=None) -> int:
+    """Deterministic-order backward (see include/bgs.h); returns the number of
+    walked (tile, entry) pairs.  Raises BgsError (status BGS_ECAPACITY, with
+    .n_occ set) when they exceed max_occ."""
+    H, W = frame.height, frame.width
+    _expect(final_T, (H, W), torch.float32, "final_T")
+    _expect(n_contrib, (H, W), torch.int32, "n_contrib")
+    _expect(dL_dcolor, (3, H, W), torch.float32, "dL_dcolor")
+    _expect(dL_dalpha, (H, W), torch.float32, "dL_dalpha")
+    _expect(dL_ddepth, (H, W), torch.float32, "dL_ddepth")
+    n = C.c_int64(0)
+    st = lib().bgs_render_bwd_det(C.byref(frame), C.byref(cfg), int(P), _ptr(final_T), _ptr(n_contrib),
+                                  _ptr(dL_dcolor), _ptr(dL_dalpha), _ptr(dL_ddepth), _ptr(_nonempty(dL_dmeans2D)),
+                                  _ptr(_nonempty(dL_dconic_opacity)), _ptr(_nonempty(dL_drgb)),
+                                  None if dL_ddepths is None else _ptr(_nonempty(dL_ddepths)), int(max_occ),
+                                  C.byref(n), _ptr(ws), ws.numel(), _stream(stream))
+    if st != BGS_OK:
+        e = BgsError("bgs_render_bwd_det", st, lib().bgs_last_error().decode(errors="replace"))
+        e.n_occ = n.value
+        raise e
+    return n.value
 
 
 def bgs_render_bwd(frame: Frame, cfg: RenderCfg, final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dmeans2D,

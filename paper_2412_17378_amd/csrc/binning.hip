@@ -186,6 +186,35 @@ __global__ __launch_bounds__(DS_THREADS) void k_ds_scatter(int64_t P, const uint
     }
 }
 
+// Stable sort of n (key, value) pairs by the low `bits` bits of the key with
+// the same passes (ceil(bits / 8) of them, first histogram included).  The
+// pairs start in (k0, v0); the sorted pairs end in (k0, v0) or (k1, v1):
+// *in_second tells which.  cnt [256 ds_blocks(n)] and tot [256] are scratch.
+bgs_status radix_sort_pairs_u32(int64_t n, int bits, uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                                uint32_t* cnt, uint32_t* tot, bool* in_second, hipStream_t stream) {
+    *in_second = false;
+    if (n <= 0) return BGS_OK;
+    const int nb = ds_blocks(n);
+    const int passes = bits <= 0 ? 0 : (bits + 7) / 8;
+    uint32_t *kin = k0, *vin = v0, *kout = k1, *vout = v1;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_ds_hist, dim3(nb), dim3(DS_THREADS), 0, stream, n, (const uint32_t*)kin, shift, cnt, nb);
+        BGS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_ds_colscan, dim3(DS_RADIX), dim3(256), 0, stream, nb, cnt, tot);
+        BGS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_ds_scatter<true>, dim3(nb), dim3(DS_THREADS), 0, stream, n, (const uint32_t*)kin,
+                           (const uint32_t*)vin, kout, vout, shift, (const uint32_t*)cnt, (const uint32_t*)tot, nb);
+        BGS_HIP(hipGetLastError());
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+        *in_second = !*in_second;
+    }
+    return BGS_OK;
+}
+
+size_t radix_sort_pairs_u32_scratch(int64_t n) { return 4 * ((size_t)DS_RADIX * ds_blocks(n > 0 ? n : 1) + DS_RADIX); }
+
 // Sorted Gaussian ids into order[P]; keys / keys2 / ids2 [P] are scratch,
 // cnt [256 ds_blocks(P)] and tot [256] the histograms.
 static bgs_status depth_order(int64_t P, const float* depth, const uint32_t* tiles_touched, uint32_t* keys,

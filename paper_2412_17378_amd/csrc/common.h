@@ -189,6 +189,13 @@ __device__ __forceinline__ int wave_reduce_scatter10(const float (&v)[10], int l
     return scatter10_slot(lane);
 }
 
+// Stable LSD radix sort of n (key, value) pairs by the low `bits` key bits
+// (binning.hip): the result is in (k0, v0), or in (k1, v1) when *in_second.
+// cnt and tot: radix_sort_pairs_u32_scratch(n) bytes.
+bgs_status radix_sort_pairs_u32(int64_t n, int bits, uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                                uint32_t* cnt, uint32_t* tot, bool* in_second, hipStream_t stream);
+size_t radix_sort_pairs_u32_scratch(int64_t n);
+
 __device__ __forceinline__ int wave_max(int v) {
     for (int off = 32; off >= 1; off >>= 1) {
         int o = __shfl_xor(v, off, 64);

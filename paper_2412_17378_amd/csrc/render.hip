@@ -26,6 +26,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprim/block/block_scan.hpp>
+
 #include "common.h"
 
 namespace bgs {
@@ -66,6 +68,10 @@ struct BwdIO {
     float* __restrict__ g_conic_opacity;
     float* __restrict__ g_rgb;
     float* __restrict__ g_depth;
+    // deterministic backward only: one 10-float partial per (tile, walked
+    // entry), at slot det_base[tile] + entry
+    float* __restrict__ det_partials;
+    const uint32_t* __restrict__ det_base;
 };
 
 // One view of a batched plan: its frame, forward outputs and backward I/O.
@@ -727,7 +733,10 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
 // instead of once per 64, and dx (shared by a lane's four pixels) once per
 // entry.  Each pixel's arithmetic is the same as in k_bwd_pixel.
 
-template <bool MV = false>
+// DET: instead of adding its per-entry totals to the gradients, the wave
+// stores them (zeros for an entry no pixel blends) at the entry's slot of
+// B.det_partials, for an ordered reduction afterwards.
+template <bool MV = false, bool DET = false>
 __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const ViewDesc* __restrict__ views,
                                                   const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
     const uint64_t t_begin = trace_begin(F0);
@@ -749,6 +758,8 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
         const uint32_t start = F.ranges[2 * tile];
         const int len = (int)(F.ranges[2 * tile + 1] - start);
         const GradLane GL = grad_lane(B, scatter10_slot(lane));
+        const int dslot = scatter10_slot(lane);
+        float* const dpart = DET ? B.det_partials + (size_t)B.det_base[tile] * 10 + dslot : nullptr;
         float T[WQ], R0[WQ], R1[WQ], R2[WQ], Rd[WQ], gC0[WQ], gC1[WQ], gC2[WQ], gD[WQ], kc[WQ], fy[WQ];
         int nc[WQ];
         int my_max = 0;
@@ -805,7 +816,10 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
                     contrib[q] = (j < nc[q]) && !(p2 > 0.0f || alpha[q] < ALPHA_MIN);
                     anyc |= contrib[q];
                 }
-                if (ballot(anyc) == 0) continue;
+                if (ballot(anyc) == 0) {
+                    if (DET && dslot >= 0) dpart[(size_t)j * 10] = 0.0f;
+                    continue;
+                }
                 const float4 cd = s_cd[wv][jj];
                 const float4 abc = s_abc[wv][jj];
                 float v[10];
@@ -838,7 +852,11 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
                 }
                 float tot;
                 wave_reduce_scatter10(v, lane, tot);
-                if (GL.base) unsafeAtomicAdd(GL.base + (size_t)__float_as_uint(abc.w) * GL.stride, tot);
+                if (DET) {
+                    if (dslot >= 0) dpart[(size_t)j * 10] = tot;
+                } else if (GL.base) {
+                    unsafeAtomicAdd(GL.base + (size_t)__float_as_uint(abc.w) * GL.stride, tot);
+                }
             }
             wave_sync();
         }
@@ -1142,6 +1160,223 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
         hipLaunchKernelGGL(k_bwd_pixel<true>, dim3(blocks), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
                            items, ctr);
     }
+    BGS_HIP(hipGetLastError());
+    return BGS_OK;
+}
+
+// ======================================================================
+// Deterministic-order backward.  The wide backward (one wave per 16x16
+// tile) produces, for every list entry a tile walks, one 10-value partial
+// from a fixed-order wave reduction; instead of adding it to the Gaussian's
+// gradient with float atomics (whose order varies from run to run), it is
+// stored at its own slot.  The (Gaussian, slot) pairs are then sorted stably
+// by Gaussian, so each Gaussian's partials come in (tile, list position)
+// order, and one wave per Gaussian sums them in a fixed order and adds the
+// sums to the gradients.  The result is the same sum up to fp32 rounding and
+// identical from run to run.
+// ======================================================================
+namespace bgs {
+
+// cnt[t] = the entries the wide backward walks in tile t: the largest
+// n_contrib of its pixels, clamped to its list (one workgroup per tile)
+__global__ __launch_bounds__(256) void k_det_count(FrameArgs F, const int* __restrict__ n_contrib,
+                                                   uint32_t* __restrict__ cnt) {
+    __shared__ int wmax[4];
+    const int t = blockIdx.x;
+    const int px = (t % F.TX) * TILE + (threadIdx.x & 15), py = (t / F.TX) * TILE + (threadIdx.x >> 4);
+    const int len = (int)(F.ranges[2 * t + 1] - F.ranges[2 * t]);
+    int n = 0;
+    if (px < F.W && py < F.H) {
+        n = n_contrib[(int64_t)py * F.W + px];
+        n = n < 0 ? 0 : (n > len ? len : n);
+    }
+    n = wave_max(n);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[t] = (uint32_t)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+}
+
+// base = exclusive scan of cnt over the tiles; total[0] = the sum (one workgroup)
+__global__ __launch_bounds__(1024) void k_det_scan(int nt, const uint32_t* __restrict__ cnt,
+                                                   uint32_t* __restrict__ base, uint64_t* __restrict__ total) {
+    using Scan = rocprim::block_scan<uint64_t, 1024>;
+    __shared__ typename Scan::storage_type s_scan;
+    const int per = (nt + 1023) / 1024;
+    const int t0 = min(nt, (int)threadIdx.x * per), t1 = min(nt, t0 + per);
+    uint64_t sum = 0;
+    for (int t = t0; t < t1; ++t) sum += cnt[t];
+    uint64_t run = 0, grand = 0;
+    Scan().exclusive_scan(sum, run, (uint64_t)0, grand, s_scan);
+    for (int t = t0; t < t1; ++t) {
+        base[t] = (uint32_t)run;
+        run += cnt[t];
+    }
+    if (threadIdx.x == 0) total[0] = grand;
+}
+
+// (Gaussian id, slot) of every walked entry, in slot order; one wave per tile
+__global__ __launch_bounds__(64) void k_det_keys(FrameArgs F, const uint32_t* __restrict__ cnt,
+                                                 const uint32_t* __restrict__ base, uint32_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ vals) {
+    const int t = blockIdx.x;
+    const uint32_t b = base[t], c = cnt[t], start = F.ranges[2 * t];
+    for (uint32_t j = threadIdx.x; j < c; j += 64) {
+        keys[b + j] = F.point_list[start + j];
+        vals[b + j] = b + j;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_det_clear(int64_t P, uint32_t* __restrict__ seg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2 * P) seg[i] = 0u;
+}
+
+// seg[2g], seg[2g + 1] = the first and one past the last position of
+// Gaussian g among the sorted keys (0, 0 when it has none)
+__global__ __launch_bounds__(256) void k_det_bounds(int64_t K, int64_t P, const uint32_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ seg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K) return;
+    const uint32_t g = keys[i];
+    if ((int64_t)g >= P) return;
+    if (i == 0 || keys[i - 1] != g) seg[2 * (size_t)g] = (uint32_t)i;
+    if (i == K - 1 || keys[i + 1] != g) seg[2 * (size_t)g + 1] = (uint32_t)(i + 1);
+}
+
+// One wave per Gaussian: lane l sums partials l, l + 64, ... of the
+// Gaussian's run in order, a fixed butterfly combines the lanes, and the
+// sums are added to the gradients (one writer per element).
+__global__ __launch_bounds__(256) void k_det_reduce(int64_t P, const uint32_t* __restrict__ seg,
+                                                    const uint32_t* __restrict__ vals,
+                                                    const float* __restrict__ partials, BwdIO B) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= P) return;  // uniform per wave
+    const uint32_t s = seg[2 * g], e = seg[2 * g + 1];
+    float v[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) v[k] = 0.0f;
+    for (uint32_t i = s + lane; i < e; i += 64) {
+        const float* pp = partials + (size_t)vals[i] * 10;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) v[k] += pp[k];
+    }
+    float tot;
+    const int slot = wave_reduce_scatter10(v, lane, tot);
+    const GradLane GL = grad_lane(B, slot);
+    if (GL.base) GL.base[(size_t)g * GL.stride] += tot;
+}
+
+struct DetLayout {
+    RenderLayout R;
+    size_t cnt, base, total, partials, keys, vals, keys2, vals2, sscr, scr_bytes, seg, bytes;
+};
+
+static DetLayout det_layout(int n_tiles, int64_t P, int64_t max_occ) {
+    DetLayout D{};
+    D.R = render_layout(n_tiles);
+    size_t off = D.R.bytes;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off = align_up(off + b, 256);
+        return o;
+    };
+    const size_t m = (size_t)(max_occ > 0 ? max_occ : 1), nt = (size_t)(n_tiles > 0 ? n_tiles : 1);
+    D.cnt = take(4 * nt);
+    D.base = take(4 * nt);
+    D.total = take(8);
+    D.partials = take(40 * m);
+    D.keys = take(4 * m);
+    D.vals = take(4 * m);
+    D.keys2 = take(4 * m);
+    D.vals2 = take(4 * m);
+    D.scr_bytes = radix_sort_pairs_u32_scratch((int64_t)m);  // digit counts, then 256 digit totals
+    D.sscr = take(D.scr_bytes);
+    D.seg = take(8 * (size_t)(P > 0 ? P : 1));
+    D.bytes = off;
+    return D;
+}
+
+}  // namespace bgs
+
+extern "C" size_t bgs_render_bwd_det_workspace_bytes(const bgs_frame* frame, int64_t P, int64_t max_occ) {
+    if (!frame || frame->width <= 0 || frame->height <= 0 || P < 0 || max_occ < 0) return 0;
+    const int n_tiles = ((frame->width + TILE - 1) / TILE) * ((frame->height + TILE - 1) / TILE);
+    return det_layout(n_tiles, P, max_occ).bytes;
+}
+
+extern "C" bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_render_cfg* cfg, int64_t P,
+                                         const float* final_T, const int32_t* n_contrib, const float* dL_dcolor,
+                                         const float* dL_dalpha, const float* dL_ddepth, float* dL_dmeans2D,
+                                         float* dL_dconic_opacity, float* dL_drgb, float* dL_ddepths,
+                                         int64_t max_occ, int64_t* n_occ_host, void* ws, size_t ws_bytes,
+                                         hipStream_t stream) {
+    FrameArgs A;
+    bgs_status st = check_frame(frame, cfg, A, "bgs_render_bwd_det");
+    if (st != BGS_OK) return st;
+    if (!tile_items(cfg))
+        return fail(BGS_EUNSUPPORTED, "bgs_render_bwd_det: needs BGS_BALANCED_PIXEL with subtile 16 "
+                                      "(one wave per tile)");
+    BGS_REQUIRE(P >= 0 && max_occ >= 0 && n_occ_host, "bgs_render_bwd_det: bad P, max_occ or n_occ_host");
+    BGS_REQUIRE(P < ((int64_t)1 << 32) && max_occ < ((int64_t)1 << 32), "bgs_render_bwd_det: sizes must be < 2^32");
+    BGS_REQUIRE(final_T && n_contrib && dL_dcolor, "bgs_render_bwd_det: null forward state or dL_dcolor");
+    BGS_REQUIRE(dL_dmeans2D && dL_dconic_opacity && dL_drgb, "bgs_render_bwd_det: null gradient output");
+    const DetLayout D = det_layout(A.n_tiles, P, max_occ);
+    BGS_REQUIRE(ws && ws_bytes >= D.bytes, "bgs_render_bwd_det: workspace too small");
+    char* w = static_cast<char*>(ws);
+    *n_occ_host = 0;
+    if (!(cfg->flags & BGS_FLAG_QUEUE_READY)) {
+        st = build_queue(A, cfg, n_contrib, w, D.R, stream);
+        if (st != BGS_OK) return st;
+    }
+    auto* cnt = reinterpret_cast<uint32_t*>(w + D.cnt);
+    auto* base = reinterpret_cast<uint32_t*>(w + D.base);
+    auto* total = reinterpret_cast<uint64_t*>(w + D.total);
+    if (A.n_tiles == 0) return BGS_OK;
+    hipLaunchKernelGGL(k_det_count, dim3(A.n_tiles), dim3(256), 0, stream, A, n_contrib, cnt);
+    BGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_det_scan, dim3(1), dim3(1024), 0, stream, A.n_tiles, cnt, base, total);
+    BGS_HIP(hipGetLastError());
+    uint64_t K = 0;
+    BGS_HIP(hipMemcpyAsync(&K, total, sizeof(K), hipMemcpyDeviceToHost, stream));
+    BGS_HIP(hipStreamSynchronize(stream));
+    *n_occ_host = (int64_t)K;
+    if ((int64_t)K > max_occ)
+        return fail(BGS_ECAPACITY, "bgs_render_bwd_det: " + std::to_string(K) + " walked entries exceed max_occ " +
+                                       std::to_string(max_occ));
+    if (K == 0 || P == 0) return BGS_OK;
+    auto* partials = reinterpret_cast<float*>(w + D.partials);
+    BwdIO B{final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepths,
+            partials, base};
+    auto* ctr = reinterpret_cast<uint32_t*>(w + D.R.ctr);
+    auto* items = reinterpret_cast<const uint32_t*>(w + D.R.items);
+    const int blocks = persistent_blocks(k_bwd_wide<false, true>, (uint32_t)A.n_tiles);
+    hipLaunchKernelGGL((k_bwd_wide<false, true>), dim3(blocks), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
+                       items, ctr);
+    BGS_HIP(hipGetLastError());
+    auto* keys = reinterpret_cast<uint32_t*>(w + D.keys);
+    auto* vals = reinterpret_cast<uint32_t*>(w + D.vals);
+    auto* keys2 = reinterpret_cast<uint32_t*>(w + D.keys2);
+    auto* vals2 = reinterpret_cast<uint32_t*>(w + D.vals2);
+    hipLaunchKernelGGL(k_det_keys, dim3(A.n_tiles), dim3(64), 0, stream, A, (const uint32_t*)cnt,
+                       (const uint32_t*)base, keys, vals);
+    BGS_HIP(hipGetLastError());
+    int bits = 1;
+    while (bits < 32 && ((int64_t)1 << bits) < P) ++bits;
+    bool second = false;
+    st = radix_sort_pairs_u32((int64_t)K, bits, keys, vals, keys2, vals2, reinterpret_cast<uint32_t*>(w + D.sscr),
+                              reinterpret_cast<uint32_t*>(w + D.sscr + D.scr_bytes - 4 * 256), &second, stream);
+    if (st != BGS_OK) return st;
+    const uint32_t* skeys = second ? keys2 : keys;
+    const uint32_t* svals = second ? vals2 : vals;
+    auto* seg = reinterpret_cast<uint32_t*>(w + D.seg);
+    hipLaunchKernelGGL(k_det_clear, dim3((unsigned)((2 * P + 255) / 256)), dim3(256), 0, stream, P, seg);
+    BGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_det_bounds, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, (int64_t)K, P, skeys,
+                       seg);
+    BGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, stream, P, (const uint32_t*)seg,
+                       svals, (const float*)partials, B);
     BGS_HIP(hipGetLastError());
     return BGS_OK;
 }

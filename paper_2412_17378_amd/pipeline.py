@@ -216,6 +216,32 @@ class Rasterizer:
                          grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], ws)
         return grads
 
+    def render_bwd_det(self, prep: Prepared, cfg: B.RenderCfg, fwd: dict, dL_dcolor, dL_dalpha=None, dL_ddepth=None,
+                       grads: Optional[dict] = None) -> dict:
+        """Deterministic-order backward (bgs_render_bwd_det; cfg must be the
+        pixel-wise variant with subtile 16): the same gradients up to fp32
+        rounding, identical from run to run.  The slot capacity grows on
+        demand (one retry)."""
+        P = prep.P
+        dev = self.device
+        if grads is None:
+            grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
+                         rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
+        f = prep.frame()
+        cap = getattr(self, "det_capacity", 1 << 20)
+        for _ in range(2):
+            ws = self.ws.get("render_det", B.bgs_render_bwd_det_workspace_bytes(f, P, cap))
+            try:
+                B.bgs_render_bwd_det(f, cfg, P, fwd["final_T"], fwd["n_contrib"], dL_dcolor, dL_dalpha, dL_ddepth,
+                                     grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], cap, ws)
+                self.det_capacity = cap
+                return grads
+            except B.BgsError as e:
+                if e.status != B.BGS_ECAPACITY:
+                    raise
+                cap = int(e.n_occ * 1.25) + 1024  # nothing was written: grow and run again
+        raise RuntimeError("bgs_render_bwd_det: capacity did not converge")
+
 
     def autotune(self, prep: Prepared, base: B.RenderCfg, dL_dcolor=None, cache_path: Optional[str] = None):
         """Time the kernel variants on this frame (bgs_autotune) and return

@@ -830,6 +830,42 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
             const bool exact_i = EXACT && __builtin_amdgcn_readlane((int)el.proper, i) != 0;
             const uint32_t roff_i = EXACT ? __builtin_amdgcn_readlane(roff, i) : 0u;  // row ty0's run in rowiv
             const float inv_w = 1.0f / (float)wi;
+            if (EXACT && exact_i && ni <= 8) {
+                // at most 8 groups: one (group, row) pair per lane, lanes 8 k ..
+                // 8 k + 7 holding the rows of group k; their column bits are
+                // OR-combined over the 8 lanes and lane 8 k writes the entry
+                const uint32_t jg = (uint32_t)lane >> 3;
+                const int rr8 = lane & 7;
+                uint32_t mlo = 0u, mhi = 0u;
+                int t = 0;
+                if (jg < ni) {
+                    int q = (int)((float)jg * inv_w);
+                    int r = (int)jg - q * wi;
+                    if (r >= wi) { ++q; r -= wi; }
+                    if (r < 0) { --q; r += wi; }
+                    const int gx = xi + r, gy = yi + q;
+                    t = gy * GX + gx;
+                    const int bx = gx * GTILES, row = gy * GTILES + rr8;
+                    if (row >= ty0 && row <= ty1) {
+                        const uint32_t iv = rowiv[roff_i + (uint32_t)(row - ty0)];
+                        const int c0 = max((int)(iv & 0xFFFFu) - bx, 0), c1 = min((int)(iv >> 16) - bx, GTILES);
+                        const uint32_t bits = c0 < c1 ? (((1u << c1) - 1u) & ~((1u << c0) - 1u)) : 0u;
+                        if (rr8 < 4) mlo = bits << (GTILES * rr8);
+                        else mhi = bits << (GTILES * (rr8 - 4));
+                    }
+                }
+#pragma unroll
+                for (int off = 1; off < 8; off <<= 1) {
+                    mlo |= (uint32_t)__shfl_xor((int)mlo, off, 64);
+                    mhi |= (uint32_t)__shfl_xor((int)mhi, off, 64);
+                }
+                if (jg < ni && rr8 == 0) {
+                    const uint32_t pos = nextpos[t];
+                    nextpos[t] = pos + 1;
+                    coarse[pos] = make_uint4(gi, mlo, mhi, 0u);
+                }
+                continue;
+            }
             for (uint32_t j = lane; j < ni; j += 64) {
                 int q = (int)((float)j * inv_w);
                 int r = (int)j - q * wi;

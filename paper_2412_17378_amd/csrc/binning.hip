@@ -1000,7 +1000,7 @@ __global__ __launch_bounds__(256) void k_seg_split(const uint64_t* __restrict__ 
 constexpr int SCAN_PARTS = 16;
 
 template <bool OFFSETS>
-__global__ __launch_bounds__(SCAN_PARTS * 64) void k_seg_scan(int TX, int TY, int GX, int ng,
+__global__ __launch_bounds__(SCAN_PARTS * 64) void k_seg_scan(int TX, int TY, int GX,
                                                                const uint32_t* __restrict__ nseg,
                                                                const uint32_t* __restrict__ segstart,
                                                                uint32_t* __restrict__ segcnt,
@@ -1208,14 +1208,14 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
                        gtotal, segcnt, (uint32_t*)nullptr, (const uint64_t*)nullptr, (uint64_t)0, (const uint64_t*)mg,
                        ccap, max_segs);
     BGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_seg_scan<false>, dim3(L.ng), dim3(SCAN_PARTS * 64), 0, stream, TX, TY, L.GX, L.ng, nseg,
+    hipLaunchKernelGGL(k_seg_scan<false>, dim3(L.ng), dim3(SCAN_PARTS * 64), 0, stream, TX, TY, L.GX, nseg,
                        segstart, segcnt, (const uint32_t*)nullptr, ttotal, (const uint64_t*)mg, ccap);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.nt, ttotal, tstart, ranges, n_pairs_dev,
                        (const uint64_t*)mg, ccap, pcap);
     BGS_HIP(hipGetLastError());
     if (capacity > 0) {
-        hipLaunchKernelGGL(k_seg_scan<true>, dim3(L.ng), dim3(SCAN_PARTS * 64), 0, stream, TX, TY, L.GX, L.ng, nseg,
+        hipLaunchKernelGGL(k_seg_scan<true>, dim3(L.ng), dim3(SCAN_PARTS * 64), 0, stream, TX, TY, L.GX, nseg,
                            segstart, segcnt, tstart, (uint32_t*)nullptr, (const uint64_t*)mg, ccap);
         BGS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_seg_split<true>, dim3(grid_split), dim3(256), 0, stream, nsegs, segmap, coarse, gstart,

@@ -1135,7 +1135,8 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
     if (st != BGS_OK) return st;
     BGS_REQUIRE(final_T && n_contrib && dL_dcolor, "bgs_render_bwd: null forward state or dL_dcolor");
     BGS_REQUIRE(dL_dmeans2D && dL_dconic_opacity && dL_drgb, "bgs_render_bwd: null gradient output");
-    BwdIO B{final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepths};
+    BwdIO B{final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dmeans2D, dL_dconic_opacity, dL_drgb,
+            dL_ddepths, nullptr, nullptr};
     if (cfg->variant == BGS_STATIC) {
         hipLaunchKernelGGL(k_bwd_pixel<false>, dim3(A.n_tiles), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
                            (const uint32_t*)nullptr, (uint32_t*)nullptr);
@@ -1464,7 +1465,7 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
         vd[v].F = A;
         vd[v].O = FwdOut{q.out_color, q.out_alpha, q.out_depth, q.final_T, q.n_contrib};
         vd[v].B = BwdIO{q.final_T,     q.n_contrib,     q.dL_dcolor,       q.dL_dalpha, q.dL_ddepth,
-                        q.dL_dmeans2D, q.dL_dconic_opacity, q.dL_drgb,     q.dL_ddepths};
+                        q.dL_dmeans2D, q.dL_dconic_opacity, q.dL_drgb,     q.dL_ddepths, nullptr, nullptr};
         vd[v].P = q.P;
         off[v + 1] = off[v] + (uint32_t)A.n_tiles;
     }

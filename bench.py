@@ -156,7 +156,7 @@ def main():
                        for k in grads)
             state["graph_ms"] = (t1 - t0) * 1e3 / steps
             state["graph_check"] = {"images_equal_eager": same_f, "max_rel_grad_diff_eager": gerr}
-            if not same_f or gerr > 1e-5:
+            if not same_f or gerr > 1e-4:
                 raise RuntimeError(f"graph replay differs from the eager step: {state['graph_check']}")
             del g
         return ms_eager, stages, state, pr, fwd, grads

@@ -55,7 +55,7 @@ def test_plan_replays_match_eager(batch):
                     ref = g_ref[k]
                     scale = float(ref.abs().max()) + 1e-30
                     err = float((plan.grads[v][k] - ref).abs().max())
-                    assert err <= 1e-5 * scale, (rep, v, k, err, scale)
+                    assert err <= 1e-4 * scale, (rep, v, k, err, scale)  # float atomics: order varies
             # the program's own eager work between replays
             x = torch.randn(1 << 20, device="cuda")
             (x * 2).sum().item()
@@ -85,7 +85,7 @@ def test_plan_wide(batch):
                     ref = eager[v][1][k]
                     scale = float(ref.abs().max()) + 1e-30
                     err = float((plan.grads[v][k] - ref).abs().max())
-                    assert err <= 1e-5 * scale, (rep, v, k, err, scale)
+                    assert err <= 1e-4 * scale, (rep, v, k, err, scale)  # float atomics: order varies
     finally:
         plan.close()
 

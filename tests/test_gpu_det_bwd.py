@@ -62,7 +62,7 @@ def test_det_backward_parity_and_repeatability(rast, name):
     torch.cuda.synchronize()
     for k in atomic:
         a, b = atomic[k], runs[0][k]
-        assert float((a - b).abs().max()) <= 1e-5 * (float(a.abs().max()) + 1e-30), k
+        assert float((a - b).abs().max()) <= 1e-4 * (float(a.abs().max()) + 1e-30), k
 
 
 def test_det_backward_full_size_repeatable(rast):
@@ -84,7 +84,7 @@ def test_det_backward_full_size_repeatable(rast):
     for k in a:
         assert torch.equal(a[k], b[k]), k
         scale = float(atomic[k].abs().max()) + 1e-30
-        assert float((a[k] - atomic[k]).abs().max()) <= 1e-5 * scale, k
+        assert float((a[k] - atomic[k]).abs().max()) <= 1e-4 * scale, k
 
 
 def test_det_backward_capacity_and_config(rast):

@@ -5,8 +5,12 @@
 // the number of 16x16 tiles the splat's square meets.
 //
 // One thread per Gaussian; fp32 throughout.  O(P) work, a few hundred flops
-// per Gaussian: bandwidth-bound on the input arrays (52 B, or 220 B with
-// degree-3 SH, per Gaussian).
+// per Gaussian: bandwidth-bound on the input arrays (52 B, or 240 B with
+// degree-3 SH, per Gaussian).  The kernels are instantiated per SH degree, so
+// the SH loops unroll and their tables stay in registers; with degree >= 1 a
+// workgroup's colour coefficients (and, in the backward, their gradients)
+// pass through LDS so that global memory sees one contiguous, coalesced run
+// per workgroup instead of one 4-byte access per Gaussian and coefficient.
 #include "common.h"
 
 namespace bgs {
@@ -19,6 +23,65 @@ struct ProjParams {
     float znear, limx, limy;
     int TX, TY;
 };
+
+constexpr int PROJ_THREADS = 256;
+
+// Colour layout per SH degree D (-1: plain RGB): NC floats per Gaussian; in
+// LDS a Gaussian's row has the odd stride NC | 1, so the 64 lanes of a wave
+// reading word j of their own rows hit 64 distinct banks.
+template <int D>
+struct ShDim {
+    static constexpr int NSH = D < 0 ? 1 : (D + 1) * (D + 1);
+    static constexpr int NC = 3 * NSH;
+    static constexpr int STRIDE = NC | 1;
+    static constexpr bool STAGED = D >= 1;
+    static constexpr int LDS_FLOATS = STAGED ? PROJ_THREADS * STRIDE : 1;
+};
+
+// Element e of the workgroup's contiguous run <-> its LDS slot.
+template <int NC, int STRIDE>
+__device__ __forceinline__ int lds_slot(int e) {
+    const int t = e / NC;
+    return t * STRIDE + (e - t * NC);
+}
+
+// LDS rows <- src[first * NC .. (first + n) * NC): coalesced, 16-byte
+// vectors when the run is 16-byte aligned.
+template <int NC, int STRIDE>
+__device__ inline void stage_in(const float* src, int64_t first, int n, float* s) {
+    const float* g = src + first * NC;
+    const int total = n * NC;
+    int e0 = 0;
+    if ((reinterpret_cast<uintptr_t>(g) & 15) == 0) {
+        const int n4 = total >> 2;
+        for (int v = threadIdx.x; v < n4; v += PROJ_THREADS) {
+            const float4 x = reinterpret_cast<const float4*>(g)[v];
+            s[lds_slot<NC, STRIDE>(4 * v)] = x.x;
+            s[lds_slot<NC, STRIDE>(4 * v + 1)] = x.y;
+            s[lds_slot<NC, STRIDE>(4 * v + 2)] = x.z;
+            s[lds_slot<NC, STRIDE>(4 * v + 3)] = x.w;
+        }
+        e0 = 4 * n4;
+    }
+    for (int e = e0 + threadIdx.x; e < total; e += PROJ_THREADS) s[lds_slot<NC, STRIDE>(e)] = g[e];
+}
+
+// dst[first * NC .. (first + n) * NC) <- LDS rows, the reverse of stage_in.
+template <int NC, int STRIDE>
+__device__ inline void stage_out(float* dst, int64_t first, int n, const float* s) {
+    float* g = dst + first * NC;
+    const int total = n * NC;
+    int e0 = 0;
+    if ((reinterpret_cast<uintptr_t>(g) & 15) == 0) {
+        const int n4 = total >> 2;
+        for (int v = threadIdx.x; v < n4; v += PROJ_THREADS)
+            reinterpret_cast<float4*>(g)[v] =
+                make_float4(s[lds_slot<NC, STRIDE>(4 * v)], s[lds_slot<NC, STRIDE>(4 * v + 1)],
+                            s[lds_slot<NC, STRIDE>(4 * v + 2)], s[lds_slot<NC, STRIDE>(4 * v + 3)]);
+        e0 = 4 * n4;
+    }
+    for (int e = e0 + threadIdx.x; e < total; e += PROJ_THREADS) g[e] = s[lds_slot<NC, STRIDE>(e)];
+}
 
 // Real spherical harmonics (no Condon-Shortley phase), index l*l + l + m,
 // at the unit vector (x, y, z), for l <= degree.  Amplitudes: C0 = 1/(2
@@ -61,25 +124,37 @@ __device__ inline void sh_basis(int degree, float x, float y, float z, float Y[1
 }
 
 // colour = max(0, 1/2 + sum_i k_i Y_i) per channel; coefficients k[i][3].
-__device__ inline void sh_colour(const float* __restrict__ k, int degree, float x, float y, float z, float out[3]) {
+template <int D>
+__device__ inline void sh_colour(const float* k, float x, float y, float z, float out[3]) {
     float Y[16];
-    sh_basis(degree, x, y, z, Y);
-    const int n = (degree + 1) * (degree + 1);
+    sh_basis(D, x, y, z, Y);
+    constexpr int n = (D + 1) * (D + 1);
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
         float s = 0.5f;
+#pragma unroll
         for (int i = 0; i < n; ++i) s += k[3 * i + c] * Y[i];
         out[c] = fmaxf(s, 0.0f);
     }
 }
 
-__global__ __launch_bounds__(256) void k_project(ProjParams pp, int64_t P, const float* __restrict__ means3D,
-                                                 const float* __restrict__ log_scales, const float* __restrict__ quats,
-                                                 const float* __restrict__ opacity, const float* __restrict__ colors,
-                                                 int sh_degree, float* __restrict__ means2D,
-                                                 float* __restrict__ conic_opacity, float* __restrict__ rgb,
-                                                 float* __restrict__ depth, int* __restrict__ radius,
-                                                 uint32_t* __restrict__ tiles_touched) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <int D>
+__global__ __launch_bounds__(PROJ_THREADS) void k_project(ProjParams pp, int64_t P, const float* __restrict__ means3D,
+                                                          const float* __restrict__ log_scales,
+                                                          const float* __restrict__ quats,
+                                                          const float* __restrict__ opacity,
+                                                          const float* __restrict__ colors, float* __restrict__ means2D,
+                                                          float* __restrict__ conic_opacity, float* __restrict__ rgb,
+                                                          float* __restrict__ depth, int* __restrict__ radius,
+                                                          uint32_t* __restrict__ tiles_touched) {
+    using S = ShDim<D>;
+    __shared__ float s_sh[S::LDS_FLOATS];
+    const int64_t first = (int64_t)blockIdx.x * PROJ_THREADS;
+    const int64_t i = first + threadIdx.x;
+    if (S::STAGED) {
+        stage_in<S::NC, S::STRIDE>(colors, first, (int)(P - first < PROJ_THREADS ? P - first : PROJ_THREADS), s_sh);
+        __syncthreads();
+    }
     if (i >= P) return;
     const float mx = means3D[3 * i], my = means3D[3 * i + 1], mz = means3D[3 * i + 2];
     const float* R = pp.R;
@@ -168,7 +243,7 @@ __global__ __launch_bounds__(256) void k_project(ProjParams pp, int64_t P, const
     radius[i] = r;
     tiles_touched[i] = on_screen ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
 
-    if (sh_degree < 0) {
+    if (D < 0) {
         rgb[3 * i] = colors[3 * i];
         rgb[3 * i + 1] = colors[3 * i + 1];
         rgb[3 * i + 2] = colors[3 * i + 2];
@@ -176,9 +251,9 @@ __global__ __launch_bounds__(256) void k_project(ProjParams pp, int64_t P, const
         float dx = mx - pp.campos[0], dy = my - pp.campos[1], dz = mz - pp.campos[2];
         const float n = rsqrtf(dx * dx + dy * dy + dz * dz);
         dx *= n; dy *= n; dz *= n;
-        const int nsh = (sh_degree + 1) * (sh_degree + 1);
         float c[3];
-        sh_colour(colors + (int64_t)3 * nsh * i, sh_degree, dx, dy, dz, c);
+        sh_colour<D < 0 ? 0 : D>(S::STAGED ? s_sh + threadIdx.x * S::STRIDE : colors + (int64_t)S::NC * i, dx, dy,
+                                 dz, c);
         rgb[3 * i] = c[0];
         rgb[3 * i + 1] = c[1];
         rgb[3 * i + 2] = c[2];
@@ -225,20 +300,19 @@ __device__ inline void sh_grad(int degree, float x, float y, float z, float g[16
 // the pinhole map and depth; Sigma = M M^T, M = Rq diag(e^s); the rotation
 // of the normalized quaternion; the SH colour along the view ray and its 0
 // clamp).  Gradients are written (=); culled Gaussians get zeros.
-__global__ __launch_bounds__(256) void k_project_bwd(ProjParams pp, int64_t P, const float* __restrict__ means3D,
-                                                     const float* __restrict__ log_scales,
-                                                     const float* __restrict__ quats,
-                                                     const float* __restrict__ colors, int sh_degree,
-                                                     const float* __restrict__ g_means2D,
-                                                     const float* __restrict__ g_conic_opacity,
-                                                     const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
-                                                     float* __restrict__ d_means3D, float* __restrict__ d_log_scales,
-                                                     float* __restrict__ d_quats, float* __restrict__ d_opacity,
-                                                     float* __restrict__ d_colors) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    const int nsh = sh_degree < 0 ? 1 : (sh_degree + 1) * (sh_degree + 1);
-    float* dc = d_colors + (int64_t)3 * nsh * i;
+// Gaussian i.  coef: its colour row (RGB or SH coefficients [j][3]); dc:
+// where its colour gradient goes, in the same layout.  In the LDS-staged
+// kernels coef and dc are the same row: each coefficient is read before its
+// slot is overwritten.
+template <int D>
+__device__ inline void project_bwd_one(const ProjParams& pp, int64_t i, const float* __restrict__ means3D,
+                                       const float* __restrict__ log_scales, const float* __restrict__ quats,
+                                       const float* coef, const float* __restrict__ g_means2D,
+                                       const float* __restrict__ g_conic_opacity, const float* __restrict__ g_rgb,
+                                       const float* __restrict__ g_depth, float* __restrict__ d_means3D,
+                                       float* __restrict__ d_log_scales, float* __restrict__ d_quats,
+                                       float* __restrict__ d_opacity, float* dc) {
+    constexpr int nsh = ShDim<D>::NSH;
     const float mx = means3D[3 * i], my = means3D[3 * i + 1], mz = means3D[3 * i + 2];
     const float* R = pp.R;
     const float p[3] = {R[0] * mx + R[1] * my + R[2] * mz + pp.t[0], R[3] * mx + R[4] * my + R[5] * mz + pp.t[1],
@@ -372,7 +446,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjParams pp, int64_t P, c
     d_opacity[i] = gco.w;
     // ---- colour
     const float* gr = g_rgb + 3 * i;
-    if (sh_degree < 0) {
+    if (D < 0) {
         dc[0] = gr[0];
         dc[1] = gr[1];
         dc[2] = gr[2];
@@ -380,28 +454,67 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjParams pp, int64_t P, c
         float v[3] = {mx - pp.campos[0], my - pp.campos[1], mz - pp.campos[2]};
         const float vn = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]), ivn = 1.0f / vn;
         const float d[3] = {v[0] * ivn, v[1] * ivn, v[2] * ivn};
-        const float* k = colors + (int64_t)3 * nsh * i;
         float Y[16], G[16][3];
-        sh_basis(sh_degree, d[0], d[1], d[2], Y);
-        sh_grad(sh_degree, d[0], d[1], d[2], G);
+        sh_basis(D, d[0], d[1], d[2], Y);
+        sh_grad(D, d[0], d[1], d[2], G);
         float c[3];  // the colour before its clamp at 0
+#pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             c[ch] = 0.5f;
-            for (int j = 0; j < nsh; ++j) c[ch] += k[3 * j + ch] * Y[j];
+#pragma unroll
+            for (int j = 0; j < nsh; ++j) c[ch] += coef[3 * j + ch] * Y[j];
         }
         float gd[3] = {0.f, 0.f, 0.f};
+#pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             const bool live = c[ch] > 0.0f;
+#pragma unroll
             for (int j = 0; j < nsh; ++j) {
+                const float kv = coef[3 * j + ch];
                 dc[3 * j + ch] = live ? gr[ch] * Y[j] : 0.0f;
                 if (live)
-                    for (int a = 0; a < 3; ++a) gd[a] += gr[ch] * k[3 * j + ch] * G[j][a];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) gd[a] += gr[ch] * kv * G[j][a];
             }
         }
         const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
         for (int a = 0; a < 3; ++a) dmu[a] += (gd[a] - d[a] * dd) * ivn;
     }
-    for (int k = 0; k < 3; ++k) d_means3D[3 * i + k] = dmu[k];
+    for (int a = 0; a < 3; ++a) d_means3D[3 * i + a] = dmu[a];
+}
+
+template <int D>
+__global__ __launch_bounds__(PROJ_THREADS) void k_project_bwd(ProjParams pp, int64_t P, const float* __restrict__ means3D,
+                                                              const float* __restrict__ log_scales,
+                                                              const float* __restrict__ quats,
+                                                              const float* __restrict__ colors,
+                                                              const float* __restrict__ g_means2D,
+                                                              const float* __restrict__ g_conic_opacity,
+                                                              const float* __restrict__ g_rgb,
+                                                              const float* __restrict__ g_depth,
+                                                              float* __restrict__ d_means3D,
+                                                              float* __restrict__ d_log_scales,
+                                                              float* __restrict__ d_quats, float* __restrict__ d_opacity,
+                                                              float* __restrict__ d_colors) {
+    using S = ShDim<D>;
+    __shared__ float s_sh[S::LDS_FLOATS];
+    const int64_t first = (int64_t)blockIdx.x * PROJ_THREADS;
+    const int64_t i = first + threadIdx.x;
+    const int n = (int)(P - first < PROJ_THREADS ? P - first : PROJ_THREADS);
+    if (S::STAGED) {
+        stage_in<S::NC, S::STRIDE>(colors, first, n, s_sh);
+        __syncthreads();
+    }
+    if (i < P) {
+        float* row = S::STAGED ? s_sh + threadIdx.x * S::STRIDE : d_colors + (int64_t)S::NC * i;
+        const float* coef = S::STAGED ? row : colors + (int64_t)S::NC * i;
+        project_bwd_one<D>(pp, i, means3D, log_scales, quats, coef, g_means2D, g_conic_opacity, g_rgb, g_depth, d_means3D,
+                           d_log_scales, d_quats, d_opacity, row);
+    }
+    if (S::STAGED) {
+        __syncthreads();
+        stage_out<S::NC, S::STRIDE>(d_colors, first, n, s_sh);
+    }
 }
 
 }  // namespace bgs
@@ -440,11 +553,20 @@ extern "C" bgs_status bgs_project(const bgs_camera* cam, int64_t P, const float*
                 "bgs_project: null array");
     BGS_REQUIRE((reinterpret_cast<uintptr_t>(conic_opacity) & 15) == 0, "bgs_project: conic_opacity must be 16-byte aligned");
     const ProjParams pp = proj_params(cam);
-    const int threads = 256;
+    const int threads = PROJ_THREADS;
     const int64_t blocks = (P + threads - 1) / threads;
     BGS_REQUIRE(blocks < (int64_t)1 << 31, "bgs_project: P too large");
-    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(threads), 0, stream, pp, P, means3D, log_scales, quats,
-                       opacity, colors, (int)sh_degree, means2D, conic_opacity, rgb, depth, radius, tiles_touched);
+    auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, pp, P, means3D, log_scales, quats,
+                           opacity, colors, means2D, conic_opacity, rgb, depth, radius, tiles_touched);
+    };
+    switch (sh_degree) {
+        case -1: launch(k_project<-1>); break;
+        case 0: launch(k_project<0>); break;
+        case 1: launch(k_project<1>); break;
+        case 2: launch(k_project<2>); break;
+        default: launch(k_project<3>); break;
+    }
     BGS_HIP(hipGetLastError());
     return BGS_OK;
 }
@@ -466,12 +588,21 @@ extern "C" bgs_status bgs_project_bwd(const bgs_camera* cam, int64_t P, const fl
                     (reinterpret_cast<uintptr_t>(dL_dquats) & 15) == 0,
                 "bgs_project_bwd: dL_dconic_opacity and dL_dquats must be 16-byte aligned");
     const ProjParams pp = proj_params(cam);
-    const int threads = 256;
+    const int threads = PROJ_THREADS;
     const int64_t blocks = (P + threads - 1) / threads;
     BGS_REQUIRE(blocks < (int64_t)1 << 31, "bgs_project_bwd: P too large");
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(threads), 0, stream, pp, P, means3D, log_scales,
-                       quats, colors, (int)sh_degree, dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepth, dL_dmeans3D,
-                       dL_dlog_scales, dL_dquats, dL_dopacity, dL_dcolors);
+    auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, pp, P, means3D, log_scales, quats,
+                           colors, dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepth, dL_dmeans3D, dL_dlog_scales,
+                           dL_dquats, dL_dopacity, dL_dcolors);
+    };
+    switch (sh_degree) {
+        case -1: launch(k_project_bwd<-1>); break;
+        case 0: launch(k_project_bwd<0>); break;
+        case 1: launch(k_project_bwd<1>); break;
+        case 2: launch(k_project_bwd<2>); break;
+        default: launch(k_project_bwd<3>); break;
+    }
     BGS_HIP(hipGetLastError());
     return BGS_OK;
 }

@@ -134,3 +134,52 @@ def test_render3d_gradients(name):
         y = o[k].reshape(-1)
         x = to_np(got[k]).reshape(-1)
         check_close(x, y, max(rms(y), 1e-30), f"{name} render3d d{k}", rtol=1e-3)
+
+
+@pytest.mark.parametrize("n", [700, 1000])
+@pytest.mark.parametrize("offset", [0, 1])
+@pytest.mark.parametrize("deg", [0, 1, 2, 3])
+def test_project_sh_degrees_staged(deg, offset, n):
+    """Every SH degree through the per-degree kernels (degrees >= 1 stage the
+    colour rows of a 256-Gaussian workgroup through LDS): P not a multiple of
+    256, colour arrays 16-byte aligned (offset 0) and not (offset one float).
+    Forward colour and backward gradients against the oracle; the words
+    around the colour-gradient run stay untouched."""
+    from paper_2412_17378_amd import bgs as B
+    s = scenes.scene_tiny(n=n, seed=31 + deg, width=96, height=64, sh_degree=deg)
+    cam = s.cameras[0]
+    P = s.P
+    print(f"[proj-sh] degree={deg} offset={offset} P={P}", flush=True)
+    dev = torch.device("cuda")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ncol = 3 * (deg + 1) ** 2
+    cbuf = torch.zeros(P * ncol + 8, device=dev)
+    colors = cbuf[offset:offset + P * ncol]
+    colors.copy_(T(s.colors.reshape(-1)))
+    f = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
+             rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev),
+             radius=torch.zeros(P, dtype=torch.int32, device=dev), tt=torch.zeros(P, dtype=torch.int32, device=dev))
+    B.bgs_project(cam, T(s.means3D), T(s.log_scales), T(s.quats), T(s.opacity), colors, deg, f["means2D"],
+                  f["conic_opacity"], f["rgb"], f["depth"], f["radius"], f["tt"])
+    rng = np.random.default_rng(9)
+    gm = rng.standard_normal((P, 2)).astype(np.float32)
+    gco = (rng.standard_normal((P, 4)) * np.array([1e-2, 1e-2, 1e-2, 1.0])).astype(np.float32)
+    gr = rng.standard_normal((P, 3)).astype(np.float32)
+    gd = rng.standard_normal(P).astype(np.float32)
+    gbuf = torch.full((P * ncol + 8,), float("nan"), device=dev)
+    out = dict(means3D=torch.zeros(P, 3, device=dev), log_scales=torch.zeros(P, 3, device=dev),
+               quats=torch.zeros(P, 4, device=dev), opacity=torch.zeros(P, device=dev),
+               colors=gbuf[offset:offset + P * ncol])
+    B.bgs_project_bwd(cam, T(s.means3D), T(s.log_scales), T(s.quats), colors, deg, T(gm), T(gco), T(gr), T(gd), out)
+    torch.cuda.synchronize()
+    o = oracle.project(cam, s.means3D, s.log_scales, s.quats, s.opacity, s.colors, deg)
+    vis = o["radius"] > 0
+    assert vis.sum() > P // 2
+    assert np.array_equal(to_np(f["radius"]) > 0, vis)
+    check_close(to_np(f["rgb"])[vis], o["rgb"][vis], max(rms(o["rgb"][vis]), 1e-6), f"deg {deg} rgb")
+    ob, sens = _ulp_sensitivity(cam, s, (gm, gco, gr, gd))
+    gpu = dict(out)
+    gpu["colors"] = out["colors"].reshape(s.colors.shape)
+    _compare(gpu, ob, sens, f"deg {deg} offset {offset}")
+    g = to_np(gbuf)
+    assert np.all(np.isnan(g[:offset])) and np.all(np.isnan(g[offset + P * ncol:]))

@@ -13,8 +13,9 @@ large), 16x16 tiles, random upstream dL/dcolor ~ N(0,1).
 value = (forward + backward Gaussian-pixel blends) per second of step time.
 A blend is one (pixel, list entry) pair the sequential per-pixel loop
 examines in the forward (skipped and stopping entries included) and one
-contributor walked in the backward; both counts come from the oracle run
-once on the GPU's own lists, outside the timed region.
+list entry walked back to front in the backward (Sum n_contrib); both counts,
+and the number of entries that actually blend (the contributors), come from
+the oracle run once on the GPU's own lists, outside the timed region.
 
 Also reported: per-stage milliseconds (HIP events on the launch stream), the
 same steps with the static one-workgroup-per-tile kernels, the roofline
@@ -39,9 +40,21 @@ PEAK_HBM_GBS = 8000.0
 N_CU, LANES, CLOCK_GHZ = 256, 64, 2.4
 PEAK_VALU_TOPS = N_CU * LANES * CLOCK_GHZ / 1000.0  # 39.3 T lane-ops/s (fp32, non-packed)
 
-# algorithmic work per unit (derivations in the design notes)
-OPS_PER_FWD_BLEND = 20.0      # VALU lane-ops per examined (pixel, Gaussian) pair
-OPS_PER_BWD_BLEND = 45.0      # VALU lane-ops per contributor walked back to front
+# algorithmic work per unit, in FP32 lane-ops (an FMA is one, a quarter-rate transcendental four;
+# derivations in the design notes)
+OPS_SKIP_TEST = 16.0          # per examined / walked (pixel, entry) pair: offset, power, exp, alpha, skip tests
+OPS_FWD_BLEND = 10.0          # more per forward entry that blends: T update, stop test, colour/depth/alpha sums
+OPS_BWD_CONTRIB = 41.0        # more per backward contributor: T recovery, colour/depth/opacity/conic/mean terms
+
+
+def fwd_ops(examined: int, contributors: int) -> float:
+    return OPS_SKIP_TEST * examined + OPS_FWD_BLEND * contributors
+
+
+def bwd_ops(walked: int, contributors: int) -> float:
+    return OPS_SKIP_TEST * walked + OPS_BWD_CONTRIB * contributors
+
+
 BYTES_PER_PAIR_SORT = 16.0    # read + write of a (u32 key, u32 value) pair
 BYTES_PER_PAIR_BIN = 8.0      # write of a (u32 key, u32 value) pair
 BYTES_PER_PAIR_LISTS = 4.0    # write of the u32 Gaussian id of a pair into its tile's list
@@ -194,10 +207,12 @@ def main():
     ofwd = oracle.render_fwd(W, H, ranges_np, pl_np, m2, co, rgb, dep, bg=scene.bg)
     fwd_blends = int(ofwd["blends"])
     bwd_blends = int(ofwd["n_contrib"].astype(np.int64).sum())
+    contributors = int(ofwd["contributors"])
     wstats = workload_stats(ofwd["n_examined"], ranges_np)
     n_contrib_gpu = fwd["n_contrib"].cpu().numpy()
     agree = float(np.mean(n_contrib_gpu == ofwd["n_contrib"]))
-    print(f"[bench] blends fwd={fwd_blends} bwd={bwd_blends} (oracle, {time.time() - t_o:.1f}s; "
+    print(f"[bench] blends fwd={fwd_blends} bwd={bwd_blends} contributors={contributors} "
+          f"(oracle, {time.time() - t_o:.1f}s; "
           f"n_contrib agreement {agree:.6f})", flush=True)
     del ofwd
 
@@ -223,12 +238,18 @@ def main():
         rg_e, pl_e = state_e["frame_bufs"][0].cpu().numpy(), state_e["frame_bufs"][1].cpu().numpy()
         of_e = oracle.render_fwd(W, H, rg_e, pl_e, m2, co, rgb, dep, bg=scene.bg)
         fb_e, bb_e = int(of_e["blends"]), int(of_e["n_contrib"].astype(np.int64).sum())
+        cb_e = int(of_e["contributors"])
         agree_e = float(np.mean(fwd_e["n_contrib"].cpu().numpy() == of_e["n_contrib"]))
         del of_e
+        roof_e = {k: dict(bound="alu", achieved=ops / (st_e[k] * 1e-3) / 1e12, peak=PEAK_VALU_TOPS, unit="TOP/s")
+                  for k, ops in (("render_fwd", fwd_ops(fb_e, cb_e)), ("render_bwd", bwd_ops(bb_e, cb_e)))}
+        for v in roof_e.values():
+            v["frac"] = v["achieved"] / v["peak"]
         same = all(torch.equal(fwd[k], fwd_e[k]) for k in ("color", "alpha", "depth", "final_T"))
         diff = max(float((fwd[k] - fwd_e[k]).abs().max()) for k in ("color", "alpha", "depth", "final_T"))
         exact = {"n_pairs": state_e["M"], "ms_per_step": ms_e, "eager_ms_per_step": ms_ee, "stages_ms": st_e,
-                 "blends": {"fwd": fb_e, "bwd": bb_e}, "value": (fb_e + bb_e) / (ms_e * 1e-3),
+                 "blends": {"fwd": fb_e, "bwd": bb_e, "contributors": cb_e}, "render_roofline": roof_e,
+                 "value": (fb_e + bb_e) / (ms_e * 1e-3),
                  "unit": "examined blends/s", "images_equal_square_rule": same, "max_abs_image_diff": diff,
                  "n_contrib_agreement_oracle": agree_e, "step_speedup_vs_square_rule": ms_step / ms_e}
         print(f"[bench] exact binning: {ms_e:.3f} ms/step ({ms_step / ms_e:.2f}x), M={state_e['M']}, stages " +
@@ -327,10 +348,10 @@ def main():
     def roof(stage):
         t = stages[stage] * 1e-3
         if stage == "render_fwd":
-            return dict(bound="alu", achieved=fwd_blends * OPS_PER_FWD_BLEND / t / 1e12, peak=PEAK_VALU_TOPS,
+            return dict(bound="alu", achieved=fwd_ops(fwd_blends, contributors) / t / 1e12, peak=PEAK_VALU_TOPS,
                         unit="TOP/s")
         if stage == "render_bwd":
-            return dict(bound="alu", achieved=bwd_blends * OPS_PER_BWD_BLEND / t / 1e12, peak=PEAK_VALU_TOPS,
+            return dict(bound="alu", achieved=bwd_ops(bwd_blends, contributors) / t / 1e12, peak=PEAK_VALU_TOPS,
                         unit="TOP/s")
         if stage == "sort":
             return dict(bound="hbm", achieved=M * BYTES_PER_PAIR_SORT / t / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
@@ -399,7 +420,10 @@ def main():
                    "backward": B.cfg_name(bcfg), "lists": "fused"},
         "autotune": tuned,
         "workload_stats": wstats,
-        "blends": {"fwd": fwd_blends, "bwd": bwd_blends},
+        "blends": {"fwd": fwd_blends, "bwd": bwd_blends, "contributors": contributors},
+        "lane_ops": {"render_fwd": fwd_ops(fwd_blends, contributors), "render_bwd": bwd_ops(bwd_blends, contributors),
+                     "per_unit": {"skip_test": OPS_SKIP_TEST, "fwd_blend": OPS_FWD_BLEND,
+                                  "bwd_contributor": OPS_BWD_CONTRIB}},
         "stages_ms": stages,
         "render_ms": render_ms,
         "render_blends_per_s": (fwd_blends + bwd_blends) / (render_ms * 1e-3),

@@ -60,7 +60,7 @@ def lib():
         L.orc_sort.restype = C.c_int
         L.orc_ranges.argtypes = [i64, vp, i32, vp]
         L.orc_ranges.restype = C.c_int
-        L.orc_render_fwd.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_render_fwd.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_render_fwd.restype = i64
         L.orc_render_bwd.argtypes = [i32, i32, i32] + [vp] * 21
         L.orc_render_bwd.restype = i64
@@ -213,19 +213,24 @@ def bin_sort_ranges(width, height, means2D, radius, depth, tile: int = TILE, win
 def render_fwd(width, height, ranges_, point_list, means2D, conic_opacity, rgb, depth, bg=(0, 0, 0),
                tile: int = TILE, window: Optional[Sequence[int]] = None) -> dict:
     """Eq. (4) per pixel with the skip / stop rules.  Outputs are planar:
-    color [3,H,W], alpha/depth/final_T/margin [H,W], n_contrib/n_examined
-    [H,W].  Pixels outside ``window`` = (x0, y0, x1, y1) stay zero."""
+    color [3,H,W], alpha/depth/final_T/margin [H,W], n_contrib/n_examined/
+    n_blended [H,W] (n_blended: entries blended, the pixel's contributors).
+    ``blends`` = examined entries, ``contributors`` = blended entries, summed
+    over the pixels.  Pixels outside ``window`` = (x0, y0, x1, y1) stay zero."""
     H, W = int(height), int(width)
     rg, pl = _i32(ranges_), _i32(point_list)
     m2, co, cl, dp, b = _f64(means2D), _f64(conic_opacity), _f64(rgb), _f64(depth), _f64(bg)
     win = None if window is None else _i32(window)
     out = dict(color=np.zeros((3, H, W)), alpha=np.zeros((H, W)), depth=np.zeros((H, W)),
                final_T=np.zeros((H, W)), n_contrib=np.zeros((H, W), np.int32),
-               n_examined=np.zeros((H, W), np.int64), margin=np.full((H, W), np.inf))
+               n_examined=np.zeros((H, W), np.int64), n_blended=np.zeros((H, W), np.int32),
+               margin=np.full((H, W), np.inf))
     tot = lib().orc_render_fwd(W, H, tile, _p(rg), _p(pl), _p(m2), _p(co), _p(cl), _p(dp), _p(b), _p(win),
                                _p(out["color"]), _p(out["alpha"]), _p(out["depth"]), _p(out["final_T"]),
-                               _p(out["n_contrib"]), _p(out["n_examined"]), _p(out["margin"]))
+                               _p(out["n_contrib"]), _p(out["n_examined"]), _p(out["n_blended"]),
+                               _p(out["margin"]))
     out["blends"] = int(tot)
+    out["contributors"] = int(out["n_blended"].sum(dtype=np.int64))
     return out
 
 

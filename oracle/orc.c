@@ -692,18 +692,19 @@ typedef struct {
  *   T' = T (1 - alpha);   stop (this entry not blended) when T' < 1e-4
  *   C += rgb alpha T;  D += depth alpha T;  A += alpha T;  T = T';  n = k + 1
  * Returns the number of list entries examined (skipped and stopping entries
- * included); *margin receives the smallest relative distance of any skip /
- * clamp / stop decision to its threshold.
+ * included); *blended receives the number of entries blended (the pixel's
+ * contributors, at most *n_out); *margin receives the smallest relative
+ * distance of any skip / clamp / stop decision to its threshold.
  */
 static int64_t pixel_forward(const orc_frame *f, int px, int py, double C[3], double *D, double *A,
-                             double *T_out, int32_t *n_out, double *margin)
+                             double *T_out, int32_t *n_out, int32_t *blended, double *margin)
 {
     const int TX = tiles_x(f->width, f->tile);
     const int t = (py / f->tile) * TX + (px / f->tile);
     const int32_t s = f->ranges[2 * t], e = f->ranges[2 * t + 1];
     const double amin = thr_alpha_min(), amax = thr_alpha_max(), tmin = thr_T_min();
     double T = 1.0, mg = INFINITY;
-    int32_t n = 0;
+    int32_t n = 0, nb = 0;
     int64_t examined = 0;
     C[0] = C[1] = C[2] = 0;
     *D = 0;
@@ -731,9 +732,11 @@ static int64_t pixel_forward(const orc_frame *f, int px, int py, double C[3], do
         *A += w;
         T = Tn;
         n = k - s + 1;
+        ++nb;
     }
     *T_out = T;
     *n_out = n;
+    *blended = nb;
     if (margin) *margin = mg;
     return examined;
 }
@@ -753,14 +756,15 @@ static void window_or_full(const int32_t *window, int32_t w, int32_t h, int32_t 
 /*
  * Forward render of the pixels in window = [x0, y0, x1, y1) (nullable: whole
  * image).  Image outputs are planar [3,H,W] / [H,W]; pixels outside the
- * window are left untouched.  out_color = C + T bg.  Returns the total number
- * of examined entries (the forward "blend" count).
+ * window are left untouched.  out_color = C + T bg.  n_examined, n_blended
+ * (entries blended per pixel) and margin are nullable.  Returns the total
+ * number of examined entries (the forward "blend" count).
  */
 int64_t orc_render_fwd(int32_t width, int32_t height, int32_t tile, const int32_t *ranges,
                        const int32_t *point_list, const double *means2D, const double *conic_opacity,
                        const double *rgb, const double *depth, const double *bg, const int32_t *window,
                        double *out_color, double *out_alpha, double *out_depth, double *final_T,
-                       int32_t *n_contrib, int64_t *n_examined, double *margin)
+                       int32_t *n_contrib, int64_t *n_examined, int32_t *n_blended, double *margin)
 {
     orc_frame f = {width, height, tile, ranges, point_list, means2D, conic_opacity, rgb, depth, bg};
     int32_t win[4];
@@ -771,8 +775,8 @@ int64_t orc_render_fwd(int32_t width, int32_t height, int32_t tile, const int32_
     for (int py = win[1]; py < win[3]; ++py) {
         for (int px = win[0]; px < win[2]; ++px) {
             double C[3], D, A, T, mg;
-            int32_t n;
-            int64_t ex = pixel_forward(&f, px, py, C, &D, &A, &T, &n, &mg);
+            int32_t n, nb;
+            int64_t ex = pixel_forward(&f, px, py, C, &D, &A, &T, &n, &nb, &mg);
             const int64_t o = (int64_t)py * width + px;
             for (int c = 0; c < 3; ++c) out_color[c * HW + o] = C[c] + T * bg[c];
             out_alpha[o] = A;
@@ -780,6 +784,7 @@ int64_t orc_render_fwd(int32_t width, int32_t height, int32_t tile, const int32_
             final_T[o] = T;
             n_contrib[o] = n;
             if (n_examined) n_examined[o] = ex;
+            if (n_blended) n_blended[o] = nb;
             if (margin) margin[o] = mg;
             total += ex;
         }

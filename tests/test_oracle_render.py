@@ -123,6 +123,7 @@ def test_identical_alpha_stack_golden(orc):
     f = orc.render_fwd(W, H, b["ranges"], b["point_list"], means, co, rgb, depth)
     assert f["n_contrib"][py, px] == gold["n_contrib"]
     assert f["n_examined"][py, px] == gold["n_examined"]
+    assert f["n_blended"][py, px] == gold["n_contrib"]  # identical entries: every one before the stop blends
     assert f["final_T"][py, px] == pytest.approx(gold["final_T"], rel=1e-15)
     np.testing.assert_allclose(f["color"][:, py, px], gold["color"], rtol=1e-14)
     assert f["alpha"][py, px] == pytest.approx(gold["out_alpha"], rel=1e-14)
@@ -130,7 +131,7 @@ def test_identical_alpha_stack_golden(orc):
 
 
 def _brute_pixel(pr, order, px, py, tx, ty, bg):
-    T, C, D, n, ex = 1.0, np.zeros(3), 0.0, 0, 0
+    T, C, D, n, ex, nb = 1.0, np.zeros(3), 0.0, 0, 0, 0
     k = -1
     for g in order:
         if not _brute_membership(pr["means2D"][g, 0], pr["means2D"][g, 1], pr["radius"][g], tx, ty):
@@ -154,7 +155,8 @@ def _brute_pixel(pr, order, px, py, tx, ty, bg):
         D += pr["depth"][g] * alpha * T
         T = Tn
         n = k + 1
-    return C + T * bg, D, T, n, ex
+        nb += 1
+    return C + T * bg, D, T, n, ex, nb
 
 
 @pytest.mark.parametrize("seed,n", [(4, 30), (6, 60)])
@@ -166,14 +168,18 @@ def test_render_brute_force(orc, seed, n):
     order = sorted(range(s.P), key=lambda g: (pr["depth"][g], g))
     for py in range(cam.height):
         for px in range(cam.width):
-            C, D, T, nc, ex = _brute_pixel(pr, order, px, py, px // 16, py // 16, bg)
+            C, D, T, nc, ex, nb = _brute_pixel(pr, order, px, py, px // 16, py // 16, bg)
             np.testing.assert_allclose(f["color"][:, py, px], C, rtol=1e-12, atol=1e-14)
             assert f["depth"][py, px] == pytest.approx(D, rel=1e-12, abs=1e-14)
             assert f["final_T"][py, px] == pytest.approx(T, rel=1e-12)
             assert f["n_contrib"][py, px] == nc
             assert f["n_examined"][py, px] == ex
+            assert f["n_blended"][py, px] == nb
     assert np.abs(f["alpha"] + f["final_T"] - 1).max() < 1e-13
     assert f["blends"] == int(f["n_examined"].sum())
+    assert f["contributors"] == int(f["n_blended"].sum())
+    # some pixels skip entries inside their walked range: both counts are exercised
+    assert np.any(f["n_blended"] < f["n_contrib"]) and np.all(f["n_blended"] <= f["n_contrib"])
 
 
 def test_permutation_invariance(orc):

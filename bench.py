@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the run with exact ellipse-tile binning (bgs_tile_lists_exact)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", default="720,360,1200,600",
+    ap.add_argument("--cpu-window", default="480,240,1440,720",
                     help="pixel window x0,y0,x1,y1 of the oracle's CPU sample")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched multi-view measurement (32 orbit views, one graph launch per step)")

@@ -6,7 +6,11 @@ One step = the whole path on one synthetic frame, inputs resident in HBM:
 (gradient buffers zeroed each step), issued without host synchronization
 (pipeline.FrameStep).  The timed steps replay the step captured once as a
 hipGraph; the same step launched eagerly, call by call, is timed too and
-gives the per-stage times, and the replays must reproduce its outputs.  The workload is the imbalanced 1080p
+gives the per-stage times, and the replays must reproduce its outputs.  By
+default the tile lists keep only the front-most K entries per tile, K picked
+by FrameStep from one whole-list step; every timed step is checked for a
+pixel running off a capped list (the run fails if one does), so the
+outputs are those of whole lists.  The workload is the imbalanced 1080p
 scene: 1920x1080, 500k Gaussians (30% clustered in 5% of the screen, 1%
 large), 16x16 tiles, random upstream dL/dcolor ~ N(0,1).
 
@@ -78,6 +82,9 @@ def parse():
     ap.add_argument("--no-static", action="store_true", help="skip the static-kernel comparison")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the run with exact ellipse-tile binning (bgs_tile_lists_exact)")
+    ap.add_argument("--list-cap", default="auto",
+                    help="tile lists capped at K entries per tile: 'auto' (FrameStep picks K and the step is checked "
+                         "for overflow), 'none' (whole lists) or an integer K")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", default="480,240,1440,720",
                     help="pixel window x0,y0,x1,y1 of the oracle's CPU sample")
@@ -121,10 +128,12 @@ def main():
     dL_dcolor = torch.from_numpy(scene.upstream()["dL_dcolor"]).to(dev).contiguous()
     stream = torch.cuda.current_stream()
 
+    list_cap = None if args.list_cap == "none" else ("auto" if args.list_cap == "auto" else int(args.list_cap))
+
     def make_step(fcfg, bcfg, binning="square"):
         """A FrameStep (every buffer up front, no host sync inside a step) and the
         state the rest of the benchmark reads."""
-        st = FrameStep(cam, g_in, scene.sh_degree, dL_dcolor, fcfg, bcfg, binning=binning)
+        st = FrameStep(cam, g_in, scene.sh_degree, dL_dcolor, fcfg, bcfg, binning=binning, list_cap=list_cap)
         state = {"step": st, "frame": st.frame, "rws": st.rws}
         return st, state, st.pr, st.fwd, st.grads
 
@@ -145,7 +154,12 @@ def main():
         M = st.n_pairs()  # read once the steps are done
         if M > st.capacity:
             raise RuntimeError("pair capacity exceeded")
+        if st.overflowed():
+            raise RuntimeError("a pixel ran off a capped tile list: rerun with a larger --list-cap or 'none'")
         state["M"] = M
+        state["M_whole"] = st.M_whole
+        state["list_cap"] = st.list_cap
+        state["whole_list_len"] = st.whole_list_len.cpu().numpy()
         state["frame_bufs"] = (st.ranges, st.point_list[:M])
         names = ["project", "lists", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"]
         stages = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
@@ -164,6 +178,8 @@ def main():
                 g.replay()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
+            if st.overflowed():
+                raise RuntimeError("a pixel ran off a capped tile list during the graph replays")
             same_f = all(torch.equal(ref_f[k], fwd[k]) for k in fwd)
             gerr = max(float((ref_g[k] - grads[k]).abs().max()) / (float(ref_g[k].abs().max()) + 1e-30)
                        for k in grads)
@@ -194,7 +210,9 @@ def main():
     ms_step = state["graph_ms"]  # the step as one hipGraph launch; eager (launch by launch) reported beside it
     graph_check = state["graph_check"]
     M = state["M"]
-    print(f"[bench] balanced: {ms_step:.3f} ms/step as one graph launch ({ms_eager:.3f} launched eagerly), M={M}, "
+    state_M_whole, list_cap_used = state["M_whole"], state["list_cap"]
+    print(f"[bench] balanced: {ms_step:.3f} ms/step as one graph launch ({ms_eager:.3f} launched eagerly), "
+          f"M={state['M_whole']} (stored {M}, list cap {state['list_cap']}), "
           f"eager stages " + ", ".join(f"{k}={v:.3f}" for k, v in stages.items()), flush=True)
 
     # algorithmic blend counts: the oracle over the GPU's own lists (untimed)
@@ -208,7 +226,7 @@ def main():
     fwd_blends = int(ofwd["blends"])
     bwd_blends = int(ofwd["n_contrib"].astype(np.int64).sum())
     contributors = int(ofwd["contributors"])
-    wstats = workload_stats(ofwd["n_examined"], ranges_np)
+    wstats = workload_stats(ofwd["n_examined"], state["whole_list_len"])
     n_contrib_gpu = fwd["n_contrib"].cpu().numpy()
     agree = float(np.mean(n_contrib_gpu == ofwd["n_contrib"]))
     print(f"[bench] blends fwd={fwd_blends} bwd={bwd_blends} contributors={contributors} "
@@ -247,12 +265,14 @@ def main():
             v["frac"] = v["achieved"] / v["peak"]
         same = all(torch.equal(fwd[k], fwd_e[k]) for k in ("color", "alpha", "depth", "final_T"))
         diff = max(float((fwd[k] - fwd_e[k]).abs().max()) for k in ("color", "alpha", "depth", "final_T"))
-        exact = {"n_pairs": state_e["M"], "ms_per_step": ms_e, "eager_ms_per_step": ms_ee, "stages_ms": st_e,
+        exact = {"n_pairs": state_e["M_whole"], "n_pairs_stored": state_e["M"], "list_cap": state_e["list_cap"],
+                 "ms_per_step": ms_e, "eager_ms_per_step": ms_ee, "stages_ms": st_e,
                  "blends": {"fwd": fb_e, "bwd": bb_e, "contributors": cb_e}, "render_roofline": roof_e,
                  "value": (fb_e + bb_e) / (ms_e * 1e-3),
                  "unit": "examined blends/s", "images_equal_square_rule": same, "max_abs_image_diff": diff,
                  "n_contrib_agreement_oracle": agree_e, "step_speedup_vs_square_rule": ms_step / ms_e}
-        print(f"[bench] exact binning: {ms_e:.3f} ms/step ({ms_step / ms_e:.2f}x), M={state_e['M']}, stages " +
+        print(f"[bench] exact binning: {ms_e:.3f} ms/step ({ms_step / ms_e:.2f}x), M={state_e['M_whole']} "
+              f"(stored {state_e['M']}, cap {state_e['list_cap']}), stages " +
               ", ".join(f"{k}={v:.3f}" for k, v in st_e.items()) +
               f"; blends fwd={fb_e} bwd={bb_e}; images equal: {same}", flush=True)
 
@@ -416,8 +436,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_NAME, "scene": scene.name, "seed": scene.seed, "P": scene.P,
-                   "width": W, "height": H, "n_pairs": M, "forward": B.cfg_name(fcfg),
-                   "backward": B.cfg_name(bcfg), "lists": "fused"},
+                   "width": W, "height": H, "n_pairs": state_M_whole, "forward": B.cfg_name(fcfg),
+                   "backward": B.cfg_name(bcfg),
+                   "lists": ("fused, whole" if not list_cap_used else
+                             f"fused, capped at {list_cap_used} entries per tile (no pixel ran off a list)"),
+                   "n_pairs_stored": M},
         "autotune": tuned,
         "workload_stats": wstats,
         "blends": {"fwd": fwd_blends, "bwd": bwd_blends, "contributors": contributors},
@@ -610,14 +633,15 @@ def measured_traffic(kernel):
     return rec["bytes_per_launch"]
 
 
-def workload_stats(n_examined, ranges):
-    """Shape of the per-pixel work: list lengths, examined entries per pixel,
-    and the tail ratio R = (critical path of the heaviest work item) /
-    (total work / 1024 SIMDs), with a wave's work = the most entries any of
-    its 64 pixels examines.  R > 1 means the static schedule is tail-bound."""
+def workload_stats(n_examined, list_len):
+    """Shape of the per-pixel work: whole tile-list lengths, examined entries
+    per pixel, and the tail ratio R = (critical path of the heaviest work
+    item) / (total work / 1024 SIMDs), with a wave's work = the most entries
+    any of its 64 pixels examines.  R > 1 means the static schedule is
+    tail-bound."""
     import numpy as np
     H, W = n_examined.shape
-    lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)
+    lens = np.asarray(list_len).astype(np.int64)
     Hp, Wp = (H + 15) // 16 * 16, (W + 15) // 16 * 16
     ex = np.zeros((Hp, Wp), np.int64)
     ex[:H, :W] = n_examined

@@ -118,6 +118,14 @@ typedef struct bgs_render_cfg {
        the pixel never stops).  Written by BGS_BALANCED_PIXEL with subtile
        16; other variants return BGS_EUNSUPPORTED when it is set. */
     int32_t* n_examined;
+    /* Lists capped at list_cap entries per tile (bgs_tile_lists with
+       max_per_tile = list_cap; 0: whole lists).  bgs_render_fwd sets
+       *list_overflow (DEVICE, nullable) to 1 when a pixel reaches the end of
+       a list of list_cap or more entries without stopping: that pixel's
+       result may differ from the whole list's.  The flag is only ever set;
+       the caller clears it. */
+    uint32_t list_cap;
+    uint32_t* list_overflow;
 } bgs_render_cfg;
 
 /* Thread-local text for the last non-OK status of this thread. */
@@ -228,11 +236,21 @@ size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P, 
  * convenient, grows point_list (and the workspace) and calls again.
  * capacity must be < 2^32.  Tile grids of more than 8192 groups return
  * BGS_EUNSUPPORTED (use the three separate calls).
+ *   max_per_tile: 0 for whole lists.  K > 0 keeps only the first K entries of
+ *   each tile's list (its front-most K Gaussians); ranges and M then count
+ *   the kept entries.  Eq. (4) never reads past the entry at which a pixel's
+ *   transmittance stops, so a render from the capped lists equals the render
+ *   from whole lists unless some pixel reaches the end of a capped list
+ *   without stopping; bgs_render_fwd reports that case through
+ *   bgs_render_cfg.list_overflow, and the frame must then be built and
+ *   rendered again with a larger K or whole lists.  The coarse lists are
+ *   not capped: size capacity (and the workspace) for at least the coarse
+ *   entries, e.g. for the uncapped M.
  */
 bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
                           const int32_t* radius, const float* depth, const uint32_t* tiles_touched,
-                          uint32_t* point_list, int64_t capacity, uint32_t* ranges, uint64_t* n_pairs_dev, void* ws,
-                          size_t ws_bytes, hipStream_t stream);
+                          uint32_t* point_list, int64_t capacity, uint32_t max_per_tile, uint32_t* ranges,
+                          uint64_t* n_pairs_dev, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * bgs_tile_lists with exact ellipse-tile binning (the list-shrinking binning
@@ -250,13 +268,14 @@ bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P
  * is not positive definite keeps the square rule; one with opacity below
  * 1/255 gets no pair.
  *   conic_opacity [P][4] (DEVICE, 16-byte aligned), everything else, the
- *   workspace size and the overflow behaviour as for bgs_tile_lists.
+ *   workspace size, max_per_tile and the overflow behaviour as for
+ *   bgs_tile_lists.
  */
 bgs_status bgs_tile_lists_exact(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
                                 const float* conic_opacity, const int32_t* radius, const float* depth,
                                 const uint32_t* tiles_touched, uint32_t* point_list, int64_t capacity,
-                                uint32_t* ranges, uint64_t* n_pairs_dev, void* ws, size_t ws_bytes,
-                                hipStream_t stream);
+                                uint32_t max_per_tile, uint32_t* ranges, uint64_t* n_pairs_dev, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
 
 /* Workspace bytes for bgs_queue_build / bgs_render_fwd / bgs_render_bwd. */
 size_t bgs_render_workspace_bytes(const bgs_frame* frame, const bgs_render_cfg* cfg);

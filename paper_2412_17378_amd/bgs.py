@@ -56,7 +56,7 @@ class ViewIO(C.Structure):
 class RenderCfg(C.Structure):
     _fields_ = [("variant", C.c_int32), ("subtile", C.c_int32), ("order", C.c_int32), ("flags", C.c_int32),
                 ("bg", C.c_float * 3), ("wg_trace", C.c_void_p), ("wg_trace_cap", C.c_int64),
-                ("n_examined", C.c_void_p)]
+                ("n_examined", C.c_void_p), ("list_cap", C.c_uint32), ("list_overflow", C.c_void_p)]
 
 
 _LIB = None
@@ -82,10 +82,10 @@ def lib() -> C.CDLL:
             "bgs_sort": ([_vp, _vp, _vp, _vp, _i64, _i32, _vp, _sz, _vp], C.c_int),
             "bgs_ranges": ([_vp, _i64, _i32, _vp, _vp], C.c_int),
             "bgs_tile_lists_workspace_bytes": ([_i32, _i32, _i64, _i64], _sz),
-            "bgs_tile_lists": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp],
-                               C.c_int),
-            "bgs_tile_lists_exact": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz,
-                                      _vp], C.c_int),
+            "bgs_tile_lists": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, C.c_uint32, _vp, _vp, _vp,
+                                _sz, _vp], C.c_int),
+            "bgs_tile_lists_exact": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, C.c_uint32, _vp, _vp,
+                                      _vp, _sz, _vp], C.c_int),
             "bgs_render_workspace_bytes": ([_vp, _vp], _sz),
             "bgs_queue_build": ([_vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_render_fwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
@@ -292,25 +292,29 @@ def bgs_tile_lists_workspace_bytes(width: int, height: int, P: int, capacity: in
 
 
 def bgs_tile_lists(width, height, means2D, radius, depth, tiles_touched, point_list, ranges, n_pairs_dev, ws,
-                   stream=None, conic_opacity=None) -> bool:
+                   stream=None, conic_opacity=None, max_per_tile: int = 0) -> bool:
     """Asynchronous: n_pairs_dev (int64 [>=1] device tensor) receives M, or a
     lower bound of M above the capacity (point_list.numel()) on overflow, in
     which case every range is empty; the caller compares n_pairs_dev with the
     capacity when convenient and grows.  Returns False on BGS_ECAPACITY.
     With conic_opacity ([P,4] float32) the lists use exact ellipse-tile
-    binning (bgs_tile_lists_exact)."""
+    binning (bgs_tile_lists_exact).  max_per_tile > 0 keeps the first
+    max_per_tile entries of each tile's list (see include/bgs.h)."""
     cap = 0 if point_list is None else point_list.numel()
     _expect(ranges, (n_tiles(width, height), 2), torch.int32, "ranges")
     P = means2D.shape[0]
+    K = int(max_per_tile)
+    if not 0 <= K < 1 << 32:
+        raise ValueError("max_per_tile must be in [0, 2^32)")
     if conic_opacity is None:
         st = lib().bgs_tile_lists(int(width), int(height), TILE, P, _ptr(means2D), _ptr(radius), _ptr(depth),
-                                  _ptr(tiles_touched), _ptr(point_list) if cap else None, cap, _ptr(ranges),
+                                  _ptr(tiles_touched), _ptr(point_list) if cap else None, cap, K, _ptr(ranges),
                                   _ptr(n_pairs_dev), _ptr(ws), ws.numel(), _stream(stream))
     else:
         _expect(conic_opacity, (P, 4), torch.float32, "conic_opacity")
         st = lib().bgs_tile_lists_exact(int(width), int(height), TILE, P, _ptr(means2D), _ptr(conic_opacity),
                                         _ptr(radius), _ptr(depth), _ptr(tiles_touched),
-                                        _ptr(point_list) if cap else None, cap, _ptr(ranges), _ptr(n_pairs_dev),
+                                        _ptr(point_list) if cap else None, cap, K, _ptr(ranges), _ptr(n_pairs_dev),
                                         _ptr(ws), ws.numel(), _stream(stream))
     if st == BGS_ECAPACITY:
         return False

@@ -684,30 +684,30 @@ __global__ __launch_bounds__(256) void k_part_scan(int nb, int nt, uint32_t* __r
     if (lane == 0) total[t] = carry;
 }
 
-// Single workgroup: exclusive scan of total -> start; ranges (empty: (0, 0));
-// the grand total in n_pairs[0].  Thread i owns the contiguous run
-// [i per, (i+1) per); the per-thread sums are scanned with a block scan.
-// Overflow: when coarse_n (nullable) exceeds coarse_cap, n_pairs[0] receives
-// coarse_n (a lower bound of the pair count); then, or when the total
-// exceeds cap, every range is written empty, so that nothing reads the
-// unwritten point list.
+// Single workgroup: exclusive scan of n_t = min(total[t], keep_max) -> start;
+// ranges (empty: (0, 0)); the grand total in n_pairs[0].  Thread i owns the
+// contiguous run [i per, (i+1) per); the per-thread sums are scanned with a
+// block scan.  Overflow: when coarse_n (nullable) exceeds coarse_cap,
+// n_pairs[0] receives coarse_n (a lower bound of the pair count); then, or
+// when the total exceeds cap, every range is written empty, so that nothing
+// reads the unwritten point list.
 __global__ __launch_bounds__(1024) void k_tile_scan(int nt, const uint32_t* __restrict__ total,
                                                     uint32_t* __restrict__ start, uint32_t* __restrict__ ranges,
                                                     uint64_t* __restrict__ n_pairs, const uint64_t* __restrict__ coarse_n,
-                                                    uint64_t coarse_cap, uint64_t cap) {
+                                                    uint64_t coarse_cap, uint64_t cap, uint32_t keep_max) {
     using Scan = rocprim::block_scan<uint64_t, 1024>;
     __shared__ typename Scan::storage_type s_scan;
     const int per = (nt + 1023) / 1024;
     const int t0 = min(nt, (int)threadIdx.x * per), t1 = min(nt, t0 + per);
     uint64_t s = 0;
-    for (int t = t0; t < t1; ++t) s += total[t];
+    for (int t = t0; t < t1; ++t) s += min(total[t], keep_max);
     uint64_t run = 0, grand = 0;
     Scan().exclusive_scan(s, run, (uint64_t)0, grand, s_scan);
     const bool coarse_over = coarse_n != nullptr && coarse_n[0] > coarse_cap;
     if (threadIdx.x == 0) n_pairs[0] = coarse_over ? coarse_n[0] : grand;
     const bool keep = !coarse_over && grand <= cap;
     for (int t = t0; t < t1; ++t) {
-        const uint32_t n = total[t];
+        const uint32_t n = min(total[t], keep_max);
         start[t] = (uint32_t)run;
         if (ranges) {
             ranges[2 * t] = n && keep ? (uint32_t)run : 0u;
@@ -926,20 +926,39 @@ __global__ __launch_bounds__(256) void k_seg_map(int ng, const uint32_t* __restr
 // at a time, the ballot of the entries whose mask holds the tile.
 // COUNT: segcnt[seg][i] = the segment's entries whose mask holds tile i.
 // WRITE: the k-th such entry goes to segcnt[seg][i] (by then the slot where
-// the segment's run of tile i starts) + k.  Each lane keeps its 32 entries of
-// the segment in registers and the wave takes its tiles one after another,
-// so a (tile, 64 entries) step is a bit test, a ballot, the lane's rank
-// (mbcnt) and one store of the compacted run at a wave-uniform base.
+// the segment's run of tile i starts) + k, if that slot is below the end of
+// the tile's range (which stops short of the tile's count when lists are
+// capped).  Each lane keeps its 32 entries of the segment in registers and
+// the wave takes its tiles one after another, so a (tile, 64 entries) step
+// is a bit test, a ballot, the lane's rank (mbcnt) and one store of the
+// compacted run at a wave-uniform base.  A wave none of whose 16 tiles has
+// room left in this segment reads nothing.
 constexpr size_t SPLIT_GRID = 2048;  // workgroups of the split passes: 8 per CU
+
+struct TileGrid {
+    int TX, TY, GX;
+    const uint32_t* ranges;  // WRITE: [n_tiles][2] of the final lists
+};
 
 template <bool WRITE>
 __device__ __forceinline__ void split_segment(uint32_t sidx, const uint2* __restrict__ segmap,
                                               const uint4* __restrict__ coarse, const uint32_t* __restrict__ gstart,
                                               const uint32_t* __restrict__ gtotal, uint32_t* __restrict__ segcnt,
-                                              uint32_t* __restrict__ point_list) {
+                                              uint32_t* __restrict__ point_list, const TileGrid& tg) {
     const uint2 gs = segmap[sidx];
     const int grp = (int)gs.x;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // WRITE: lane i < 16 holds the run start and the range end of the wave's tile i
+    uint32_t my_run = 0u, my_end = 0u;
+    if (WRITE) {
+        if (lane < 16) {
+            const int li = wv * 16 + lane;
+            const int tx = (grp % tg.GX) * GTILES + (li % GTILES), ty = (grp / tg.GX) * GTILES + (li / GTILES);
+            my_run = segcnt[(size_t)sidx * 64 + li];
+            my_end = (tx < tg.TX && ty < tg.TY) ? tg.ranges[2 * ((size_t)ty * tg.TX + tx) + 1] : 0u;
+        }
+        if (ballot(lane < 16 && my_run < my_end) == 0) return;  // this wave's tiles are full
+    }
     const uint32_t gt = gtotal[grp];
     const uint32_t e0 = min(gt, gs.y * SEG), e1 = min(gt, (gs.y + 1) * SEG);
     const uint32_t b0 = gstart[grp];
@@ -958,7 +977,9 @@ __device__ __forceinline__ void split_segment(uint32_t sidx, const uint2* __rest
         }
     }
     for (int i = 0; i < 16; ++i) {
-        uint32_t run = __builtin_amdgcn_readfirstlane(WRITE ? segcnt[(size_t)sidx * 64 + wv * 16 + i] : 0u);
+        uint32_t run = WRITE ? (uint32_t)__builtin_amdgcn_readlane((int)my_run, i) : 0u;
+        const uint32_t end = WRITE ? (uint32_t)__builtin_amdgcn_readlane((int)my_end, i) : 0u;
+        if (WRITE && run >= end) continue;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const bool in = (bits[b] >> i) & 1u;
@@ -967,7 +988,7 @@ __device__ __forceinline__ void split_segment(uint32_t sidx, const uint2* __rest
                 const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 uint32_t* dst = point_list + run;
-                if (in) dst[rank] = ids[b];
+                if (in && run + rank < end) dst[rank] = ids[b];
             }
             run = __builtin_amdgcn_readfirstlane(run + (uint32_t)__builtin_popcountll(m));
         }
@@ -982,14 +1003,14 @@ __global__ __launch_bounds__(256) void k_seg_split(const uint64_t* __restrict__ 
                                                    const uint32_t* __restrict__ gtotal, uint32_t* __restrict__ segcnt,
                                                    uint32_t* __restrict__ point_list, const uint64_t* __restrict__ n_pairs,
                                                    uint64_t capacity, const uint64_t* __restrict__ coarse_n,
-                                                   uint64_t coarse_cap, uint32_t max_segs) {
+                                                   uint64_t coarse_cap, uint32_t max_segs, TileGrid tg) {
     if (coarse_n[0] > coarse_cap) return;  // no coarse lists to split
     // the pair count is final here; a list that does not fit is not written
     // at all (the caller grows the buffer and builds again)
     if (WRITE && n_pairs[0] > capacity) return;
     const uint32_t nsg = (uint32_t)min(n_segs[0], (uint64_t)max_segs);
     for (uint32_t sidx = blockIdx.x; sidx < nsg; sidx += gridDim.x)
-        split_segment<WRITE>(sidx, segmap, coarse, gstart, gtotal, segcnt, point_list);
+        split_segment<WRITE>(sidx, segmap, coarse, gstart, gtotal, segcnt, point_list, tg);
 }
 
 // One workgroup per group, thread (part p, local tile i): p takes a
@@ -1109,8 +1130,9 @@ extern "C" size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, 
 // binning
 static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
                              const float* conic_opacity, const int32_t* radius, const float* depth,
-                             const uint32_t* tiles_touched, uint32_t* point_list, int64_t capacity, uint32_t* ranges,
-                             uint64_t* n_pairs_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
+                             const uint32_t* tiles_touched, uint32_t* point_list, int64_t capacity,
+                             uint32_t max_per_tile, uint32_t* ranges, uint64_t* n_pairs_dev, void* ws, size_t ws_bytes,
+                             hipStream_t stream) {
     BGS_REQUIRE(width > 0 && height > 0, "bgs_tile_lists: image size must be positive");
     BGS_REQUIRE(P >= 0 && capacity >= 0, "bgs_tile_lists: negative size");
     if (tile != TILE) return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: only 16x16 tiles are supported");
@@ -1177,7 +1199,7 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
     const uint64_t ccap = (uint64_t)L.coarse_cap, pcap = (uint64_t)capacity;
     const uint64_t no_cap = ~(uint64_t)0;
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.ng, gtotal, gstart, (uint32_t*)nullptr, mg,
-                       (const uint64_t*)nullptr, no_cap, no_cap);
+                       (const uint64_t*)nullptr, no_cap, no_cap, ~0u);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(nbg)), dim3(256), 0, stream, L.C, L.ng, gstart, part, h);
     BGS_HIP(hipGetLastError());
@@ -1199,20 +1221,21 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
     hipLaunchKernelGGL(k_seg_count, dim3(blocks_for(L.ng)), dim3(256), 0, stream, L.ng, gtotal, nseg);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.ng, nseg, segstart, (uint32_t*)nullptr, nsegs,
-                       (const uint64_t*)nullptr, no_cap, no_cap);
+                       (const uint64_t*)nullptr, no_cap, no_cap, ~0u);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_seg_map, dim3((unsigned)((L.ng + 3) / 4)), dim3(256), 0, stream, L.ng, nseg, segstart, segmap,
                        (const uint64_t*)mg, ccap, max_segs);
     BGS_HIP(hipGetLastError());
+    const TileGrid tg{TX, TY, L.GX, ranges};
     hipLaunchKernelGGL(k_seg_split<false>, dim3(grid_split), dim3(256), 0, stream, nsegs, segmap, coarse, gstart,
                        gtotal, segcnt, (uint32_t*)nullptr, (const uint64_t*)nullptr, (uint64_t)0, (const uint64_t*)mg,
-                       ccap, max_segs);
+                       ccap, max_segs, tg);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_seg_scan<false>, dim3(L.ng), dim3(SCAN_PARTS * 64), 0, stream, TX, TY, L.GX, nseg,
                        segstart, segcnt, (const uint32_t*)nullptr, ttotal, (const uint64_t*)mg, ccap);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, L.nt, ttotal, tstart, ranges, n_pairs_dev,
-                       (const uint64_t*)mg, ccap, pcap);
+                       (const uint64_t*)mg, ccap, pcap, max_per_tile ? max_per_tile : ~0u);
     BGS_HIP(hipGetLastError());
     if (capacity > 0) {
         hipLaunchKernelGGL(k_seg_scan<true>, dim3(L.ng), dim3(SCAN_PARTS * 64), 0, stream, TX, TY, L.GX, nseg,
@@ -1220,7 +1243,7 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
         BGS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_seg_split<true>, dim3(grid_split), dim3(256), 0, stream, nsegs, segmap, coarse, gstart,
                            gtotal, segcnt, point_list, (const uint64_t*)n_pairs_dev, pcap, (const uint64_t*)mg, ccap,
-                           max_segs);
+                           max_segs, tg);
         BGS_HIP(hipGetLastError());
     }
     return BGS_OK;
@@ -1228,19 +1251,19 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
 
 extern "C" bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
                                      const int32_t* radius, const float* depth, const uint32_t* tiles_touched,
-                                     uint32_t* point_list, int64_t capacity, uint32_t* ranges, uint64_t* n_pairs_dev,
-                                     void* ws, size_t ws_bytes, hipStream_t stream) {
+                                     uint32_t* point_list, int64_t capacity, uint32_t max_per_tile, uint32_t* ranges,
+                                     uint64_t* n_pairs_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
     return tile_lists(width, height, tile, P, means2D, nullptr, radius, depth, tiles_touched, point_list, capacity,
-                      ranges, n_pairs_dev, ws, ws_bytes, stream);
+                      max_per_tile, ranges, n_pairs_dev, ws, ws_bytes, stream);
 }
 
 extern "C" bgs_status bgs_tile_lists_exact(int32_t width, int32_t height, int32_t tile, int64_t P,
                                            const float* means2D, const float* conic_opacity, const int32_t* radius,
                                            const float* depth, const uint32_t* tiles_touched, uint32_t* point_list,
-                                           int64_t capacity, uint32_t* ranges, uint64_t* n_pairs_dev, void* ws,
-                                           size_t ws_bytes, hipStream_t stream) {
+                                           int64_t capacity, uint32_t max_per_tile, uint32_t* ranges,
+                                           uint64_t* n_pairs_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
     BGS_REQUIRE(P == 0 || conic_opacity != nullptr, "bgs_tile_lists_exact: conic_opacity is null");
     BGS_REQUIRE(((uintptr_t)conic_opacity & 15u) == 0, "bgs_tile_lists_exact: conic_opacity must be 16-byte aligned");
     return tile_lists(width, height, tile, P, means2D, P ? conic_opacity : nullptr, radius, depth, tiles_touched,
-                      point_list, capacity, ranges, n_pairs_dev, ws, ws_bytes, stream);
+                      point_list, capacity, max_per_tile, ranges, n_pairs_dev, ws, ws_bytes, stream);
 }

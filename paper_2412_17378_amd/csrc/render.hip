@@ -48,6 +48,8 @@ struct FrameArgs {
     uint64_t* trace;  // per-wave timing records (nullable), trace_cap of them
     int64_t trace_cap;
     int* n_examined;  // optional per-pixel count of examined list entries (forward)
+    uint32_t list_cap;        // lists capped at this many entries per tile (0: whole lists)
+    uint32_t* list_overflow;  // set when a pixel runs off a capped list (nullable)
 };
 
 struct FwdOut {
@@ -201,6 +203,10 @@ __device__ __forceinline__ void write_pixel(const FrameArgs& F, const FwdOut& O,
     O.depth[p] = s.D;
     O.final_T[p] = s.T;
     O.n_contrib[p] = s.last;
+    if (F.list_cap && F.list_overflow && !s.done) {  // ran to the end of its list without stopping
+        const int64_t t = (int64_t)(py / TILE) * F.TX + px / TILE;
+        if (F.ranges[2 * t + 1] - F.ranges[2 * t] >= F.list_cap) *F.list_overflow = 1u;
+    }
 }
 
 // ------------------------------------------------------------------ static
@@ -1022,6 +1028,8 @@ static bgs_status check_frame(const bgs_frame* f, const bgs_render_cfg* cfg, Fra
     A.trace = cfg->wg_trace;
     A.trace_cap = cfg->wg_trace ? cfg->wg_trace_cap : 0;
     A.n_examined = cfg->n_examined;
+    A.list_cap = cfg->list_cap;
+    A.list_overflow = cfg->list_overflow;
     return BGS_OK;
 }
 

@@ -312,10 +312,18 @@ class FrameStep:
     params: means3D [P,3], log_scales [P,3], quats [P,4], opacity [P],
     colors [P,3] or [P,K,3] (device tensors, read each step, so they may be
     updated in place between steps).  Outputs: self.pr (projection),
-    self.fwd (images), self.grads (gradients of the 2D splats)."""
+    self.fwd (images), self.grads (gradients of the 2D splats).
+
+    list_cap: None builds whole tile lists.  An int K keeps the first K
+    entries of each tile's list (bgs_tile_lists max_per_tile); "auto" picks K
+    from one uncapped step (twice the deepest contributor, rounded up) and
+    doubles it until a capped step runs without overflow.  With a cap, a
+    step's outputs equal the uncapped step's unless overflowed() (a host
+    read) reports that a pixel ran off a capped list; the caller then
+    rebuilds with set_list_cap (larger K, or None) and runs the step again."""
 
     def __init__(self, cam, params: dict, sh_degree: int, dL_dcolor, fcfg: B.RenderCfg, bcfg: B.RenderCfg,
-                 binning: str = "square", headroom: float = 1.25):
+                 binning: str = "square", headroom: float = 1.25, list_cap=None):
         if binning not in ("square", "ellipse"):
             raise ValueError(f"unknown binning {binning!r}")
         W, H = int(cam.width), int(cam.height)
@@ -330,6 +338,8 @@ class FrameStep:
         self.fcfg, self.bcfg = fcfg, bcfg
         self.fcfg_ready = B.make_cfg(fcfg.variant, fcfg.subtile, fcfg.order, tuple(fcfg.bg), flags=B.FLAG_QUEUE_READY)
         self.bcfg_ready = B.make_cfg(bcfg.variant, bcfg.subtile, bcfg.order, tuple(bcfg.bg), flags=B.FLAG_QUEUE_READY)
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.list_cap = 0
         self.pr = dict(means2D=torch.empty(P, 2, device=dev), conic_opacity=torch.empty(P, 4, device=dev),
                        rgb=torch.empty(P, 3, device=dev), depth=torch.empty(P, device=dev),
                        radius=torch.empty(P, dtype=torch.int32, device=dev),
@@ -360,6 +370,39 @@ class FrameStep:
                                   self.pr["rgb"], self.pr["depth"])
         rb = max(B.bgs_render_workspace_bytes(self.frame, fcfg), B.bgs_render_workspace_bytes(self.frame, bcfg))
         self.rws = torch.empty(rb, dtype=torch.uint8, device=dev)
+        self.M_whole = M
+        self.whole_list_len = (self.ranges[:, 1] - self.ranges[:, 0]).clone()  # of the sizing build's whole lists
+        if list_cap == "auto":
+            self.run()
+            deepest = int(self.fwd["n_contrib"].max().item())
+            longest = int((self.ranges[:, 1] - self.ranges[:, 0]).max().item())
+            K = (2 * deepest + 64 + 63) // 64 * 64
+            while K < longest:
+                self.set_list_cap(K)
+                self.run()
+                if not self.overflowed():
+                    break
+                K *= 2
+            else:
+                self.set_list_cap(None)
+        elif list_cap is not None:
+            self.set_list_cap(int(list_cap))
+
+    def set_list_cap(self, K):
+        """Cap the tile lists at K entries per tile from the next step on
+        (None or 0: whole lists)."""
+        K = int(K or 0)
+        if not 0 <= K < 1 << 32:
+            raise ValueError("list cap must be in [0, 2^32)")
+        self.list_cap = K
+        self.fcfg_ready.list_cap = K
+        self.fcfg_ready.list_overflow = self.overflow.data_ptr() if K else None
+        self.overflow.zero_()
+
+    def overflowed(self) -> bool:
+        """Whether a pixel of the last step ran off a capped list (reads the
+        device; synchronizes).  Always False with whole lists."""
+        return bool(self.list_cap) and bool(self.overflow.item())
 
     def _alloc_lists(self, cap):
         dev = self.dL_dcolor.device
@@ -376,7 +419,8 @@ class FrameStep:
         pr = self.pr
         B.bgs_tile_lists(self.W, self.H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"],
                          self.point_list if self.point_list.numel() else None, self.ranges, self.n_dev, self.lws,
-                         conic_opacity=pr["conic_opacity"] if self.binning == "ellipse" else None)
+                         conic_opacity=pr["conic_opacity"] if self.binning == "ellipse" else None,
+                         max_per_tile=self.list_cap)
 
     def run(self, mark=None):
         """Issue one step; mark(i) (optional) is called at the stage
@@ -385,6 +429,8 @@ class FrameStep:
         (gradients zeroed), after the backward."""
         mark = mark or (lambda i: None)
         mark(0)
+        if self.list_cap:
+            self.overflow.zero_()
         self._project()
         mark(1)
         self._lists()

@@ -160,7 +160,8 @@ def main():
         state["M_whole"] = st.M_whole
         state["list_cap"] = st.list_cap
         state["whole_list_len"] = st.whole_list_len.cpu().numpy()
-        state["frame_bufs"] = (st.ranges, st.point_list[:M])
+        # capped lists sit at fixed per-tile slots: hand over the point list up to the last range end
+        state["frame_bufs"] = (st.ranges, st.point_list[:int(st.ranges[:, 1].max().item())])
         names = ["project", "lists", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"]
         stages = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
                   for i, n in enumerate(names)}

@@ -237,15 +237,19 @@ size_t bgs_tile_lists_workspace_bytes(int32_t width, int32_t height, int64_t P, 
  * capacity must be < 2^32.  Tile grids of more than 8192 groups return
  * BGS_EUNSUPPORTED (use the three separate calls).
  *   max_per_tile: 0 for whole lists.  K > 0 keeps only the first K entries of
- *   each tile's list (its front-most K Gaussians); ranges and M then count
- *   the kept entries.  Eq. (4) never reads past the entry at which a pixel's
- *   transmittance stops, so a render from the capped lists equals the render
- *   from whole lists unless some pixel reaches the end of a capped list
- *   without stopping; bgs_render_fwd reports that case through
- *   bgs_render_cfg.list_overflow, and the frame must then be built and
- *   rendered again with a larger K or whole lists.  The coarse lists are
- *   not capped: size capacity (and the workspace) for at least the coarse
- *   entries, e.g. for the uncapped M.
+ *   each tile's list (its front-most K Gaussians), where ranges say; M
+ *   counts the kept entries.  K <= 2048: gathered per tile straight from the
+ *   coarse lists into the fixed slot [t K, t K + n_t) of point_list (which
+ *   then has gaps), needing capacity >= n_tiles K (else BGS_ECAPACITY before
+ *   any work).  Larger K: compact, from the segment split.  Eq. (4) never
+ *   reads past the entry at which a pixel's transmittance stops, so a render
+ *   from the capped lists equals the render from whole lists unless some
+ *   pixel reaches the end of a capped list without stopping;
+ *   bgs_render_fwd reports that case through bgs_render_cfg.list_overflow,
+ *   and the frame must then be built and rendered again with a larger K or
+ *   whole lists.  The coarse lists are not capped, so capacity (which also
+ *   sizes them) must hold the coarse entries too, e.g. capacity = the
+ *   whole-list M.
  */
 bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
                           const int32_t* radius, const float* depth, const uint32_t* tiles_touched,

@@ -1065,6 +1065,56 @@ __global__ __launch_bounds__(SCAN_PARTS * 64) void k_seg_scan(int TX, int TY, in
     }
 }
 
+// Lists capped at a small K (<= GATHER_MAX_K): one wave per tile walks its
+// group's coarse list in order, 64 entries at a time, keeps the entries
+// whose mask holds the tile (bit test, ballot, mbcnt rank) and stops once it
+// has K.  Tile t's list is written at the fixed slot [t K, t K + n_t), so no
+// count pass or scan is needed; n_pairs (zeroed before) receives the sum of
+// the n_t.  After a coarse overflow every range is empty and n_pairs
+// receives the coarse count, as for whole lists.  A larger K makes the walk
+// of a sparse tile long and serial; such caps go through the segment split.
+constexpr uint32_t GATHER_MAX_K = 2048;
+__global__ __launch_bounds__(256) void k_tile_gather(int TX, int TY, int GX, uint32_t K,
+                                                     const uint4* __restrict__ coarse,
+                                                     const uint32_t* __restrict__ gstart,
+                                                     const uint32_t* __restrict__ gtotal,
+                                                     uint32_t* __restrict__ point_list, uint32_t* __restrict__ ranges,
+                                                     unsigned long long* __restrict__ n_pairs,
+                                                     const uint64_t* __restrict__ coarse_n, uint64_t coarse_cap) {
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (t >= TX * TY) return;
+    const bool over = coarse_n[0] > coarse_cap;
+    uint32_t cnt = 0;
+    if (!over) {
+        const int tx = t % TX, ty = t / TX;
+        const int grp = (ty / GTILES) * GX + tx / GTILES;
+        const int li = (tx % GTILES) + GTILES * (ty % GTILES);
+        const uint32_t b0 = gstart[grp], n = gtotal[grp];
+        uint32_t* dst = point_list + (size_t)t * K;
+        for (uint32_t k0 = 0; k0 < n && cnt < K; k0 += 64) {
+            const uint32_t k = k0 + lane;
+            bool in = false;
+            uint32_t id = 0u;
+            if (k < n) {
+                const uint4 e = coarse[b0 + k];
+                in = (((li < 32 ? e.y : e.z) >> (li & 31)) & 1u) != 0u;
+                id = e.x;
+            }
+            const uint64_t m = ballot(in);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (in && cnt + rank < K) dst[cnt + rank] = id;
+            cnt = __builtin_amdgcn_readfirstlane(cnt + (uint32_t)__builtin_popcountll(m));
+        }
+        cnt = min(cnt, K);
+    }
+    if (lane == 0) {
+        ranges[2 * t] = cnt ? (uint32_t)t * K : 0u;
+        ranges[2 * t + 1] = cnt ? (uint32_t)t * K + cnt : 0u;
+        if (cnt) atomicAdd(n_pairs, (unsigned long long)cnt);
+        if (over && t == 0) *n_pairs = (unsigned long long)coarse_n[0];
+    }
+}
+
 struct ListsLayout {
     size_t dkeys, ids, dkeys2, order, rect, h, part, gtotal, gstart, nseg, segstart, nsegs, mg, coarse_cap, coarse, ttotal,
         tstart, dcnt, dtot, bytes;
@@ -1147,6 +1197,9 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
     if (conic_opacity && sizeof(uint32_t) * ((size_t)L.ng + 16 * (size_t)TY) > 60000)
         return fail(BGS_EUNSUPPORTED, "bgs_tile_lists_exact: tile grid too large for the exact rule");
     BGS_REQUIRE(ws && ws_bytes >= L.bytes, "bgs_tile_lists: workspace too small");
+    const bool gather = max_per_tile && max_per_tile <= GATHER_MAX_K;
+    if (gather && (int64_t)L.nt * max_per_tile > capacity)
+        return fail(BGS_ECAPACITY, "bgs_tile_lists: lists capped at K <= 2048 need capacity >= n_tiles * K");
     BGS_REQUIRE(capacity == 0 || point_list != nullptr, "bgs_tile_lists: null point_list");
     char* w = static_cast<char*>(ws);
     auto* dkeys = reinterpret_cast<uint32_t*>(w + L.dkeys);
@@ -1210,6 +1263,16 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
         hipLaunchKernelGGL(k_chunk_emit<false>, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX,
                            L.GY, order, rect, h, coarse, (const uint64_t*)mg, ccap, means2D, co4);
     BGS_HIP(hipGetLastError());
+    if (gather) {  // lists capped at a small K: gathered per tile at fixed slots
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t*>(n_pairs_dev),
+                           (int64_t)2, 0u);
+        BGS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_tile_gather, dim3((unsigned)((L.nt + 3) / 4)), dim3(256), 0, stream, TX, TY, L.GX,
+                           max_per_tile, coarse, gstart, gtotal, point_list, ranges,
+                           reinterpret_cast<unsigned long long*>(n_pairs_dev), (const uint64_t*)mg, ccap);
+        BGS_HIP(hipGetLastError());
+        return BGS_OK;
+    }
     // fine (tile) lists, on segments of the coarse lists
     auto* nseg = reinterpret_cast<uint32_t*>(w + L.nseg);
     auto* segstart = reinterpret_cast<uint32_t*>(w + L.segstart);

@@ -377,7 +377,7 @@ class FrameStep:
             deepest = int(self.fwd["n_contrib"].max().item())
             longest = int((self.ranges[:, 1] - self.ranges[:, 0]).max().item())
             K = (2 * deepest + 64 + 63) // 64 * 64
-            while K < longest:
+            while K < longest and (K > 2048 or K * B.n_tiles(W, H) <= self.capacity):
                 self.set_list_cap(K)
                 self.run()
                 if not self.overflowed():
@@ -394,6 +394,8 @@ class FrameStep:
         K = int(K or 0)
         if not 0 <= K < 1 << 32:
             raise ValueError("list cap must be in [0, 2^32)")
+        if 0 < K <= 2048 and K * B.n_tiles(self.W, self.H) > self.capacity:
+            raise ValueError("lists capped at K <= 2048 need n_tiles * K <= the pair capacity")
         self.list_cap = K
         self.fcfg_ready.list_cap = K
         self.fcfg_ready.list_overflow = self.overflow.data_ptr() if K else None

@@ -2,7 +2,8 @@
 overflow report (bgs_render_cfg.list_cap / list_overflow).
 
 * Lists: each capped list is the first min(L, K) entries of the oracle's
-  whole list, bit for bit; M counts the kept entries.
+  whole list, bit for bit, at its tile's fixed slot; M counts the kept
+  entries; a capacity below n_tiles K is refused before any work.
 * Forward: every variant raises the flag when some pixel examines more than
   K entries of a tile list (it cannot have stopped inside the capped list),
   never when K exceeds every pixel's examined count, and whenever the flag
@@ -32,6 +33,8 @@ def _scene(name):
 
 
 def _lists(B, W, H, P, pr, K, cap):
+    if K <= 2048:  # fixed per-tile slots
+        cap = max(cap, K * B.n_tiles(W, H))
     dev = pr["means2D"].device
     n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
     ranges = torch.full((B.n_tiles(W, H), 2), 7, dtype=torch.int32, device=dev)
@@ -55,7 +58,7 @@ def test_capped_lists_are_prefixes(name):
     ob = oracle.bin_sort_ranges(W, H, to_np(pr["means2D"]), to_np(pr["radius"]), to_np(pr["depth"]))
     orr, opl = ob["ranges"], ob["point_list"]
     L = (orr[:, 1] - orr[:, 0]).astype(np.int64)
-    for K in (1, 7, 64, int(L.max()), int(L.max()) + 5):
+    for K in (1, 7, 64, int(L.max()), int(L.max()) + 5, 2049, 5000):
         print(f"[capped] lists case={name} K={K}", flush=True)
         pl, ranges, n_dev = _lists(B, W, H, s.P, pr, K, int(ob["n_pairs"]))
         torch.cuda.synchronize()
@@ -64,7 +67,55 @@ def test_capped_lists_are_prefixes(name):
         np.testing.assert_array_equal(rg[:, 1] - rg[:, 0], np.minimum(L, K))
         got = to_np(pl)
         for t in np.nonzero(L)[0]:
+            assert K > 2048 or rg[t, 0] == t * K
             np.testing.assert_array_equal(got[rg[t, 0]:rg[t, 1]], opl[orr[t, 0]:orr[t, 0] + min(L[t], K)])
+    # too small a capacity for the fixed slots: refused, nothing written
+    nt = B.n_tiles(W, H)
+    K = min(2048, int(ob["n_pairs"]) // nt + 64)
+    cap = nt * K - 1  # holds the whole lists, one short of the fixed slots
+    n_dev = torch.full((1,), 3, dtype=torch.int64, device=pr["means2D"].device)
+    ranges = torch.full((nt, 2), 7, dtype=torch.int32, device=n_dev.device)
+    pl = torch.full((cap,), -5, dtype=torch.int32, device=n_dev.device)
+    ws = torch.empty(B.bgs_tile_lists_workspace_bytes(W, H, s.P, cap), dtype=torch.uint8, device=n_dev.device)
+    assert not B.bgs_tile_lists(W, H, pr["means2D"], pr["radius"], pr["depth"], pr["tiles_touched"], pl, ranges,
+                                n_dev, ws, max_per_tile=K)
+    torch.cuda.synchronize()
+    assert bool(torch.all(ranges == 7)) and int(n_dev.item()) == 3 and bool(torch.all(pl == -5))
+
+
+def test_capped_compact_lists_full_size():
+    """K above 2048 goes through the segment split and keeps the lists
+    compact: on the 1080p scene (lists up to 95 k) each capped list is the
+    prefix of the whole list the same builder writes (whole lists are checked
+    against the oracle elsewhere), ranges are packed front to back."""
+    from paper_2412_17378_amd import Rasterizer
+    from paper_2412_17378_amd import bgs as B
+    s = scenes.make("1")
+    cam = s.cameras[0]
+    W, H = cam.width, cam.height
+    rast = Rasterizer("cuda")
+    pr = rast.project(cam, s.means3D, s.log_scales, s.quats, s.opacity, s.colors, s.sh_degree)
+    torch.cuda.synchronize()
+    whole_pl, whole_rg, n_whole = _lists(B, W, H, s.P, pr, 0, 160_000_000)
+    torch.cuda.synchronize()
+    M = int(n_whole.item())
+    wr = to_np(whole_rg)
+    L = (wr[:, 1] - wr[:, 0]).astype(np.int64)
+    wpl = to_np(whole_pl[:M])
+    del whole_pl
+    for K in (2049, 3000):
+        print(f"[capped] compact K={K}", flush=True)
+        pl, ranges, n_dev = _lists(B, W, H, s.P, pr, K, M)
+        torch.cuda.synchronize()
+        keep = np.minimum(L, K)
+        assert int(n_dev.item()) == int(keep.sum())
+        rg = to_np(ranges)
+        np.testing.assert_array_equal(rg[:, 1] - rg[:, 0], keep)
+        start = np.concatenate([[0], np.cumsum(keep)[:-1]])
+        np.testing.assert_array_equal(rg[keep > 0, 0], start[keep > 0])
+        got = to_np(pl[:int(keep.sum())])
+        for t in np.nonzero(L)[0]:
+            np.testing.assert_array_equal(got[rg[t, 0]:rg[t, 1]], wpl[wr[t, 0]:wr[t, 0] + keep[t]])
 
 
 @pytest.mark.parametrize("name", ["0", "tiny-300"])
@@ -114,7 +165,7 @@ def _params(s, dev):
             for k in ("means3D", "log_scales", "quats", "opacity", "colors")}
 
 
-@pytest.mark.parametrize("name", ["1", "3-early"])
+@pytest.mark.parametrize("name", ["1", "3-early", "2"])
 def test_frame_step_capped(name):
     from paper_2412_17378_amd import make_cfg
     from paper_2412_17378_amd.pipeline import FrameStep

@@ -661,7 +661,9 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
             // background seen through T_N and the alpha output
             const float kconst = TN * (gC0 * F.bg0 + gC1 * F.bg1 + gC2 * F.bg2) - gA * TN;
             const int max_n = wave_max(nc);
-            float T = TN, R0 = 0.f, R1 = 0.f, R2 = 0.f, Rd = 0.f;
+            // S = dL/dC . (colour, depth accumulated behind the entry) + kconst:
+            // the only use of those sums, so one scalar carries them
+            float T = TN, S = kconst;
             const float fx = (float)px, fy = (float)py;
             for (int hi = max_n; hi > 0; hi -= 64) {
                 const int lo = hi > 64 ? hi - 64 : 0;
@@ -698,12 +700,9 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
                         v7 = w * gC1;
                         v8 = w * gC2;
                         v9 = w * gD;
-                        const float dA = Tb * (gC0 * cd.x + gC1 * cd.y + gC2 * cd.z + gD * cd.w) -
-                                         inv * (gC0 * R0 + gC1 * R1 + gC2 * R2 + gD * Rd + kconst);
-                        R0 = __builtin_fmaf(cd.x, w, R0);
-                        R1 = __builtin_fmaf(cd.y, w, R1);
-                        R2 = __builtin_fmaf(cd.z, w, R2);
-                        Rd = __builtin_fmaf(cd.w, w, Rd);
+                        const float gc = gC0 * cd.x + gC1 * cd.y + gC2 * cd.z + gD * cd.w;
+                        const float dA = Tb * gc - inv * S;
+                        S = __builtin_fmaf(gc, w, S);
                         T = Tb;
                         if (ga <= ALPHA_MAX) {
                             const float4 abc = s_abc[wv][jj];
@@ -766,7 +765,9 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
         const GradLane GL = grad_lane(B, scatter10_slot(lane));
         const int dslot = scatter10_slot(lane);
         float* const dpart = DET ? B.det_partials + (size_t)B.det_base[tile] * 10 + dslot : nullptr;
-        float T[WQ], R0[WQ], R1[WQ], R2[WQ], Rd[WQ], gC0[WQ], gC1[WQ], gC2[WQ], gD[WQ], kc[WQ], fy[WQ];
+        // S[q]: dL/dC . (colour, depth accumulated behind the entry) + the
+        // entry-independent part of dL/dalpha, as in k_bwd_pixel
+        float T[WQ], S[WQ], gC0[WQ], gC1[WQ], gC2[WQ], gD[WQ], fy[WQ];
         int nc[WQ];
         int my_max = 0;
 #pragma unroll
@@ -784,9 +785,8 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
             gC2[q] = inside ? B.dL_dcolor[2 * HW + p] : 0.f;
             const float ga = (inside && B.dL_dalpha) ? B.dL_dalpha[p] : 0.f;
             gD[q] = (inside && B.dL_ddepth) ? B.dL_ddepth[p] : 0.f;
-            kc[q] = TN * (gC0[q] * F.bg0 + gC1[q] * F.bg1 + gC2[q] * F.bg2) - ga * TN;
+            S[q] = TN * (gC0[q] * F.bg0 + gC1[q] * F.bg1 + gC2[q] * F.bg2) - ga * TN;
             T[q] = TN;
-            R0[q] = R1[q] = R2[q] = Rd[q] = 0.f;
             fy[q] = (float)py;
         }
         const int max_n = wave_max(my_max);
@@ -840,12 +840,9 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
                     v[7] = __builtin_fmaf(w, gC1[q], v[7]);
                     v[8] = __builtin_fmaf(w, gC2[q], v[8]);
                     v[9] = __builtin_fmaf(w, gD[q], v[9]);
-                    const float dA = Tb * (gC0[q] * cd.x + gC1[q] * cd.y + gC2[q] * cd.z + gD[q] * cd.w) -
-                                     inv * (gC0[q] * R0[q] + gC1[q] * R1[q] + gC2[q] * R2[q] + gD[q] * Rd[q] + kc[q]);
-                    R0[q] = __builtin_fmaf(cd.x, w, R0[q]);
-                    R1[q] = __builtin_fmaf(cd.y, w, R1[q]);
-                    R2[q] = __builtin_fmaf(cd.z, w, R2[q]);
-                    Rd[q] = __builtin_fmaf(cd.w, w, Rd[q]);
+                    const float gc = gC0[q] * cd.x + gC1[q] * cd.y + gC2[q] * cd.z + gD[q] * cd.w;
+                    const float dA = Tb * gc - inv * S[q];
+                    S[q] = __builtin_fmaf(gc, w, S[q]);
                     T[q] = contrib[q] ? Tb : T[q];
                     const bool unclamped = contrib[q] && ga[q] <= ALPHA_MAX;
                     const float dP = unclamped ? ga[q] * dA : 0.0f;  // dL/dpower

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include <rocprim/block/block_reduce.hpp>
 #include <rocprim/block/block_scan.hpp>
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
@@ -1069,17 +1070,18 @@ __global__ __launch_bounds__(SCAN_PARTS * 64) void k_seg_scan(int TX, int TY, in
 // group's coarse list in order, 64 entries at a time, keeps the entries
 // whose mask holds the tile (bit test, ballot, mbcnt rank) and stops once it
 // has K.  Tile t's list is written at the fixed slot [t K, t K + n_t), so no
-// count pass or scan is needed; n_pairs (zeroed before) receives the sum of
-// the n_t.  After a coarse overflow every range is empty and n_pairs
+// count pass or scan is needed; k_sum_ranges then puts the sum of the n_t in
+// n_pairs (one reduction: 8160 same-address atomics would serialize for
+// ~0.1 ms).  After a coarse overflow every range is empty and n_pairs
 // receives the coarse count, as for whole lists.  A larger K makes the walk
 // of a sparse tile long and serial; such caps go through the segment split.
 constexpr uint32_t GATHER_MAX_K = 2048;
+constexpr int GATHER_BATCHES = 8;
 __global__ __launch_bounds__(256) void k_tile_gather(int TX, int TY, int GX, uint32_t K,
                                                      const uint4* __restrict__ coarse,
                                                      const uint32_t* __restrict__ gstart,
                                                      const uint32_t* __restrict__ gtotal,
                                                      uint32_t* __restrict__ point_list, uint32_t* __restrict__ ranges,
-                                                     unsigned long long* __restrict__ n_pairs,
                                                      const uint64_t* __restrict__ coarse_n, uint64_t coarse_cap) {
     const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (t >= TX * TY) return;
@@ -1091,28 +1093,51 @@ __global__ __launch_bounds__(256) void k_tile_gather(int TX, int TY, int GX, uin
         const int li = (tx % GTILES) + GTILES * (ty % GTILES);
         const uint32_t b0 = gstart[grp], n = gtotal[grp];
         uint32_t* dst = point_list + (size_t)t * K;
-        for (uint32_t k0 = 0; k0 < n && cnt < K; k0 += 64) {
-            const uint32_t k = k0 + lane;
-            bool in = false;
-            uint32_t id = 0u;
-            if (k < n) {
-                const uint4 e = coarse[b0 + k];
-                in = (((li < 32 ? e.y : e.z) >> (li & 31)) & 1u) != 0u;
-                id = e.x;
+        // GATHER_BATCHES batches of 64 entries are loaded at once, so the walk
+        // pays one memory round trip per 512 entries
+        for (uint32_t k0 = 0; k0 < n && cnt < K; k0 += 64 * GATHER_BATCHES) {
+            uint32_t ids[GATHER_BATCHES];
+            bool in[GATHER_BATCHES];
+#pragma unroll
+            for (int u = 0; u < GATHER_BATCHES; ++u) {
+                const uint32_t k = k0 + 64 * u + lane;
+                in[u] = false;
+                ids[u] = 0u;
+                if (k < n) {
+                    const uint4 e = coarse[b0 + k];
+                    in[u] = (((li < 32 ? e.y : e.z) >> (li & 31)) & 1u) != 0u;
+                    ids[u] = e.x;
+                }
             }
-            const uint64_t m = ballot(in);
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            if (in && cnt + rank < K) dst[cnt + rank] = id;
-            cnt = __builtin_amdgcn_readfirstlane(cnt + (uint32_t)__builtin_popcountll(m));
+#pragma unroll
+            for (int u = 0; u < GATHER_BATCHES; ++u) {
+                const uint64_t m = ballot(in[u]);
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (in[u] && cnt + rank < K) dst[cnt + rank] = ids[u];
+                cnt = __builtin_amdgcn_readfirstlane(cnt + (uint32_t)__builtin_popcountll(m));
+            }
         }
         cnt = min(cnt, K);
     }
     if (lane == 0) {
         ranges[2 * t] = cnt ? (uint32_t)t * K : 0u;
         ranges[2 * t + 1] = cnt ? (uint32_t)t * K + cnt : 0u;
-        if (cnt) atomicAdd(n_pairs, (unsigned long long)cnt);
-        if (over && t == 0) *n_pairs = (unsigned long long)coarse_n[0];
     }
+}
+
+// Single workgroup: n_pairs[0] = the sum of the range lengths, or the coarse
+// count after a coarse overflow.
+__global__ __launch_bounds__(1024) void k_sum_ranges(int nt, const uint32_t* __restrict__ ranges,
+                                                     uint64_t* __restrict__ n_pairs,
+                                                     const uint64_t* __restrict__ coarse_n, uint64_t coarse_cap) {
+    using Reduce = rocprim::block_reduce<uint64_t, 1024>;
+    __shared__ typename Reduce::storage_type s_red;
+    uint64_t sum = 0;
+    for (int t = threadIdx.x; t < nt; t += 1024) sum += ranges[2 * t + 1] - ranges[2 * t];
+    uint64_t total = 0;
+    Reduce().reduce(sum, total, s_red);
+    if (threadIdx.x == 0) n_pairs[0] = coarse_n[0] > coarse_cap ? coarse_n[0] : total;
 }
 
 struct ListsLayout {
@@ -1264,12 +1289,11 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
                            L.GY, order, rect, h, coarse, (const uint64_t*)mg, ccap, means2D, co4);
     BGS_HIP(hipGetLastError());
     if (gather) {  // lists capped at a small K: gathered per tile at fixed slots
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t*>(n_pairs_dev),
-                           (int64_t)2, 0u);
-        BGS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_tile_gather, dim3((unsigned)((L.nt + 3) / 4)), dim3(256), 0, stream, TX, TY, L.GX,
-                           max_per_tile, coarse, gstart, gtotal, point_list, ranges,
-                           reinterpret_cast<unsigned long long*>(n_pairs_dev), (const uint64_t*)mg, ccap);
+                           max_per_tile, coarse, gstart, gtotal, point_list, ranges, (const uint64_t*)mg, ccap);
+        BGS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_sum_ranges, dim3(1), dim3(1024), 0, stream, L.nt, ranges, n_pairs_dev,
+                           (const uint64_t*)mg, ccap);
         BGS_HIP(hipGetLastError());
         return BGS_OK;
     }

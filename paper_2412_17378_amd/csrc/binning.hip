@@ -898,6 +898,106 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, co
     }
 }
 
+// The square rule's emit with the chunk's (Gaussian, group) pairs flattened
+// over the lanes, 64 at a time in (Gaussian, group) order -- the order in
+// which the one-Gaussian-at-a-time emit above writes them.  A pair's slot is
+// its group's running position plus the number of lower lanes of the batch
+// with the same group id (found with one ballot per bit of the id), and the
+// last such lane advances the running position.  Same entries at the same
+// slots, with a lane per pair instead of a loop over the Gaussians.
+__global__ __launch_bounds__(64) void k_chunk_emit_flat(int64_t P, int GX, int GY, int gbits,
+                                                        const uint32_t* __restrict__ order,
+                                                        const uint2* __restrict__ rect,
+                                                        const uint32_t* __restrict__ base, uint4* __restrict__ coarse,
+                                                        const uint64_t* __restrict__ coarse_n, uint64_t coarse_cap) {
+    extern __shared__ uint32_t nextpos[];  // ng running slots
+    __shared__ uint32_t s_off[65];         // first pair of each Gaussian of the chunk; s_off[64] = pairs
+    __shared__ uint32_t s_g[64];
+    __shared__ uint2 s_rr[64];
+    __shared__ int4 s_grp[64];  // group rectangle: x0, y0, width, -
+    __shared__ float s_invw[64];
+    if (coarse_n[0] > coarse_cap) return;  // the coarse lists do not fit: nothing is written
+    static_assert(CHUNK == 64, "one Gaussian per lane");
+    const int ng = GX * GY;
+    const int lane = threadIdx.x;
+    const int c = blockIdx.x;
+    const uint32_t* bc = base + (int64_t)c * ng;
+    for (int t = lane; t < ng; t += 64) nextpos[t] = bc[t];
+    const int64_t k = (int64_t)c * CHUNK + lane;
+    uint32_t g = 0, n = 0;
+    uint2 rr = make_uint2(1u, 0u);
+    int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+    if (k < P) {
+        g = order[k];
+        rr = rect[g];
+        if (group_rect(rr, x0, y0, x1, y1)) n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+    }
+    uint32_t incl = n;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+    s_off[lane] = incl - n;
+    if (lane == 63) s_off[64] = total;
+    s_g[lane] = g;
+    s_rr[lane] = rr;
+    s_grp[lane] = make_int4(x0, y0, x1 - x0 + 1, 0);
+    s_invw[lane] = 1.0f / (float)(x1 - x0 + 1 > 0 ? x1 - x0 + 1 : 1);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+        const uint32_t p = p0 + lane;
+        const bool valid = p < total;
+        int i = 0;  // the pair's Gaussian: the last lane whose first pair is at or before p
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (s_off[i + step] <= p) i += step;  // i + step <= 63
+        int t = 0;
+        uint64_t mask = 0;
+        if (valid) {
+            const int4 gr = s_grp[i];
+            const int wi = gr.z;
+            const int j = (int)(p - s_off[i]);
+            int q = (int)((float)j * s_invw[i]);
+            int r = j - q * wi;
+            if (r >= wi) { ++q; r -= wi; }
+            if (r < 0) { --q; r += wi; }
+            const int gx = gr.x + r, gy = gr.y + q;
+            t = gy * GX + gx;
+            const uint2 rk = s_rr[i];
+            const int tx0 = (int)(rk.x & 0xFFFF), ty0 = (int)(rk.x >> 16), tx1 = (int)(rk.y & 0xFFFF),
+                      ty1 = (int)(rk.y >> 16);
+            // the tile rectangle is clamped to the image, so the mask only
+            // holds tiles inside it
+            const int bx = gx * GTILES, by = gy * GTILES;
+            const int cl = max(tx0 - bx, 0), ch = min(tx1 - bx + 1, GTILES);
+            const int rl = max(ty0 - by, 0), rh = min(ty1 - by + 1, GTILES);
+            const uint32_t cols = ((1u << ch) - 1u) & ~((1u << cl) - 1u);
+            const uint32_t rows = ((1u << rh) - 1u) & ~((1u << rl) - 1u);
+            mask = (uint64_t)cols * spread_rows(rows);
+        }
+        uint64_t eq = ballot(valid);  // lanes of the batch with this lane's group id
+        for (int b = 0; b < gbits; ++b) {
+            const bool bit = ((t >> b) & 1) != 0;
+            const uint64_t m = ballot(bit);
+            eq &= bit ? m : ~m;
+        }
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(eq >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)eq, 0u));
+        const uint32_t pos = valid ? nextpos[t] + rank : 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (valid && rank + 1 == (uint32_t)__builtin_popcountll(eq)) nextpos[t] = pos + 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (valid) coarse[pos] = make_uint4(s_g[i], (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
+    }
+}
+
 // The fine split runs on segments of SEG consecutive coarse entries of one
 // group, so that a heavily covered group does not serialize on one
 // workgroup.  nseg[g] = ceil(gtotal[g] / SEG).
@@ -1285,8 +1385,9 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
         hipLaunchKernelGGL(k_chunk_emit<true>, dim3(L.C), dim3(64), sizeof(uint32_t) * ((size_t)L.ng + 16 * TY), stream, P,
                            L.GX, L.GY, order, rect, h, coarse, (const uint64_t*)mg, ccap, means2D, co4);
     else
-        hipLaunchKernelGGL(k_chunk_emit<false>, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX,
-                           L.GY, order, rect, h, coarse, (const uint64_t*)mg, ccap, means2D, co4);
+        hipLaunchKernelGGL(k_chunk_emit_flat, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX,
+                           L.GY, L.ng > 1 ? 32 - __builtin_clz((unsigned)(L.ng - 1)) : 0, order, rect, h, coarse,
+                           (const uint64_t*)mg, ccap);
     BGS_HIP(hipGetLastError());
     if (gather) {  // lists capped at a small K: gathered per tile at fixed slots
         hipLaunchKernelGGL(k_tile_gather, dim3((unsigned)((L.nt + 3) / 4)), dim3(256), 0, stream, TX, TY, L.GX,

@@ -86,7 +86,7 @@ def parse():
                     help="tile lists capped at K entries per tile: 'auto' (FrameStep picks K and the step is checked "
                          "for overflow), 'none' (whole lists) or an integer K")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", default="480,240,1440,720",
+    ap.add_argument("--cpu-window", default="480,180,1440,900",
                     help="pixel window x0,y0,x1,y1 of the oracle's CPU sample")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched multi-view measurement (32 orbit views, one graph launch per step)")

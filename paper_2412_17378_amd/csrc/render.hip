@@ -660,7 +660,7 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
             // part of dL/dalpha that does not depend on the entry: the
             // background seen through T_N and the alpha output
             const float kconst = TN * (gC0 * F.bg0 + gC1 * F.bg1 + gC2 * F.bg2) - gA * TN;
-            const int max_n = wave_max(nc);
+            const int max_n = __builtin_amdgcn_readfirstlane(wave_max(nc));  // uniform: the loop runs on scalars
             // S = dL/dC . (colour, depth accumulated behind the entry) + kconst:
             // the only use of those sums, so one scalar carries them
             float T = TN, S = kconst;
@@ -789,7 +789,7 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
             T[q] = TN;
             fy[q] = (float)py;
         }
-        const int max_n = wave_max(my_max);
+        const int max_n = __builtin_amdgcn_readfirstlane(wave_max(my_max));  // uniform: the loop runs on scalars
         const float fx = (float)px;
         for (int hi = max_n; hi > 0; hi -= 64) {
             const int lo = hi > 64 ? hi - 64 : 0;

@@ -9,8 +9,18 @@ and projected quantities.
 Discrete decisions (skip at alpha < 1/255, stop at T < 1e-4, the 0.99 clamp)
 are taken by each side in its own precision.  A pixel whose oracle decisions
 lie within MARGIN (relative) of a threshold may legitimately differ; such
-pixels are excluded from the element-wise image check, counted, and their
-upstream gradient is zeroed on both sides for the gradient check.
+pixels are excluded from the element-wise image check, counted (at most
+MAX_FLAGGED_FRACTION of the checked pixels; the orbit views of the batched
+scene, whose pixels examine ~2400 low-opacity entries, pass
+MAX_FLAGGED_FRACTION_ORBIT), and their upstream gradient is zeroed on both
+sides for the gradient check.
+
+Gradients: a gradient element is a sum over pixels of terms of both signs.
+The floor s of an element is max(RMS(y), m), m the oracle's sum of the
+element's absolute per-pixel terms (pinned by the oracle tests).  Every
+comparison also reports, per tensor, the worst ratio under the plain floor
+RMS(y) and how many elements pass only because of m; at most
+MAX_MAG_ONLY_FRACTION of a tensor's elements may need it.
 """
 from __future__ import annotations
 
@@ -20,7 +30,9 @@ import oracle
 
 RTOL = 1e-4
 MARGIN = 1e-4
-MAX_FLAGGED_FRACTION = 5e-2  # a property of the workload: ~2% where pixels examine ~2400 low-opacity entries
+MAX_FLAGGED_FRACTION = 1e-2        # measured <= 0.5% on the single-view scenes
+MAX_FLAGGED_FRACTION_ORBIT = 3e-2  # measured ~2% on the orbit views
+MAX_MAG_ONLY_FRACTION = 1e-4
 
 
 def to_np(t):
@@ -65,7 +77,7 @@ def oracle_bwd_from_gpu(prep, gC, gA=None, gD=None, bg=(0.0, 0.0, 0.0), window=N
                              gC, gA, gD, bg=bg, window=window)
 
 
-def compare_forward(gpu, orc, window=None, name=""):
+def compare_forward(gpu, orc, window=None, name="", max_flagged=MAX_FLAGGED_FRACTION):
     """Image parity on unflagged pixels (inside window, if given)."""
     H, W = orc["final_T"].shape
     valid = np.ones((H, W), bool)
@@ -76,7 +88,9 @@ def compare_forward(gpu, orc, window=None, name=""):
     flagged = (orc["margin"] < MARGIN) & valid
     ok = valid & ~flagged
     n_valid = int(valid.sum())
-    assert flagged.sum() <= max(4, MAX_FLAGGED_FRACTION * n_valid), (name, int(flagged.sum()), n_valid)
+    n_flag = int(flagged.sum())
+    print(f"[parity] {name}: flagged {n_flag} of {n_valid} pixels ({n_flag / max(1, n_valid):.2e})", flush=True)
+    assert n_flag <= max(4, max_flagged * n_valid), (name, n_flag, n_valid)
     stats = {}
     stats["color"] = check_close(to_np(gpu["color"]), orc["color"], 1e-2, name + " color", mask=ok[None])
     stats["alpha"] = check_close(to_np(gpu["alpha"]), orc["alpha"], 1e-2, name + " alpha", mask=ok)
@@ -92,7 +106,10 @@ def compare_grads(gpu, orc, name=""):
     """Gradient parity: |x - y| <= 1e-4 max(|y|, RMS(y), m) per element, m the
     oracle's sum of the element's absolute per-pixel terms (a gradient is a
     sum over pixels of terms of both signs; 1e-4 relative is taken against
-    the magnitude being summed, which equals |y| when the terms do not cancel)."""
+    the magnitude being summed, which equals |y| when the terms do not
+    cancel).  Prints, per tensor, the worst ratio under max(|y|, RMS(y)) alone
+    and the number of elements that pass only because of m, and fails when
+    more than MAX_MAG_ONLY_FRACTION of the elements need m."""
     stats = {}
     mag = orc.get("mag", {})
     pairs = [("means2D", gpu["means2D"], orc["means2D"]),
@@ -103,8 +120,17 @@ def compare_grads(gpu, orc, name=""):
         pairs.append(("depth", gpu["depth"], orc["depth"]))
     for nm, g, o in pairs:
         g = to_np(g) if not isinstance(g, np.ndarray) else g
-        floor = max(rms(o), 1e-30)
+        rms_floor = max(rms(o), 1e-30)
+        floor = rms_floor
         if nm in mag:
-            floor = np.maximum(mag[nm], floor)
+            floor = np.maximum(mag[nm], rms_floor)
         stats[nm] = check_close(g, o, floor, f"{name} d{nm}")
+        plain = np.abs(np.asarray(g, np.float64) - o) / (RTOL * np.maximum(np.abs(o), rms_floor))
+        n_mag_only = int((plain > 1.0).sum())
+        worst_plain = float(plain.max()) if plain.size else 0.0
+        print(f"[parity] {name} d{nm}: worst {stats[nm][0]:.3g} (floor max(|y|,RMS,m)), "
+              f"worst {worst_plain:.3g} under max(|y|,RMS); {n_mag_only} of {plain.size} pass only via m",
+              flush=True)
+        assert n_mag_only <= max(2, MAX_MAG_ONLY_FRACTION * plain.size), (name, nm, n_mag_only, plain.size)
+        stats[nm] = stats[nm] + (worst_plain, n_mag_only)
     return stats

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import oracle
-from parity import MARGIN, compare_forward, compare_grads, to_np
+from parity import MARGIN, MAX_FLAGGED_FRACTION, MAX_FLAGGED_FRACTION_ORBIT, compare_forward, compare_grads, to_np
 from workloads import scenes
 
 pytestmark = pytest.mark.gpu
@@ -82,7 +82,8 @@ def test_config_crops(name, view):
         out = rast.render_fwd(prep, fc)
         torch.cuda.synchronize()
         for w, o in zip(wins, orcs):
-            compare_forward(out, o, window=w, name=f"{name}/{view} {w}")
+            compare_forward(out, o, window=w, name=f"{name}/{view} {w}",
+                            max_flagged=MAX_FLAGGED_FRACTION_ORBIT if name == "4" else MAX_FLAGGED_FRACTION)
         grads = rast.render_bwd(prep, bc, out, gC_dev)
         torch.cuda.synchronize()
         compare_grads(grads, acc, name=f"{name}/{view} bwd variant={bc.variant}/{bc.subtile}")

@@ -89,3 +89,97 @@ def test_single_gaussian_opacity_gradient_closed_form(orc):
         assert o * G < 0.99 and o * G > 1 / 255
         assert bw["opacity"][0] == pytest.approx(G * (rgb[0, c] - bg[c]), rel=1e-12)
         assert bw["rgb"][0, c] == pytest.approx(o * G, rel=1e-12)
+
+
+# ---------------------------------------------------------------- mag pins
+# The oracle's backward also returns, per gradient element, m = the sum over
+# pixels of the absolute value of that pixel's term.  The parity rule uses m
+# as a floor of the gradient tolerance, so it is pinned here on its own.  A
+# Gaussian sits at most once in a pixel's list, so each pixel adds exactly
+# one term to each element, and m is the sum over pixels of |the gradient the
+# pixel alone produces|.
+
+_KEYS = ("means2D", "conic", "opacity", "rgb", "depth")
+
+
+def _small(orc, seed, W=20, H=18):
+    s = scenes.scene_tiny(n=16, seed=seed, width=W, height=H, log_scale_mu=-1.4)
+    cam = s.cameras[0]
+    pr = orc.project_scene(s)
+    b = orc.bin_sort_ranges(W, H, pr["means2D"], pr["radius"], pr["depth"])
+    return cam, pr, b
+
+
+def _bwd(orc, cam, pr, b, gC, gA=None, gD=None, bg=(0.2, 0.5, 0.1)):
+    return orc.render_bwd(cam.width, cam.height, b["ranges"], b["point_list"], pr["means2D"], pr["conic_opacity"],
+                          pr["rgb"], pr["depth"], gC, gA, gD, bg=bg)
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_mag_is_sum_of_per_pixel_absolute_terms(orc, seed):
+    """Brute force: one backward per pixel with the upstream gradient of that
+    pixel alone; m must equal the sum of the absolute per-pixel gradients."""
+    cam, pr, b = _small(orc, seed)
+    W, H = cam.width, cam.height
+    rng = np.random.default_rng(seed)
+    gC = rng.standard_normal((3, H, W))
+    gA = rng.standard_normal((H, W))
+    gD = rng.standard_normal((H, W))
+    full = _bwd(orc, cam, pr, b, gC, gA, gD)
+    acc = {k: np.zeros_like(full[k]) for k in _KEYS}
+    summed = {k: np.zeros_like(full[k]) for k in _KEYS}
+    for py in range(H):
+        for px in range(W):
+            one = [np.zeros_like(gC), np.zeros_like(gA), np.zeros_like(gD)]
+            one[0][:, py, px] = gC[:, py, px]
+            one[1][py, px] = gA[py, px]
+            one[2][py, px] = gD[py, px]
+            o = _bwd(orc, cam, pr, b, *one)
+            for k in _KEYS:
+                acc[k] += np.abs(o[k])
+                summed[k] += o[k]
+    for k in _KEYS:
+        scale = float(np.abs(acc[k]).max()) + 1e-300
+        np.testing.assert_allclose(full["mag"][k], acc[k], rtol=1e-12, atol=1e-13 * scale, err_msg=k)
+        np.testing.assert_allclose(full[k], summed[k], rtol=1e-10, atol=1e-12 * scale, err_msg=k)
+    assert any(float(np.abs(full[k]).max()) > 0 for k in _KEYS)
+
+
+def test_mag_bounds_the_gradient(orc):
+    """Triangle inequality m >= |y| element by element, with strict excess
+    somewhere (terms of both signs cancel for the mean and conic gradients)."""
+    cam, pr, b = _small(orc, 33, W=48, H=40)
+    rng = np.random.default_rng(33)
+    o = _bwd(orc, cam, pr, b, rng.standard_normal((3, 40, 48)), rng.standard_normal((40, 48)),
+             rng.standard_normal((40, 48)))
+    for k in _KEYS:
+        assert np.all(o["mag"][k] >= np.abs(o[k]) * (1 - 1e-12)), k
+    assert np.any(o["mag"]["means2D"] > 1.01 * np.abs(o["means2D"]))
+
+
+def test_mag_equals_gradient_when_every_term_is_positive(orc):
+    """With positive upstream colour and depth gradients every per-pixel term
+    of d/drgb (w g_C) and d/ddepth (w g_D) is non-negative: m == y."""
+    cam, pr, b = _small(orc, 34)
+    W, H = cam.width, cam.height
+    rng = np.random.default_rng(34)
+    o = _bwd(orc, cam, pr, b, rng.uniform(0.1, 1.0, (3, H, W)), None, rng.uniform(0.1, 1.0, (H, W)))
+    assert float(o["rgb"].max()) > 0 and float(o["depth"].max()) > 0
+    np.testing.assert_allclose(o["mag"]["rgb"], o["rgb"], rtol=1e-13, atol=0)
+    np.testing.assert_allclose(o["mag"]["depth"], o["depth"], rtol=1e-13, atol=0)
+
+
+def test_mag_single_gaussian_single_pixel(orc):
+    """One Gaussian seen by one pixel: one term per element, so m == |y|."""
+    W = H = 1
+    inv = np.linalg.inv(np.array([[3.0, 0.7], [0.7, 2.0]]))
+    mu = np.array([[0.4, -0.3]])
+    co = np.array([[inv[0, 0], inv[0, 1], inv[1, 1], 0.7]])
+    rgb, depth = np.array([[0.3, 0.9, 0.6]]), np.array([2.5])
+    b = orc.bin_sort_ranges(W, H, mu, np.array([3], np.int32), depth)
+    assert b["n_pairs"] == 1
+    o = orc.render_bwd(W, H, b["ranges"], b["point_list"], mu, co, rgb, depth, np.array([[[0.8]], [[-1.3]], [[0.4]]]),
+                       np.array([[0.6]]), np.array([[-0.9]]), bg=(0.2, 0.1, 0.4))
+    for k in _KEYS:
+        assert np.any(o[k] != 0), k
+        np.testing.assert_allclose(o["mag"][k], np.abs(o[k]), rtol=1e-15, atol=0, err_msg=k)

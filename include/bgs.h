@@ -79,7 +79,11 @@ typedef enum bgs_variant {
     BGS_STATIC = 0,           /* one 256-lane workgroup per 16x16 tile, grid-static */
     BGS_BALANCED_PIXEL = 1,   /* persistent waves, atomic sub-tile queue, lane = pixel */
     BGS_BALANCED_GAUSS = 2,   /* persistent waves, atomic sub-tile queue, lane = Gaussian */
-    BGS_BALANCED_HYBRID = 3   /* lane = pixel, stragglers finished lane = Gaussian */
+    BGS_BALANCED_HYBRID = 3,  /* lane = pixel, stragglers finished lane = Gaussian */
+    BGS_STATIC_WAVE = 4       /* the wave-per-tile code of BGS_BALANCED_PIXEL with
+                                 subtile 16, dispatched grid-statically: wave w of the
+                                 grid renders tile w (raster order), no queue; the
+                                 baseline that isolates the task pool's scheduling */
 } bgs_variant;
 
 /* Queue order of the balanced variants. */
@@ -99,8 +103,10 @@ typedef struct bgs_render_cfg {
     int32_t variant;          /* bgs_variant */
     int32_t subtile;          /* balanced variants: work-item edge.  8: one wave per
                                  8x8 sub-tile (one pixel per lane).  16 (BGS_BALANCED_PIXEL
-                                 only): one wave per whole 16x16 tile, four pixels per
-                                 lane, forward and backward */
+                                 and BGS_STATIC_WAVE): one wave per whole 16x16 tile,
+                                 four pixels per lane, forward and backward.  32
+                                 (BGS_BALANCED_PIXEL only): one wave per 32x32 block of
+                                 2x2 tiles, rendered tile after tile */
     int32_t order;            /* bgs_order */
     int32_t flags;            /* BGS_FLAG_* */
     float bg[3];              /* background colour */
@@ -126,6 +132,13 @@ typedef struct bgs_render_cfg {
        the caller clears it. */
     uint32_t list_cap;
     uint32_t* list_overflow;
+    /* Optional queue audit (DEVICE, nullable, caller-zeroed): the balanced
+       kernels of a one-view render add 1 to item_claims[i] each time a wave
+       takes work item i from the task pool (Alg. 1), so after a render every
+       entry is 1.  Items: subtile 8 -> tile * 4 + quadrant (4 n_tiles of
+       them), subtile 16 -> tile, subtile 32 -> block (ty / 2) *
+       ceil(TX / 2) + tx / 2.  Ignored by the static variants and by plans. */
+    uint32_t* item_claims;
 } bgs_render_cfg;
 
 /* Thread-local text for the last non-OK status of this thread. */
@@ -286,12 +299,15 @@ size_t bgs_render_workspace_bytes(const bgs_frame* frame, const bgs_render_cfg* 
 
 /*
  * Task pool of the balanced renderer (Sec. 4.1 steps 1-4, Sec. 4.3): writes
- * the sub-tile work items of `frame` into the workspace in the order
- * cfg->order asks for and resets the global fetch counter.  For
- * BGS_ORDER_COST the forward cost estimate of a sub-tile is its tile's list
- * length; when n_contrib (nullable, [H][W] from the forward pass) is given the
- * cost is the largest n_contrib in the sub-tile (the backward's exact walk).
- * bgs_render_fwd / bgs_render_bwd call this themselves.
+ * the work items of `frame` (8x8 sub-tiles, 16x16 tiles or 32x32 blocks of
+ * 2x2 tiles, by cfg->subtile) into the workspace in the order cfg->order asks
+ * for and resets the fetch counters.  For BGS_ORDER_COST the forward cost
+ * estimate of a tile is its list length; when n_contrib (nullable, [H][W]
+ * from the forward pass) is given the cost is the largest n_contrib in the
+ * tile (the backward's exact walk); a block costs the sum of its tiles.
+ * bgs_render_fwd / bgs_render_bwd call this themselves.  The workspace
+ * begins with the queue's state: 64 uint32 fetch counters 128 bytes apart
+ * (counter q at byte 128 q), then at byte 8192 the number of items.
  */
 bgs_status bgs_queue_build(const bgs_frame* frame, const bgs_render_cfg* cfg, const int32_t* n_contrib,
                            void* ws, size_t ws_bytes, hipStream_t stream);
@@ -358,13 +374,15 @@ bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_render_cfg* cfg,
 
 /*
  * Variant selection by measurement (the self-adaptive kernel selection of
- * Sec. 4.4, generalized): runs every forward candidate (static; pixel-wise 8x8
- * raster and cost-ordered; one wave per 16x16 tile; hybrid; Gaussian-wise) on
+ * Sec. 4.4, generalized): runs every forward candidate (static; one wave per
+ * tile dispatched statically; pixel-wise 8x8 raster and cost-ordered; one wave
+ * per 16x16 tile; one wave per 32x32 block; hybrid; Gaussian-wise) on
  * `frame` with base's background, times each with HIP events (one warm-up,
  * two timed runs) and returns the fastest in *best_fwd; then renders once with
  * it and, if dL_dcolor and the gradient buffers are given, times the backward
- * candidates (static; balanced 8x8 raster and cost-ordered; wave per 16x16
- * tile) into *best_bwd.  The
+ * candidates (static; wave per tile dispatched statically; balanced 8x8
+ * raster and cost-ordered; wave per 16x16 tile; wave per 32x32 block) into
+ * *best_bwd.  The
  * output and gradient buffers are scratch (the gradients end up holding sums
  * of several runs).  When cache_path (HOST string, nullable) names a file,
  * the winners are appended to it under a workload signature (image size and

@@ -19,12 +19,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbgs.so")
 
 BGS_OK, BGS_EINVAL, BGS_ECAPACITY, BGS_EHIP, BGS_EUNSUPPORTED, BGS_EINTERNAL = 0, -1, -2, -3, -4, -5
-STATIC, BALANCED_PIXEL, BALANCED_GAUSS, BALANCED_HYBRID = 0, 1, 2, 3
+STATIC, BALANCED_PIXEL, BALANCED_GAUSS, BALANCED_HYBRID, STATIC_WAVE = 0, 1, 2, 3, 4
 ORDER_RASTER, ORDER_COST = 0, 1
 FLAG_QUEUE_READY = 1
 TILE = 16
 
-VARIANTS = {"static": STATIC, "pixel": BALANCED_PIXEL, "gauss": BALANCED_GAUSS, "hybrid": BALANCED_HYBRID}
+VARIANTS = {"static": STATIC, "pixel": BALANCED_PIXEL, "gauss": BALANCED_GAUSS, "hybrid": BALANCED_HYBRID,
+            "static_wave": STATIC_WAVE}
 ORDERS = {"raster": ORDER_RASTER, "cost": ORDER_COST}
 
 
@@ -56,7 +57,8 @@ class ViewIO(C.Structure):
 class RenderCfg(C.Structure):
     _fields_ = [("variant", C.c_int32), ("subtile", C.c_int32), ("order", C.c_int32), ("flags", C.c_int32),
                 ("bg", C.c_float * 3), ("wg_trace", C.c_void_p), ("wg_trace_cap", C.c_int64),
-                ("n_examined", C.c_void_p), ("list_cap", C.c_uint32), ("list_overflow", C.c_void_p)]
+                ("n_examined", C.c_void_p), ("list_cap", C.c_uint32), ("list_overflow", C.c_void_p),
+                ("item_claims", C.c_void_p)]
 
 
 _LIB = None

@@ -50,6 +50,7 @@ struct FrameArgs {
     int* n_examined;  // optional per-pixel count of examined list entries (forward)
     uint32_t list_cap;        // lists capped at this many entries per tile (0: whole lists)
     uint32_t* list_overflow;  // set when a pixel runs off a capped list (nullable)
+    uint32_t* item_claims;    // per-item claim counts of the task pool (nullable)
 };
 
 struct FwdOut {
@@ -282,40 +283,83 @@ constexpr int NQ = 64;
 constexpr int QSTRIDE = 32;  // u32 words between two counters (128 bytes)
 constexpr int QGROUPS = NQ / 4;
 
+// First round without atomics: wave w of the persistent grid (nw waves) takes
+// items[w] -- entry w / 64 of its home queue w mod 64 -- directly, so the
+// first nw items cost no counter round trip.  A claim from queue q then draws
+// t from the counter and takes entry t + first(q), first(q) = the number of
+// waves whose home is q.  The offset comes from the launch itself (gridDim),
+// so a queue is valid for any persistent grid; the counters start at 0.
 struct WorkQueue {
     uint32_t* ctr;           // ctr[q * QSTRIDE], q < NQ; ctr[NQ * QSTRIDE] = number of items
     const uint32_t* items;   // items[i * NQ + q] = i-th item of queue q
-    uint32_t n;
+    uint32_t* claims;        // claims[item] += 1 per claim (nullable; one-view launches only)
+    uint32_t n;              // number of items
+    uint32_t nw;             // waves of the persistent grid
     int cur;
     __device__ __forceinline__ uint32_t size(int q) const { return n > (uint32_t)q ? (n - q - 1) / NQ + 1 : 0u; }
+    __device__ __forceinline__ uint32_t first(int q) const { return nw > (uint32_t)q ? (nw - q - 1) / NQ + 1 : 0u; }
 };
 
-__device__ __forceinline__ WorkQueue make_queue(uint32_t* ctr, const uint32_t* items, int wave_global) {
+__device__ __forceinline__ WorkQueue make_queue(uint32_t* ctr, const uint32_t* items, int wave_global,
+                                                uint32_t* claims = nullptr) {
     WorkQueue Q;
     Q.ctr = ctr;
     Q.items = items;
+    Q.claims = claims;
     Q.n = ctr[NQ * QSTRIDE];
+    Q.nw = gridDim.x * (blockDim.x / WAVE);
     Q.cur = wave_global & (NQ - 1);
+    if (claims && wave_global == 0 && (threadIdx.x & (WAVE - 1)) == 0) ctr[NQ * QSTRIDE + 1] = Q.nw;  // for audits
     return Q;
 }
 
-// Claim the next item for this wave (all 64 lanes active); false when every
-// queue is drained.  Counters only grow, so the exit is final.
-__device__ __forceinline__ bool queue_next(WorkQueue& Q, int lane, uint32_t& item) {
+__device__ __forceinline__ void note_claim(const WorkQueue& Q, int lane, uint32_t item) {
+    if (Q.claims && lane == 0) atomicAdd(&Q.claims[item & LOCAL_MASK], 1u);
+}
+
+// Counter value t of queue q -> the item, if q still holds one.
+__device__ __forceinline__ bool queue_slot(const WorkQueue& Q, int q, uint32_t t, int lane, uint32_t& item) {
+    const uint32_t i = t + Q.first(q);
+    if (i >= Q.size(q)) return false;
+    item = __builtin_amdgcn_readfirstlane(Q.items[(size_t)i * NQ + q]);
+    note_claim(Q, lane, item);
+    return true;
+}
+
+// Every queue's home counter has run past its size: probe all 64 counters
+// with one vector load (lane q reads counter q), move to the next non-empty
+// queue and claim from it; false once every queue is drained.  Counters only
+// grow, so the exit is final.
+__device__ __forceinline__ bool queue_steal(WorkQueue& Q, int lane, uint32_t& item) {
     for (;;) {
-        uint32_t q = 0;
-        if (lane == 0) q = atomicAdd(&Q.ctr[Q.cur * QSTRIDE], 1u);
-        q = __builtin_amdgcn_readfirstlane(q);
-        if (q < Q.size(Q.cur)) {
-            item = Q.items[(size_t)q * NQ + Q.cur];
-            return true;
-        }
         const uint32_t c = __hip_atomic_load(&Q.ctr[lane * QSTRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t m = ballot(c < Q.size(lane));
+        const uint64_t m = ballot(c + Q.first(lane) < Q.size(lane));
         if (m == 0) return false;
         const uint64_t rot = Q.cur ? ((m >> Q.cur) | (m << (64 - Q.cur))) : m;
         Q.cur = (Q.cur + (int)__builtin_ctzll(rot)) & (NQ - 1);
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(&Q.ctr[Q.cur * QSTRIDE], 1u);
+        if (queue_slot(Q, Q.cur, __builtin_amdgcn_readfirstlane(t), lane, item)) return true;
     }
+}
+
+// Claim the next item for this wave (all 64 lanes active); false when every
+// queue is drained.
+__device__ __forceinline__ bool queue_next(WorkQueue& Q, int lane, uint32_t& item) {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(&Q.ctr[Q.cur * QSTRIDE], 1u);
+    if (queue_slot(Q, Q.cur, __builtin_amdgcn_readfirstlane(t), lane, item)) return true;
+    return queue_steal(Q, lane, item);
+}
+
+// The wave's first item: its own slot of the first round, else a claim.
+__device__ __forceinline__ bool queue_first(WorkQueue& Q, int wave_global, int lane, uint32_t& item) {
+    if ((uint32_t)wave_global < Q.n) {
+        item = __builtin_amdgcn_readfirstlane(Q.items[wave_global]);
+        note_claim(Q, lane, item);
+        return true;
+    }
+    return queue_next(Q, lane, item);
 }
 
 template <bool PERSISTENT, bool MV = false>
@@ -327,11 +371,13 @@ __global__ __launch_bounds__(256) void k_fwd_pixel(FrameArgs F0, FwdOut O0, cons
     __shared__ float4 s_cd[4][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     WorkQueue Q;
-    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
+    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv, MV ? nullptr : F0.item_claims);
+    bool first = true;
     for (;;) {
         uint32_t item;
         if (PERSISTENT) {
-            if (!queue_next(Q, lane, item)) break;
+            if (!(first ? queue_first(Q, blockIdx.x * 4 + wv, lane, item) : queue_next(Q, lane, item))) break;
+            first = false;
         } else {
             item = blockIdx.x * 4 + wv;
         }
@@ -454,10 +500,10 @@ __global__ __launch_bounds__(256) void k_fwd_hybrid(FrameArgs F, FwdOut O, const
     __shared__ float4 s_co[4][64];
     __shared__ float4 s_cd[4][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    WorkQueue Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
-    for (;;) {
+    WorkQueue Q = make_queue(ctr, items, blockIdx.x * 4 + wv, F.item_claims);
+    for (bool first = true;; first = false) {
         uint32_t item;
-        if (!queue_next(Q, lane, item)) break;
+        if (!(first ? queue_first(Q, blockIdx.x * 4 + wv, lane, item) : queue_next(Q, lane, item))) break;
         int tile, px, py;
         bool any_inside;
         item_pixel(F, item, lane, tile, px, py, any_inside);
@@ -508,95 +554,277 @@ __global__ __launch_bounds__(256) void k_fwd_hybrid(FrameArgs F, FwdOut O, const
 // ------------------------------------------------- tile-granular persistent
 // Persistent waves take whole 16x16 tiles from the queue (the inter-block
 // dynamic distribution of Sec. 4.1, Alg. 1, with a wave as the worker):
-// lane l owns the four pixels (l mod 16, l / 16 + 4q), q = 0..3.  One wave
-// per tile loads the tile's list once (a 256-lane workgroup per tile would
-// load it once too but synchronizes its four waves per batch; four 8x8
-// waves load it four times), and each staged entry is read from LDS once
-// for four pixels.  Pixel q of every lane forms a 16x4 block that is skipped
-// as soon as all its pixels have stopped; a lane leaves the entry loop once
-// its four pixels have, the wave once all 256 have.  Per pixel the arithmetic is that of
-// blend(), so the result equals the other variants bit for bit.
-// COUNT: also write F.n_examined[p] = list entries the sequential loop
-// examines for pixel p (the stopping entry included).
-template <bool MV = false, bool COUNT = false>
+// lane l owns the four pixels (l mod 16, l / 16 + 4q), q = 0..3, so pixel
+// row q of the lanes forms the 16x4 block q.  One wave per tile loads the
+// tile's list once (four 8x8 waves load it four times, a 256-lane workgroup
+// synchronizes its four waves per batch), and each staged entry is read from
+// LDS once for four pixels.
+//
+// Per list entry the wave works at the granularity of a block, on uniform
+// (scalar) branches only:
+//  * staging computes, per entry, the 4-bit mask of the blocks that the
+//    entry's alpha >= 1/255 ellipse can reach (block_mask); a block outside
+//    it skips the entry without evaluating it, since every one of its pixels
+//    would skip it anyway;
+//  * a block whose 64 pixels have all stopped leaves the walk, the wave
+//    leaves once all four have;
+//  * a block evaluates the entry's exponent and alpha and, only if one of its
+//    pixels takes the entry, the blend (blend_u).
+// Per pixel the arithmetic is that of blend(), so every variant gives the
+// same image bit for bit.
+
+// Global-memory form of one list entry, loaded without any arithmetic so that
+// the loads of the next chunk stay in flight while the wave renders this one.
+struct RawSplat {
+    float2 xy;
+    float4 con;  // a, b, c, opacity
+    float r, g, b, d;
+    uint32_t id;
+};
+
+__device__ __forceinline__ void load_raw(const FrameArgs& F, uint32_t id, RawSplat& s) {
+    s.xy = F.means2D[id];
+    s.con = F.conic_opacity[id];
+    s.r = F.rgb[3 * (size_t)id];
+    s.g = F.rgb[3 * (size_t)id + 1];
+    s.b = F.rgb[3 * (size_t)id + 2];
+    s.d = F.depth[id];
+    s.id = id;
+}
+
+// Bit q (q = 0..3) is set when the 16x4 pixel block of rows y0 + 4q ..
+// y0 + 4q + 3, columns x0 .. x0 + 15, meets the bounding box of the entry's
+// ellipse {d : a dx^2 + 2 b dx dy + c dy^2 <= tau}, tau = 2 ln(255 o): outside
+// it alpha = o exp(-q(d) / 2) < 1/255 and every pixel skips the entry.  The box
+// half-extents sqrt(tau c / det), sqrt(tau a / det) are padded (tau by 2^-8
+// relative and absolute, the extents by 2^-10 relative and 1/64 px) far beyond
+// the few-ulp error of the fp32 exponent, so a clear bit never hides a pixel
+// that blends.  A conic that is not positive definite (or NaN) gets all four
+// bits; opacity below 1/255 with a positive-definite conic gets none
+// (alpha <= o there).
+__device__ __forceinline__ uint32_t block_mask(float u, float v, float a, float b, float c, float o, int x0,
+                                               int y0) {
+    const float bb = b * b;
+    const float bb_err = __builtin_fmaf(b, b, -bb);
+    const float det = __builtin_fmaf(a, c, -bb) - bb_err;
+    if (!(a > 0.0f && det > 0.0f)) return 0xFu;
+    if (!(o >= ALPHA_MIN)) return 0u;
+    constexpr float TWO_LN2 = 1.3862943611198906f;
+    constexpr float PAD = 1.0f / 256.0f;
+    const float tau = __builtin_fmaf(TWO_LN2 * __builtin_amdgcn_logf(255.0f * o), 1.0f + PAD, PAD);
+    const float inv_det = 1.0f / det;
+    const float ex = __builtin_sqrtf(tau * c * inv_det) * (1.0f + 1.0f / 1024.0f) + 1.0f / 64.0f;
+    const float ey = __builtin_sqrtf(tau * a * inv_det) * (1.0f + 1.0f / 1024.0f) + 1.0f / 64.0f;
+    if (u + ex < (float)x0 || u - ex > (float)(x0 + TILE - 1)) return 0u;
+    uint32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < WQ; ++q) {
+        const float r0 = (float)(y0 + 4 * q), r1 = r0 + 3.0f;
+        if (!(v + ey < r0) && !(v - ey > r1)) m |= 1u << q;
+    }
+    return m;
+}
+
+// LDS slice of one wave: 64 staged entries.  xym = (x, y, block mask bits,
+// Gaussian id bits), co = (a2, r, q2, opacity) of splat_power2, cd = (rgb,
+// depth), abc = the raw conic (backward only).
+struct WaveStage {
+    float4 xym[64];
+    float4 co[64];
+    float4 cd[64];
+};
+
+// Stages the lane's entry and returns its block mask (0 for an invalid lane).
+__device__ __forceinline__ uint32_t stage_entry(WaveStage& st, int lane, const RawSplat& r, bool valid, int x0,
+                                                int y0) {
+    const float3 k = stage_conic(r.con.x, r.con.y, r.con.z);
+    const uint32_t m = valid ? block_mask(r.xy.x, r.xy.y, r.con.x, r.con.y, r.con.z, r.con.w, x0, y0) : 0u;
+    st.xym[lane] = make_float4(r.xy.x, r.xy.y, 0.0f, __uint_as_float(r.id));
+    st.co[lane] = make_float4(k.x, k.y, k.z, r.con.w);
+    st.cd[lane] = make_float4(r.r, r.g, r.b, r.d);
+    return m;
+}
+
+// Entries of a staged chunk per block, as 64-bit masks in scalar registers:
+// bit j of mq[q] is set when chunk entry j may reach block q.
+__device__ __forceinline__ void chunk_masks(uint32_t m, uint64_t (&mq)[WQ]) {
+#pragma unroll
+    for (int q = 0; q < WQ; ++q) mq[q] = ballot((m >> q) & 1u);
+}
+
+// Entries still to visit: those that reach a block in `live`.
+__device__ __forceinline__ uint64_t chunk_todo(const uint64_t (&mq)[WQ], uint32_t live) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int q = 0; q < WQ; ++q)
+        if (live & (1u << q)) t |= mq[q];
+    return t;
+}
+
+// Running state of the four pixels of a lane (one per block).  Which pixels
+// of block q have stopped is one 64-bit mask per block, uniform across the
+// wave (scalar registers); a lane reads its own bit with inverse_ballot.
+struct PixQ {
+    float T[WQ], C0[WQ], C1[WQ], C2[WQ], D[WQ];
+    int last[WQ], stop_at[WQ];
+    uint64_t done_m[WQ];
+};
+
+__device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// blend() for block q (pixel q of every lane) and one entry, with the blend
+// part behind a uniform branch: the block only pays for it when one of its
+// pixels takes the entry.  Same arithmetic as blend().  Returns true
+// (uniform) when a pixel of the block stopped at this entry.
+// Offset of the first entry of list chunk base for this lane, clamped into
+// the list (lanes past the end re-read its last entry; their slots are
+// staged as empty).
+__device__ __forceinline__ uint32_t chunk_id(const FrameArgs& F, uint32_t base, uint32_t end, int lane) {
+    const uint32_t k = base + (uint32_t)lane;
+    return F.point_list[k < end ? k : end - 1];
+}
+
+// One wave renders tile `tile` of F into O.  COUNT: also n_examined.
+template <bool COUNT>
+__device__ __forceinline__ void fwd_tile(const FrameArgs& F, const FwdOut& O, int tile, int lane, WaveStage& st) {
+    const int tx = tile % F.TX, ty = tile / F.TX;
+    const int x0 = tx * TILE, y0 = ty * TILE;
+    const int px = x0 + (lane & 15);
+    const float fx = (float)px;
+    PixQ s;
+    float fy[WQ];
+    uint32_t live = 0;  // blocks with a pixel still walking (uniform)
+#pragma unroll
+    for (int q = 0; q < WQ; ++q) {
+        const int py = y0 + (lane >> 4) + 4 * q;
+        fy[q] = (float)py;
+        s.T[q] = 1.0f;
+        s.C0[q] = s.C1[q] = s.C2[q] = s.D[q] = 0.0f;
+        s.last[q] = 0;
+        s.stop_at[q] = -1;
+        s.done_m[q] = ~ballot(px < F.W && py < F.H);  // pixels outside the image never walk
+        if (~s.done_m[q]) live |= 1u << q;
+    }
+    const uint32_t start = __builtin_amdgcn_readfirstlane(F.ranges[2 * tile]);
+    const uint32_t end = __builtin_amdgcn_readfirstlane(F.ranges[2 * tile + 1]);
+    // two-stage prefetch: ids two chunks ahead, raw splat data one chunk ahead
+    RawSplat cur{}, nxt{};
+    uint32_t idn = 0;
+    if (start < end) {
+        load_raw(F, chunk_id(F, start, end, lane), cur);
+        if (start + 64 < end) idn = chunk_id(F, start + 64, end, lane);
+    }
+    for (uint32_t base = start; base < end && live; base += 64) {
+        // the chunk's entries that reach a live block; a block that stops
+        // inside the chunk computes nothing more
+        uint64_t todo = ballot((stage_entry(st, lane, cur, base + lane < end, x0, y0) & live) != 0u);
+        wave_sync();
+        if (base + 64 < end) load_raw(F, idn, nxt);
+        if (base + 128 < end) idn = chunk_id(F, base + 128, end, lane);
+        const int pos0 = (int)(base - start);
+        // visit them front to back; per entry every block is evaluated
+        // branch-free -- the four exponents as independent chains, then the
+        // blends under lane masks combined on the scalar unit -- since a
+        // uniform branch per block costs the scalar unit about what it saves
+        // the vector unit
+        while (todo && live) {
+            const int j = (int)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const float4 xym = st.xym[j];
+            const float4 co = st.co[j];
+            const float4 cd = st.cd[j];
+            const float dx = fx - xym.x;
+            float al[WQ], pw[WQ];
+#pragma unroll
+            for (int q = 0; q < WQ; ++q) {
+                pw[q] = splat_power2(dx, fy[q] - xym.y, co.x, co.y, co.z);
+                al[q] = fminf(ALPHA_MAX, co.w * exp2_fast(pw[q]));
+            }
+            uint64_t stops = 0;
+#pragma unroll
+            for (int q = 0; q < WQ; ++q) {
+                // pixels still walking that do not skip the entry (single
+                // compares as lane masks, combined on the scalar unit)
+                const uint64_t cand = ballot(!(pw[q] > 0.0f)) & ballot(!(al[q] < ALPHA_MIN)) & ~s.done_m[q];
+                const float w = al[q] * s.T[q];
+                const float Tn = s.T[q] - w;
+                const uint64_t stop = cand & ballot(Tn < T_MIN);
+                const bool take = lane_bit(cand & ~stop);
+                const float we = take ? w : 0.0f;
+                s.C0[q] = __builtin_fmaf(cd.x, we, s.C0[q]);
+                s.C1[q] = __builtin_fmaf(cd.y, we, s.C1[q]);
+                s.C2[q] = __builtin_fmaf(cd.z, we, s.C2[q]);
+                s.D[q] = __builtin_fmaf(cd.w, we, s.D[q]);
+                s.T[q] = take ? Tn : s.T[q];
+                s.last[q] = take ? pos0 + j + 1 : s.last[q];
+                if (COUNT) s.stop_at[q] = lane_bit(stop) ? pos0 + j + 1 : s.stop_at[q];
+                s.done_m[q] |= stop;
+                stops |= stop;
+            }
+            if (stops) {
+#pragma unroll
+                for (int q = 0; q < WQ; ++q)
+                    if (s.done_m[q] == ~0ull) live &= ~(1u << q);
+            }
+        }
+        wave_sync();
+        cur = nxt;
+    }
+#pragma unroll
+    for (int q = 0; q < WQ; ++q) {
+        const int py = y0 + (lane >> 4) + 4 * q;
+        if (px < F.W && py < F.H) {
+            write_pixel(F, O, px, py, Pix{s.T[q], s.C0[q], s.C1[q], s.C2[q], s.D[q], s.last[q], lane_bit(s.done_m[q])});
+            if (COUNT)
+                F.n_examined[(int64_t)py * F.W + px] = s.stop_at[q] >= 0 ? s.stop_at[q] : (int)(end - start);
+        }
+    }
+}
+
+// Tiles of a work item: TPI = 1 -> the item is a tile; TPI = 4 -> the item
+// is a 32x32 block of 2x2 tiles (those inside the grid), rendered in turn.
+template <int TPI>
+__device__ __forceinline__ int item_tiles(const FrameArgs& F, uint32_t item, int (&tiles)[TPI]) {
+    if (TPI == 1) {
+        tiles[0] = (int)item;
+        return 1;
+    }
+    const int BX = (F.TX + 1) >> 1;
+    const int bx = (int)item % BX, by = (int)item / BX;
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < TPI; ++k) {
+        const int tx = 2 * bx + (k & 1), ty = 2 * by + (k >> 1);
+        if (tx < F.TX && ty < F.TY) tiles[n++] = ty * F.TX + tx;
+    }
+    return n;
+}
+
+// PERSISTENT: waves take items from the task pool (early claim); otherwise
+// wave w of the grid renders item w (grid-static dispatch of the same code).
+template <bool MV = false, bool COUNT = false, bool PERSISTENT = true, int TPI = 1>
 __global__ __launch_bounds__(256) void k_fwd_wide(FrameArgs F0, FwdOut O0, const ViewDesc* __restrict__ views,
-                                                  const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
+                                                  const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr,
+                                                  uint32_t n_static) {
     const uint64_t t_begin = trace_begin(F0);
-    __shared__ float2 s_xy[4][64];
-    __shared__ float4 s_co[4][64];
-    __shared__ float4 s_cd[4][64];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    WorkQueue Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
-    for (;;) {
+    __shared__ WaveStage s_st[4];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    WorkQueue Q;
+    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv, MV ? nullptr : F0.item_claims);
+    for (bool first = true;; first = false) {
         uint32_t item;
-        if (!queue_next(Q, lane, item)) break;
+        if (PERSISTENT) {
+            if (!(first ? queue_first(Q, blockIdx.x * 4 + wv, lane, item) : queue_next(Q, lane, item))) break;
+        } else {
+            item = blockIdx.x * 4 + wv;
+            if (item >= n_static) break;
+        }
         const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
         const FwdOut O = MV ? views[item >> VIEW_SHIFT].O : O0;
-        const int tile = (int)(item & LOCAL_MASK);
-        const int tx = tile % F.TX, ty = tile / F.TX;
-        const int px = tx * TILE + (lane & 15);
-        const float fx = (float)px;
-        Pix s[WQ];
-        float fy[WQ];
-        int stop_at[WQ];
-#pragma unroll
-        for (int q = 0; q < WQ; ++q) {
-            const int py = ty * TILE + (lane >> 4) + 4 * q;
-            fy[q] = (float)py;
-            s[q] = Pix{1.0f, 0.f, 0.f, 0.f, 0.f, 0, !(px < F.W && py < F.H)};
-            stop_at[q] = -1;
-        }
-        const uint32_t start = F.ranges[2 * tile], end = F.ranges[2 * tile + 1];
-        // two-stage prefetch: ids two chunks ahead, splat data one chunk ahead
-        SplatRegs cur{}, nxt{};
-        {
-            const uint32_t k0 = start + lane;
-            gather_splat(F, k0 < end, k0 < end ? F.point_list[k0] : 0u, cur);
-        }
-        uint32_t k1 = start + 64 + lane;
-        uint32_t id1 = k1 < end ? F.point_list[k1] : 0u;
-        for (uint32_t base = start; base < end; base += 64) {
-            bool all_done = true;
-#pragma unroll
-            for (int q = 0; q < WQ; ++q) all_done &= s[q].done;
-            if (ballot(!all_done) == 0) break;
-            s_xy[wv][lane] = cur.xy;
-            s_co[wv][lane] = cur.co;
-            s_cd[wv][lane] = cur.cd;
-            wave_sync();
-            gather_splat(F, k1 < end, id1, nxt);
-            k1 += 64;
-            id1 = k1 < end ? F.point_list[k1] : 0u;
-            const int cnt = (int)min(64u, end - base);
-            const int pos0 = (int)(base - start);
-            for (int j = 0; j < cnt; ++j) {
-                if (all_done) break;
-                const float2 xy = s_xy[wv][j];
-                const float4 co = s_co[wv][j];
-                const float4 cd = s_cd[wv][j];
-                all_done = true;
-#pragma unroll
-                for (int q = 0; q < WQ; ++q) {
-                    // skipped by the whole wave once the 16x4 block q has stopped
-                    if (!s[q].done) {
-                        blend(fx, fy[q], xy, co, cd, pos0 + j, s[q]);
-                        if (COUNT && s[q].done) stop_at[q] = pos0 + j + 1;
-                    }
-                    all_done &= s[q].done;
-                }
-            }
-            wave_sync();
-            cur = nxt;
-        }
-#pragma unroll
-        for (int q = 0; q < WQ; ++q) {
-            const int py = ty * TILE + (lane >> 4) + 4 * q;
-            if (px < F.W && py < F.H) {
-                write_pixel(F, O, px, py, s[q]);
-                if (COUNT)
-                    F.n_examined[(int64_t)py * F.W + px] = stop_at[q] >= 0 ? stop_at[q] : (int)(end - start);
-            }
-        }
+        int tiles[TPI];
+        const int nt = item_tiles<TPI>(F, item & LOCAL_MASK, tiles);
+        for (int k = 0; k < nt; ++k) fwd_tile<COUNT>(F, O, tiles[k], lane, s_st[wv]);
+        if (!PERSISTENT) break;
     }
     trace_end(F0, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
@@ -628,11 +856,13 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
     __shared__ float4 s_abc[4][64];  // raw conic a, b, c and the Gaussian id (bits)
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     WorkQueue Q;
-    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
+    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv, MV ? nullptr : F0.item_claims);
+    bool first = true;
     for (;;) {
         uint32_t item;
         if (PERSISTENT) {
-            if (!queue_next(Q, lane, item)) break;
+            if (!(first ? queue_first(Q, blockIdx.x * 4 + wv, lane, item) : queue_next(Q, lane, item))) break;
+            first = false;
         } else {
             item = blockIdx.x * 4 + wv;
         }
@@ -732,137 +962,182 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
 }
 
 // Backward with one wave per 16x16 tile: lane l owns the four pixels
-// (l mod 16, l / 16 + 4q), q = 0..3, of the tile.  The per-entry work that
-// does not scale with pixels -- the LDS reads, the 10-value wave reduction
-// and the one multi-lane gradient atomic -- is paid once per 256 pixels
-// instead of once per 64, and dx (shared by a lane's four pixels) once per
-// entry.  Each pixel's arithmetic is the same as in k_bwd_pixel.
+// (l mod 16, l / 16 + 4q), q = 0..3, of the tile (block q = pixel row q of
+// the lanes).  The per-entry work that does not scale with pixels -- the LDS
+// reads, the 10-value wave reduction and the one multi-lane gradient atomic --
+// is paid once per 256 pixels instead of once per 64, and dx (shared by a
+// lane's four pixels) once per entry.  Each pixel's arithmetic is the same as
+// in k_bwd_pixel.  Per entry a block is visited on uniform branches only: not
+// at all when the entry lies beyond every n_contrib of the block or outside
+// the block's ellipse mask (staged as in the forward), and its gradient terms
+// only when one of its pixels blended the entry.  The chunks of 64 entries are
+// walked back to front with the forward's two-stage prefetch (ids two chunks
+// ahead, raw splat data one chunk ahead).
 
 // DET: instead of adding its per-entry totals to the gradients, the wave
 // stores them (zeros for an entry no pixel blends) at the entry's slot of
 // B.det_partials, for an ordered reduction afterwards.
-template <bool MV = false, bool DET = false>
-__global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const ViewDesc* __restrict__ views,
-                                                  const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
-    const uint64_t t_begin = trace_begin(F0);
-    __shared__ float2 s_xy[4][64];
-    __shared__ float4 s_co[4][64];
-    __shared__ float4 s_cd[4][64];
-    __shared__ float4 s_abc[4][64];  // raw conic a, b, c and the Gaussian id (bits)
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    WorkQueue Q = make_queue(ctr, items, blockIdx.x * 4 + wv);
-    for (;;) {
-        uint32_t item;
-        if (!queue_next(Q, lane, item)) break;
-        const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
-        const BwdIO B = MV ? views[item >> VIEW_SHIFT].B : B0;
-        const int tile = (int)(item & LOCAL_MASK);
-        const int64_t HW = (int64_t)F.W * F.H;
-        const int tx = tile % F.TX, ty = tile / F.TX;
-        const int px = tx * TILE + (lane & 15);
-        const uint32_t start = F.ranges[2 * tile];
-        const int len = (int)(F.ranges[2 * tile + 1] - start);
-        const GradLane GL = grad_lane(B, scatter10_slot(lane));
-        const int dslot = scatter10_slot(lane);
-        float* const dpart = DET ? B.det_partials + (size_t)B.det_base[tile] * 10 + dslot : nullptr;
-        // S[q]: dL/dC . (colour, depth accumulated behind the entry) + the
-        // entry-independent part of dL/dalpha, as in k_bwd_pixel
-        float T[WQ], S[WQ], gC0[WQ], gC1[WQ], gC2[WQ], gD[WQ], fy[WQ];
-        int nc[WQ];
-        int my_max = 0;
+template <bool DET>
+__device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int tile, int lane, WaveStage& st,
+                                         float4* __restrict__ s_abc) {
+    const int64_t HW = (int64_t)F.W * F.H;
+    const int tx = tile % F.TX, ty = tile / F.TX;
+    const int x0 = tx * TILE, y0 = ty * TILE;
+    const int px = x0 + (lane & 15);
+    const uint32_t start = __builtin_amdgcn_readfirstlane(F.ranges[2 * tile]);
+    const int len = (int)(__builtin_amdgcn_readfirstlane(F.ranges[2 * tile + 1]) - start);
+    const GradLane GL = grad_lane(B, scatter10_slot(lane));
+    const int dslot = scatter10_slot(lane);
+    float* const dpart = DET ? B.det_partials + (size_t)B.det_base[tile] * 10 + dslot : nullptr;
+    // S[q]: dL/dC . (colour, depth accumulated behind the entry) + the
+    // entry-independent part of dL/dalpha, as in k_bwd_pixel
+    float T[WQ], S[WQ], gC0[WQ], gC1[WQ], gC2[WQ], gD[WQ], fy[WQ];
+    int nc[WQ], bmax[WQ];
+    int max_n = 0;
+#pragma unroll
+    for (int q = 0; q < WQ; ++q) {
+        const int py = y0 + (lane >> 4) + 4 * q;
+        const bool inside = px < F.W && py < F.H;
+        const int64_t p = inside ? (int64_t)py * F.W + px : 0;
+        const float TN = inside ? B.final_T[p] : 1.0f;
+        int n = inside ? B.n_contrib[p] : 0;
+        n = n < 0 ? 0 : (n > len ? len : n);  // stay inside the tile's list
+        nc[q] = n;
+        gC0[q] = inside ? B.dL_dcolor[p] : 0.f;
+        gC1[q] = inside ? B.dL_dcolor[HW + p] : 0.f;
+        gC2[q] = inside ? B.dL_dcolor[2 * HW + p] : 0.f;
+        const float ga = (inside && B.dL_dalpha) ? B.dL_dalpha[p] : 0.f;
+        gD[q] = (inside && B.dL_ddepth) ? B.dL_ddepth[p] : 0.f;
+        S[q] = TN * (gC0[q] * F.bg0 + gC1[q] * F.bg1 + gC2[q] * F.bg2) - ga * TN;
+        T[q] = TN;
+        fy[q] = (float)py;
+    }
+#pragma unroll
+    for (int q = 0; q < WQ; ++q) {
+        bmax[q] = __builtin_amdgcn_readfirstlane(wave_max(nc[q]));  // uniform: block q walks entries < bmax[q]
+        max_n = bmax[q] > max_n ? bmax[q] : max_n;
+    }
+    const float fx = (float)px;
+    RawSplat cur{}, nxt{};
+    uint32_t idn = 0;
+    if (max_n > 0) {
+        const uint32_t lo0 = max_n > 64 ? (uint32_t)max_n - 64 : 0u;
+        load_raw(F, chunk_id(F, start + lo0, start + (uint32_t)max_n, lane), cur);
+        if (lo0 > 0) idn = chunk_id(F, start + (lo0 > 64 ? lo0 - 64 : 0u), start + lo0, lane);
+    }
+    float* const dchunk = DET ? B.det_partials + (size_t)B.det_base[tile] * 10 : nullptr;
+    for (int hi = max_n; hi > 0; hi -= 64) {
+        const int lo = hi > 64 ? hi - 64 : 0;
+        uint64_t mq[WQ];
+        chunk_masks(stage_entry(st, lane, cur, lo + lane < hi, x0, y0), mq);
+        s_abc[lane] = make_float4(cur.con.x, cur.con.y, cur.con.z, 0.0f);
+        // block q walks only the entries below its deepest n_contrib
 #pragma unroll
         for (int q = 0; q < WQ; ++q) {
-            const int py = ty * TILE + (lane >> 4) + 4 * q;
-            const bool inside = px < F.W && py < F.H;
-            const int64_t p = inside ? (int64_t)py * F.W + px : 0;
-            const float TN = inside ? B.final_T[p] : 1.0f;
-            int n = inside ? B.n_contrib[p] : 0;
-            n = n < 0 ? 0 : (n > len ? len : n);  // stay inside the tile's list
-            nc[q] = n;
-            my_max = n > my_max ? n : my_max;
-            gC0[q] = inside ? B.dL_dcolor[p] : 0.f;
-            gC1[q] = inside ? B.dL_dcolor[HW + p] : 0.f;
-            gC2[q] = inside ? B.dL_dcolor[2 * HW + p] : 0.f;
-            const float ga = (inside && B.dL_dalpha) ? B.dL_dalpha[p] : 0.f;
-            gD[q] = (inside && B.dL_ddepth) ? B.dL_ddepth[p] : 0.f;
-            S[q] = TN * (gC0[q] * F.bg0 + gC1[q] * F.bg1 + gC2[q] * F.bg2) - ga * TN;
-            T[q] = TN;
-            fy[q] = (float)py;
+            const int n = bmax[q] - lo;
+            mq[q] &= n >= 64 ? ~0ull : (n > 0 ? (1ull << n) - 1ull : 0ull);
         }
-        const int max_n = __builtin_amdgcn_readfirstlane(wave_max(my_max));  // uniform: the loop runs on scalars
-        const float fx = (float)px;
-        for (int hi = max_n; hi > 0; hi -= 64) {
-            const int lo = hi > 64 ? hi - 64 : 0;
-            if (lo + lane < hi) {
-                const uint32_t g = F.point_list[start + lo + lane];
-                float2 xy; float4 co, cd;
-                load_splat(F, g, xy, co, cd);
-                const float4 raw = F.conic_opacity[g];
-                s_xy[wv][lane] = xy;
-                s_co[wv][lane] = co;
-                s_cd[wv][lane] = cd;
-                s_abc[wv][lane] = make_float4(raw.x, raw.y, raw.z, __uint_as_float(g));
-            }
-            wave_sync();
-            for (int j = hi - 1; j >= lo; --j) {
-                const int jj = j - lo;
-                const float2 xy = s_xy[wv][jj];
-                const float4 co = s_co[wv][jj];
-                const float dx = fx - xy.x;
-                float dy[WQ], G[WQ], ga[WQ], alpha[WQ];
-                bool contrib[WQ];
-                bool anyc = false;
-#pragma unroll
-                for (int q = 0; q < WQ; ++q) {
-                    dy[q] = fy[q] - xy.y;
-                    const float p2 = splat_power2(dx, dy[q], co.x, co.y, co.z);
-                    G[q] = exp2_fast(p2);
-                    ga[q] = co.w * G[q];
-                    alpha[q] = fminf(ALPHA_MAX, ga[q]);
-                    contrib[q] = (j < nc[q]) && !(p2 > 0.0f || alpha[q] < ALPHA_MIN);
-                    anyc |= contrib[q];
-                }
-                if (ballot(anyc) == 0) {
-                    if (DET && dslot >= 0) dpart[(size_t)j * 10] = 0.0f;
-                    continue;
-                }
-                const float4 cd = s_cd[wv][jj];
-                const float4 abc = s_abc[wv][jj];
-                float v[10];
-#pragma unroll
-                for (int i = 0; i < 10; ++i) v[i] = 0.f;
-#pragma unroll
-                for (int q = 0; q < WQ; ++q) {
-                    const float inv = __builtin_amdgcn_rcpf(1.0f - alpha[q]);
-                    const float Tb = T[q] * inv;
-                    const float w = contrib[q] ? alpha[q] * Tb : 0.0f;
-                    v[6] = __builtin_fmaf(w, gC0[q], v[6]);
-                    v[7] = __builtin_fmaf(w, gC1[q], v[7]);
-                    v[8] = __builtin_fmaf(w, gC2[q], v[8]);
-                    v[9] = __builtin_fmaf(w, gD[q], v[9]);
-                    const float gc = gC0[q] * cd.x + gC1[q] * cd.y + gC2[q] * cd.z + gD[q] * cd.w;
-                    const float dA = Tb * gc - inv * S[q];
-                    S[q] = __builtin_fmaf(gc, w, S[q]);
-                    T[q] = contrib[q] ? Tb : T[q];
-                    const bool unclamped = contrib[q] && ga[q] <= ALPHA_MAX;
-                    const float dP = unclamped ? ga[q] * dA : 0.0f;  // dL/dpower
-                    v[5] += unclamped ? G[q] * dA : 0.0f;            // dL/dopacity
-                    v[2] += -0.5f * dx * dx * dP;
-                    v[3] += -dx * dy[q] * dP;
-                    v[4] += -0.5f * dy[q] * dy[q] * dP;
-                    v[0] += (abc.x * dx + abc.y * dy[q]) * dP;
-                    v[1] += (abc.y * dx + abc.z * dy[q]) * dP;
-                }
-                float tot;
-                wave_reduce_scatter10(v, lane, tot);
-                if (DET) {
-                    if (dslot >= 0) dpart[(size_t)j * 10] = tot;
-                } else if (GL.base) {
-                    unsafeAtomicAdd(GL.base + (size_t)__float_as_uint(abc.w) * GL.stride, tot);
-                }
-            }
-            wave_sync();
+        wave_sync();
+        if (lo > 0) load_raw(F, idn, nxt);  // the chunk [max(lo - 64, 0), lo)
+        if (lo > 64) {
+            const uint32_t nlo = (uint32_t)lo - 64;
+            idn = chunk_id(F, start + (nlo > 64 ? nlo - 64 : 0u), start + nlo, lane);
         }
+        uint64_t todo = chunk_todo(mq, 0xFu);
+        uint64_t wrote = 0;  // DET: entries whose partial slot holds a total
+        // visit back to front only the entries that reach a block
+        while (todo) {
+            const int jj = 63 - (int)__builtin_clzll(todo);
+            todo &= ~(1ull << jj);
+            const int j = lo + jj;
+            const float4 xym = st.xym[jj];
+            uint32_t m = 0;
+#pragma unroll
+            for (int q = 0; q < WQ; ++q) m |= (uint32_t)((mq[q] >> jj) & 1u) << q;
+            const float4 co = st.co[jj];
+            const float4 cd = st.cd[jj];
+            const float4 abc = s_abc[jj];
+            const float dx = fx - xym.x;
+            float v[10];
+#pragma unroll
+            for (int i = 0; i < 10; ++i) v[i] = 0.f;
+            bool any = false;  // a block had a pixel that blended the entry (uniform)
+#pragma unroll
+            for (int q = 0; q < WQ; ++q) {
+                if (!(m & (1u << q))) continue;
+                const float dy = fy[q] - xym.y;
+                const float p2 = splat_power2(dx, dy, co.x, co.y, co.z);
+                const float G = exp2_fast(p2);
+                const float ga = co.w * G;
+                const float alpha = fminf(ALPHA_MAX, ga);
+                const uint64_t cm = ballot(j < nc[q]) & ballot(!(p2 > 0.0f)) & ballot(!(alpha < ALPHA_MIN));
+                if (cm == 0) continue;
+                const bool contrib = lane_bit(cm);
+                any = true;
+                const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                const float Tb = T[q] * inv;
+                const float w = contrib ? alpha * Tb : 0.0f;
+                v[6] = __builtin_fmaf(w, gC0[q], v[6]);
+                v[7] = __builtin_fmaf(w, gC1[q], v[7]);
+                v[8] = __builtin_fmaf(w, gC2[q], v[8]);
+                v[9] = __builtin_fmaf(w, gD[q], v[9]);
+                const float gc = gC0[q] * cd.x + gC1[q] * cd.y + gC2[q] * cd.z + gD[q] * cd.w;
+                const float dA = Tb * gc - inv * S[q];
+                S[q] = __builtin_fmaf(gc, w, S[q]);
+                T[q] = contrib ? Tb : T[q];
+                const bool unclamped = lane_bit(cm & ballot(ga <= ALPHA_MAX));
+                const float dP = unclamped ? ga * dA : 0.0f;  // dL/dpower
+                v[5] += unclamped ? G * dA : 0.0f;            // dL/dopacity
+                v[2] += -0.5f * dx * dx * dP;
+                v[3] += -dx * dy * dP;
+                v[4] += -0.5f * dy * dy * dP;
+                v[0] += (abc.x * dx + abc.y * dy) * dP;
+                v[1] += (abc.y * dx + abc.z * dy) * dP;
+            }
+            if (!any) continue;
+            float tot;
+            wave_reduce_scatter10(v, lane, tot);
+            if (DET) {
+                if (dslot >= 0) dpart[(size_t)j * 10] = tot;
+                wrote |= 1ull << jj;
+            } else if (GL.base) {
+                unsafeAtomicAdd(GL.base + (size_t)__float_as_uint(xym.w) * GL.stride, tot);
+            }
+        }
+        if (DET && lo + lane < hi && !((wrote >> lane) & 1ull)) {  // zeros for the entries no pixel blended
+            float* z = dchunk + (size_t)(lo + lane) * 10;
+#pragma unroll
+            for (int k = 0; k < 10; ++k) z[k] = 0.0f;
+        }
+        wave_sync();
+        cur = nxt;
+    }
+}
+
+template <bool MV = false, bool DET = false, bool PERSISTENT = true, int TPI = 1>
+__global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const ViewDesc* __restrict__ views,
+                                                  const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr,
+                                                  uint32_t n_static) {
+    const uint64_t t_begin = trace_begin(F0);
+    __shared__ WaveStage s_st[4];
+    __shared__ float4 s_abc[4][64];  // raw conic a, b, c
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    WorkQueue Q;
+    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv, MV ? nullptr : F0.item_claims);
+    for (bool first = true;; first = false) {
+        uint32_t item;
+        if (PERSISTENT) {
+            if (!(first ? queue_first(Q, blockIdx.x * 4 + wv, lane, item) : queue_next(Q, lane, item))) break;
+        } else {
+            item = blockIdx.x * 4 + wv;
+            if (item >= n_static) break;
+        }
+        const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
+        const BwdIO B = MV ? views[item >> VIEW_SHIFT].B : B0;
+        int tiles[TPI];
+        const int nt = item_tiles<TPI>(F, item & LOCAL_MASK, tiles);
+        for (int k = 0; k < nt; ++k) bwd_tile<DET>(F, B, tiles[k], lane, s_st[wv], s_abc[wv]);
+        if (!PERSISTENT) break;
     }
     trace_end(F0, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
@@ -874,25 +1149,36 @@ __device__ __forceinline__ int cost_bucket(uint32_t c) {
     return b < NBUCKET - 1 ? b : NBUCKET - 1;
 }
 
-// Cost of every tile: forward = its list length; backward = the largest
-// n_contrib among its 256 pixels (one workgroup per tile).
-__global__ __launch_bounds__(256) void k_tile_costs(FrameArgs F, const int* __restrict__ n_contrib,
+// Cost of every work item (one workgroup per item): a tile costs its list
+// length (forward) or the largest n_contrib among its 256 pixels (backward);
+// with block2 the item is a 32x32 block and costs the sum over its tiles.
+__global__ __launch_bounds__(256) void k_tile_costs(FrameArgs F, const int* __restrict__ n_contrib, int block2,
                                                     uint32_t* __restrict__ cost) {
     __shared__ int wmax[4];
-    const int tile = blockIdx.x;
-    uint32_t c = 0;
-    if (n_contrib) {
-        const int tx = tile % F.TX, ty = tile / F.TX;
-        const int px = tx * TILE + (threadIdx.x & 15), py = ty * TILE + (threadIdx.x >> 4);
-        const int nc = (px < F.W && py < F.H) ? n_contrib[(int64_t)py * F.W + px] : 0;
-        const int m = wave_max(nc);
-        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-        __syncthreads();
-        c = (uint32_t)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    int tiles[4];
+    int nt = 1;
+    if (block2) {
+        nt = item_tiles<4>(F, blockIdx.x, tiles);
     } else {
-        c = F.ranges[2 * tile + 1] - F.ranges[2 * tile];
+        tiles[0] = blockIdx.x;
     }
-    if (threadIdx.x == 0) cost[tile] = c;
+    uint32_t c = 0;
+    for (int k = 0; k < nt; ++k) {
+        const int tile = tiles[k];
+        if (n_contrib) {
+            const int tx = tile % F.TX, ty = tile / F.TX;
+            const int px = tx * TILE + (threadIdx.x & 15), py = ty * TILE + (threadIdx.x >> 4);
+            const int nc = (px < F.W && py < F.H) ? n_contrib[(int64_t)py * F.W + px] : 0;
+            const int m = wave_max(nc);
+            if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+            __syncthreads();
+            c += (uint32_t)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+            __syncthreads();
+        } else {
+            c += F.ranges[2 * tile + 1] - F.ranges[2 * tile];
+        }
+    }
+    if (threadIdx.x == 0) cost[blockIdx.x] = c;
 }
 
 // Batched views: global tile g (over all views, tile_off = per-view prefix of
@@ -1002,10 +1288,14 @@ static bgs_status check_frame(const bgs_frame* f, const bgs_render_cfg* cfg, Fra
         return fail(BGS_EINVAL, std::string(who) + ": null frame array");
     if ((reinterpret_cast<uintptr_t>(f->conic_opacity) & 15) || (reinterpret_cast<uintptr_t>(f->means2D) & 7))
         return fail(BGS_EINVAL, std::string(who) + ": means2D must be 8-byte and conic_opacity 16-byte aligned");
-    if (cfg->variant < BGS_STATIC || cfg->variant > BGS_BALANCED_HYBRID)
+    if (cfg->variant < BGS_STATIC || cfg->variant > BGS_STATIC_WAVE)
         return fail(BGS_EINVAL, std::string(who) + ": unknown variant");
-    if (cfg->variant != BGS_STATIC && cfg->subtile != 8 && !(cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 16))
-        return fail(BGS_EUNSUPPORTED, std::string(who) + ": sub-tile must be 8, or 16 with the pixel-wise variant");
+    if (cfg->variant == BGS_STATIC_WAVE && cfg->subtile != 16)
+        return fail(BGS_EUNSUPPORTED, std::string(who) + ": the static wave-per-tile variant needs sub-tile 16");
+    if (cfg->variant != BGS_STATIC && cfg->variant != BGS_STATIC_WAVE && cfg->subtile != 8 &&
+        !(cfg->variant == BGS_BALANCED_PIXEL && (cfg->subtile == 16 || cfg->subtile == 32)))
+        return fail(BGS_EUNSUPPORTED,
+                    std::string(who) + ": sub-tile must be 8, or 16 or 32 with the pixel-wise variant");
     if (cfg->order != BGS_ORDER_RASTER && cfg->order != BGS_ORDER_COST)
         return fail(BGS_EINVAL, std::string(who) + ": unknown order");
     A.W = f->width;
@@ -1027,6 +1317,7 @@ static bgs_status check_frame(const bgs_frame* f, const bgs_render_cfg* cfg, Fra
     A.n_examined = cfg->n_examined;
     A.list_cap = cfg->list_cap;
     A.list_overflow = cfg->list_overflow;
+    A.item_claims = cfg->item_claims;
     return BGS_OK;
 }
 
@@ -1039,10 +1330,20 @@ static int persistent_blocks(K kernel, uint32_t n_items) {
     return (int)(want < cap ? want : (cap > 0 ? cap : 1));
 }
 
-// Whole 16x16 tiles as work items: the forward's and the backward's
-// wave-per-tile kernels.
+// Whole 16x16 tiles (or 32x32 blocks of them) as work items: the forward's
+// and the backward's wave-per-tile kernels.
 static bool tile_items(const bgs_render_cfg* cfg) {
-    return cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 16;
+    return cfg->variant == BGS_BALANCED_PIXEL && (cfg->subtile == 16 || cfg->subtile == 32);
+}
+
+static bool block_items(const bgs_render_cfg* cfg) {
+    return cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 32;
+}
+
+// Number of queue entries: blocks, tiles, or 8x8 sub-tiles.
+static uint32_t queue_items(const FrameArgs& A, const bgs_render_cfg* cfg) {
+    if (block_items(cfg)) return (uint32_t)(((A.TX + 1) / 2) * ((A.TY + 1) / 2));
+    return (uint32_t)A.n_tiles * (tile_items(cfg) ? 1u : 4u);
 }
 
 static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, const int* n_contrib, char* ws,
@@ -1051,12 +1352,14 @@ static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, con
     auto* items = reinterpret_cast<uint32_t*>(ws + L.items);
     auto* cost = reinterpret_cast<uint32_t*>(ws + L.cost);
     const int by_cost = cfg->order == BGS_ORDER_COST;
-    if (by_cost) {
-        hipLaunchKernelGGL(k_tile_costs, dim3(A.n_tiles), dim3(256), 0, stream, A, n_contrib, cost);
+    const bool blocks = block_items(cfg);
+    const int n_cost = blocks ? (int)queue_items(A, cfg) : A.n_tiles;
+    if (by_cost && n_cost > 0) {
+        hipLaunchKernelGGL(k_tile_costs, dim3(n_cost), dim3(256), 0, stream, A, n_contrib, blocks ? 1 : 0, cost);
         BGS_HIP(hipGetLastError());
     }
     const int per_tile = tile_items(cfg) ? 1 : 0;
-    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, A.n_tiles, cost, by_cost, per_tile,
+    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, n_cost, cost, by_cost, per_tile,
                        (const uint32_t*)nullptr, 1, items, ctr);
     BGS_HIP(hipGetLastError());
     return BGS_OK;
@@ -1090,11 +1393,19 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
     bgs_status st = check_frame(frame, cfg, A, "bgs_render_fwd");
     if (st != BGS_OK) return st;
     BGS_REQUIRE(out_color && out_alpha && out_depth && final_T && n_contrib, "bgs_render_fwd: null output");
-    if (cfg->n_examined && !tile_items(cfg))
+    if (cfg->n_examined && !(tile_items(cfg) && cfg->subtile == 16))
         return fail(BGS_EUNSUPPORTED, "bgs_render_fwd: n_examined is written by the pixel-wise subtile-16 variant");
     FwdOut O{out_color, out_alpha, out_depth, final_T, n_contrib};
     if (cfg->variant == BGS_STATIC) {
         hipLaunchKernelGGL(k_fwd_static, dim3(A.n_tiles), dim3(256), 0, stream, A, O);
+        BGS_HIP(hipGetLastError());
+        return BGS_OK;
+    }
+    if (cfg->variant == BGS_STATIC_WAVE) {
+        if (A.n_tiles > 0)
+            hipLaunchKernelGGL((k_fwd_wide<false, false, false>), dim3((A.n_tiles + 3) / 4), dim3(256), 0, stream,
+                               A, O, (const ViewDesc*)nullptr, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                               (uint32_t)A.n_tiles);
         BGS_HIP(hipGetLastError());
         return BGS_OK;
     }
@@ -1107,14 +1418,19 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
     }
     auto* ctr = reinterpret_cast<uint32_t*>(w + L.ctr);
     auto* items = reinterpret_cast<const uint32_t*>(w + L.items);
-    if (tile_items(cfg) && A.n_examined) {
-        const int blocks = persistent_blocks(k_fwd_wide<false, true>, (uint32_t)A.n_tiles);
+    const uint32_t n_items = queue_items(A, cfg);
+    if (block_items(cfg)) {
+        const int blocks = persistent_blocks(k_fwd_wide<false, false, true, 4>, n_items);
+        hipLaunchKernelGGL((k_fwd_wide<false, false, true, 4>), dim3(blocks), dim3(256), 0, stream, A, O,
+                           (const ViewDesc*)nullptr, items, ctr, 0u);
+    } else if (tile_items(cfg) && A.n_examined) {
+        const int blocks = persistent_blocks(k_fwd_wide<false, true>, n_items);
         hipLaunchKernelGGL((k_fwd_wide<false, true>), dim3(blocks), dim3(256), 0, stream, A, O,
-                           (const ViewDesc*)nullptr, items, ctr);
+                           (const ViewDesc*)nullptr, items, ctr, 0u);
     } else if (tile_items(cfg)) {
-        const int blocks = persistent_blocks(k_fwd_wide<false>, (uint32_t)A.n_tiles);
+        const int blocks = persistent_blocks(k_fwd_wide<false>, n_items);
         hipLaunchKernelGGL(k_fwd_wide<false>, dim3(blocks), dim3(256), 0, stream, A, O, (const ViewDesc*)nullptr,
-                           items, ctr);
+                           items, ctr, 0u);
     } else if (cfg->variant == BGS_BALANCED_GAUSS) {
         const int blocks = persistent_blocks(k_fwd_hybrid<64>, L.n_items);
         hipLaunchKernelGGL(k_fwd_hybrid<64>, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
@@ -1148,6 +1464,14 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
         BGS_HIP(hipGetLastError());
         return BGS_OK;
     }
+    if (cfg->variant == BGS_STATIC_WAVE) {
+        if (A.n_tiles > 0)
+            hipLaunchKernelGGL((k_bwd_wide<false, false, false>), dim3((A.n_tiles + 3) / 4), dim3(256), 0, stream,
+                               A, B, (const ViewDesc*)nullptr, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                               (uint32_t)A.n_tiles);
+        BGS_HIP(hipGetLastError());
+        return BGS_OK;
+    }
     const RenderLayout L = render_layout(A.n_tiles);
     BGS_REQUIRE(ws && ws_bytes >= L.bytes, "bgs_render_bwd: workspace too small");
     char* w = static_cast<char*>(ws);
@@ -1157,10 +1481,15 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
     }
     auto* ctr = reinterpret_cast<uint32_t*>(w + L.ctr);
     auto* items = reinterpret_cast<const uint32_t*>(w + L.items);
-    if (tile_items(cfg)) {
-        const int blocks = persistent_blocks(k_bwd_wide<false>, (uint32_t)A.n_tiles);
+    const uint32_t n_items = queue_items(A, cfg);
+    if (block_items(cfg)) {
+        const int blocks = persistent_blocks(k_bwd_wide<false, false, true, 4>, n_items);
+        hipLaunchKernelGGL((k_bwd_wide<false, false, true, 4>), dim3(blocks), dim3(256), 0, stream, A, B,
+                           (const ViewDesc*)nullptr, items, ctr, 0u);
+    } else if (tile_items(cfg)) {
+        const int blocks = persistent_blocks(k_bwd_wide<false>, n_items);
         hipLaunchKernelGGL(k_bwd_wide<false>, dim3(blocks), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
-                           items, ctr);
+                           items, ctr, 0u);
     } else {
         const int blocks = persistent_blocks(k_bwd_pixel<true>, L.n_items);
         hipLaunchKernelGGL(k_bwd_pixel<true>, dim3(blocks), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
@@ -1320,7 +1649,7 @@ extern "C" bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_rende
     FrameArgs A;
     bgs_status st = check_frame(frame, cfg, A, "bgs_render_bwd_det");
     if (st != BGS_OK) return st;
-    if (!tile_items(cfg))
+    if (!(tile_items(cfg) && cfg->subtile == 16))
         return fail(BGS_EUNSUPPORTED, "bgs_render_bwd_det: needs BGS_BALANCED_PIXEL with subtile 16 "
                                       "(one wave per tile)");
     BGS_REQUIRE(P >= 0 && max_occ >= 0 && n_occ_host, "bgs_render_bwd_det: bad P, max_occ or n_occ_host");
@@ -1358,7 +1687,7 @@ extern "C" bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_rende
     auto* items = reinterpret_cast<const uint32_t*>(w + D.R.items);
     const int blocks = persistent_blocks(k_bwd_wide<false, true>, (uint32_t)A.n_tiles);
     hipLaunchKernelGGL((k_bwd_wide<false, true>), dim3(blocks), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
-                       items, ctr);
+                       items, ctr, 0u);
     BGS_HIP(hipGetLastError());
     auto* keys = reinterpret_cast<uint32_t*>(w + D.keys);
     auto* vals = reinterpret_cast<uint32_t*>(w + D.vals);
@@ -1534,7 +1863,7 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
                        fwd_wide ? 1 : 0, plan->d_tile_off, n_views, plan->d_items, plan->d_ctr);
     if (fwd_wide)
         hipLaunchKernelGGL((k_fwd_wide<true>), dim3(fblocks), dim3(256), 0, stream, F0, O0, plan->d_views,
-                           plan->d_items, plan->d_ctr);
+                           plan->d_items, plan->d_ctr, 0u);
     else
         hipLaunchKernelGGL((k_fwd_pixel<true, true>), dim3(fblocks), dim3(256), 0, stream, F0, O0, plan->d_views,
                            plan->d_items, plan->d_ctr);
@@ -1545,7 +1874,7 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
                        bwd_wide ? 1 : 0, plan->d_tile_off, n_views, plan->d_items, plan->d_ctr);
     if (bwd_wide)
         hipLaunchKernelGGL((k_bwd_wide<true>), dim3(bblocks), dim3(256), 0, stream, F0, B0, plan->d_views,
-                           plan->d_items, plan->d_ctr);
+                           plan->d_items, plan->d_ctr, 0u);
     else
         hipLaunchKernelGGL((k_bwd_pixel<true, true>), dim3(bblocks), dim3(256), 0, stream, F0, B0, plan->d_views,
                            plan->d_items, plan->d_ctr);

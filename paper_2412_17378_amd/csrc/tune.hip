@@ -1,10 +1,12 @@
 // Timing-based variant selection: the project's stand-in for the paper's
 // self-adaptive kernel selection (Sec. 4.4), which times the balanced and the
 // shared-memory static kernel on the current data and keeps the faster.  Here
-// every forward candidate (static, pixel-wise 8x8 raster / cost-ordered,
-// wave per 16x16 tile, hybrid, Gaussian-wise) and every backward
-// candidate (static, balanced 8x8 raster / cost-ordered, wave per 16x16
-// tile) is run on the caller's frame and timed with HIP events; the winners
+// every forward candidate (static, wave per tile dispatched statically,
+// pixel-wise 8x8 raster / cost-ordered, wave per 16x16 tile, wave per 32x32
+// block, hybrid, Gaussian-wise) and every backward candidate (static, wave
+// per tile dispatched statically, balanced 8x8 raster / cost-ordered, wave
+// per 16x16 tile, wave per 32x32 block) is run on the caller's frame and
+// timed with HIP events; the winners
 // are returned and cached in a
 // text file keyed by a workload signature (image size and log2 buckets of the
 // pair count and of the 50th / 99th / 100th percentile tile-list lengths), so
@@ -122,13 +124,15 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
         if (bwd_ms_out) *bwd_ms_out = e.bms;
         return BGS_OK;
     }
-    const int fwd_cands[][3] = {{BGS_STATIC, 16, BGS_ORDER_RASTER},       {BGS_BALANCED_PIXEL, 8, BGS_ORDER_RASTER},
-                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST},   {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST},
-                                {BGS_BALANCED_HYBRID, 8, BGS_ORDER_COST},  {BGS_BALANCED_GAUSS, 8, BGS_ORDER_COST}};
-    const int bwd_cands[][3] = {{BGS_STATIC, 16, BGS_ORDER_RASTER},
-                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_RASTER},
-                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST},
-                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST}};
+    const int fwd_cands[][3] = {{BGS_STATIC, 16, BGS_ORDER_RASTER},        {BGS_STATIC_WAVE, 16, BGS_ORDER_RASTER},
+                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_RASTER},  {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST},
+                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_RASTER}, {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST},
+                                {BGS_BALANCED_PIXEL, 32, BGS_ORDER_COST},   {BGS_BALANCED_HYBRID, 8, BGS_ORDER_COST},
+                                {BGS_BALANCED_GAUSS, 8, BGS_ORDER_COST}};
+    const int bwd_cands[][3] = {{BGS_STATIC, 16, BGS_ORDER_RASTER},         {BGS_STATIC_WAVE, 16, BGS_ORDER_RASTER},
+                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_RASTER},   {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST},
+                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_RASTER},  {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST},
+                                {BGS_BALANCED_PIXEL, 32, BGS_ORDER_COST}};
     hipEvent_t e0, e1;
     BGS_HIP(hipEventCreate(&e0));
     BGS_HIP(hipEventCreate(&e1));

@@ -60,15 +60,24 @@ def key_bits_for(n_tiles: int) -> int:
     return max(1, int(n_tiles - 1).bit_length())
 
 
+def poison_fwd(out: dict) -> None:
+    """Fill forward outputs with values no render writes (NaN, and -1 for
+    n_contrib), so that a pixel a kernel never wrote stays visible."""
+    for k, t in out.items():
+        t.fill_(-1 if k == "n_contrib" else float("nan"))
+
+
 class Rasterizer:
     def __init__(self, device: str = "cuda", reuse_pairs: bool = False, lists_method: str = "fused",
-                 binning: str = "square"):
+                 binning: str = "square", poison_outputs: bool = False):
         """reuse_pairs: the sorted lists of a prepared frame live in buffers
         that the next prepare() overwrites (no per-frame allocation); off by
         default so that several prepared frames can coexist.  binning:
         "square" (the 3-sigma square tile rule) or "ellipse" (exact
         ellipse-tile binning: shorter lists, the same renders; fused lists
-        only)."""
+        only).  poison_outputs: a debugging aid that fills the forward outputs
+        with NaN (n_contrib with -1) before every render, so a work item the
+        kernel drops cannot pass on values a buffer held before."""
         if binning not in ("square", "ellipse"):
             raise ValueError(f"unknown binning {binning!r}")
         B.lib()
@@ -78,6 +87,7 @@ class Rasterizer:
         self.reuse_pairs = reuse_pairs
         self.lists_method = lists_method
         self.binning = binning
+        self.poison_outputs = poison_outputs
 
     def _t(self, a, dtype=torch.float32):
         if isinstance(a, torch.Tensor):
@@ -186,6 +196,8 @@ class Rasterizer:
             out = dict(color=torch.empty(3, H, W, device=dev), alpha=torch.empty(H, W, device=dev),
                        depth=torch.empty(H, W, device=dev), final_T=torch.empty(H, W, device=dev),
                        n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
+        if self.poison_outputs:
+            poison_fwd(out)
         f = prep.frame()
         ws = self.ws.get("render", B.bgs_render_workspace_bytes(f, cfg))
         B.bgs_render_fwd(f, cfg, out["color"], out["alpha"], out["depth"], out["final_T"], out["n_contrib"], ws)
@@ -286,6 +298,12 @@ class BatchedPlan:
     def launch(self):
         B.bgs_plan_launch(self.handle)
 
+    def poison(self):
+        """Fill every view's forward outputs with NaN (n_contrib with -1), so
+        a pixel the next launch does not write stays visible."""
+        for out in self.outs:
+            poison_fwd(out)
+
     def close(self):
         if self.handle is not None:
             B.bgs_plan_destroy(self.handle)
@@ -314,6 +332,9 @@ class FrameStep:
     updated in place between steps).  Outputs: self.pr (projection),
     self.fwd (images), self.grads (gradients of the 2D splats).
 
+    poison_outputs: fill the forward outputs with NaN (n_contrib -1) at the
+    start of every step, also inside a captured graph (a debugging aid).
+
     list_cap: None builds whole tile lists.  An int K keeps the first K
     entries of each tile's list (bgs_tile_lists max_per_tile); "auto" picks K
     from one uncapped step (twice the deepest contributor, rounded up) and
@@ -323,7 +344,7 @@ class FrameStep:
     rebuilds with set_list_cap (larger K, or None) and runs the step again."""
 
     def __init__(self, cam, params: dict, sh_degree: int, dL_dcolor, fcfg: B.RenderCfg, bcfg: B.RenderCfg,
-                 binning: str = "square", headroom: float = 1.25, list_cap=None):
+                 binning: str = "square", headroom: float = 1.25, list_cap=None, poison_outputs: bool = False):
         if binning not in ("square", "ellipse"):
             raise ValueError(f"unknown binning {binning!r}")
         W, H = int(cam.width), int(cam.height)
@@ -331,6 +352,7 @@ class FrameStep:
             raise ValueError("FrameStep needs the fused list builder (tile grid too large)")
         self.cam, self.params, self.sh_degree = cam, params, int(sh_degree)
         self.W, self.H, self.binning = W, H, binning
+        self.poison_outputs = poison_outputs
         self.dL_dcolor = dL_dcolor.contiguous()
         dev = self.dL_dcolor.device
         P = params["means3D"].shape[0]
@@ -441,6 +463,8 @@ class FrameStep:
             B.bgs_queue_build(self.frame, self.fcfg, None, self.rws)
         mark(3)
         f = self.fwd
+        if self.poison_outputs:
+            poison_fwd(f)
         B.bgs_render_fwd(self.frame, self.fcfg_ready, f["color"], f["alpha"], f["depth"], f["final_T"],
                          f["n_contrib"], self.rws)
         mark(4)

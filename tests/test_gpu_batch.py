@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 def batch():
     from paper_2412_17378_amd import Rasterizer, make_cfg
     s = scenes.scene4(n=20000, n_views=6)
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     print(f"[batch] {len(s.cameras)} views P={s.P}", flush=True)
     preps = [rast.prepare_scene(s, v) for v in range(len(s.cameras))]
     rng = np.random.default_rng(4)
@@ -45,6 +45,7 @@ def test_plan_replays_match_eager(batch):
     try:
         for rep in range(3):
             print(f"[batch] replay {rep}", flush=True)
+            plan.poison()
             plan.launch()
             torch.cuda.synchronize()
             for v in range(len(preps)):
@@ -76,6 +77,7 @@ def test_plan_wide(batch):
     try:
         for rep in range(2):
             print(f"[batch-wide] replay {rep}", flush=True)
+            plan.poison()
             plan.launch()
             torch.cuda.synchronize()
             for v in range(len(preps)):
@@ -100,6 +102,7 @@ def test_plan_views_against_oracle(batch, sub):
     c = make_cfg("pixel", sub, "cost")
     plan = BatchedPlan(rast, preps, ups, c, c)
     try:
+        plan.poison()
         plan.launch()
         torch.cuda.synchronize()
         for v in range(len(preps)):

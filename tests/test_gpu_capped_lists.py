@@ -52,7 +52,7 @@ def test_capped_lists_are_prefixes(name):
     s = _scene(name)
     cam = s.cameras[0]
     W, H = cam.width, cam.height
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     pr = rast.project(cam, s.means3D, s.log_scales, s.quats, s.opacity, s.colors, s.sh_degree)
     torch.cuda.synchronize()
     ob = oracle.bin_sort_ranges(W, H, to_np(pr["means2D"]), to_np(pr["radius"]), to_np(pr["depth"]))
@@ -93,7 +93,7 @@ def test_capped_compact_lists_full_size():
     s = scenes.make("1")
     cam = s.cameras[0]
     W, H = cam.width, cam.height
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     pr = rast.project(cam, s.means3D, s.log_scales, s.quats, s.opacity, s.colors, s.sh_degree)
     torch.cuda.synchronize()
     whole_pl, whole_rg, n_whole = _lists(B, W, H, s.P, pr, 0, 160_000_000)
@@ -125,7 +125,7 @@ def test_capped_render_and_overflow_flag(name):
     s = _scene(name)
     cam = s.cameras[0]
     W, H = cam.width, cam.height
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     prep = rast.prepare_scene(s)
     pr = dict(means2D=prep.means2D, radius=prep.radius, depth=prep.depth, tiles_touched=prep.tiles_touched)
     torch.cuda.synchronize()
@@ -177,14 +177,14 @@ def test_frame_step_capped(name):
     fc = make_cfg("static", 16, "raster", tuple(s.bg))
     bc = make_cfg("pixel", 16, "cost", tuple(s.bg))
     print(f"[capped] frame step scene={name}", flush=True)
-    whole = FrameStep(cam, params, s.sh_degree, up, fc, bc)
+    whole = FrameStep(cam, params, s.sh_degree, up, fc, bc, poison_outputs=True)
     whole.run()
     torch.cuda.synchronize()
     ref_f = {k: v.clone() for k, v in whole.fwd.items()}
     ref_g = {k: v.clone() for k, v in whole.grads.items()}
     M = whole.n_pairs()
     del whole
-    capped = FrameStep(cam, params, s.sh_degree, up, fc, bc, list_cap="auto")
+    capped = FrameStep(cam, params, s.sh_degree, up, fc, bc, list_cap="auto", poison_outputs=True)
     K = capped.list_cap
     print(f"[capped] scene={name} K={K} M={M}", flush=True)
     assert K > 0 and capped.M_whole == M

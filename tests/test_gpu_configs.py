@@ -40,7 +40,7 @@ def test_config_crops(name, view):
     cam = s.cameras[view]
     W, H = cam.width, cam.height
     print(f"[config] scene={name} view={view} {W}x{H} P={s.P}", flush=True)
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     prep = rast.prepare_scene(s, view)
     print(f"[config] M={prep.n_pairs}", flush=True)
     host = dict(ranges=to_np(prep.ranges), point_list=to_np(prep.point_list), means2D=to_np(prep.means2D),

@@ -21,7 +21,7 @@ def _scene(name):
 @pytest.fixture(scope="module")
 def rast():
     from paper_2412_17378_amd import Rasterizer
-    return Rasterizer("cuda")
+    return Rasterizer("cuda", poison_outputs=True)
 
 
 def _upstream(s, orc_f, seed=5):

@@ -34,7 +34,7 @@ def _scene(name):
 @pytest.fixture(scope="module")
 def rasts():
     from paper_2412_17378_amd import Rasterizer
-    return Rasterizer("cuda"), Rasterizer("cuda", binning="ellipse")
+    return Rasterizer("cuda", poison_outputs=True), Rasterizer("cuda", binning="ellipse", poison_outputs=True)
 
 
 def _near_boundary(W, H, tile_id, g, m2, co):
@@ -126,8 +126,8 @@ def test_exact_lists_full_size():
     s = scenes.make("1")
     cam = s.cameras[0]
     print(f"[exact-bin] full size P={s.P}", flush=True)
-    sq = Rasterizer("cuda", reuse_pairs=False)
-    ex = Rasterizer("cuda", reuse_pairs=False, binning="ellipse")
+    sq = Rasterizer("cuda", reuse_pairs=False, poison_outputs=True)
+    ex = Rasterizer("cuda", reuse_pairs=False, binning="ellipse", poison_outputs=True)
     p_sq = sq.prepare_scene(s)
     p_ex = ex.prepare_scene(s)
     torch.cuda.synchronize()

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 def full():
     from paper_2412_17378_amd import Rasterizer, make_cfg
     s = scenes.make("1")
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     print(f"[full] scene 1 P={s.P}", flush=True)
     prep = rast.prepare_scene(s)
     cfg = make_cfg("pixel", 8, "cost")

@@ -48,7 +48,7 @@ def test_graph_step_replays(name, binning, cfg):
     params = _params(s, dev)
     up = torch.from_numpy(s.upstream()["dL_dcolor"]).to(dev)
     c = make_cfg(*cfg, tuple(s.bg))
-    step = FrameStep(cam, params, s.sh_degree, up, c, c, binning=binning)
+    step = FrameStep(cam, params, s.sh_degree, up, c, c, binning=binning, poison_outputs=True)
     step.run()
     torch.cuda.synchronize()
     assert step.n_pairs() <= step.capacity

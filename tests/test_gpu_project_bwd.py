@@ -68,7 +68,7 @@ def test_project_forward_parity_full_size(name):
     s = scenes.scene4(n_views=32) if name == "4" else scenes.make(name)
     cam = s.cameras[4 if name == "4" else 0]
     print(f"[proj-fwd] case={name} P={s.P}", flush=True)
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     g = rast.project(cam, s.means3D, s.log_scales, s.quats, s.opacity, s.colors, s.sh_degree)
     torch.cuda.synchronize()
     o = oracle.project(cam, s.means3D, s.log_scales, s.quats, s.opacity, s.colors, s.sh_degree)
@@ -88,7 +88,7 @@ def test_project_bwd_parity(name):
     s = _scene(name)
     cam = s.cameras[0]
     print(f"[proj-bwd] case={name} P={s.P}", flush=True)
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     rng = np.random.default_rng(5)
     P = s.P
     gm = rng.standard_normal((P, 2)).astype(np.float32)
@@ -111,7 +111,7 @@ def test_render3d_gradients(name):
     s = _scene(name)
     cam = s.cameras[0]
     print(f"[render3d] case={name} P={s.P}", flush=True)
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     dev = torch.device("cuda")
     params = [torch.from_numpy(np.ascontiguousarray(getattr(s, k))).to(dev).requires_grad_(True)
               for k in ("means3D", "log_scales", "quats", "opacity", "colors")]

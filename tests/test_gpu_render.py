@@ -19,13 +19,14 @@ pytestmark = pytest.mark.gpu
 
 # (variant, sub-tile, queue order)
 VARIANTS = [("static", 16, "raster"), ("pixel", 8, "raster"), ("pixel", 8, "cost"), ("pixel", 16, "cost"),
-            ("gauss", 8, "cost"), ("hybrid", 8, "cost")]
+            ("pixel", 16, "raster"), ("pixel", 32, "cost"), ("static_wave", 16, "raster"), ("gauss", 8, "cost"),
+            ("hybrid", 8, "cost")]
 
 
 @pytest.fixture(scope="module")
 def rast():
     from paper_2412_17378_amd import Rasterizer
-    return Rasterizer("cuda")
+    return Rasterizer("cuda", poison_outputs=True)
 
 
 def _scene(name):
@@ -57,15 +58,15 @@ def test_static_and_balanced_bit_identical(rast, name):
     print(f"[fwd-bitwise] case={name}", flush=True)
     prep = rast.prepare_scene(s)
     a = rast.render_fwd(prep, make_cfg("static"))
-    for sub in (8, 16):
-        b = rast.render_fwd(prep, make_cfg("pixel", sub, "cost"))
+    for v, sub in (("pixel", 8), ("pixel", 16), ("pixel", 32), ("static_wave", 16)):
+        b = rast.render_fwd(prep, make_cfg(v, sub, "cost"))
         torch.cuda.synchronize()
         for k in a:
-            assert torch.equal(a[k], b[k]), (k, sub)
+            assert torch.equal(a[k], b[k]), (k, v, sub)
 
 
 @pytest.mark.parametrize("name", ["tiny-60", "ragged", "0", "sh3"])
-@pytest.mark.parametrize("variant,sub,order", [v for v in VARIANTS if v[0] in ("static", "pixel")])
+@pytest.mark.parametrize("variant,sub,order", [v for v in VARIANTS if v[0] in ("static", "pixel", "static_wave")])
 def test_backward_parity(rast, name, variant, sub, order):
     from paper_2412_17378_amd import make_cfg
     s = _scene(name)

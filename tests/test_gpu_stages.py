@@ -31,7 +31,7 @@ def _scene(name):
 @pytest.fixture(scope="module")
 def rast():
     from paper_2412_17378_amd import Rasterizer
-    return Rasterizer("cuda")
+    return Rasterizer("cuda", poison_outputs=True)
 
 
 def _near_boundary(orc_pr, cam, tol=1e-4):

@@ -18,7 +18,7 @@ def test_fit_with_adaptive_selection():
     s = scenes.scene_tiny(n=300, seed=31, width=80, height=64, log_scale_mu=-2.5)
     cams = [_orbit_camera(80, 64, az=a, el=0.15 * (-1) ** k, radius=4.0, centre=(0.0, 0.0, 4.0))
             for k, a in enumerate((0.0, 0.5, -0.5, 1.0))]
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     dev = torch.device("cuda")
     true = {k: torch.from_numpy(np.ascontiguousarray(getattr(s, k))).to(dev)
             for k in ("means3D", "log_scales", "quats", "opacity", "colors")}

@@ -15,7 +15,7 @@ def test_autotune_choice_cache_and_parity(tmp_path):
     from paper_2412_17378_amd import Rasterizer, make_cfg
     from paper_2412_17378_amd import bgs as B
     s = scenes.make("0")
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     prep = rast.prepare_scene(s)
     g = torch.from_numpy(s.upstream()["dL_dcolor"]).cuda()
     cache = str(tmp_path / "tune.txt")
@@ -47,7 +47,7 @@ def test_adaptive_selector_retunes_on_interval():
     from paper_2412_17378_amd import Rasterizer, make_cfg
     from paper_2412_17378_amd.pipeline import AdaptiveSelector
     s = scenes.make("0")
-    rast = Rasterizer("cuda")
+    rast = Rasterizer("cuda", poison_outputs=True)
     prep = rast.prepare_scene(s)
     sel = AdaptiveSelector(rast, make_cfg("pixel", 8, "cost"), interval=2)
     calls = []

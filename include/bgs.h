@@ -330,6 +330,23 @@ bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cfg* cfg, flo
                           hipStream_t stream);
 
 /*
+ * bgs_render_fwd without a workspace, for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid hipMalloc): the same render, same arguments minus ws / ws_bytes,
+ * with the balanced variants' work queue kept in a device array inside the
+ * library (bgs_render_fwd_noalloc_max_bytes() bytes per device, held until
+ * the process ends; queues of up to 65 536 tiles).  Allocates nothing and
+ * builds the queue on every call (BGS_FLAG_QUEUE_READY is ignored).  A frame
+ * whose queue does not fit returns BGS_ECAPACITY before any work is queued.
+ * All calls on one device share that array: calls that overlap on one device
+ * (other streams, other threads) race and must be ordered by the caller.
+ */
+bgs_status bgs_render_fwd_noalloc(const bgs_frame* frame, const bgs_render_cfg* cfg, float* out_color,
+                                  float* out_alpha, float* out_depth, float* final_T, int32_t* n_contrib,
+                                  hipStream_t stream);
+size_t bgs_render_fwd_noalloc_max_bytes(void);
+
+/*
  * Backward render: the derivative of bgs_render_fwd for
  * L = <dL_dcolor, out_color> + <dL_dalpha, out_alpha> + <dL_ddepth, out_depth>
  * with every skip / stop decision of the forward held fixed.  Per pixel it

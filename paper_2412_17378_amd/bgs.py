@@ -91,6 +91,8 @@ def lib() -> C.CDLL:
             "bgs_render_workspace_bytes": ([_vp, _vp], _sz),
             "bgs_queue_build": ([_vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_render_fwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
+            "bgs_render_fwd_noalloc": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+            "bgs_render_fwd_noalloc_max_bytes": ([], _sz),
             "bgs_render_bwd": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_render_bwd_det_workspace_bytes": ([_vp, _i64, _i64], _sz),
             "bgs_render_bwd_det": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _sz,
@@ -115,7 +117,8 @@ def exported_symbols():
             "bgs_sort_workspace_bytes", "bgs_sort", "bgs_ranges", "bgs_tile_lists_workspace_bytes", "bgs_tile_lists",
             "bgs_tile_lists_exact", "bgs_render_workspace_bytes", "bgs_queue_build", "bgs_autotune", "bgs_plan_create", "bgs_plan_launch",
             "bgs_plan_destroy",
-            "bgs_render_fwd", "bgs_render_bwd", "bgs_render_bwd_det_workspace_bytes", "bgs_render_bwd_det"]
+            "bgs_render_fwd", "bgs_render_fwd_noalloc", "bgs_render_fwd_noalloc_max_bytes", "bgs_render_bwd",
+            "bgs_render_bwd_det_workspace_bytes", "bgs_render_bwd_det"]
 
 
 def _check(fn: str, st: int):
@@ -343,6 +346,24 @@ def bgs_render_fwd(frame: Frame, cfg: RenderCfg, out_color, out_alpha, out_depth
     _check("bgs_render_fwd", lib().bgs_render_fwd(C.byref(frame), C.byref(cfg), _ptr(out_color), _ptr(out_alpha),
                                                   _ptr(out_depth), _ptr(final_T), _ptr(n_contrib), _ptr(ws),
                                                   ws.numel(), _stream(stream)))
+
+
+def bgs_render_fwd_noalloc(frame: Frame, cfg: RenderCfg, out_color, out_alpha, out_depth, final_T, n_contrib,
+                           stream=None):
+    """bgs_render_fwd with the queue in the library's own device array (no
+    workspace, nothing allocated)."""
+    H, W = frame.height, frame.width
+    _expect(out_color, (3, H, W), torch.float32, "out_color")
+    for t, nm in ((out_alpha, "out_alpha"), (out_depth, "out_depth"), (final_T, "final_T")):
+        _expect(t, (H, W), torch.float32, nm)
+    _expect(n_contrib, (H, W), torch.int32, "n_contrib")
+    _check("bgs_render_fwd_noalloc",
+           lib().bgs_render_fwd_noalloc(C.byref(frame), C.byref(cfg), _ptr(out_color), _ptr(out_alpha),
+                                        _ptr(out_depth), _ptr(final_T), _ptr(n_contrib), _stream(stream)))
+
+
+def bgs_render_fwd_noalloc_max_bytes() -> int:
+    return int(lib().bgs_render_fwd_noalloc_max_bytes())
 
 
 def bgs_autotune(frame: Frame, base: RenderCfg, out: dict, dL_dcolor, grads: Optional[dict], ws,

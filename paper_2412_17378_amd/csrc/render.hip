@@ -23,6 +23,7 @@
 // (pixel, Gaussian) pair the forward spends ~22 VALU issues, the backward
 // ~45 plus the wave reduction.
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1444,6 +1445,61 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
     }
     BGS_HIP(hipGetLastError());
     return BGS_OK;
+}
+
+// ---------------------------------------------------------- no-alloc forward
+// bgs_render_fwd for callers that cannot allocate device memory: the work
+// queue (fetch counters, dealt items, tile costs) lives in this file-scope
+// device array instead of a caller workspace.  Each device holds its own copy
+// until the process ends; its address is looked up once per device.
+namespace bgs {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)3 << 19;  // 1.5 MiB: queues of up to 65 536 tiles
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on the current device.  In host code the
+// array's name is only a stand-in; kernels must get this address.
+static bgs_status scratch_address(void** out) {
+    int dev = 0;
+    BGS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(BGS_EUNSUPPORTED, "bgs_render_fwd_noalloc: device index >= 64");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        BGS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(BGS_EINTERNAL, "bgs_render_fwd_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BGS_OK;
+}
+
+}  // namespace bgs
+
+extern "C" size_t bgs_render_fwd_noalloc_max_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+extern "C" bgs_status bgs_render_fwd_noalloc(const bgs_frame* frame, const bgs_render_cfg* cfg, float* out_color,
+                                             float* out_alpha, float* out_depth, float* final_T,
+                                             int32_t* n_contrib, hipStream_t stream) {
+    FrameArgs A;
+    bgs_status st = check_frame(frame, cfg, A, "bgs_render_fwd_noalloc");
+    if (st != BGS_OK) return st;
+    const RenderLayout L = render_layout(A.n_tiles);
+    if (L.bytes > NOALLOC_SCRATCH_BYTES)
+        return fail(BGS_ECAPACITY, "bgs_render_fwd_noalloc: " + std::to_string(A.n_tiles) + " tiles need " +
+                                       std::to_string(L.bytes) + " bytes of queue state, more than the " +
+                                       std::to_string(NOALLOC_SCRATCH_BYTES) + " the library holds");
+    void* ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != BGS_OK) return st;
+    // the array keeps the previous call's queue: always build this call's
+    bgs_render_cfg c = *cfg;
+    c.flags &= ~BGS_FLAG_QUEUE_READY;
+    return bgs_render_fwd(frame, &c, out_color, out_alpha, out_depth, final_T, n_contrib, ws, L.bytes, stream);
 }
 
 extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cfg* cfg, const float* final_T,

@@ -21,10 +21,16 @@ list entry walked back to front in the backward (Sum n_contrib); both counts,
 and the number of entries that actually blend (the contributors), come from
 the oracle run once on the GPU's own lists, outside the timed region.
 
-Also reported: per-stage milliseconds (HIP events on the launch stream), the
-same steps with the static one-workgroup-per-tile kernels, the roofline
-fraction of the dominant kernel, and the FP64 oracle timed on the host over a
-bounded window of the same frame.
+Also reported: per-stage milliseconds (HIP events on the launch stream); the
+same step with the static one-workgroup-per-tile kernels (the paper's naive
+kernel) and with the wave-per-tile code dispatched grid-statically (the same
+per-tile code as the balanced kernels, no queue: the comparison that isolates
+the task pool); the step on whole (uncapped) tile lists; the roofline
+fraction of the dominant kernel; the FP64 oracle timed on the host over a
+bounded window of the same frame; and, each in its own block, the other
+workloads' steps with the autotuner's picks (the 3M-Gaussian SH-3 scene, the
+three training stages, a labelled hot-spot variant of the headline scene)
+and the batched 32-view plan.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -59,9 +65,6 @@ def bwd_ops(walked: int, contributors: int) -> float:
     return OPS_SKIP_TEST * walked + OPS_BWD_CONTRIB * contributors
 
 
-BYTES_PER_PAIR_SORT = 16.0    # read + write of a (u32 key, u32 value) pair
-BYTES_PER_PAIR_BIN = 8.0      # write of a (u32 key, u32 value) pair
-BYTES_PER_PAIR_LISTS = 4.0    # write of the u32 Gaussian id of a pair into its tile's list
 BYTES_PER_GAUSS_PROJECT = 104.0
 
 WORKLOAD_NAME = ("imbalanced 1080p: 1920x1080, 500k Gaussians (69% uniform, 30% clustered in 5% of the screen, "
@@ -91,57 +94,50 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched multi-view measurement (32 orbit views, one graph launch per step)")
     ap.add_argument("--batched-views", type=int, default=32)
+    ap.add_argument("--no-whole", action="store_true", help="skip the whole-list (uncapped) step")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (3M-Gaussian SH-3 scene, the three training stages)")
+    ap.add_argument("--no-hotspot", action="store_true", help="skip the supplementary hot-spot workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the measurement, run a plain 256 MiB device copy three times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "this build has no multi-GPU path.", file=sys.stderr)
-        sys.exit(2)
+class Workload:
+    """One synthetic frame on the GPU and the FrameStep machinery to time its
+    whole step (see the module docstring)."""
 
-    import numpy as np
-    import torch
+    def __init__(self, name, dev, list_cap):
+        import torch
+        from workloads import scenes
+        t_gen = time.time()
+        self.scene = scenes.make(name)
+        self.cam = self.scene.cameras[0]
+        self.H, self.W = self.cam.height, self.cam.width
+        self.dev = dev
+        self.list_cap = list_cap
+        self.bg = tuple(self.scene.bg)
+        self.g_in = {k: torch.from_numpy(getattr(self.scene, k)).to(dev).contiguous()
+                     for k in ("means3D", "log_scales", "quats", "opacity", "colors")}
+        self.dL_dcolor = torch.from_numpy(self.scene.upstream()["dL_dcolor"]).to(dev).contiguous()
+        print(f"[bench] scene {self.scene.name}: P={self.scene.P} {self.W}x{self.H} generated in "
+              f"{time.time() - t_gen:.1f}s", flush=True)
 
-    from paper_2412_17378_amd import bgs as B
-    from paper_2412_17378_amd.pipeline import FrameStep
-    from workloads import scenes
+    def make_step(self, fcfg, bcfg, binning="square", list_cap="default"):
+        from paper_2412_17378_amd.pipeline import FrameStep
+        cap = self.list_cap if list_cap == "default" else list_cap
+        return FrameStep(self.cam, self.g_in, self.scene.sh_degree, self.dL_dcolor, fcfg, bcfg, binning=binning,
+                         list_cap=cap)
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    t_gen = time.time()
-    scene = scenes.make(args.scene)
-    cam = scene.cameras[0]
-    H, W = cam.height, cam.width
-    print(f"[bench] scene {scene.name}: P={scene.P} {W}x{H} generated in {time.time() - t_gen:.1f}s", flush=True)
-
-    g_in = {k: torch.from_numpy(getattr(scene, k)).to(dev).contiguous()
-            for k in ("means3D", "log_scales", "quats", "opacity", "colors")}
-    dL_dcolor = torch.from_numpy(scene.upstream()["dL_dcolor"]).to(dev).contiguous()
-    stream = torch.cuda.current_stream()
-
-    list_cap = None if args.list_cap == "none" else ("auto" if args.list_cap == "auto" else int(args.list_cap))
-
-    def make_step(fcfg, bcfg, binning="square"):
-        """A FrameStep (every buffer up front, no host sync inside a step) and the
-        state the rest of the benchmark reads."""
-        st = FrameStep(cam, g_in, scene.sh_degree, dL_dcolor, fcfg, bcfg, binning=binning, list_cap=list_cap)
-        state = {"step": st, "frame": st.frame, "rws": st.rws}
-        return st, state, st.pr, st.fwd, st.grads
-
-    def run(fcfg, bcfg, steps, warmup, binning="square", graph=True):
+    def run(self, fcfg, bcfg, steps, warmup, binning="square", graph=True, list_cap="default"):
         """Eager steps with HIP events at the stage boundaries, then (graph) the
         same step captured once and replayed: ms per step of both, and a check
         that the replays reproduce the eager step's outputs."""
-        st, state, pr, fwd, grads = make_step(fcfg, bcfg, binning)
+        import numpy as np
+        import torch
+        stream = torch.cuda.current_stream()
+        st = self.make_step(fcfg, bcfg, binning, list_cap)
         for _ in range(warmup):
             st.run()
         torch.cuda.synchronize()
@@ -156,18 +152,15 @@ def main():
             raise RuntimeError("pair capacity exceeded")
         if st.overflowed():
             raise RuntimeError("a pixel ran off a capped tile list: rerun with a larger --list-cap or 'none'")
-        state["M"] = M
-        state["M_whole"] = st.M_whole
-        state["list_cap"] = st.list_cap
-        state["whole_list_len"] = st.whole_list_len.cpu().numpy()
-        # capped lists sit at fixed per-tile slots: hand over the point list up to the last range end
-        state["frame_bufs"] = (st.ranges, st.point_list[:int(st.ranges[:, 1].max().item())])
         names = ["project", "lists", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"]
         stages = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
                   for i, n in enumerate(names)}
-        ms_eager = (t1 - t0) * 1e3 / steps
-        state["eager_ms"] = ms_eager
+        r = {"step": st, "M": M, "M_whole": st.M_whole, "list_cap": st.list_cap, "stages": stages,
+             "eager_ms": (t1 - t0) * 1e3 / steps, "whole_list_len": st.whole_list_len.cpu().numpy(),
+             # capped lists sit at fixed per-tile slots: hand over the point list up to the last range end
+             "frame_bufs": (st.ranges, st.point_list[:int(st.ranges[:, 1].max().item())])}
         if graph:
+            fwd, grads = st.fwd, st.grads
             ref_f = {k: v.clone() for k, v in fwd.items()}
             ref_g = {k: v.clone() for k, v in grads.items()}
             g = st.capture()
@@ -184,50 +177,162 @@ def main():
             same_f = all(torch.equal(ref_f[k], fwd[k]) for k in fwd)
             gerr = max(float((ref_g[k] - grads[k]).abs().max()) / (float(ref_g[k].abs().max()) + 1e-30)
                        for k in grads)
-            state["graph_ms"] = (t1 - t0) * 1e3 / steps
-            state["graph_check"] = {"images_equal_eager": same_f, "max_rel_grad_diff_eager": gerr}
+            r["graph_ms"] = (t1 - t0) * 1e3 / steps
+            r["graph_check"] = {"images_equal_eager": same_f, "max_rel_grad_diff_eager": gerr}
             if not same_f or gerr > 1e-4:
-                raise RuntimeError(f"graph replay differs from the eager step: {state['graph_check']}")
+                raise RuntimeError(f"graph replay differs from the eager step: {r['graph_check']}")
             del g
-        return ms_eager, stages, state, pr, fwd, grads
+        r["ms"] = r.get("graph_ms", r["eager_ms"])
+        return r
 
-    bg = tuple(scene.bg)
+    def autotune(self):
+        """bgs_autotune on this frame (capped lists as the timed step builds
+        them): the fastest forward and backward variants and their times."""
+        import torch
+        from paper_2412_17378_amd import bgs as B
+        default = B.make_cfg("pixel", 16, "cost", self.bg)
+        st = self.make_step(default, default)
+        st.run()
+        torch.cuda.synchronize()
+        fcfg, bcfg, fms, bms = B.bgs_autotune(st.frame, default, st.fwd, self.dL_dcolor, st.grads, st.rws)
+        del st
+        info = {"forward": B.cfg_name(fcfg), "backward": B.cfg_name(bcfg), "forward_ms": fms, "backward_ms": bms}
+        print(f"[bench] autotune {self.scene.name}: forward {info['forward']} ({fms:.3f} ms), backward "
+              f"{info['backward']} ({bms:.3f} ms)", flush=True)
+        return fcfg, bcfg, info
+
+    def gpu_blends(self, st):
+        """Forward blends (entries examined per pixel, from the wave-per-tile
+        kernel's work counter) and backward blends (sum of n_contrib) of a
+        step's frame, counted on the GPU."""
+        import torch
+        from paper_2412_17378_amd import bgs as B
+        n = torch.empty(self.H, self.W, dtype=torch.int32, device=self.dev)
+        c = B.make_cfg("pixel", 16, "cost", self.bg)
+        c.n_examined = n.data_ptr()
+        if st.list_cap:
+            c.list_cap = st.list_cap
+        f = {k: torch.empty_like(v) for k, v in st.fwd.items()}
+        B.bgs_render_fwd(st.frame, c, f["color"], f["alpha"], f["depth"], f["final_T"], f["n_contrib"], st.rws)
+        torch.cuda.synchronize()
+        return int(n.to(torch.int64).sum()), int(f["n_contrib"].to(torch.int64).sum()), n
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def same_code_comparison(wl, fcfg_bal, bcfg_bal, steps, warmup, B, balanced_run=None):
+    """The step with the wave-per-tile kernels taken from the task pool against
+    the same kernels dispatched grid-statically (BGS_STATIC_WAVE): identical
+    per-tile code, so the ratio isolates the queue's scheduling."""
+    static_wave = B.make_cfg("static_wave", 16, "raster", wl.bg)
+    rs = wl.run(static_wave, static_wave, steps, warmup)
+    rb = balanced_run if balanced_run is not None else wl.run(fcfg_bal, bcfg_bal, steps, warmup)
+    out = {"balanced": {"forward": B.cfg_name(fcfg_bal), "backward": B.cfg_name(bcfg_bal), "ms_per_step": rb["ms"],
+                        "render_fwd_ms": rb["stages"]["render_fwd"], "render_bwd_ms": rb["stages"]["render_bwd"]},
+           "static_same_code": {"forward": B.cfg_name(static_wave), "backward": B.cfg_name(static_wave),
+                                "ms_per_step": rs["ms"], "render_fwd_ms": rs["stages"]["render_fwd"],
+                                "render_bwd_ms": rs["stages"]["render_bwd"]}}
+    out["queue_speedup"] = {"render_fwd": rs["stages"]["render_fwd"] / rb["stages"]["render_fwd"],
+                            "render_bwd": rs["stages"]["render_bwd"] / rb["stages"]["render_bwd"],
+                            "step": rs["ms"] / rb["ms"]}
+    print(f"[bench] {wl.scene.name} same code: queue fwd {rb['stages']['render_fwd']:.3f} / bwd "
+          f"{rb['stages']['render_bwd']:.3f} ms against grid-static fwd {rs['stages']['render_fwd']:.3f} / bwd "
+          f"{rs['stages']['render_bwd']:.3f} ms", flush=True)
+    del rs
+    return out
+
+
+def config_block(name, dev, steps, warmup, B, compare_static=False):
+    """Another workload's step, autotuned on its own frame: the tuner's picks,
+    ms per step, stage times and blends (GPU work counters)."""
+    import torch
+    wl = Workload(name, dev, "auto")
+    fcfg, bcfg, tuned = wl.autotune()
+    r = wl.run(fcfg, bcfg, steps, warmup)
+    fb, bb, nex = wl.gpu_blends(r["step"])
+    out = {"P": wl.scene.P, "width": wl.W, "height": wl.H, "sh_degree": wl.scene.sh_degree, "seed": wl.scene.seed,
+           "autotune": tuned, "n_pairs": r["M_whole"], "list_cap": r["list_cap"], "n_pairs_stored": r["M"],
+           "ms_per_step": r["ms"], "eager_ms_per_step": r["eager_ms"], "stages_ms": r["stages"],
+           "blends": {"fwd": fb, "bwd": bb, "counted_by": "GPU work counters"},
+           "value": (fb + bb) / (r["ms"] * 1e-3), "unit": "blends/s",
+           "workload_stats": workload_stats(nex.cpu().numpy(), r["whole_list_len"])}
+    del nex
+    print(f"[bench] {name}: {r['ms']:.3f} ms/step ({tuned['forward']} / {tuned['backward']}), "
+          f"{out['value']:.3e} blends/s, stages " + ", ".join(f"{k}={v:.3f}" for k, v in r["stages"].items()),
+          flush=True)
+    if compare_static:
+        naive = B.make_cfg("static", 16, "raster", wl.bg)
+        rn = wl.run(naive, naive, steps, warmup)
+        out["static"] = {"ms_per_step": rn["ms"], "render_fwd_ms": rn["stages"]["render_fwd"],
+                         "render_bwd_ms": rn["stages"]["render_bwd"]}
+        del rn
+        bal_f = B.make_cfg("pixel", 16, "cost", wl.bg)
+        out["same_code"] = same_code_comparison(wl, bal_f, bal_f, steps, warmup, B)
+    del r, wl
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "this build has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2412_17378_amd import bgs as B
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    list_cap = None if args.list_cap == "none" else ("auto" if args.list_cap == "auto" else int(args.list_cap))
+    wl = Workload(args.scene, dev, list_cap)
+    scene, W, H, bg = wl.scene, wl.W, wl.H, wl.bg
     tuned = None
     if args.variant == "auto":
-        # one step with a default configuration builds the frame, then the autotuner picks
-        default = B.make_cfg("pixel", 8, "cost", bg)
-        step0, st0, _, fwd0, grads0 = make_step(default, default)
-        step0.run()
-        torch.cuda.synchronize()
-        fcfg, bcfg, fms, bms = B.bgs_autotune(st0["frame"], default, fwd0, dL_dcolor, grads0, st0["rws"])
-        tuned = {"forward": B.cfg_name(fcfg), "backward": B.cfg_name(bcfg), "forward_ms": fms, "backward_ms": bms}
-        print(f"[bench] autotune: forward {tuned['forward']} ({fms:.3f} ms), backward {tuned['backward']} "
-              f"({bms:.3f} ms)", flush=True)
+        fcfg, bcfg, tuned = wl.autotune()
     else:
         fcfg = bcfg = B.make_cfg(args.variant, args.subtile, args.order, bg)
     print(f"[bench] timed run: forward {B.cfg_name(fcfg)} backward {B.cfg_name(bcfg)} warmup={args.warmup} "
           f"steps={args.steps}", flush=True)
-    ms_eager, stages, state, pr, fwd, grads = run(fcfg, bcfg, args.steps, args.warmup)
-    ms_step = state["graph_ms"]  # the step as one hipGraph launch; eager (launch by launch) reported beside it
-    graph_check = state["graph_check"]
-    M = state["M"]
-    state_M_whole, list_cap_used = state["M_whole"], state["list_cap"]
+    main_run = wl.run(fcfg, bcfg, args.steps, args.warmup)
+    st = main_run["step"]
+    pr, fwd, grads, stages = st.pr, st.fwd, st.grads, main_run["stages"]
+    ms_step, ms_eager = main_run["graph_ms"], main_run["eager_ms"]
+    graph_check = main_run["graph_check"]
+    M, state_M_whole, list_cap_used = main_run["M"], main_run["M_whole"], main_run["list_cap"]
     print(f"[bench] balanced: {ms_step:.3f} ms/step as one graph launch ({ms_eager:.3f} launched eagerly), "
-          f"M={state['M_whole']} (stored {M}, list cap {state['list_cap']}), "
+          f"M={state_M_whole} (stored {M}, list cap {list_cap_used}), "
           f"eager stages " + ", ".join(f"{k}={v:.3f}" for k, v in stages.items()), flush=True)
 
     # algorithmic blend counts: the oracle over the GPU's own lists (untimed)
     import oracle
     t_o = time.time()
-    ranges_np = pr_ranges = state["frame_bufs"][0].cpu().numpy()
-    pl_np = state["frame_bufs"][1].cpu().numpy()
+    ranges_np = main_run["frame_bufs"][0].cpu().numpy()
+    pl_np = main_run["frame_bufs"][1].cpu().numpy()
     m2, co = pr["means2D"].cpu().numpy(), pr["conic_opacity"].cpu().numpy()
     rgb, dep = pr["rgb"].cpu().numpy(), pr["depth"].cpu().numpy()
     ofwd = oracle.render_fwd(W, H, ranges_np, pl_np, m2, co, rgb, dep, bg=scene.bg)
     fwd_blends = int(ofwd["blends"])
     bwd_blends = int(ofwd["n_contrib"].astype(np.int64).sum())
     contributors = int(ofwd["contributors"])
-    wstats = workload_stats(ofwd["n_examined"], state["whole_list_len"])
+    wstats = workload_stats(ofwd["n_examined"], main_run["whole_list_len"])
     n_contrib_gpu = fwd["n_contrib"].cpu().numpy()
     agree = float(np.mean(n_contrib_gpu == ofwd["n_contrib"]))
     print(f"[bench] blends fwd={fwd_blends} bwd={bwd_blends} contributors={contributors} "
@@ -236,15 +341,35 @@ def main():
     del ofwd
 
     static = None
+    same_code = None
     if not args.no_static:
         print("[bench] static run", flush=True)
         scfg = B.make_cfg("static", 16, "raster", bg)
-        ms_se, st_s, state_s, _, _, _ = run(scfg, scfg, max(3, args.steps // 2), 2)
-        ms_s = state_s["graph_ms"]
-        static = dict(ms_per_step=ms_s, eager_ms_per_step=ms_se, render_fwd_ms=st_s["render_fwd"],
-                      render_bwd_ms=st_s["render_bwd"])
-        print(f"[bench] static: {ms_s:.3f} ms/step as one graph launch ({ms_se:.3f} eagerly), "
-              f"fwd {st_s['render_fwd']:.3f} ms, bwd {st_s['render_bwd']:.3f} ms", flush=True)
+        rs = wl.run(scfg, scfg, max(3, args.steps // 2), 2)
+        static = dict(ms_per_step=rs["ms"], eager_ms_per_step=rs["eager_ms"], render_fwd_ms=rs["stages"]["render_fwd"],
+                      render_bwd_ms=rs["stages"]["render_bwd"])
+        del rs
+        print(f"[bench] static: {static['ms_per_step']:.3f} ms/step as one graph launch "
+              f"({static['eager_ms_per_step']:.3f} eagerly), fwd {static['render_fwd_ms']:.3f} ms, "
+              f"bwd {static['render_bwd_ms']:.3f} ms", flush=True)
+        # the queue against grid-static dispatch of the same wave-per-tile code
+        wide_f = fcfg if (fcfg.variant == B.BALANCED_PIXEL and fcfg.subtile == 16) else \
+            B.make_cfg("pixel", 16, "raster", bg)
+        wide_b = bcfg if (bcfg.variant == B.BALANCED_PIXEL and bcfg.subtile == 16) else \
+            B.make_cfg("pixel", 16, "cost", bg)
+        same = main_run if (wide_f is fcfg and wide_b is bcfg) else None
+        same_code = same_code_comparison(wl, wide_f, wide_b, max(3, args.steps // 2), 2, B, same)
+
+    whole = None
+    if list_cap_used and not args.no_whole:
+        print("[bench] whole-list run", flush=True)
+        rw = wl.run(fcfg, bcfg, max(3, args.steps // 2), 2, list_cap=None)
+        whole = {"ms_per_step": rw["ms"], "eager_ms_per_step": rw["eager_ms"], "stages_ms": rw["stages"],
+                 "n_pairs": rw["M"], "value": (fwd_blends + bwd_blends) / (rw["ms"] * 1e-3),
+                 "note": "the same step on whole (uncapped) tile lists, same kernels; no list cap to discover"}
+        del rw
+        print(f"[bench] whole lists: {whole['ms_per_step']:.3f} ms/step, stages " +
+              ", ".join(f"{k}={v:.3f}" for k, v in whole["stages_ms"].items()), flush=True)
 
     # the same step with exact ellipse-tile binning: identical images from shorter lists.  Its blends
     # are the entries its own pixel loops examine (fewer: the removed entries were all skipped), so
@@ -252,9 +377,9 @@ def main():
     exact = None
     if not args.no_exact:
         print("[bench] exact ellipse-tile binning run", flush=True)
-        ms_ee, st_e, state_e, _, fwd_e, _ = run(fcfg, bcfg, args.steps, args.warmup, binning="ellipse")
-        ms_e = state_e["graph_ms"]
-        rg_e, pl_e = state_e["frame_bufs"][0].cpu().numpy(), state_e["frame_bufs"][1].cpu().numpy()
+        re_ = wl.run(fcfg, bcfg, args.steps, args.warmup, binning="ellipse")
+        st_e, ms_e, ms_ee, fwd_e = re_["stages"], re_["ms"], re_["eager_ms"], re_["step"].fwd
+        rg_e, pl_e = re_["frame_bufs"][0].cpu().numpy(), re_["frame_bufs"][1].cpu().numpy()
         of_e = oracle.render_fwd(W, H, rg_e, pl_e, m2, co, rgb, dep, bg=scene.bg)
         fb_e, bb_e = int(of_e["blends"]), int(of_e["n_contrib"].astype(np.int64).sum())
         cb_e = int(of_e["contributors"])
@@ -266,27 +391,29 @@ def main():
             v["frac"] = v["achieved"] / v["peak"]
         same = all(torch.equal(fwd[k], fwd_e[k]) for k in ("color", "alpha", "depth", "final_T"))
         diff = max(float((fwd[k] - fwd_e[k]).abs().max()) for k in ("color", "alpha", "depth", "final_T"))
-        exact = {"n_pairs": state_e["M_whole"], "n_pairs_stored": state_e["M"], "list_cap": state_e["list_cap"],
+        exact = {"n_pairs": re_["M_whole"], "n_pairs_stored": re_["M"], "list_cap": re_["list_cap"],
                  "ms_per_step": ms_e, "eager_ms_per_step": ms_ee, "stages_ms": st_e,
                  "blends": {"fwd": fb_e, "bwd": bb_e, "contributors": cb_e}, "render_roofline": roof_e,
                  "value": (fb_e + bb_e) / (ms_e * 1e-3),
                  "unit": "examined blends/s", "images_equal_square_rule": same, "max_abs_image_diff": diff,
                  "n_contrib_agreement_oracle": agree_e, "step_speedup_vs_square_rule": ms_step / ms_e}
-        print(f"[bench] exact binning: {ms_e:.3f} ms/step ({ms_step / ms_e:.2f}x), M={state_e['M_whole']} "
-              f"(stored {state_e['M']}, cap {state_e['list_cap']}), stages " +
+        print(f"[bench] exact binning: {ms_e:.3f} ms/step ({ms_step / ms_e:.2f}x), M={re_['M_whole']} "
+              f"(stored {re_['M']}, cap {re_['list_cap']}), stages " +
               ", ".join(f"{k}={v:.3f}" for k, v in st_e.items()) +
               f"; blends fwd={fb_e} bwd={bb_e}; images equal: {same}", flush=True)
+        del re_, fwd_e
 
     # supplementary: the projection's derivative on the same frame (the step before the hot path in a
     # training step; not part of ms_per_step)
     def project_bwd_ms():
         P = scene.P
+        g_in = wl.g_in
         out = dict(means3D=torch.empty(P, 3, device=dev), log_scales=torch.empty(P, 3, device=dev),
                    quats=torch.empty(P, 4, device=dev), opacity=torch.empty(P, device=dev),
                    colors=torch.empty_like(g_in["colors"]))
-        run1 = lambda: B.bgs_project_bwd(cam, g_in["means3D"], g_in["log_scales"], g_in["quats"], g_in["colors"],
-                                         scene.sh_degree, grads["means2D"], grads["conic_opacity"], grads["rgb"],
-                                         grads["depth"], out)
+        run1 = lambda: B.bgs_project_bwd(wl.cam, g_in["means3D"], g_in["log_scales"], g_in["quats"],
+                                         g_in["colors"], scene.sh_degree, grads["means2D"], grads["conic_opacity"],
+                                         grads["rgb"], grads["depth"], out)
         run1()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -302,7 +429,6 @@ def main():
 
     # supplementary: the deterministic-order backward on the same frame (one host sync per call, included)
     def det_bwd():
-        st = state["step"]
         dcfg = B.make_cfg("pixel", 16, "cost", bg)
         P = scene.P
         f = st.fwd
@@ -311,8 +437,8 @@ def main():
         for _ in range(2):
             ws = torch.empty(B.bgs_render_bwd_det_workspace_bytes(st.frame, P, cap), dtype=torch.uint8, device=dev)
             try:
-                B.bgs_render_bwd_det(st.frame, dcfg, P, f["final_T"], f["n_contrib"], dL_dcolor, None, None, *gd, cap,
-                                     ws)
+                B.bgs_render_bwd_det(st.frame, dcfg, P, f["final_T"], f["n_contrib"], wl.dL_dcolor, None, None, *gd,
+                                     cap, ws)
                 break
             except B.BgsError as e:
                 if e.status != B.BGS_ECAPACITY:
@@ -324,7 +450,7 @@ def main():
         for r in range(runs):
             for g in gd:
                 g.zero_()
-            K = B.bgs_render_bwd_det(st.frame, dcfg, P, f["final_T"], f["n_contrib"], dL_dcolor, None, None, *gd,
+            K = B.bgs_render_bwd_det(st.frame, dcfg, P, f["final_T"], f["n_contrib"], wl.dL_dcolor, None, None, *gd,
                                      cap, ws)
             if r < 2:
                 torch.cuda.synchronize()
@@ -341,7 +467,7 @@ def main():
 
     # per-CU load balance of the render kernels: one traced run of each (untimed)
     def cu_balance(fcfg_, bcfg_):
-        frame, rws = state["frame"], state["rws"]
+        frame, rws = st.frame, st.rws
         out = {}
         for name, c in (("render_fwd", fcfg_), ("render_bwd", bcfg_)):
             cap = 4 * max(B.n_tiles(W, H), 16384)
@@ -349,21 +475,26 @@ def main():
             tc = B.make_cfg(c.variant, c.subtile, c.order, bg)
             tc.wg_trace, tc.wg_trace_cap = rec.data_ptr(), cap
             if name == "render_fwd":
+                tc.list_cap = st.list_cap
                 B.bgs_render_fwd(frame, tc, fwd["color"], fwd["alpha"], fwd["depth"], fwd["final_T"],
                                  fwd["n_contrib"], rws)
             else:
-                B.bgs_render_bwd(frame, tc, fwd["final_T"], fwd["n_contrib"], dL_dcolor, None, None,
+                B.bgs_render_bwd(frame, tc, fwd["final_T"], fwd["n_contrib"], wl.dL_dcolor, None, None,
                                  grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], rws)
             torch.cuda.synchronize()
             out[name] = balance_stats(rec.cpu().numpy())
         return out
 
+    naive_cfg, sw_cfg = B.make_cfg("static", 16, "raster", bg), B.make_cfg("static_wave", 16, "raster", bg)
     balance = cu_balance(fcfg, bcfg)
-    balance_static = cu_balance(B.make_cfg("static", 16, "raster", bg), B.make_cfg("static", 16, "raster", bg))
+    balance_static = cu_balance(naive_cfg, naive_cfg)
+    balance_static_wave = cu_balance(sw_cfg, sw_cfg)
     for k in balance:
         print(f"[bench] {k} per-CU finish spread: tuned {balance[k]['spread']:.3f} "
               f"(CU busy {balance[k]['mean_busy']:.3f}), static {balance_static[k]['spread']:.3f} "
-              f"(CU busy {balance_static[k]['mean_busy']:.3f})", flush=True)
+              f"(CU busy {balance_static[k]['mean_busy']:.3f}), grid-static same code "
+              f"{balance_static_wave[k]['spread']:.3f} (CU busy {balance_static_wave[k]['mean_busy']:.3f})",
+              flush=True)
 
     # roofline of the dominant kernel
     def roof(stage):
@@ -374,19 +505,13 @@ def main():
         if stage == "render_bwd":
             return dict(bound="alu", achieved=bwd_ops(bwd_blends, contributors) / t / 1e12, peak=PEAK_VALU_TOPS,
                         unit="TOP/s")
-        if stage == "sort":
-            return dict(bound="hbm", achieved=M * BYTES_PER_PAIR_SORT / t / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
-        if stage == "bin":
-            return dict(bound="hbm", achieved=M * BYTES_PER_PAIR_BIN / t / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
-        if stage == "lists":
-            return dict(bound="hbm", achieved=M * BYTES_PER_PAIR_LISTS / t / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
         if stage == "project":
             return dict(bound="hbm", achieved=scene.P * BYTES_PER_GAUSS_PROJECT / t / 1e9, peak=PEAK_HBM_GBS,
                         unit="GB/s")
         return None
 
-    # the dominant single-kernel stage of the step (the list build is several kernels; it is reported in
-    # stage_roofline instead)
+    # the dominant single-kernel stage of the step (the list build is several kernels; its time is in
+    # stages_ms)
     single = {k: stages[k] for k in ("project", "render_fwd", "render_bwd")}
     dom = max(single, key=single.get)
     rl = roof(dom)
@@ -409,10 +534,35 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, [int(x) for x in args.cpu_window.split(",")])
 
+    del st, pr, fwd, grads, main_run, wl
+    torch.cuda.empty_cache()
+
+    configs = {}
+    if not args.no_configs:
+        for name in ("2", "3-early", "3-mid", "3-late"):
+            try:
+                configs[name] = config_block(name, dev, max(3, args.steps // 2), 2, B)
+            except Exception as e:  # reported, never fatal for the headline line
+                configs[name] = {"error": f"{type(e).__name__}: {e}"}
+                print(f"[bench] config {name} failed: {configs[name]['error']}", flush=True)
+            torch.cuda.empty_cache()
+    selection = [{"stage": k, "forward": configs[k]["autotune"]["forward"],
+                  "backward": configs[k]["autotune"]["backward"]}
+                 for k in ("3-early", "3-mid", "3-late") if "autotune" in configs.get(k, {})]
+
+    hotspot = None
+    if not args.no_hotspot:
+        try:
+            hotspot = config_block("1-hotspot", dev, max(3, args.steps // 2), 2, B, compare_static=True)
+            hotspot["label"] = ("supplementary stress variant of the headline scene with a late hot spot (tail ratio "
+                                "R > 1); reported beside it, never instead")
+        except Exception as e:
+            hotspot = {"error": f"{type(e).__name__}: {e}"}
+            print(f"[bench] hot-spot run failed: {hotspot['error']}", flush=True)
+        torch.cuda.empty_cache()
+
     batched = None
     if not args.no_batched:
-        del state, pr, fwd, grads
-        torch.cuda.empty_cache()
         try:
             batched = batched_views(args, dev)
         except Exception as e:  # reported, never fatal for the headline line
@@ -421,6 +571,7 @@ def main():
 
     value = (fwd_blends + bwd_blends) / (ms_step * 1e-3)
     render_ms = stages["render_fwd"] + stages["render_bwd"]
+    fwd_same_kernel = fcfg.variant == B.STATIC
     out = {
         "metric": "Gaussian-pixel blends/s (fwd+bwd) over the whole render path",
         "value": value,
@@ -440,7 +591,8 @@ def main():
                    "width": W, "height": H, "n_pairs": state_M_whole, "forward": B.cfg_name(fcfg),
                    "backward": B.cfg_name(bcfg),
                    "lists": ("fused, whole" if not list_cap_used else
-                             f"fused, capped at {list_cap_used} entries per tile (no pixel ran off a list)"),
+                             f"fused, capped at {list_cap_used} entries per tile (K chosen from a whole-list step of "
+                             f"this frame before the timed steps; no pixel ran off a list)"),
                    "n_pairs_stored": M},
         "autotune": tuned,
         "workload_stats": wstats,
@@ -453,14 +605,21 @@ def main():
         "render_blends_per_s": (fwd_blends + bwd_blends) / (render_ms * 1e-3),
         "render_roofline": render_roofs,
         "stage_roofline": stage_roofs,
+        "whole_lists": whole,
         "static": static,
+        "same_code": same_code,
         "exact_binning": exact,
-        "cu_balance": {"tuned": balance, "static": balance_static},
+        "cu_balance": {"tuned": balance, "static": balance_static, "static_same_code": balance_static_wave},
         "project_bwd_ms": pbwd_ms,
         "deterministic_backward": det,
+        "configs": configs,
+        "selection": selection,
+        "hotspot": hotspot,
         "batched_views": batched,
         "speedup_vs_static": (None if static is None else
-                              {"render_fwd": static["render_fwd_ms"] / stages["render_fwd"],
+                              {"render_fwd": 1.0 if fwd_same_kernel else static["render_fwd_ms"] / stages["render_fwd"],
+                               "render_fwd_note": ("the tuner chose the static kernel itself: same kernel"
+                                                   if fwd_same_kernel else "tuned forward against the static kernel"),
                                "render_bwd": static["render_bwd_ms"] / stages["render_bwd"],
                                "render_fwd_bwd": (static["render_fwd_ms"] + static["render_bwd_ms"]) / render_ms,
                                "step": static["ms_per_step"] / ms_step}),
@@ -590,7 +749,7 @@ def kernel_of(stage, cfg, B):
     """Name of the kernel a stage launches for a render configuration."""
     if stage == "project":
         return "k_project"
-    wide = cfg.variant == B.BALANCED_PIXEL and cfg.subtile == 16
+    wide = (cfg.variant == B.BALANCED_PIXEL and cfg.subtile in (16, 32)) or cfg.variant == B.STATIC_WAVE
     if stage == "render_fwd":
         if cfg.variant == B.STATIC:
             return "k_fwd_static"
@@ -685,6 +844,7 @@ def cpu_baseline(scene, window_px):
     blends = f["blends"] + bw["blends"]
     print(f"[bench] cpu oracle: {blends} blends in {dt:.1f}s on {oracle.num_threads()} threads", flush=True)
     return {"value": blends / dt, "unit": "blends/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"pixel window {x0},{y0}-{x1},{y1} of the same frame ({(x1 - x0) * (y1 - y0)} px, "
                       f"{b['n_pairs']} pairs): project all Gaussians + bin/sort/ranges of the window's tiles + "
                       f"fwd + bwd render of its pixels, FP64",

@@ -96,7 +96,16 @@ typedef enum bgs_order {
 enum {
     /* the workspace already holds a queue from bgs_queue_build for this frame
        and cfg (with the counter reset); render calls then skip building it */
-    BGS_FLAG_QUEUE_READY = 1
+    BGS_FLAG_QUEUE_READY = 1,
+    /* backward of BGS_BALANCED_PIXEL, subtile 16, cost order: a tile whose walk
+       reaches 128 list entries becomes two work items, the entries below a
+       split point k (near half the walk, a multiple of 64) walked front to back
+       from T = 1 and the entries from k on walked back to front from final_T.
+       Needs the forward's outputs in split_color and split_depth (the sum over
+       the whole walk that the lower part starts from is read off them).
+       Halves the heaviest work items, so the queue balances better; the
+       gradients equal the unsplit ones up to fp32 rounding. */
+    BGS_FLAG_SPLIT_WALKS = 2
 };
 
 typedef struct bgs_render_cfg {
@@ -137,8 +146,15 @@ typedef struct bgs_render_cfg {
        takes work item i from the task pool (Alg. 1), so after a render every
        entry is 1.  Items: subtile 8 -> tile * 4 + quadrant (4 n_tiles of
        them), subtile 16 -> tile, subtile 32 -> block (ty / 2) *
-       ceil(TX / 2) + tx / 2.  Ignored by the static variants and by plans. */
+       ceil(TX / 2) + tx / 2.  With BGS_FLAG_SPLIT_WALKS the two parts of a
+       split tile t count at item_claims[t] (lower) and item_claims[n_tiles +
+       t] (upper), so the array needs 2 n_tiles entries.  Ignored by the
+       static variants and by plans. */
     uint32_t* item_claims;
+    /* With BGS_FLAG_SPLIT_WALKS: the forward's out_color [3][H][W] and
+       out_depth [H][W] of this frame (DEVICE, read only by the backward). */
+    const float* split_color;
+    const float* split_depth;
 } bgs_render_cfg;
 
 /* Thread-local text for the last non-OK status of this thread. */

@@ -22,6 +22,7 @@ BGS_OK, BGS_EINVAL, BGS_ECAPACITY, BGS_EHIP, BGS_EUNSUPPORTED, BGS_EINTERNAL = 0
 STATIC, BALANCED_PIXEL, BALANCED_GAUSS, BALANCED_HYBRID, STATIC_WAVE = 0, 1, 2, 3, 4
 ORDER_RASTER, ORDER_COST = 0, 1
 FLAG_QUEUE_READY = 1
+FLAG_SPLIT_WALKS = 2
 TILE = 16
 
 VARIANTS = {"static": STATIC, "pixel": BALANCED_PIXEL, "gauss": BALANCED_GAUSS, "hybrid": BALANCED_HYBRID,
@@ -58,7 +59,7 @@ class RenderCfg(C.Structure):
     _fields_ = [("variant", C.c_int32), ("subtile", C.c_int32), ("order", C.c_int32), ("flags", C.c_int32),
                 ("bg", C.c_float * 3), ("wg_trace", C.c_void_p), ("wg_trace_cap", C.c_int64),
                 ("n_examined", C.c_void_p), ("list_cap", C.c_uint32), ("list_overflow", C.c_void_p),
-                ("item_claims", C.c_void_p)]
+                ("item_claims", C.c_void_p), ("split_color", C.c_void_p), ("split_depth", C.c_void_p)]
 
 
 _LIB = None
@@ -171,6 +172,23 @@ def make_cfg(variant="pixel", subtile: int = 8, order="raster", bg=(0.0, 0.0, 0.
     for k in range(3):
         c.bg[k] = float(bg[k])
     return c
+
+
+def copy_cfg(c: RenderCfg) -> RenderCfg:
+    d = RenderCfg()
+    C.pointer(d)[0] = c
+    return d
+
+
+def with_forward_outputs(c: RenderCfg, out_color, out_depth) -> RenderCfg:
+    """A copy of a backward configuration that carries the forward's outputs
+    (needed by split walks, FLAG_SPLIT_WALKS); other configurations are
+    returned unchanged."""
+    if not c.flags & FLAG_SPLIT_WALKS:
+        return c
+    d = copy_cfg(c)
+    d.split_color, d.split_depth = _ptr(out_color), _ptr(out_depth)
+    return d
 
 
 def n_tiles(width: int, height: int) -> int:
@@ -414,7 +432,8 @@ def bgs_plan_destroy(plan):
 
 def cfg_name(c: RenderCfg) -> str:
     names = {v: k for k, v in VARIANTS.items()}
-    return f"{names.get(c.variant, c.variant)}{c.subtile}/{'cost' if c.order == ORDER_COST else 'raster'}"
+    base = f"{names.get(c.variant, c.variant)}{c.subtile}/{'cost' if c.order == ORDER_COST else 'raster'}"
+    return base + ("/split" if c.flags & FLAG_SPLIT_WALKS else "")
 
 
 def bgs_render_bwd_det_workspace_bytes(frame: Frame, P: int, max_occ: int) -> int:

@@ -76,6 +76,9 @@ struct BwdIO {
     // entry), at slot det_base[tile] + entry
     float* __restrict__ det_partials;
     const uint32_t* __restrict__ det_base;
+    // split walks only: the forward's out_color [3][H][W] and out_depth [H][W]
+    const float* __restrict__ out_color;
+    const float* __restrict__ out_depth;
 };
 
 // One view of a batched plan: its frame, forward outputs and backward I/O.
@@ -296,14 +299,16 @@ struct WorkQueue {
     uint32_t* claims;        // claims[item] += 1 per claim (nullable; one-view launches only)
     uint32_t n;              // number of items
     uint32_t nw;             // waves of the persistent grid
+    uint32_t nt;             // tiles of the frame (claim index of split walks' upper parts)
     int cur;
     __device__ __forceinline__ uint32_t size(int q) const { return n > (uint32_t)q ? (n - q - 1) / NQ + 1 : 0u; }
     __device__ __forceinline__ uint32_t first(int q) const { return nw > (uint32_t)q ? (nw - q - 1) / NQ + 1 : 0u; }
 };
 
 __device__ __forceinline__ WorkQueue make_queue(uint32_t* ctr, const uint32_t* items, int wave_global,
-                                                uint32_t* claims = nullptr) {
+                                                uint32_t* claims = nullptr, uint32_t n_tiles = 0) {
     WorkQueue Q;
+    Q.nt = n_tiles;
     Q.ctr = ctr;
     Q.items = items;
     Q.claims = claims;
@@ -315,7 +320,11 @@ __device__ __forceinline__ WorkQueue make_queue(uint32_t* ctr, const uint32_t* i
 }
 
 __device__ __forceinline__ void note_claim(const WorkQueue& Q, int lane, uint32_t item) {
-    if (Q.claims && lane == 0) atomicAdd(&Q.claims[item & LOCAL_MASK], 1u);
+    if (Q.claims && lane == 0) {
+        uint32_t i = item & LOCAL_MASK;
+        if (i & (1u << 25)) i = (i & ((1u << 24) - 1u)) + ((i & (1u << 24)) ? Q.nt : 0u);  // part of a split walk
+        atomicAdd(&Q.claims[i], 1u);
+    }
 }
 
 // Counter value t of queue q -> the item, if q still holds one.
@@ -972,15 +981,61 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
 // at all when the entry lies beyond every n_contrib of the block or outside
 // the block's ellipse mask (staged as in the forward), and its gradient terms
 // only when one of its pixels blended the entry.  The chunks of 64 entries are
-// walked back to front with the forward's two-stage prefetch (ids two chunks
-// ahead, raw splat data one chunk ahead).
+// walked with the forward's two-stage prefetch (ids two chunks ahead, raw
+// splat data one chunk ahead).
+//
+// Split walks.  A long walk can be cut at list position k into two work
+// items that run in parallel, because every quantity an entry's derivative
+// needs is known at both ends of the walk.  Writing w_m = alpha_m T_m for the
+// weight of entry m and g_m for the upstream gradient dotted with its colour
+// and depth, the derivative at entry j needs T_j and the sum S_j of g_m w_m
+// over the entries behind it (plus the background and alpha-output terms).
+//  * Upper part [k, N): back to front from T_N = final_T and S = those terms,
+//    T_j recovered by division -- the unsplit walk, stopped at k.
+//  * Lower part [0, k): front to back from T_0 = 1, T advanced exactly as the
+//    forward advances it, and S_j = S_total - (prefix of g_m w_m up to and
+//    including j), where S_total is the same sum over the whole walk, which
+//    the forward's outputs give directly: S_total = dL/dC . out_color +
+//    dL/dD . out_depth - dL/dA . T_N (the background terms cancel).
+// The split point of a tile with deepest n_contrib N is split_point(N); the
+// queue builder and the kernel compute it from the same N.
+
+// Split point of a walk of n entries (n >= SPLIT_MIN): near n / 2, a
+// multiple of 64, at least 64, below n.
+constexpr int SPLIT_MIN = 128;
+constexpr uint32_t ITEM_SPLIT = 1u << 25;  // the item is one part of a split walk ...
+constexpr uint32_t ITEM_UPPER = 1u << 24;  // ... the upper part [k, N) (else the lower [0, k))
+constexpr uint32_t ITEM_TILE = (1u << 24) - 1u;
+
+__host__ __device__ __forceinline__ int split_point(int n) {
+    const int k = ((n / 2 + 32) / 64) * 64;
+    return k < 64 ? 64 : k;
+}
+
+// Gradient terms of one (pixel, entry) pair added into the lane's ten sums.
+__device__ __forceinline__ void add_terms(float (&v)[10], float w, float dA, float G, float ga, bool unclamped,
+                                          float gC0, float gC1, float gC2, float gD, float dx, float dy,
+                                          float4 abc) {
+    v[6] = __builtin_fmaf(w, gC0, v[6]);
+    v[7] = __builtin_fmaf(w, gC1, v[7]);
+    v[8] = __builtin_fmaf(w, gC2, v[8]);
+    v[9] = __builtin_fmaf(w, gD, v[9]);
+    const float dP = unclamped ? ga * dA : 0.0f;  // dL/dpower
+    v[5] += unclamped ? G * dA : 0.0f;            // dL/dopacity
+    v[2] += -0.5f * dx * dx * dP;
+    v[3] += -dx * dy * dP;
+    v[4] += -0.5f * dy * dy * dP;
+    v[0] += (abc.x * dx + abc.y * dy) * dP;
+    v[1] += (abc.y * dx + abc.z * dy) * dP;
+}
 
 // DET: instead of adding its per-entry totals to the gradients, the wave
 // stores them (zeros for an entry no pixel blends) at the entry's slot of
 // B.det_partials, for an ordered reduction afterwards.
+// part: 0 the whole walk, 1 the lower part of a split walk, 2 the upper part.
 template <bool DET>
 __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int tile, int lane, WaveStage& st,
-                                         float4* __restrict__ s_abc) {
+                                         float4* __restrict__ s_abc, int part) {
     const int64_t HW = (int64_t)F.W * F.H;
     const int tx = tile % F.TX, ty = tile / F.TX;
     const int x0 = tx * TILE, y0 = ty * TILE;
@@ -991,7 +1046,8 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
     const int dslot = scatter10_slot(lane);
     float* const dpart = DET ? B.det_partials + (size_t)B.det_base[tile] * 10 + dslot : nullptr;
     // S[q]: dL/dC . (colour, depth accumulated behind the entry) + the
-    // entry-independent part of dL/dalpha, as in k_bwd_pixel
+    // entry-independent part of dL/dalpha, as in k_bwd_pixel (lower part:
+    // S_total, the same sum over the whole walk)
     float T[WQ], S[WQ], gC0[WQ], gC1[WQ], gC2[WQ], gD[WQ], fy[WQ];
     int nc[WQ], bmax[WQ];
     int max_n = 0;
@@ -1009,8 +1065,15 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
         gC2[q] = inside ? B.dL_dcolor[2 * HW + p] : 0.f;
         const float ga = (inside && B.dL_dalpha) ? B.dL_dalpha[p] : 0.f;
         gD[q] = (inside && B.dL_ddepth) ? B.dL_ddepth[p] : 0.f;
-        S[q] = TN * (gC0[q] * F.bg0 + gC1[q] * F.bg1 + gC2[q] * F.bg2) - ga * TN;
-        T[q] = TN;
+        if (part == 1) {
+            const float c0 = inside ? B.out_color[p] : 0.f, c1 = inside ? B.out_color[HW + p] : 0.f;
+            const float c2 = inside ? B.out_color[2 * HW + p] : 0.f, d = inside ? B.out_depth[p] : 0.f;
+            S[q] = gC0[q] * c0 + gC1[q] * c1 + gC2[q] * c2 + gD[q] * d - ga * TN;
+            T[q] = 1.0f;
+        } else {
+            S[q] = TN * (gC0[q] * F.bg0 + gC1[q] * F.bg1 + gC2[q] * F.bg2) - ga * TN;
+            T[q] = TN;
+        }
         fy[q] = (float)py;
     }
 #pragma unroll
@@ -1018,17 +1081,95 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
         bmax[q] = __builtin_amdgcn_readfirstlane(wave_max(nc[q]));  // uniform: block q walks entries < bmax[q]
         max_n = bmax[q] > max_n ? bmax[q] : max_n;
     }
+    const int k = part ? split_point(max_n) : 0;
+    // the entries this item walks: [lo_end, hi_end)
+    const int lo_end = part == 2 ? k : 0;
+    const int hi_end = part == 1 ? (k < max_n ? k : max_n) : max_n;
     const float fx = (float)px;
+    float* const dchunk = DET ? B.det_partials + (size_t)B.det_base[tile] * 10 : nullptr;
     RawSplat cur{}, nxt{};
     uint32_t idn = 0;
-    if (max_n > 0) {
-        const uint32_t lo0 = max_n > 64 ? (uint32_t)max_n - 64 : 0u;
-        load_raw(F, chunk_id(F, start + lo0, start + (uint32_t)max_n, lane), cur);
-        if (lo0 > 0) idn = chunk_id(F, start + (lo0 > 64 ? lo0 - 64 : 0u), start + lo0, lane);
+    if (part == 1) {
+        // ---- lower part, front to back over [0, hi_end)
+        float Pf[WQ];  // prefix of g_m w_m over the entries before the current one
+#pragma unroll
+        for (int q = 0; q < WQ; ++q) Pf[q] = 0.0f;
+        const uint32_t end = start + (uint32_t)hi_end;
+        if (hi_end > 0) {
+            load_raw(F, chunk_id(F, start, end, lane), cur);
+            if (64 < hi_end) idn = chunk_id(F, start + 64, end, lane);
+        }
+        for (int base = 0; base < hi_end; base += 64) {
+            const int cnt = hi_end - base < 64 ? hi_end - base : 64;
+            uint64_t mq[WQ];
+            chunk_masks(stage_entry(st, lane, cur, lane < cnt, x0, y0), mq);
+            s_abc[lane] = make_float4(cur.con.x, cur.con.y, cur.con.z, 0.0f);
+#pragma unroll
+            for (int q = 0; q < WQ; ++q) {
+                const int n = bmax[q] - base;
+                mq[q] &= n >= 64 ? ~0ull : (n > 0 ? (1ull << n) - 1ull : 0ull);
+            }
+            wave_sync();
+            if (base + 64 < hi_end) load_raw(F, idn, nxt);
+            if (base + 128 < hi_end) idn = chunk_id(F, start + (uint32_t)base + 128, end, lane);
+            uint64_t todo = chunk_todo(mq, 0xFu);
+            while (todo) {
+                const int jj = (int)__builtin_ctzll(todo);
+                todo &= todo - 1;
+                const int j = base + jj;
+                const float4 xym = st.xym[jj];
+                const float4 co = st.co[jj];
+                const float4 cd = st.cd[jj];
+                const float4 abc = s_abc[jj];
+                const float dx = fx - xym.x;
+                float v[10];
+#pragma unroll
+                for (int i = 0; i < 10; ++i) v[i] = 0.f;
+                bool any = false;  // a block had a pixel that blended the entry (uniform)
+#pragma unroll
+                for (int q = 0; q < WQ; ++q) {
+                    if (!((mq[q] >> jj) & 1u)) continue;
+                    const float dy = fy[q] - xym.y;
+                    const float p2 = splat_power2(dx, dy, co.x, co.y, co.z);
+                    const float G = exp2_fast(p2);
+                    const float ga = co.w * G;
+                    const float alpha = fminf(ALPHA_MAX, ga);
+                    const uint64_t cm = ballot(j < nc[q]) & ballot(!(p2 > 0.0f)) & ballot(!(alpha < ALPHA_MIN));
+                    if (cm == 0) continue;
+                    const bool contrib = lane_bit(cm);
+                    any = true;
+                    const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                    const float Tb = T[q];
+                    const float w = contrib ? alpha * Tb : 0.0f;
+                    const float gc = gC0[q] * cd.x + gC1[q] * cd.y + gC2[q] * cd.z + gD[q] * cd.w;
+                    const float Pn = __builtin_fmaf(gc, w, Pf[q]);
+                    const float dA = Tb * gc - inv * (S[q] - Pn);  // S[q] - Pn: the sum behind the entry
+                    Pf[q] = Pn;
+                    T[q] = contrib ? Tb - w : T[q];  // as the forward advances T
+                    add_terms(v, w, dA, G, ga, lane_bit(cm & ballot(ga <= ALPHA_MAX)), gC0[q], gC1[q], gC2[q],
+                              gD[q], dx, dy, abc);
+                }
+                if (!any) continue;
+                float tot;
+                wave_reduce_scatter10(v, lane, tot);
+                if (GL.base) unsafeAtomicAdd(GL.base + (size_t)__float_as_uint(xym.w) * GL.stride, tot);
+            }
+            wave_sync();
+            cur = nxt;
+        }
+        return;
     }
-    float* const dchunk = DET ? B.det_partials + (size_t)B.det_base[tile] * 10 : nullptr;
-    for (int hi = max_n; hi > 0; hi -= 64) {
-        const int lo = hi > 64 ? hi - 64 : 0;
+    // ---- whole walk or upper part, back to front over [lo_end, hi_end)
+    if (hi_end > lo_end) {
+        const int lo0 = hi_end - 64 > lo_end ? hi_end - 64 : lo_end;
+        load_raw(F, chunk_id(F, start + (uint32_t)lo0, start + (uint32_t)hi_end, lane), cur);
+        if (lo0 > lo_end) {
+            const int nlo = lo0 - 64 > lo_end ? lo0 - 64 : lo_end;
+            idn = chunk_id(F, start + (uint32_t)nlo, start + (uint32_t)lo0, lane);
+        }
+    }
+    for (int hi = hi_end; hi > lo_end; hi -= 64) {
+        const int lo = hi - 64 > lo_end ? hi - 64 : lo_end;
         uint64_t mq[WQ];
         chunk_masks(stage_entry(st, lane, cur, lo + lane < hi, x0, y0), mq);
         s_abc[lane] = make_float4(cur.con.x, cur.con.y, cur.con.z, 0.0f);
@@ -1039,10 +1180,13 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
             mq[q] &= n >= 64 ? ~0ull : (n > 0 ? (1ull << n) - 1ull : 0ull);
         }
         wave_sync();
-        if (lo > 0) load_raw(F, idn, nxt);  // the chunk [max(lo - 64, 0), lo)
-        if (lo > 64) {
-            const uint32_t nlo = (uint32_t)lo - 64;
-            idn = chunk_id(F, start + (nlo > 64 ? nlo - 64 : 0u), start + nlo, lane);
+        if (lo > lo_end) {  // the chunk [max(lo - 64, lo_end), lo)
+            load_raw(F, idn, nxt);
+            const int nlo = lo - 64 > lo_end ? lo - 64 : lo_end;
+            if (nlo > lo_end) {
+                const int nnlo = nlo - 64 > lo_end ? nlo - 64 : lo_end;
+                idn = chunk_id(F, start + (uint32_t)nnlo, start + (uint32_t)nlo, lane);
+            }
         }
         uint64_t todo = chunk_todo(mq, 0xFu);
         uint64_t wrote = 0;  // DET: entries whose partial slot holds a total
@@ -1052,9 +1196,6 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
             todo &= ~(1ull << jj);
             const int j = lo + jj;
             const float4 xym = st.xym[jj];
-            uint32_t m = 0;
-#pragma unroll
-            for (int q = 0; q < WQ; ++q) m |= (uint32_t)((mq[q] >> jj) & 1u) << q;
             const float4 co = st.co[jj];
             const float4 cd = st.cd[jj];
             const float4 abc = s_abc[jj];
@@ -1065,7 +1206,7 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
             bool any = false;  // a block had a pixel that blended the entry (uniform)
 #pragma unroll
             for (int q = 0; q < WQ; ++q) {
-                if (!(m & (1u << q))) continue;
+                if (!((mq[q] >> jj) & 1u)) continue;
                 const float dy = fy[q] - xym.y;
                 const float p2 = splat_power2(dx, dy, co.x, co.y, co.z);
                 const float G = exp2_fast(p2);
@@ -1078,22 +1219,12 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
                 const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
                 const float Tb = T[q] * inv;
                 const float w = contrib ? alpha * Tb : 0.0f;
-                v[6] = __builtin_fmaf(w, gC0[q], v[6]);
-                v[7] = __builtin_fmaf(w, gC1[q], v[7]);
-                v[8] = __builtin_fmaf(w, gC2[q], v[8]);
-                v[9] = __builtin_fmaf(w, gD[q], v[9]);
                 const float gc = gC0[q] * cd.x + gC1[q] * cd.y + gC2[q] * cd.z + gD[q] * cd.w;
                 const float dA = Tb * gc - inv * S[q];
                 S[q] = __builtin_fmaf(gc, w, S[q]);
                 T[q] = contrib ? Tb : T[q];
-                const bool unclamped = lane_bit(cm & ballot(ga <= ALPHA_MAX));
-                const float dP = unclamped ? ga * dA : 0.0f;  // dL/dpower
-                v[5] += unclamped ? G * dA : 0.0f;            // dL/dopacity
-                v[2] += -0.5f * dx * dx * dP;
-                v[3] += -dx * dy * dP;
-                v[4] += -0.5f * dy * dy * dP;
-                v[0] += (abc.x * dx + abc.y * dy) * dP;
-                v[1] += (abc.y * dx + abc.z * dy) * dP;
+                add_terms(v, w, dA, G, ga, lane_bit(cm & ballot(ga <= ALPHA_MAX)), gC0[q], gC1[q], gC2[q], gD[q],
+                          dx, dy, abc);
             }
             if (!any) continue;
             float tot;
@@ -1108,14 +1239,14 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
         if (DET && lo + lane < hi && !((wrote >> lane) & 1ull)) {  // zeros for the entries no pixel blended
             float* z = dchunk + (size_t)(lo + lane) * 10;
 #pragma unroll
-            for (int k = 0; k < 10; ++k) z[k] = 0.0f;
+            for (int k2 = 0; k2 < 10; ++k2) z[k2] = 0.0f;
         }
         wave_sync();
         cur = nxt;
     }
 }
 
-template <bool MV = false, bool DET = false, bool PERSISTENT = true, int TPI = 1>
+template <bool MV = false, bool DET = false, bool PERSISTENT = true, int TPI = 1, bool SPLIT = false>
 __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const ViewDesc* __restrict__ views,
                                                   const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr,
                                                   uint32_t n_static) {
@@ -1124,7 +1255,7 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
     __shared__ float4 s_abc[4][64];  // raw conic a, b, c
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     WorkQueue Q;
-    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv, MV ? nullptr : F0.item_claims);
+    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv, MV ? nullptr : F0.item_claims, (uint32_t)F0.n_tiles);
     for (bool first = true;; first = false) {
         uint32_t item;
         if (PERSISTENT) {
@@ -1135,9 +1266,14 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
         }
         const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
         const BwdIO B = MV ? views[item >> VIEW_SHIFT].B : B0;
-        int tiles[TPI];
-        const int nt = item_tiles<TPI>(F, item & LOCAL_MASK, tiles);
-        for (int k = 0; k < nt; ++k) bwd_tile<DET>(F, B, tiles[k], lane, s_st[wv], s_abc[wv]);
+        const uint32_t code = item & LOCAL_MASK;
+        if (SPLIT && TPI == 1 && (code & ITEM_SPLIT)) {
+            bwd_tile<DET>(F, B, (int)(code & ITEM_TILE), lane, s_st[wv], s_abc[wv], (code & ITEM_UPPER) ? 2 : 1);
+        } else {
+            int tiles[TPI];
+            const int nt = item_tiles<TPI>(F, code, tiles);
+            for (int k = 0; k < nt; ++k) bwd_tile<DET>(F, B, tiles[k], lane, s_st[wv], s_abc[wv], 0);
+        }
         if (!PERSISTENT) break;
     }
     trace_end(F0, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
@@ -1169,7 +1305,9 @@ __global__ __launch_bounds__(256) void k_tile_costs(FrameArgs F, const int* __re
         if (n_contrib) {
             const int tx = tile % F.TX, ty = tile / F.TX;
             const int px = tx * TILE + (threadIdx.x & 15), py = ty * TILE + (threadIdx.x >> 4);
-            const int nc = (px < F.W && py < F.H) ? n_contrib[(int64_t)py * F.W + px] : 0;
+            const int len = (int)(F.ranges[2 * tile + 1] - F.ranges[2 * tile]);
+            int nc = (px < F.W && py < F.H) ? n_contrib[(int64_t)py * F.W + px] : 0;
+            nc = nc < 0 ? 0 : (nc > len ? len : nc);  // as the backward clamps it
             const int m = wave_max(nc);
             if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
             __syncthreads();
@@ -1216,9 +1354,11 @@ __global__ __launch_bounds__(256) void k_tile_costs_mv(const ViewDesc* __restric
 // counters and stores the item count.
 __global__ __launch_bounds__(1024) void k_queue(int n_tiles, const uint32_t* __restrict__ cost, int by_cost,
                                                 int per_tile, const uint32_t* __restrict__ tile_off, int n_views,
-                                                uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
+                                                int split_min, uint32_t* __restrict__ items,
+                                                uint32_t* __restrict__ ctr) {
     __shared__ uint32_t hist[NBUCKET];
-    auto deal = [&](uint32_t r, uint32_t tile) {
+    __shared__ uint32_t n_units;
+    auto deal = [&](uint32_t r, uint32_t tile, uint32_t part_bits) {
         uint32_t vbits = 0;
         if (tile_off) {  // batched views: global tile -> (view, tile of the view)
             int v = 0;
@@ -1227,19 +1367,35 @@ __global__ __launch_bounds__(1024) void k_queue(int n_tiles, const uint32_t* __r
             vbits = (uint32_t)v << VIEW_SHIFT;
         }
         if (per_tile) {  // tile of rank r: queue r mod 64, position r / 64, i.e. items[r]
-            items[r] = vbits | tile;
+            items[r] = vbits | part_bits | tile;
             return;
         }
         const uint32_t grp = r % QGROUPS, pos = r / QGROUPS;
         for (uint32_t sub = 0; sub < 4; ++sub) items[(size_t)pos * NQ + grp * 4 + sub] = vbits | (tile * 4 + sub);
     };
+    // split walks (per-tile items, cost order): a tile whose walk has at least
+    // split_min entries becomes two items, ranked by the length of each part
+    const bool split = by_cost && per_tile && split_min > 0 && !tile_off;
     if (!by_cost) {
-        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x) deal(t, t);
+        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x) deal(t, t, 0u);
     } else {
         for (int b = threadIdx.x; b < NBUCKET; b += blockDim.x) hist[b] = 0;
+        if (threadIdx.x == 0) n_units = 0;
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x)
-            atomicAdd(&hist[NBUCKET - 1 - cost_bucket(cost[t])], 1u);
+        uint32_t units = 0;
+        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x) {
+            const uint32_t c = cost[t];
+            if (split && c >= (uint32_t)split_min) {
+                const uint32_t k = (uint32_t)split_point((int)c);
+                atomicAdd(&hist[NBUCKET - 1 - cost_bucket(k)], 1u);
+                atomicAdd(&hist[NBUCKET - 1 - cost_bucket(c - k)], 1u);
+                units += 2;
+            } else {
+                atomicAdd(&hist[NBUCKET - 1 - cost_bucket(c)], 1u);
+                units += 1;
+            }
+        }
+        atomicAdd(&n_units, units);
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t run = 0;
@@ -1250,11 +1406,19 @@ __global__ __launch_bounds__(1024) void k_queue(int n_tiles, const uint32_t* __r
             }
         }
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x)
-            deal(atomicAdd(&hist[NBUCKET - 1 - cost_bucket(cost[t])], 1u), t);
+        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x) {
+            const uint32_t c = cost[t];
+            if (split && c >= (uint32_t)split_min) {
+                const uint32_t k = (uint32_t)split_point((int)c);
+                deal(atomicAdd(&hist[NBUCKET - 1 - cost_bucket(k)], 1u), t, ITEM_SPLIT);
+                deal(atomicAdd(&hist[NBUCKET - 1 - cost_bucket(c - k)], 1u), t, ITEM_SPLIT | ITEM_UPPER);
+            } else {
+                deal(atomicAdd(&hist[NBUCKET - 1 - cost_bucket(c)], 1u), t, 0u);
+            }
+        }
     }
     for (int q = threadIdx.x; q < NQ; q += blockDim.x) ctr[q * QSTRIDE] = 0;
-    if (threadIdx.x == 0) ctr[NQ * QSTRIDE] = (uint32_t)n_tiles * (per_tile ? 1u : 4u);
+    if (threadIdx.x == 0) ctr[NQ * QSTRIDE] = split ? n_units : (uint32_t)n_tiles * (per_tile ? 1u : 4u);
 }
 
 // ---------------------------------------------------------------- host side
@@ -1341,6 +1505,12 @@ static bool block_items(const bgs_render_cfg* cfg) {
     return cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 32;
 }
 
+// Split backward walks: the wave-per-tile backward with cost order and the flag.
+static bool split_walks(const bgs_render_cfg* cfg) {
+    return (cfg->flags & BGS_FLAG_SPLIT_WALKS) && cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 16 &&
+           cfg->order == BGS_ORDER_COST;
+}
+
 // Number of queue entries: blocks, tiles, or 8x8 sub-tiles.
 static uint32_t queue_items(const FrameArgs& A, const bgs_render_cfg* cfg) {
     if (block_items(cfg)) return (uint32_t)(((A.TX + 1) / 2) * ((A.TY + 1) / 2));
@@ -1360,8 +1530,10 @@ static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, con
         BGS_HIP(hipGetLastError());
     }
     const int per_tile = tile_items(cfg) ? 1 : 0;
+    // split walks: backward queues (n_contrib given) of the wave-per-tile kernels only
+    const int split_min = (split_walks(cfg) && n_contrib) ? SPLIT_MIN : 0;
     hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, n_cost, cost, by_cost, per_tile,
-                       (const uint32_t*)nullptr, 1, items, ctr);
+                       (const uint32_t*)nullptr, 1, split_min, items, ctr);
     BGS_HIP(hipGetLastError());
     return BGS_OK;
 }
@@ -1513,7 +1685,12 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
     BGS_REQUIRE(final_T && n_contrib && dL_dcolor, "bgs_render_bwd: null forward state or dL_dcolor");
     BGS_REQUIRE(dL_dmeans2D && dL_dconic_opacity && dL_drgb, "bgs_render_bwd: null gradient output");
     BwdIO B{final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dmeans2D, dL_dconic_opacity, dL_drgb,
-            dL_ddepths, nullptr, nullptr};
+            dL_ddepths, nullptr, nullptr, cfg->split_color, cfg->split_depth};
+    if ((cfg->flags & BGS_FLAG_SPLIT_WALKS) && !split_walks(cfg))
+        return fail(BGS_EUNSUPPORTED, "bgs_render_bwd: split walks need BGS_BALANCED_PIXEL, subtile 16, cost order");
+    if (split_walks(cfg) && !(cfg->split_color && cfg->split_depth))
+        return fail(BGS_EINVAL, "bgs_render_bwd: split walks need the forward's out_color and out_depth "
+                                "(cfg.split_color, cfg.split_depth)");
     if (cfg->variant == BGS_STATIC) {
         hipLaunchKernelGGL(k_bwd_pixel<false>, dim3(A.n_tiles), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
                            (const uint32_t*)nullptr, (uint32_t*)nullptr);
@@ -1541,6 +1718,10 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
     if (block_items(cfg)) {
         const int blocks = persistent_blocks(k_bwd_wide<false, false, true, 4>, n_items);
         hipLaunchKernelGGL((k_bwd_wide<false, false, true, 4>), dim3(blocks), dim3(256), 0, stream, A, B,
+                           (const ViewDesc*)nullptr, items, ctr, 0u);
+    } else if (split_walks(cfg)) {  // up to two items per tile
+        const int blocks = persistent_blocks(k_bwd_wide<false, false, true, 1, true>, 2 * n_items);
+        hipLaunchKernelGGL((k_bwd_wide<false, false, true, 1, true>), dim3(blocks), dim3(256), 0, stream, A, B,
                            (const ViewDesc*)nullptr, items, ctr, 0u);
     } else if (tile_items(cfg)) {
         const int blocks = persistent_blocks(k_bwd_wide<false>, n_items);
@@ -1916,7 +2097,7 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
         hipLaunchKernelGGL(k_tile_costs_mv, dim3(plan->total_tiles), dim3(256), 0, stream, plan->d_views,
                            plan->d_tile_off, n_views, 0, plan->d_cost);
     hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, (int)plan->total_tiles, plan->d_cost, by_cost,
-                       fwd_wide ? 1 : 0, plan->d_tile_off, n_views, plan->d_items, plan->d_ctr);
+                       fwd_wide ? 1 : 0, plan->d_tile_off, n_views, 0, plan->d_items, plan->d_ctr);
     if (fwd_wide)
         hipLaunchKernelGGL((k_fwd_wide<true>), dim3(fblocks), dim3(256), 0, stream, F0, O0, plan->d_views,
                            plan->d_items, plan->d_ctr, 0u);
@@ -1927,7 +2108,7 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
         hipLaunchKernelGGL(k_tile_costs_mv, dim3(plan->total_tiles), dim3(256), 0, stream, plan->d_views,
                            plan->d_tile_off, n_views, 1, plan->d_cost);
     hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, (int)plan->total_tiles, plan->d_cost, bwd_by_cost,
-                       bwd_wide ? 1 : 0, plan->d_tile_off, n_views, plan->d_items, plan->d_ctr);
+                       bwd_wide ? 1 : 0, plan->d_tile_off, n_views, 0, plan->d_items, plan->d_ctr);
     if (bwd_wide)
         hipLaunchKernelGGL((k_bwd_wide<true>), dim3(bblocks), dim3(256), 0, stream, F0, B0, plan->d_views,
                            plan->d_items, plan->d_ctr, 0u);

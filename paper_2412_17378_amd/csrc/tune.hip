@@ -118,8 +118,8 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
         *best_bwd = *base;
         best_bwd->variant = e.bv;
         best_bwd->subtile = e.bs;
-        best_bwd->order = e.bo;
-        best_bwd->flags = 0;
+        best_bwd->order = e.bo & 15;  // the backward's flags ride in the order field's upper bits
+        best_bwd->flags = e.bo >> 4;
         if (fwd_ms_out) *fwd_ms_out = e.fms;
         if (bwd_ms_out) *bwd_ms_out = e.bms;
         return BGS_OK;
@@ -129,10 +129,15 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
                                 {BGS_BALANCED_PIXEL, 16, BGS_ORDER_RASTER}, {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST},
                                 {BGS_BALANCED_PIXEL, 32, BGS_ORDER_COST},   {BGS_BALANCED_HYBRID, 8, BGS_ORDER_COST},
                                 {BGS_BALANCED_GAUSS, 8, BGS_ORDER_COST}};
-    const int bwd_cands[][3] = {{BGS_STATIC, 16, BGS_ORDER_RASTER},         {BGS_STATIC_WAVE, 16, BGS_ORDER_RASTER},
-                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_RASTER},   {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST},
-                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_RASTER},  {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST},
-                                {BGS_BALANCED_PIXEL, 32, BGS_ORDER_COST}};
+    // variant, sub-tile, order, flags
+    const int bwd_cands[][4] = {{BGS_STATIC, 16, BGS_ORDER_RASTER, 0},
+                                {BGS_STATIC_WAVE, 16, BGS_ORDER_RASTER, 0},
+                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_RASTER, 0},
+                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST, 0},
+                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_RASTER, 0},
+                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST, 0},
+                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST, BGS_FLAG_SPLIT_WALKS},
+                                {BGS_BALANCED_PIXEL, 32, BGS_ORDER_COST, 0}};
     hipEvent_t e0, e1;
     BGS_HIP(hipEventCreate(&e0));
     BGS_HIP(hipEventCreate(&e1));
@@ -182,7 +187,9 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
             bc.variant = bwd_cands[c][0];
             bc.subtile = bwd_cands[c][1];
             bc.order = bwd_cands[c][2];
-            bc.flags = 0;
+            bc.flags = bwd_cands[c][3];
+            bc.split_color = out_color;  // the winner forward's outputs, rendered just above
+            bc.split_depth = out_depth;
             float ms = 0;
             // gradients accumulate; their values are scratch here
             st = timed([&] {
@@ -208,11 +215,11 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
     best_bwd->variant = bwd_cands[bb][0];
     best_bwd->subtile = bwd_cands[bb][1];
     best_bwd->order = bwd_cands[bb][2];
-    best_bwd->flags = 0;
+    best_bwd->flags = bwd_cands[bb][3];  // split walks: the caller sets split_color / split_depth
     if (fwd_ms_out) *fwd_ms_out = best_f;
     if (bwd_ms_out) *bwd_ms_out = std::isinf(best_b) ? -1.0f : best_b;
     TuneEntry ne{key, best_fwd->variant, best_fwd->subtile, best_fwd->order, best_bwd->variant, best_bwd->subtile,
-                 best_bwd->order, best_f, std::isinf(best_b) ? -1.0f : best_b};
+                 best_bwd->order | (best_bwd->flags << 4), best_f, std::isinf(best_b) ? -1.0f : best_b};
     if (!std::isinf(best_b)) cache_store(cache_path, ne);
     return BGS_OK;
 }

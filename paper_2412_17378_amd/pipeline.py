@@ -224,6 +224,8 @@ class Rasterizer:
                          depth=torch.zeros(P, device=dev) if want_depth else None)
         f = prep.frame()
         ws = self.ws.get("render", B.bgs_render_workspace_bytes(f, cfg))
+        if cfg.flags & B.FLAG_SPLIT_WALKS:  # split walks read the forward's colour and depth
+            cfg = B.with_forward_outputs(cfg, fwd["color"], fwd["depth"])
         B.bgs_render_bwd(f, cfg, fwd["final_T"], fwd["n_contrib"], dL_dcolor, dL_dalpha, dL_ddepth,
                          grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], ws)
         return grads
@@ -359,7 +361,8 @@ class FrameStep:
         self.P = P
         self.fcfg, self.bcfg = fcfg, bcfg
         self.fcfg_ready = B.make_cfg(fcfg.variant, fcfg.subtile, fcfg.order, tuple(fcfg.bg), flags=B.FLAG_QUEUE_READY)
-        self.bcfg_ready = B.make_cfg(bcfg.variant, bcfg.subtile, bcfg.order, tuple(bcfg.bg), flags=B.FLAG_QUEUE_READY)
+        self.bcfg_ready = B.make_cfg(bcfg.variant, bcfg.subtile, bcfg.order, tuple(bcfg.bg),
+                                     flags=B.FLAG_QUEUE_READY | (bcfg.flags & B.FLAG_SPLIT_WALKS))
         self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
         self.list_cap = 0
         self.pr = dict(means2D=torch.empty(P, 2, device=dev), conic_opacity=torch.empty(P, 4, device=dev),
@@ -369,6 +372,9 @@ class FrameStep:
         self.fwd = dict(color=torch.empty(3, H, W, device=dev), alpha=torch.empty(H, W, device=dev),
                         depth=torch.empty(H, W, device=dev), final_T=torch.empty(H, W, device=dev),
                         n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
+        # split walks read the forward's colour and depth
+        self.bcfg_ready.split_color = self.fwd["color"].data_ptr()
+        self.bcfg_ready.split_depth = self.fwd["depth"].data_ptr()
         # separate allocations (the backward's atomics spread better over the
         # memory channels than with the four in one buffer), zeroed by one
         # multi-tensor fill
@@ -523,6 +529,9 @@ class RenderFn(torch.autograd.Function):
         ctx.prep, ctx.cfg, ctx.rast = p2, cfg, rast
         ctx.save_for_backward(out["final_T"], out["n_contrib"])
         ctx.mark_non_differentiable(out["final_T"], out["n_contrib"])
+        # split walks read the forward's colour and depth (kept as plain copies)
+        ctx.split_out = ((out["color"].detach().clone(), out["depth"].detach().clone())
+                         if cfg.flags & B.FLAG_SPLIT_WALKS else None)
         return out["color"], out["alpha"], out["depth"]
 
     @staticmethod
@@ -534,7 +543,10 @@ class RenderFn(torch.autograd.Function):
         g_color = torch.zeros(3, H, W, device=dev) if g_color is None else g_color.contiguous()
         g_alpha = None if g_alpha is None else g_alpha.contiguous()
         g_depth = None if g_depth is None else g_depth.contiguous()
-        grads = rast.render_bwd(prep, ctx.cfg, dict(final_T=final_T, n_contrib=n_contrib), g_color, g_alpha, g_depth)
+        fwd = dict(final_T=final_T, n_contrib=n_contrib)
+        if ctx.split_out is not None:
+            fwd["color"], fwd["depth"] = ctx.split_out
+        grads = rast.render_bwd(prep, ctx.cfg, fwd, g_color, g_alpha, g_depth)
         return grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], None, None, None
 
 

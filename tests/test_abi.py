@@ -64,6 +64,20 @@ def test_invalid_arguments_are_status_codes():
     cfg.n_examined = 1
     st = L.bgs_render_fwd(ctypes.byref(f), ctypes.byref(cfg), None, None, None, None, None, None, 0, None)
     assert st == B.BGS_EINVAL  # (null frame arrays are checked first)
+    # split walks: need the forward's colour and depth, and the wave-per-tile cost-ordered backward
+    buf = (ctypes.c_float * 64)()
+    f2 = B.Frame()
+    f2.width, f2.height, f2.tile = 32, 32, 16
+    f2.ranges = f2.point_list = f2.means2D = f2.rgb = f2.depth = ctypes.addressof(buf)
+    f2.conic_opacity = (ctypes.addressof(buf) + 15) // 16 * 16
+    f2.means2D = (ctypes.addressof(buf) + 7) // 8 * 8
+    p = ctypes.addressof(buf)
+    sc = B.make_cfg("pixel", 16, "cost", flags=B.FLAG_SPLIT_WALKS)
+    st = L.bgs_render_bwd(ctypes.byref(f2), ctypes.byref(sc), p, p, p, None, None, p, p, p, None, p, 1 << 16, None)
+    assert st == B.BGS_EINVAL and b"split" in L.bgs_last_error()
+    sc = B.make_cfg("pixel", 8, "cost", flags=B.FLAG_SPLIT_WALKS)
+    st = L.bgs_render_bwd(ctypes.byref(f2), ctypes.byref(sc), p, p, p, None, None, p, p, p, None, p, 1 << 16, None)
+    assert st == B.BGS_EUNSUPPORTED
     st = L.bgs_autotune(None, None, None, None, None, None, None, None, None, None, None, None, 0, None, None, None,
                         None, None, None)
     assert st == B.BGS_EINVAL

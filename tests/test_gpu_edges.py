@@ -19,7 +19,13 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 VARIANTS = [("static", 16, "raster"), ("pixel", 8, "raster"), ("pixel", 8, "cost"), ("pixel", 16, "cost"),
             ("pixel", 32, "cost"), ("static_wave", 16, "raster"), ("gauss", 8, "cost"), ("hybrid", 8, "cost")]
-BWD_VARIANTS = [v for v in VARIANTS if v[0] in ("static", "pixel", "static_wave")]
+BWD_VARIANTS = [v for v in VARIANTS if v[0] in ("static", "pixel", "static_wave")] + [("pixel", 16, "cost", "split")]
+
+
+def _cfg(v, bg=(0.0, 0.0, 0.0)):
+    from paper_2412_17378_amd import make_cfg
+    from paper_2412_17378_amd import bgs as B
+    return make_cfg(*v[:3], bg, flags=B.FLAG_SPLIT_WALKS if "split" in v[3:] else 0)
 
 
 @pytest.fixture(scope="module")
@@ -177,7 +183,7 @@ def _check_backward(rast, prep, name, bg=(0.0, 0.0, 0.0), seed=11):
     dev = torch.device("cuda")
     for v in BWD_VARIANTS:
         print(f"[edge-bwd] case={name} cfg={v}", flush=True)
-        cfg = make_cfg(*v, bg)
+        cfg = _cfg(v, bg)
         fwd = rast.render_fwd(prep, cfg)
         grads = rast.render_bwd(prep, cfg, fwd, torch.from_numpy(gC).to(dev), torch.from_numpy(gA).to(dev),
                                 torch.from_numpy(gD).to(dev))
@@ -234,7 +240,7 @@ def test_backward_zero_opacity(rast):
     H, W = prep.height, prep.width
     gC = torch.randn(3, H, W, device="cuda")
     for v in BWD_VARIANTS:
-        cfg = make_cfg(*v, (0.3, 0.6, 0.9))
+        cfg = _cfg(v, (0.3, 0.6, 0.9))
         fwd = rast.render_fwd(prep, cfg)
         grads = rast.render_bwd(prep, cfg, fwd, gC)
         torch.cuda.synchronize()

@@ -106,7 +106,9 @@ def test_full_backward_cropped(full):
         gC[:, y0:y1, x0:x1][:, m] = 0.0
     from paper_2412_17378_amd import make_cfg
     runs = []
-    for c in (cfg, make_cfg("pixel", 16, "cost"), make_cfg("static")):
+    from paper_2412_17378_amd import bgs as B
+    for c in (cfg, make_cfg("pixel", 16, "cost"), make_cfg("pixel", 16, "cost", flags=B.FLAG_SPLIT_WALKS),
+              make_cfg("static_wave", 16, "raster"), make_cfg("static")):
         print(f"[full-bwd] cfg variant={c.variant} sub={c.subtile}", flush=True)
         runs.append((c, rast.render_bwd(prep, c, fwd, torch.from_numpy(gC).cuda())))
     torch.cuda.synchronize()
@@ -120,4 +122,4 @@ def test_full_backward_cropped(full):
                 acc["mag"][k] = acc["mag"][k] + o["mag"][k]
                 acc[k] = acc[k] + o[k]
     for c, grads in runs:
-        compare_grads(grads, acc, name=f"full bwd variant={c.variant} sub={c.subtile}")
+        compare_grads(grads, acc, name=f"full bwd variant={c.variant} sub={c.subtile} flags={c.flags}")

@@ -104,3 +104,41 @@ def test_static_variants_take_no_claims(rast):
         rast.render_bwd(prep, cfg, fwd, torch.randn(3, prep.height, prep.width, device="cuda"))
     torch.cuda.synchronize()
     assert int(claims.abs().sum()) == 0
+
+
+@pytest.mark.parametrize("name", ["0", "1"])
+def test_split_walks_claim_both_parts_once(rast, name):
+    """Split backward walks: every tile is claimed once at claims[tile] (its
+    whole walk, or the lower part), and the upper part of exactly the tiles
+    whose walk reaches 128 entries once at claims[n_tiles + tile]."""
+    from paper_2412_17378_amd import make_cfg
+    from paper_2412_17378_amd import bgs as B
+    s = _scene(name)
+    W, H = s.cameras[0].width, s.cameras[0].height
+    prep = rast.prepare_scene(s)
+    cfg = make_cfg("pixel", 16, "cost", tuple(s.bg), flags=B.FLAG_SPLIT_WALKS)
+    fwd = rast.render_fwd(prep, cfg)
+    nt = B.n_tiles(W, H)
+    claims = torch.zeros(2 * nt + 64, dtype=torch.int32, device="cuda")
+    cfg.item_claims = claims.data_ptr()
+    print(f"[queue] split case={name}", flush=True)
+    rast.render_bwd(prep, cfg, fwd, torch.randn(3, H, W, device="cuda"))
+    torch.cuda.synchronize()
+    # each tile's walk: the deepest n_contrib of its pixels, within its list
+    nc = fwd["n_contrib"].cpu().numpy().astype(np.int64)
+    rg = prep.ranges.cpu().numpy().astype(np.int64)
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    pad = np.zeros((TY * 16, TX * 16), np.int64)
+    pad[:H, :W] = nc
+    walk = pad.reshape(TY, 16, TX, 16).max(axis=(1, 3)).ravel()
+    walk = np.minimum(walk, rg[:, 1] - rg[:, 0])
+    split = walk >= 128
+    c = claims.cpu().numpy()
+    assert np.all(c[:nt] == 1), np.nonzero(c[:nt] != 1)[0][:8]
+    np.testing.assert_array_equal(c[nt:2 * nt], split.astype(np.int32))
+    assert np.all(c[2 * nt:] == 0)
+    n = int(rast.ws.get("render", 0).view(torch.int32)[NQ * QSTRIDE].item())
+    assert n == nt + int(split.sum()), (n, nt, int(split.sum()))
+    print(f"[queue] split case={name}: {int(split.sum())} of {nt} tiles split", flush=True)
+    if name == "1":
+        assert split.any()

@@ -124,3 +124,33 @@ def test_autograd_function(rast):
     for t, r in ((m2.grad, ref["means2D"]), (co.grad, ref["conic_opacity"]), (rgb.grad, ref["rgb"])):
         scale = float(r.abs().max()) + 1e-30
         assert float((t - r).abs().max()) <= 1e-4 * scale  # float atomics: order varies
+
+
+@pytest.mark.parametrize("name", ["0", "sh3"])
+def test_backward_split_walks_parity(rast, name):
+    """Split backward walks (lower part front to back, upper part back to
+    front) against the oracle, with colour, alpha and depth upstream."""
+    from paper_2412_17378_amd import make_cfg
+    from paper_2412_17378_amd import bgs as B
+    s = _scene(name)
+    bg = (0.3, 0.1, 0.2)
+    prep = rast.prepare_scene(s)
+    cfg = make_cfg("pixel", 16, "cost", bg, flags=B.FLAG_SPLIT_WALKS)
+    fwd = rast.render_fwd(prep, cfg)
+    torch.cuda.synchronize()
+    orc_f = oracle_render_from_gpu(prep, bg=bg)
+    flagged = orc_f["margin"] < MARGIN
+    cam = s.cameras[0]
+    rng = np.random.default_rng(21)
+    gC = rng.standard_normal((3, cam.height, cam.width)).astype(np.float32)
+    gA = rng.standard_normal((cam.height, cam.width)).astype(np.float32)
+    gD = rng.standard_normal((cam.height, cam.width)).astype(np.float32)
+    gC[:, flagged] = 0.0
+    gA[flagged] = 0.0
+    gD[flagged] = 0.0
+    print(f"[bwd-split] case={name} deepest walk {int(fwd['n_contrib'].max())}", flush=True)
+    grads = rast.render_bwd(prep, cfg, fwd, torch.from_numpy(gC).cuda(), torch.from_numpy(gA).cuda(),
+                            torch.from_numpy(gD).cuda())
+    torch.cuda.synchronize()
+    ob = oracle_bwd_from_gpu(prep, gC, gA, gD, bg=bg)
+    compare_grads(grads, ob, name=f"{name} split")

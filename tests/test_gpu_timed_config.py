@@ -19,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 PAIRS = [(("static", 16, "raster"), ("pixel", 16, "cost")),
          (("pixel", 16, "cost"), ("pixel", 16, "cost")),
+         (("pixel", 16, "raster"), ("pixel", 16, "cost", "split")),
          (("pixel", 32, "cost"), ("pixel", 32, "cost")),
          (("static_wave", 16, "raster"), ("static_wave", 16, "raster"))]
 
@@ -89,8 +90,10 @@ def test_timed_step_against_oracle(ref, fwd, bwd):
     dev = torch.device("cuda")
     cam = s.cameras[0]
     print(f"[timed] fwd={fwd} bwd={bwd}", flush=True)
+    from paper_2412_17378_amd import bgs as B
+    bc = make_cfg(*bwd[:3], tuple(s.bg), flags=B.FLAG_SPLIT_WALKS if "split" in bwd[3:] else 0)
     step = FrameStep(cam, _params(s, dev), s.sh_degree, torch.from_numpy(gC).to(dev), make_cfg(*fwd, tuple(s.bg)),
-                     make_cfg(*bwd, tuple(s.bg)), list_cap="auto", poison_outputs=True)
+                     bc, list_cap="auto", poison_outputs=True)
     assert 0 < step.list_cap <= 2048, step.list_cap
 
     def check(what):

@@ -29,6 +29,14 @@ Recipes (sizes follow the five measured workloads; seeds are 17378 + id):
         supplementary stress variant of "1": every opacity U[0.02, 0.03], so
         few pixels reach the transmittance cut-off and per-pixel work follows
         the per-tile list length.  Reported beside "1", never instead of it.
+  "1-hotspot"
+        supplementary stress variant of "1" with a hot spot: 20 000 more
+        Gaussians with log-scales N(-2.5, 0.2) and opacity U[0.005, 0.008],
+        centred within +-0.02 (x, y) of (-0.3, 0.9) at z in [3, 5] -- a few
+        tiles near the bottom of the frame, late in raster order, whose pixels
+        each walk thousands of faint entries before stopping, so the heaviest
+        tile outweighs a SIMD's fair share (tail ratio R > 1).  Reported
+        beside "1", never instead of it.
   "tiny-N"
         small scenes for brute-force checks (N Gaussians, 48x40 image, f=48).
 """
@@ -192,6 +200,19 @@ def scene1_translucent(seed: Optional[int] = None, n_total: int = 500_000) -> Sc
     return _finish("1-translucent", seed, means, ls, q, op, rgb, -1, [_axis_camera(1920, 1080, 1920)])
 
 
+def scene1_hotspot(seed: Optional[int] = None, n_total: int = 500_000, n_hot: int = 20_000) -> Scene:
+    seed = SEED_BASE + 102 if seed is None else seed
+    rng = _rng(seed)
+    means, ls, q, op, rgb = _scene1_arrays(rng, n_total)
+    hot = _uniform_box(rng, n_hot, -0.32, -0.28, 0.88, 0.92)
+    means = np.concatenate([means, hot])
+    ls = np.concatenate([ls, rng.normal(-2.5, 0.2, (n_hot, 3))])
+    q = np.concatenate([q, _quats(rng, n_hot)])
+    op = np.concatenate([op, rng.uniform(0.005, 0.008, n_hot)])
+    rgb = np.concatenate([rgb, rng.uniform(0.0, 1.0, (n_hot, 3))])
+    return _finish("1-hotspot", seed, means, ls, q, op, rgb, -1, [_axis_camera(1920, 1080, 1920)])
+
+
 def _scene2_arrays(rng, n):
     means = _uniform_box(rng, n)
     ls = rng.normal(-4.0, 1.0, (n, 3))
@@ -268,13 +289,15 @@ def scene_tiny(n: int = 24, seed: int = 5, width: int = 48, height: int = 40, sh
 
 def make(name: str, **kw) -> Scene:
     """Build a scene by workload name ("0", "1", "2", "3-early", "3-mid", "3-late", "4",
-    "1-translucent", "tiny-N")."""
+    "1-translucent", "1-hotspot", "tiny-N")."""
     if name == "0":
         return scene0(**kw)
     if name == "1":
         return scene1(**kw)
     if name == "1-translucent":
         return scene1_translucent(**kw)
+    if name == "1-hotspot":
+        return scene1_hotspot(**kw)
     if name == "2":
         return scene2(**kw)
     if name.startswith("3-"):

@@ -318,9 +318,11 @@ size_t bgs_render_workspace_bytes(const bgs_frame* frame, const bgs_render_cfg* 
  * the work items of `frame` (8x8 sub-tiles, 16x16 tiles or 32x32 blocks of
  * 2x2 tiles, by cfg->subtile) into the workspace in the order cfg->order asks
  * for and resets the fetch counters.  For BGS_ORDER_COST the forward cost
- * estimate of a tile is its list length; when n_contrib (nullable, [H][W]
- * from the forward pass) is given the cost is the largest n_contrib in the
- * tile (the backward's exact walk); a block costs the sum of its tiles.
+ * estimate of a tile is the list position by which its entries' opacities
+ * alone could first take the transmittance below 1e-4 (the shortest walk any
+ * of its pixels can have); when n_contrib (nullable, [H][W] from the forward
+ * pass) is given the cost is the largest n_contrib in the tile (the
+ * backward's exact walk); a block costs the sum of its tiles.
  * bgs_render_fwd / bgs_render_bwd call this themselves.  The workspace
  * begins with the queue's state: 64 uint32 fetch counters 128 bytes apart
  * (counter q at byte 128 q), then at byte 8192 the number of items.

@@ -1286,9 +1286,10 @@ __device__ __forceinline__ int cost_bucket(uint32_t c) {
     return b < NBUCKET - 1 ? b : NBUCKET - 1;
 }
 
-// Cost of every work item (one workgroup per item): a tile costs its list
-// length (forward) or the largest n_contrib among its 256 pixels (backward);
-// with block2 the item is a 32x32 block and costs the sum over its tiles.
+// Backward cost of every work item (one workgroup per item): a tile costs
+// the largest n_contrib among its 256 pixels (clamped into its list, as the
+// backward clamps it) -- the length of the walk; with block2 the item is a
+// 32x32 block and costs the sum over its tiles.
 __global__ __launch_bounds__(256) void k_tile_costs(FrameArgs F, const int* __restrict__ n_contrib, int block2,
                                                     uint32_t* __restrict__ cost) {
     __shared__ int wmax[4];
@@ -1302,22 +1303,68 @@ __global__ __launch_bounds__(256) void k_tile_costs(FrameArgs F, const int* __re
     uint32_t c = 0;
     for (int k = 0; k < nt; ++k) {
         const int tile = tiles[k];
-        if (n_contrib) {
-            const int tx = tile % F.TX, ty = tile / F.TX;
-            const int px = tx * TILE + (threadIdx.x & 15), py = ty * TILE + (threadIdx.x >> 4);
-            const int len = (int)(F.ranges[2 * tile + 1] - F.ranges[2 * tile]);
-            int nc = (px < F.W && py < F.H) ? n_contrib[(int64_t)py * F.W + px] : 0;
-            nc = nc < 0 ? 0 : (nc > len ? len : nc);  // as the backward clamps it
-            const int m = wave_max(nc);
-            if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-            __syncthreads();
-            c += (uint32_t)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
-            __syncthreads();
-        } else {
-            c += F.ranges[2 * tile + 1] - F.ranges[2 * tile];
-        }
+        const int tx = tile % F.TX, ty = tile / F.TX;
+        const int px = tx * TILE + (threadIdx.x & 15), py = ty * TILE + (threadIdx.x >> 4);
+        const int len = (int)(F.ranges[2 * tile + 1] - F.ranges[2 * tile]);
+        int nc = (px < F.W && py < F.H) ? n_contrib[(int64_t)py * F.W + px] : 0;
+        nc = nc < 0 ? 0 : (nc > len ? len : nc);
+        const int m = wave_max(nc);
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+        __syncthreads();
+        c += (uint32_t)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+        __syncthreads();
     }
     if (threadIdx.x == 0) cost[blockIdx.x] = c;
+}
+
+// Forward cost estimate of a work item, one wave per item: the list position
+// by which the entries' opacities alone could first take T below 1e-4,
+// i.e. the first position where sum_i -log2(1 - min(0.99, o_i)) reaches
+// log2(1e4) -- the shortest walk any pixel of the tile can have, met when every
+// entry covers the pixel at its peak (the list length if never).  It ranks a
+// tile behind many faint entries (a long walk) above one whose first entries
+// are opaque, where the list length, the same K for every capped list, cannot.
+// A block item costs the sum over its tiles.
+__global__ __launch_bounds__(256) void k_fwd_costs(FrameArgs F, int block2, int n_items, uint32_t* __restrict__ cost) {
+    const int item = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (item >= n_items) return;  // uniform per wave
+    int tiles[4];
+    int nt = 1;
+    if (block2) {
+        nt = item_tiles<4>(F, (uint32_t)item, tiles);
+    } else {
+        tiles[0] = item;
+    }
+    constexpr float BUDGET = 13.287712379549449f;  // log2(1 / 1e-4)
+    uint32_t c = 0;
+    for (int k = 0; k < nt; ++k) {
+        const uint32_t start = __builtin_amdgcn_readfirstlane(F.ranges[2 * tiles[k]]);
+        const uint32_t end = __builtin_amdgcn_readfirstlane(F.ranges[2 * tiles[k] + 1]);
+        float acc = 0.0f;
+        uint32_t walk = end - start;
+        for (uint32_t base = start; base < end; base += 64) {
+            const uint32_t i = base + (uint32_t)lane;
+            const float o = i < end ? F.conic_opacity[F.point_list[i]].w : 0.0f;
+            const float w = -__builtin_amdgcn_logf(1.0f - fminf(ALPHA_MAX, fmaxf(o, 0.0f)));
+            // inclusive prefix sum over the wave (identity 0 for the shifted-in lanes)
+            float x = w;
+            x += dpp_or<0x111>(x, 0.0f);       // row_shr:1
+            x += dpp_or<0x112>(x, 0.0f);       // row_shr:2
+            x += dpp_or<0x114>(x, 0.0f);       // row_shr:4
+            x += dpp_or<0x118>(x, 0.0f);       // row_shr:8
+            x += dpp_or<0x142, 0xA>(x, 0.0f);  // row_bcast:15
+            x += dpp_or<0x143, 0xC>(x, 0.0f);  // row_bcast:31
+            const uint64_t hit = ballot(i < end && acc + x >= BUDGET);
+            if (hit) {
+                walk = base + (uint32_t)__builtin_ctzll(hit) + 1u - start;
+                break;
+            }
+            acc += readlane_f(x, 63);
+        }
+        c += walk;
+    }
+    if (lane == 0) cost[item] = c;
 }
 
 // Batched views: global tile g (over all views, tile_off = per-view prefix of
@@ -1526,7 +1573,11 @@ static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, con
     const bool blocks = block_items(cfg);
     const int n_cost = blocks ? (int)queue_items(A, cfg) : A.n_tiles;
     if (by_cost && n_cost > 0) {
-        hipLaunchKernelGGL(k_tile_costs, dim3(n_cost), dim3(256), 0, stream, A, n_contrib, blocks ? 1 : 0, cost);
+        if (n_contrib)  // backward: the exact walk
+            hipLaunchKernelGGL(k_tile_costs, dim3(n_cost), dim3(256), 0, stream, A, n_contrib, blocks ? 1 : 0, cost);
+        else  // forward: the opacity-budget estimate
+            hipLaunchKernelGGL(k_fwd_costs, dim3((n_cost + 3) / 4), dim3(256), 0, stream, A, blocks ? 1 : 0, n_cost,
+                               cost);
         BGS_HIP(hipGetLastError());
     }
     const int per_tile = tile_items(cfg) ? 1 : 0;

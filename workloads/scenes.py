@@ -30,13 +30,13 @@ Recipes (sizes follow the five measured workloads; seeds are 17378 + id):
         few pixels reach the transmittance cut-off and per-pixel work follows
         the per-tile list length.  Reported beside "1", never instead of it.
   "1-hotspot"
-        supplementary stress variant of "1" with a hot spot: 20 000 more
-        Gaussians with log-scales N(-2.5, 0.2) and opacity U[0.005, 0.008],
-        centred within +-0.02 (x, y) of (-0.3, 0.9) at z in [3, 5] -- a few
-        tiles near the bottom of the frame, late in raster order, whose pixels
-        each walk thousands of faint entries before stopping, so the heaviest
-        tile outweighs a SIMD's fair share (tail ratio R > 1).  Reported
-        beside "1", never instead of it.
+        supplementary stress variant of "1" with a hot spot: 3 000 more faint
+        Gaussians (log-scales N(-4.3, 0.1), opacity U[0.006, 0.009]) at z in
+        [2.2, 2.8], in front of the scene box, all projecting within 6 px of
+        pixel (730, 930) -- a few tiles near the bottom of the frame, late in
+        raster order, whose pixels each walk thousands of faint entries before
+        stopping, so the heaviest tile outweighs a SIMD's fair share (tail
+        ratio R > 1).  Reported beside "1", never instead of it.
   "tiny-N"
         small scenes for brute-force checks (N Gaussians, 48x40 image, f=48).
 """
@@ -200,15 +200,19 @@ def scene1_translucent(seed: Optional[int] = None, n_total: int = 500_000) -> Sc
     return _finish("1-translucent", seed, means, ls, q, op, rgb, -1, [_axis_camera(1920, 1080, 1920)])
 
 
-def scene1_hotspot(seed: Optional[int] = None, n_total: int = 500_000, n_hot: int = 20_000) -> Scene:
+def scene1_hotspot(seed: Optional[int] = None, n_total: int = 500_000, n_hot: int = 3_000) -> Scene:
     seed = SEED_BASE + 102 if seed is None else seed
     rng = _rng(seed)
     means, ls, q, op, rgb = _scene1_arrays(rng, n_total)
-    hot = _uniform_box(rng, n_hot, -0.32, -0.28, 0.88, 0.92)
+    # in front of the scene box, all projecting within +-6 px of pixel (730, 930)
+    z = rng.uniform(2.2, 2.8, n_hot)
+    u = 730.0 + rng.uniform(-6.0, 6.0, n_hot)
+    v = 930.0 + rng.uniform(-6.0, 6.0, n_hot)
+    hot = np.stack([(u + 0.5 - 960.0) * z / 1920.0, (v + 0.5 - 540.0) * z / 1920.0, z], axis=1)
     means = np.concatenate([means, hot])
-    ls = np.concatenate([ls, rng.normal(-2.5, 0.2, (n_hot, 3))])
+    ls = np.concatenate([ls, rng.normal(-4.3, 0.1, (n_hot, 3))])
     q = np.concatenate([q, _quats(rng, n_hot)])
-    op = np.concatenate([op, rng.uniform(0.005, 0.008, n_hot)])
+    op = np.concatenate([op, rng.uniform(0.006, 0.009, n_hot)])
     rgb = np.concatenate([rgb, rng.uniform(0.0, 1.0, (n_hot, 3))])
     return _finish("1-hotspot", seed, means, ls, q, op, rgb, -1, [_axis_camera(1920, 1080, 1920)])
 

@@ -144,12 +144,15 @@ typedef struct bgs_render_cfg {
     /* Optional queue audit (DEVICE, nullable, caller-zeroed): the balanced
        kernels of a one-view render add 1 to item_claims[i] each time a wave
        takes work item i from the task pool (Alg. 1), so after a render every
-       entry is 1.  Items: subtile 8 -> tile * 4 + quadrant (4 n_tiles of
-       them), subtile 16 -> tile, subtile 32 -> block (ty / 2) *
-       ceil(TX / 2) + tx / 2.  With BGS_FLAG_SPLIT_WALKS the two parts of a
-       split tile t count at item_claims[t] (lower) and item_claims[n_tiles +
-       t] (upper), so the array needs 2 n_tiles entries.  Ignored by the
-       static variants and by plans. */
+       dealt item shows exactly 1.  Items: subtile 8 -> tile * 4 + quadrant
+       (4 n_tiles of them); subtile 32 -> block (ty / 2) * ceil(TX / 2) +
+       tx / 2; subtile 16 -> tile + u * n_tiles with u the part of the tile's
+       work the item covers: 0 the whole tile, 1 / 2 the lower / upper part of
+       its backward walk (BGS_FLAG_SPLIT_WALKS), 3 + q the 16x4 pixel block q
+       alone, 7 + 2 q + p part p of block q's walk -- cost-ordered queues deal
+       a tile whose cost reaches a threshold as four blocks (and, with split
+       walks, parts), so the array needs 15 n_tiles entries there.  Ignored by
+       the static variants and by plans. */
     uint32_t* item_claims;
     /* With BGS_FLAG_SPLIT_WALKS: the forward's out_color [3][H][W] and
        out_depth [H][W] of this frame (DEVICE, read only by the backward). */
@@ -352,8 +355,8 @@ bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cfg* cfg, flo
  * device memory (code under stream capture, serving loops, harnesses that
  * forbid hipMalloc): the same render, same arguments minus ws / ws_bytes,
  * with the balanced variants' work queue kept in a device array inside the
- * library (bgs_render_fwd_noalloc_max_bytes() bytes per device, held until
- * the process ends; queues of up to 65 536 tiles).  Allocates nothing and
+ * library (bgs_render_fwd_noalloc_max_bytes() = 2.5 MiB per device, held
+ * until the process ends; queues of up to 65 536 tiles).  Allocates nothing and
  * builds the queue on every call (BGS_FLAG_QUEUE_READY is ignored).  A frame
  * whose queue does not fit returns BGS_ECAPACITY before any work is queued.
  * All calls on one device share that array: calls that overlap on one device

@@ -34,6 +34,7 @@
 namespace bgs {
 
 constexpr int NBUCKET = 136;         // cost buckets: 0 and quarter-octaves of 1 .. 2^33
+static_assert(NBUCKET <= 3 * 64, "k_queue_deal scans three buckets per lane");
 constexpr int HYBRID_SWITCH = 16;    // hybrid: Gaussian-wise once <= 16 of 64 pixels are active
 constexpr int WQ = 4;                // pixels per lane of the wave-per-tile kernels
 
@@ -321,9 +322,8 @@ __device__ __forceinline__ WorkQueue make_queue(uint32_t* ctr, const uint32_t* i
 
 __device__ __forceinline__ void note_claim(const WorkQueue& Q, int lane, uint32_t item) {
     if (Q.claims && lane == 0) {
-        uint32_t i = item & LOCAL_MASK;
-        if (i & (1u << 25)) i = (i & ((1u << 24) - 1u)) + ((i & (1u << 24)) ? Q.nt : 0u);  // part of a split walk
-        atomicAdd(&Q.claims[i], 1u);
+        // one-view items: tile + unit * n_tiles (unit 0 for sub-tile and block items)
+        atomicAdd(&Q.claims[(item & ((1u << 24) - 1u)) + (item >> 24) * Q.nt], 1u);
     }
 }
 
@@ -635,6 +635,37 @@ __device__ __forceinline__ uint32_t block_mask(float u, float v, float a, float 
     return m;
 }
 
+// Work items of the wave-per-tile kernels.  A one-view item is a tile id
+// (bits 0-23) and a unit u (bits 24-27) naming the part of the tile's work it
+// covers: u = 0 the whole tile; u = 1 / 2 the lower / upper part of its
+// backward walk (split walks, below); u = 3 + q block q alone, the 16x4
+// pixels of pixel row q of the lanes; u = 7 + 2q + p part p of block q's walk.
+// The queue builder deals a tile whose cost reaches BLOCK_MIN as four block
+// items -- four waves instead of one on the tile's critical path (the finer
+// tasks of Sec. 4.3, used only where a tile would otherwise dominate the
+// kernel) -- and, with split walks, a backward walk of SPLIT_MIN entries or
+// more as two parts.  The tile id space is 24 bits (at most 16.7 M tiles).
+constexpr uint32_t ITEM_TILE = (1u << 24) - 1u;
+constexpr int UNIT_SHIFT = 24;
+constexpr int SPLIT_MIN = 128;       // backward walks of at least this many entries split in two
+constexpr int BLOCK_MIN_FWD = 256;   // forward cost estimate at which a tile becomes four block items
+constexpr int BLOCK_MIN_BWD = 512;   // backward walk at which a tile becomes four block items
+
+// Blocks an item covers (4 bits) and the part of the walk (0 whole, 1 lower, 2 upper).
+__host__ __device__ __forceinline__ uint32_t unit_blocks(uint32_t u) {
+    return u >= 7 ? 1u << ((u - 7) >> 1) : (u >= 3 ? 1u << (u - 3) : 0xFu);
+}
+__host__ __device__ __forceinline__ int unit_part(uint32_t u) {
+    return u >= 7 ? 1 + (int)((u - 7) & 1u) : (u == 1 ? 1 : (u == 2 ? 2 : 0));
+}
+
+// Split point of a walk of n entries (n >= SPLIT_MIN): near n / 2, a
+// multiple of 64, at least 64, below n.
+__host__ __device__ __forceinline__ int split_point(int n) {
+    const int k = ((n / 2 + 32) / 64) * 64;
+    return k < 64 ? 64 : k;
+}
+
 // LDS slice of one wave: 64 staged entries.  xym = (x, y, block mask bits,
 // Gaussian id bits), co = (a2, r, q2, opacity) of splat_power2, cd = (rgb,
 // depth), abc = the raw conic (backward only).
@@ -791,6 +822,92 @@ __device__ __forceinline__ void fwd_tile(const FrameArgs& F, const FwdOut& O, in
     }
 }
 
+// One wave renders block q of tile `tile` alone (one pixel per lane): the
+// block items of heavy tiles.  The walk is fwd_tile's restricted to the
+// entries whose block mask has bit q.  When a heavy tile is all that is left
+// its waves are alone on their SIMDs and the walk's latency is the cost, so
+// entries go in groups of FB_GROUP: their LDS reads, exponents and alphas
+// are independent and overlap, and only the transmittance update runs entry
+// after entry, front to back.  A group short of entries repeats its first
+// one with an empty lane mask, which takes nothing (its blend adds colour
+// times zero, as for every entry a pixel skips).  Same per-pixel arithmetic
+// as blend().
+constexpr int FB_GROUP = 4;
+template <bool COUNT>
+__device__ __forceinline__ void fwd_block(const FrameArgs& F, const FwdOut& O, int tile, int q, int lane,
+                                          WaveStage& st) {
+    constexpr int G = FB_GROUP;
+    const int tx = tile % F.TX, ty = tile / F.TX;
+    const int x0 = tx * TILE, y0 = ty * TILE;
+    const int px = x0 + (lane & 15), py = y0 + (lane >> 4) + 4 * q;
+    const float fx = (float)px, fy = (float)py;
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
+    int last = 0, stop_at = -1;
+    uint64_t done_m = ~ballot(px < F.W && py < F.H);
+    const uint32_t start = __builtin_amdgcn_readfirstlane(F.ranges[2 * tile]);
+    const uint32_t end = __builtin_amdgcn_readfirstlane(F.ranges[2 * tile + 1]);
+    RawSplat cur{}, nxt{};
+    uint32_t idn = 0;
+    if (start < end) {
+        load_raw(F, chunk_id(F, start, end, lane), cur);
+        if (start + 64 < end) idn = chunk_id(F, start + 64, end, lane);
+    }
+    for (uint32_t base = start; base < end && ~done_m; base += 64) {
+        uint64_t todo = ballot((stage_entry(st, lane, cur, base + lane < end, x0, y0) >> q) & 1u);
+        wave_sync();
+        if (base + 64 < end) load_raw(F, idn, nxt);
+        if (base + 128 < end) idn = chunk_id(F, base + 128, end, lane);
+        const int pos0 = (int)(base - start) + 1;
+        while (todo && ~done_m) {
+            int j[G];
+            uint64_t use[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const bool has = todo != 0;
+                j[k] = has ? (int)__builtin_ctzll(todo) : j[0];
+                use[k] = has ? ~0ull : 0ull;
+                todo &= todo - 1;
+            }
+            float4 xym[G], co[G], cd[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                xym[k] = st.xym[j[k]];
+                co[k] = st.co[j[k]];
+                cd[k] = st.cd[j[k]];
+            }
+            float pw[G], al[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                pw[k] = splat_power2(fx - xym[k].x, fy - xym[k].y, co[k].x, co[k].y, co[k].z);
+                al[k] = fminf(ALPHA_MAX, co[k].w * exp2_fast(pw[k]));
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const uint64_t cand = ballot(!(pw[k] > 0.0f)) & ballot(!(al[k] < ALPHA_MIN)) & ~done_m & use[k];
+                const float w = al[k] * T;
+                const float Tn = T - w;
+                const uint64_t stop = cand & ballot(Tn < T_MIN);
+                const bool take = lane_bit(cand & ~stop);
+                const float we = take ? w : 0.0f;
+                C0 = __builtin_fmaf(cd[k].x, we, C0);
+                C1 = __builtin_fmaf(cd[k].y, we, C1);
+                C2 = __builtin_fmaf(cd[k].z, we, C2);
+                D = __builtin_fmaf(cd[k].w, we, D);
+                T = take ? Tn : T;
+                last = take ? pos0 + j[k] : last;
+                if (COUNT) stop_at = lane_bit(stop) ? pos0 + j[k] : stop_at;
+                done_m |= stop;
+            }
+        }
+        wave_sync();
+        cur = nxt;
+    }
+    if (px < F.W && py < F.H) {
+        write_pixel(F, O, px, py, Pix{T, C0, C1, C2, D, last, lane_bit(done_m)});
+        if (COUNT) F.n_examined[(int64_t)py * F.W + px] = stop_at >= 0 ? stop_at : (int)(end - start);
+    }
+}
+
 // Tiles of a work item: TPI = 1 -> the item is a tile; TPI = 4 -> the item
 // is a 32x32 block of 2x2 tiles (those inside the grid), rendered in turn.
 template <int TPI>
@@ -810,12 +927,14 @@ __device__ __forceinline__ int item_tiles(const FrameArgs& F, uint32_t item, int
     return n;
 }
 
-// PERSISTENT: waves take items from the task pool (early claim); otherwise
-// wave w of the grid renders item w (grid-static dispatch of the same code).
+// PERSISTENT: waves take items from the task pool; otherwise wave w of the
+// grid renders item w (grid-static dispatch of the same code).  Five waves
+// per SIMD: the register budget of 96 leaves one scalar-spill register
+// to memory, outside the walk.
 template <bool MV = false, bool COUNT = false, bool PERSISTENT = true, int TPI = 1>
-__global__ __launch_bounds__(256) void k_fwd_wide(FrameArgs F0, FwdOut O0, const ViewDesc* __restrict__ views,
-                                                  const uint32_t* __restrict__ items, uint32_t* __restrict__ ctr,
-                                                  uint32_t n_static) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_fwd_wide(
+    FrameArgs F0, FwdOut O0, const ViewDesc* __restrict__ views, const uint32_t* __restrict__ items,
+    uint32_t* __restrict__ ctr, uint32_t n_static) {
     const uint64_t t_begin = trace_begin(F0);
     __shared__ WaveStage s_st[4];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -831,9 +950,18 @@ __global__ __launch_bounds__(256) void k_fwd_wide(FrameArgs F0, FwdOut O0, const
         }
         const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
         const FwdOut O = MV ? views[item >> VIEW_SHIFT].O : O0;
-        int tiles[TPI];
-        const int nt = item_tiles<TPI>(F, item & LOCAL_MASK, tiles);
-        for (int k = 0; k < nt; ++k) fwd_tile<COUNT>(F, O, tiles[k], lane, s_st[wv]);
+        const uint32_t code = MV ? (item & LOCAL_MASK) : item;
+        if (TPI == 1) {
+            const uint32_t u = code >> UNIT_SHIFT;  // 0: the whole tile, 3 + q: block q (forward units)
+            if (u >= 3)
+                fwd_block<COUNT>(F, O, (int)(code & ITEM_TILE), (int)(u - 3), lane, s_st[wv]);
+            else
+                fwd_tile<COUNT>(F, O, (int)(code & ITEM_TILE), lane, s_st[wv]);
+        } else {
+            int tiles[TPI];
+            const int nt = item_tiles<TPI>(F, code, tiles);
+            for (int k = 0; k < nt; ++k) fwd_tile<COUNT>(F, O, tiles[k], lane, s_st[wv]);
+        }
         if (!PERSISTENT) break;
     }
     trace_end(F0, t_begin, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
@@ -1000,17 +1128,6 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
 // The split point of a tile with deepest n_contrib N is split_point(N); the
 // queue builder and the kernel compute it from the same N.
 
-// Split point of a walk of n entries (n >= SPLIT_MIN): near n / 2, a
-// multiple of 64, at least 64, below n.
-constexpr int SPLIT_MIN = 128;
-constexpr uint32_t ITEM_SPLIT = 1u << 25;  // the item is one part of a split walk ...
-constexpr uint32_t ITEM_UPPER = 1u << 24;  // ... the upper part [k, N) (else the lower [0, k))
-constexpr uint32_t ITEM_TILE = (1u << 24) - 1u;
-
-__host__ __device__ __forceinline__ int split_point(int n) {
-    const int k = ((n / 2 + 32) / 64) * 64;
-    return k < 64 ? 64 : k;
-}
 
 // Gradient terms of one (pixel, entry) pair added into the lane's ten sums.
 __device__ __forceinline__ void add_terms(float (&v)[10], float w, float dA, float G, float ga, bool unclamped,
@@ -1035,7 +1152,7 @@ __device__ __forceinline__ void add_terms(float (&v)[10], float w, float dA, flo
 // part: 0 the whole walk, 1 the lower part of a split walk, 2 the upper part.
 template <bool DET>
 __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int tile, int lane, WaveStage& st,
-                                         float4* __restrict__ s_abc, int part) {
+                                         float4* __restrict__ s_abc, int part, uint32_t bmask = 0xFu) {
     const int64_t HW = (int64_t)F.W * F.H;
     const int tx = tile % F.TX, ty = tile / F.TX;
     const int x0 = tx * TILE, y0 = ty * TILE;
@@ -1051,15 +1168,18 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
     float T[WQ], S[WQ], gC0[WQ], gC1[WQ], gC2[WQ], gD[WQ], fy[WQ];
     int nc[WQ], bmax[WQ];
     int max_n = 0;
+    int tile_max = 0;  // the deepest walk of the whole tile: the split point comes from it
 #pragma unroll
     for (int q = 0; q < WQ; ++q) {
         const int py = y0 + (lane >> 4) + 4 * q;
-        const bool inside = px < F.W && py < F.H;
-        const int64_t p = inside ? (int64_t)py * F.W + px : 0;
-        const float TN = inside ? B.final_T[p] : 1.0f;
-        int n = inside ? B.n_contrib[p] : 0;
+        const bool in_image = px < F.W && py < F.H;
+        const int64_t p = in_image ? (int64_t)py * F.W + px : 0;
+        int n = in_image ? B.n_contrib[p] : 0;
         n = n < 0 ? 0 : (n > len ? len : n);  // stay inside the tile's list
-        nc[q] = n;
+        tile_max = n > tile_max ? n : tile_max;
+        const bool inside = in_image && ((bmask >> q) & 1u);  // pixels of a block this item covers
+        const float TN = inside ? B.final_T[p] : 1.0f;
+        nc[q] = inside ? n : 0;
         gC0[q] = inside ? B.dL_dcolor[p] : 0.f;
         gC1[q] = inside ? B.dL_dcolor[HW + p] : 0.f;
         gC2[q] = inside ? B.dL_dcolor[2 * HW + p] : 0.f;
@@ -1081,7 +1201,7 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
         bmax[q] = __builtin_amdgcn_readfirstlane(wave_max(nc[q]));  // uniform: block q walks entries < bmax[q]
         max_n = bmax[q] > max_n ? bmax[q] : max_n;
     }
-    const int k = part ? split_point(max_n) : 0;
+    const int k = part ? split_point(__builtin_amdgcn_readfirstlane(wave_max(tile_max))) : 0;
     // the entries this item walks: [lo_end, hi_end)
     const int lo_end = part == 2 ? k : 0;
     const int hi_end = part == 1 ? (k < max_n ? k : max_n) : max_n;
@@ -1266,9 +1386,11 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
         }
         const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
         const BwdIO B = MV ? views[item >> VIEW_SHIFT].B : B0;
-        const uint32_t code = item & LOCAL_MASK;
-        if (SPLIT && TPI == 1 && (code & ITEM_SPLIT)) {
-            bwd_tile<DET>(F, B, (int)(code & ITEM_TILE), lane, s_st[wv], s_abc[wv], (code & ITEM_UPPER) ? 2 : 1);
+        const uint32_t code = MV ? (item & LOCAL_MASK) : item;
+        if (TPI == 1) {
+            const uint32_t u = code >> UNIT_SHIFT;
+            bwd_tile<DET>(F, B, (int)(code & ITEM_TILE), lane, s_st[wv], s_abc[wv], SPLIT ? unit_part(u) : 0,
+                          unit_blocks(u));
         } else {
             int tiles[TPI];
             const int nt = item_tiles<TPI>(F, code, tiles);
@@ -1399,13 +1521,93 @@ __global__ __launch_bounds__(256) void k_tile_costs_mv(const ViewDesc* __restric
 // its sub-tile s to queue 4 (r mod 16) + s, at queue position r / 16.  Tile
 // items (per_tile): queue r mod 64, position r / 64.  Also resets the 64 fetch
 // counters and stores the item count.
-__global__ __launch_bounds__(1024) void k_queue(int n_tiles, const uint32_t* __restrict__ cost, int by_cost,
-                                                int per_tile, const uint32_t* __restrict__ tile_off, int n_views,
-                                                int split_min, uint32_t* __restrict__ items,
-                                                uint32_t* __restrict__ ctr) {
+// Units a tile of cost c is dealt as (per-tile items, cost order, one view):
+// the whole tile; the two parts of its backward walk (c >= split_min); its
+// four blocks (c >= block_min); or both.  Returns the count; unit i has
+// unit code u[i] and cost w[i].
+__device__ __forceinline__ int tile_units(uint32_t c, int split_min, int block_min, uint32_t (&u)[8],
+                                          uint32_t (&w)[8]) {
+    const bool blk = block_min > 0 && c >= (uint32_t)block_min;
+    const bool prt = split_min > 0 && c >= (uint32_t)split_min;
+    const uint32_t k = prt ? (uint32_t)split_point((int)c) : 0u;
+    if (!blk && !prt) {
+        u[0] = 0; w[0] = c;
+        return 1;
+    }
+    if (!blk) {
+        u[0] = 1; w[0] = k;
+        u[1] = 2; w[1] = c - k;
+        return 2;
+    }
+    if (!prt) {
+        for (int q = 0; q < 4; ++q) {
+            u[q] = 3 + q; w[q] = c;
+        }
+        return 4;
+    }
+    for (int q = 0; q < 4; ++q) {
+        u[2 * q] = 7 + 2 * q; w[2 * q] = k;
+        u[2 * q + 1] = 8 + 2 * q; w[2 * q + 1] = c - k;
+    }
+    return 8;
+}
+
+// The cost-order queue is a counting sort of the work units by descending
+// cost bucket, spread over workgroups of QB tiles: k_queue_count takes each
+// workgroup's bucket histogram, k_queue_deal gives every unit its rank --
+// the units of all higher buckets, of its own bucket in earlier workgroups,
+// and an LDS atomic within its workgroup -- and deals it.  (One workgroup
+// for the whole frame spends its time on same-address LDS atomics: tiles of
+// a frame fall into a few buckets.)
+constexpr int QB = 1024;
+
+__host__ __device__ __forceinline__ int queue_groups(int n_tiles) { return n_tiles > 0 ? (n_tiles + QB - 1) / QB : 1; }
+
+// Units of tile t (0 past the end), with codes u and costs w.
+__device__ __forceinline__ int queue_units(uint32_t t, int n_tiles, const uint32_t* __restrict__ cost, bool units,
+                                           int split_min, int block_min, uint32_t (&u)[8], uint32_t (&w)[8]) {
+    if (t >= (uint32_t)n_tiles) return 0;
+    const uint32_t c = cost[t];
+    if (units) return tile_units(c, split_min, block_min, u, w);
+    u[0] = 0;
+    w[0] = c;
+    return 1;
+}
+
+// Finer units for heavy tiles: one-view per-tile items in cost order only.
+__device__ __forceinline__ bool queue_has_units(int by_cost, int per_tile, const uint32_t* tile_off, int split_min,
+                                                int block_min) {
+    return by_cost && per_tile && !tile_off && (split_min > 0 || block_min > 0);
+}
+
+__global__ __launch_bounds__(QB) void k_queue_count(int n_tiles, const uint32_t* __restrict__ cost, int per_tile,
+                                                    const uint32_t* __restrict__ tile_off, int split_min,
+                                                    int block_min, uint32_t* __restrict__ qhist) {
     __shared__ uint32_t hist[NBUCKET];
+    for (int b = threadIdx.x; b < NBUCKET; b += QB) hist[b] = 0;
+    __syncthreads();
+    const bool units = queue_has_units(1, per_tile, tile_off, split_min, block_min);
+    uint32_t u[8], w[8];
+    const int n = queue_units(blockIdx.x * QB + threadIdx.x, n_tiles, cost, units, split_min, block_min, u, w);
+    for (int i = 0; i < n; ++i) atomicAdd(&hist[NBUCKET - 1 - cost_bucket(w[i])], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < NBUCKET; b += QB) qhist[(size_t)blockIdx.x * NBUCKET + b] = hist[b];
+}
+
+// Ranks tiles (raster order, or by descending cost bucket from the
+// histograms of k_queue_count) and deals them.  Sub-tile items: tile of rank
+// r goes to queue group r mod 16, its sub-tile s to queue 4 (r mod 16) + s,
+// at queue position r / 16.  Tile items (per_tile): queue r mod 64, position
+// r / 64.  Workgroup 0 also resets the 64 fetch counters and stores the
+// item count.
+__global__ __launch_bounds__(QB) void k_queue_deal(int n_tiles, const uint32_t* __restrict__ cost, int by_cost,
+                                                   int per_tile, const uint32_t* __restrict__ tile_off, int n_views,
+                                                   int split_min, int block_min, const uint32_t* __restrict__ qhist,
+                                                   uint32_t* __restrict__ items, uint32_t* __restrict__ ctr) {
+    __shared__ uint32_t tot[NBUCKET], pre[NBUCKET];
     __shared__ uint32_t n_units;
-    auto deal = [&](uint32_t r, uint32_t tile, uint32_t part_bits) {
+    const int lane = threadIdx.x & 63;
+    auto deal = [&](uint32_t r, uint32_t tile, uint32_t unit) {
         uint32_t vbits = 0;
         if (tile_off) {  // batched views: global tile -> (view, tile of the view)
             int v = 0;
@@ -1414,63 +1616,80 @@ __global__ __launch_bounds__(1024) void k_queue(int n_tiles, const uint32_t* __r
             vbits = (uint32_t)v << VIEW_SHIFT;
         }
         if (per_tile) {  // tile of rank r: queue r mod 64, position r / 64, i.e. items[r]
-            items[r] = vbits | part_bits | tile;
+            items[r] = vbits | (unit << UNIT_SHIFT) | tile;
             return;
         }
         const uint32_t grp = r % QGROUPS, pos = r / QGROUPS;
         for (uint32_t sub = 0; sub < 4; ++sub) items[(size_t)pos * NQ + grp * 4 + sub] = vbits | (tile * 4 + sub);
     };
-    // split walks (per-tile items, cost order): a tile whose walk has at least
-    // split_min entries becomes two items, ranked by the length of each part
-    const bool split = by_cost && per_tile && split_min > 0 && !tile_off;
+    const bool units = queue_has_units(by_cost, per_tile, tile_off, split_min, block_min);
+    const uint32_t t = blockIdx.x * QB + threadIdx.x;
     if (!by_cost) {
-        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x) deal(t, t, 0u);
+        if (t < (uint32_t)n_tiles) deal(t, t, 0u);
     } else {
-        for (int b = threadIdx.x; b < NBUCKET; b += blockDim.x) hist[b] = 0;
-        if (threadIdx.x == 0) n_units = 0;
+        for (int b = threadIdx.x; b < NBUCKET; b += QB) tot[b] = pre[b] = 0;
         __syncthreads();
-        uint32_t units = 0;
-        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x) {
-            const uint32_t c = cost[t];
-            if (split && c >= (uint32_t)split_min) {
-                const uint32_t k = (uint32_t)split_point((int)c);
-                atomicAdd(&hist[NBUCKET - 1 - cost_bucket(k)], 1u);
-                atomicAdd(&hist[NBUCKET - 1 - cost_bucket(c - k)], 1u);
-                units += 2;
-            } else {
-                atomicAdd(&hist[NBUCKET - 1 - cost_bucket(c)], 1u);
-                units += 1;
-            }
-        }
-        atomicAdd(&n_units, units);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t run = 0;
-            for (int b = 0; b < NBUCKET; ++b) {
-                const uint32_t h = hist[b];
-                hist[b] = run;
-                run += h;
+        // bucket totals over all workgroups, and this workgroup's predecessors' share
+        const int ng = (int)gridDim.x;
+        for (int k = threadIdx.x; k < ng * NBUCKET; k += QB) {
+            const uint32_t h = qhist[k];
+            const int g = k / NBUCKET, b = k - g * NBUCKET;
+            if (h) {
+                atomicAdd(&tot[b], h);
+                if (g < (int)blockIdx.x) atomicAdd(&pre[b], h);
             }
         }
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < (uint32_t)n_tiles; t += blockDim.x) {
-            const uint32_t c = cost[t];
-            if (split && c >= (uint32_t)split_min) {
-                const uint32_t k = (uint32_t)split_point((int)c);
-                deal(atomicAdd(&hist[NBUCKET - 1 - cost_bucket(k)], 1u), t, ITEM_SPLIT);
-                deal(atomicAdd(&hist[NBUCKET - 1 - cost_bucket(c - k)], 1u), t, ITEM_SPLIT | ITEM_UPPER);
-            } else {
-                deal(atomicAdd(&hist[NBUCKET - 1 - cost_bucket(c)], 1u), t, 0u);
+        if (threadIdx.x < 64) {  // exclusive scan of the totals, three buckets per lane
+            uint32_t h[3], sum = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int b = 3 * lane + k;
+                h[k] = b < NBUCKET ? tot[b] : 0u;
+                sum += h[k];
             }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t o = (uint32_t)__shfl_up((int)incl, off, 64);
+                if (lane >= off) incl += o;
+            }
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int b = 3 * lane + k;
+                if (b < NBUCKET) pre[b] += run;  // first rank of the bucket in this workgroup
+                run += h[k];
+            }
+            if (lane == 63) n_units = incl;
         }
+        __syncthreads();
+        uint32_t u[8], w[8];
+        const int n = queue_units(t, n_tiles, cost, units, split_min, block_min, u, w);
+        for (int i = 0; i < n; ++i) deal(atomicAdd(&pre[NBUCKET - 1 - cost_bucket(w[i])], 1u), t, u[i]);
     }
-    for (int q = threadIdx.x; q < NQ; q += blockDim.x) ctr[q * QSTRIDE] = 0;
-    if (threadIdx.x == 0) ctr[NQ * QSTRIDE] = split ? n_units : (uint32_t)n_tiles * (per_tile ? 1u : 4u);
+    if (blockIdx.x == 0) {
+        for (int q = threadIdx.x; q < NQ; q += QB) ctr[q * QSTRIDE] = 0;
+        if (threadIdx.x == 0) ctr[NQ * QSTRIDE] = units ? n_units : (uint32_t)n_tiles * (per_tile ? 1u : 4u);
+    }
+}
+
+// Queue of n_tiles tiles (see k_queue_deal); qhist: queue_groups(n_tiles) *
+// NBUCKET words, used in cost order.
+static void launch_queue(hipStream_t stream, int n_tiles, const uint32_t* cost, int by_cost, int per_tile,
+                         const uint32_t* tile_off, int n_views, int split_min, int block_min, uint32_t* qhist,
+                         uint32_t* items, uint32_t* ctr) {
+    const int ng = queue_groups(n_tiles);
+    if (by_cost)
+        hipLaunchKernelGGL(k_queue_count, dim3(ng), dim3(QB), 0, stream, n_tiles, cost, per_tile, tile_off, split_min,
+                           block_min, qhist);
+    hipLaunchKernelGGL(k_queue_deal, dim3(ng), dim3(QB), 0, stream, n_tiles, cost, by_cost, per_tile, tile_off,
+                       n_views, split_min, block_min, (const uint32_t*)qhist, items, ctr);
 }
 
 // ---------------------------------------------------------------- host side
 struct RenderLayout {
-    size_t ctr, items, cost, bytes;
+    size_t ctr, items, cost, qhist, bytes;
     uint32_t n_items;
 };
 
@@ -1484,10 +1703,12 @@ static RenderLayout render_layout(int n_tiles) {
         return o;
     };
     L.ctr = take(4 * (size_t)(NQ * QSTRIDE + QSTRIDE));
-    // the item array is padded to whole rounds of NQ
-    const size_t rounds = ((size_t)n_tiles + QGROUPS - 1) / QGROUPS;
+    // the item array: room for four sub-tiles or up to eight units per tile
+    // (blocks, walk parts), padded to whole rounds of NQ
+    const size_t rounds = (8 * (size_t)n_tiles + NQ - 1) / NQ;
     L.items = take(4 * (rounds * NQ > 0 ? rounds * NQ : 1));
     L.cost = take(4 * (size_t)(n_tiles ? n_tiles : 1));
+    L.qhist = take(4 * (size_t)queue_groups(n_tiles) * NBUCKET);
     L.bytes = off;
     return L;
 }
@@ -1564,8 +1785,11 @@ static uint32_t queue_items(const FrameArgs& A, const bgs_render_cfg* cfg) {
     return (uint32_t)A.n_tiles * (tile_items(cfg) ? 1u : 4u);
 }
 
+// units: deal heavy tiles as finer units (blocks, walk parts) where the
+// configuration allows it (not for the deterministic backward, which keeps
+// one item per tile).
 static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, const int* n_contrib, char* ws,
-                              const RenderLayout& L, hipStream_t stream) {
+                              const RenderLayout& L, hipStream_t stream, bool units = true) {
     auto* ctr = reinterpret_cast<uint32_t*>(ws + L.ctr);
     auto* items = reinterpret_cast<uint32_t*>(ws + L.items);
     auto* cost = reinterpret_cast<uint32_t*>(ws + L.cost);
@@ -1581,10 +1805,13 @@ static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, con
         BGS_HIP(hipGetLastError());
     }
     const int per_tile = tile_items(cfg) ? 1 : 0;
-    // split walks: backward queues (n_contrib given) of the wave-per-tile kernels only
-    const int split_min = (split_walks(cfg) && n_contrib) ? SPLIT_MIN : 0;
-    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, n_cost, cost, by_cost, per_tile,
-                       (const uint32_t*)nullptr, 1, split_min, items, ctr);
+    // finer units for heavy tiles of the one-wave-per-tile kernels: four blocks
+    // in either direction, and split walks for backward queues (n_contrib given)
+    const bool wave_tile = units && cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 16;
+    const int split_min = (wave_tile && split_walks(cfg) && n_contrib) ? SPLIT_MIN : 0;
+    const int block_min = wave_tile ? (n_contrib ? BLOCK_MIN_BWD : BLOCK_MIN_FWD) : 0;
+    launch_queue(stream, n_cost, cost, by_cost, per_tile, nullptr, 1, split_min, block_min,
+                 reinterpret_cast<uint32_t*>(ws + L.qhist), items, ctr);
     BGS_HIP(hipGetLastError());
     return BGS_OK;
 }
@@ -1648,11 +1875,11 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
         hipLaunchKernelGGL((k_fwd_wide<false, false, true, 4>), dim3(blocks), dim3(256), 0, stream, A, O,
                            (const ViewDesc*)nullptr, items, ctr, 0u);
     } else if (tile_items(cfg) && A.n_examined) {
-        const int blocks = persistent_blocks(k_fwd_wide<false, true>, n_items);
+        const int blocks = persistent_blocks(k_fwd_wide<false, true>, 4 * n_items);
         hipLaunchKernelGGL((k_fwd_wide<false, true>), dim3(blocks), dim3(256), 0, stream, A, O,
                            (const ViewDesc*)nullptr, items, ctr, 0u);
     } else if (tile_items(cfg)) {
-        const int blocks = persistent_blocks(k_fwd_wide<false>, n_items);
+        const int blocks = persistent_blocks(k_fwd_wide<false>, 4 * n_items);  // up to four blocks per tile
         hipLaunchKernelGGL(k_fwd_wide<false>, dim3(blocks), dim3(256), 0, stream, A, O, (const ViewDesc*)nullptr,
                            items, ctr, 0u);
     } else if (cfg->variant == BGS_BALANCED_GAUSS) {
@@ -1677,7 +1904,7 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
 // until the process ends; its address is looked up once per device.
 namespace bgs {
 
-constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)3 << 19;  // 1.5 MiB: queues of up to 65 536 tiles
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)5 << 19;  // 2.5 MiB: queues of up to 65 536 tiles
 static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 constexpr int MAX_DEVICES = 64;
@@ -1770,12 +1997,12 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
         const int blocks = persistent_blocks(k_bwd_wide<false, false, true, 4>, n_items);
         hipLaunchKernelGGL((k_bwd_wide<false, false, true, 4>), dim3(blocks), dim3(256), 0, stream, A, B,
                            (const ViewDesc*)nullptr, items, ctr, 0u);
-    } else if (split_walks(cfg)) {  // up to two items per tile
-        const int blocks = persistent_blocks(k_bwd_wide<false, false, true, 1, true>, 2 * n_items);
+    } else if (split_walks(cfg)) {  // up to eight units per tile
+        const int blocks = persistent_blocks(k_bwd_wide<false, false, true, 1, true>, 8 * n_items);
         hipLaunchKernelGGL((k_bwd_wide<false, false, true, 1, true>), dim3(blocks), dim3(256), 0, stream, A, B,
                            (const ViewDesc*)nullptr, items, ctr, 0u);
     } else if (tile_items(cfg)) {
-        const int blocks = persistent_blocks(k_bwd_wide<false>, n_items);
+        const int blocks = persistent_blocks(k_bwd_wide<false>, 4 * n_items);  // up to four blocks per tile
         hipLaunchKernelGGL(k_bwd_wide<false>, dim3(blocks), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
                            items, ctr, 0u);
     } else {
@@ -1949,7 +2176,7 @@ extern "C" bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_rende
     char* w = static_cast<char*>(ws);
     *n_occ_host = 0;
     if (!(cfg->flags & BGS_FLAG_QUEUE_READY)) {
-        st = build_queue(A, cfg, n_contrib, w, D.R, stream);
+        st = build_queue(A, cfg, n_contrib, w, D.R, stream, false);  // one item per tile: one writer per slot
         if (st != BGS_OK) return st;
     }
     auto* cnt = reinterpret_cast<uint32_t*>(w + D.cnt);
@@ -2039,6 +2266,7 @@ struct bgs_plan {
     uint32_t* d_items = nullptr;
     uint32_t* d_cost = nullptr;
     uint32_t* d_ctr = nullptr;
+    uint32_t* d_qhist = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -2052,6 +2280,7 @@ extern "C" void bgs_plan_destroy(bgs_plan* plan) {
     (void)hipFree(plan->d_items);
     (void)hipFree(plan->d_cost);
     (void)hipFree(plan->d_ctr);
+    (void)hipFree(plan->d_qhist);
     delete plan;
 }
 
@@ -2109,6 +2338,9 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
         return cleanup_fail("hipMalloc", e);
     if ((e = hipMalloc(&plan->d_ctr, sizeof(uint32_t) * (NQ * QSTRIDE + QSTRIDE))) != hipSuccess)
         return cleanup_fail("hipMalloc", e);
+    if ((e = hipMalloc(&plan->d_qhist, sizeof(uint32_t) * NBUCKET * queue_groups((int)plan->total_tiles))) !=
+        hipSuccess)
+        return cleanup_fail("hipMalloc", e);
     if ((e = hipMemcpyAsync(plan->d_views, vd.data(), sizeof(ViewDesc) * n_views, hipMemcpyHostToDevice, stream)) !=
         hipSuccess)
         return cleanup_fail("hipMemcpyAsync", e);
@@ -2147,8 +2379,8 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
     if (by_cost)
         hipLaunchKernelGGL(k_tile_costs_mv, dim3(plan->total_tiles), dim3(256), 0, stream, plan->d_views,
                            plan->d_tile_off, n_views, 0, plan->d_cost);
-    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, (int)plan->total_tiles, plan->d_cost, by_cost,
-                       fwd_wide ? 1 : 0, plan->d_tile_off, n_views, 0, plan->d_items, plan->d_ctr);
+    launch_queue(stream, (int)plan->total_tiles, plan->d_cost, by_cost, fwd_wide ? 1 : 0, plan->d_tile_off, n_views,
+                 0, 0, plan->d_qhist, plan->d_items, plan->d_ctr);
     if (fwd_wide)
         hipLaunchKernelGGL((k_fwd_wide<true>), dim3(fblocks), dim3(256), 0, stream, F0, O0, plan->d_views,
                            plan->d_items, plan->d_ctr, 0u);
@@ -2158,8 +2390,8 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
     if (bwd_by_cost)
         hipLaunchKernelGGL(k_tile_costs_mv, dim3(plan->total_tiles), dim3(256), 0, stream, plan->d_views,
                            plan->d_tile_off, n_views, 1, plan->d_cost);
-    hipLaunchKernelGGL(k_queue, dim3(1), dim3(1024), 0, stream, (int)plan->total_tiles, plan->d_cost, bwd_by_cost,
-                       bwd_wide ? 1 : 0, plan->d_tile_off, n_views, 0, plan->d_items, plan->d_ctr);
+    launch_queue(stream, (int)plan->total_tiles, plan->d_cost, bwd_by_cost, bwd_wide ? 1 : 0, plan->d_tile_off,
+                 n_views, 0, 0, plan->d_qhist, plan->d_items, plan->d_ctr);
     if (bwd_wide)
         hipLaunchKernelGGL((k_bwd_wide<true>), dim3(bblocks), dim3(256), 0, stream, F0, B0, plan->d_views,
                            plan->d_items, plan->d_ctr, 0u);

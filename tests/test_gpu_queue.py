@@ -33,24 +33,44 @@ def _scene(name):
     return scenes.make(name)
 
 
+N_UNITS = 15  # parts of a tile's work a wave-per-tile item may cover (include/bgs.h, item_claims)
+# the ways a tile's work may be dealt: whole; two walk parts; four blocks; four blocks in two parts
+PARTITIONS = [{0}, {1, 2}, {3, 4, 5, 6}, set(range(7, 15))]
+
+
 def _n_items(W, H, sub):
     tx, ty = (W + 15) // 16, (H + 15) // 16
-    return {8: 4 * tx * ty, 16: tx * ty, 32: ((tx + 1) // 2) * ((ty + 1) // 2)}[sub]
+    return {8: 4 * tx * ty, 16: N_UNITS * tx * ty, 32: ((tx + 1) // 2) * ((ty + 1) // 2)}[sub]
 
 
-def _check_queue(rast, claims, n_items, what):
+def _check_queue(rast, claims, n_slots, what, nt=None):
+    """Every dealt item claimed exactly once.  For wave-per-tile queues (nt
+    given) the claims are per (tile, unit): each tile's claimed units must be
+    exactly one of the partitions of its work.  Then the queue state: the item
+    count as dealt, every counter at or past its queue's size."""
     c = claims.cpu().numpy()
-    assert np.all(c[:n_items] == 1), (what, "claims != 1 at", np.nonzero(c[:n_items] != 1)[0][:8],
-                                      c[:n_items][c[:n_items] != 1][:8])
-    assert np.all(c[n_items:] == 0), (what, "claim beyond the items")
-    ws = rast.ws.get("render", 0).view(torch.int32)[:NQ * QSTRIDE + 1].cpu().numpy().astype(np.int64)
-    n = int(ws[NQ * QSTRIDE])
-    assert n == n_items, (what, n, n_items)
+    assert np.all(c[n_slots:] == 0), (what, "claim beyond the items")
+    if nt is None:
+        assert np.all(c[:n_slots] == 1), (what, "claims != 1 at", np.nonzero(c[:n_slots] != 1)[0][:8],
+                                          c[:n_slots][c[:n_slots] != 1][:8])
+        n_dealt = n_slots
+    else:
+        per = c[:N_UNITS * nt].reshape(N_UNITS, nt)
+        assert per.max() <= 1, (what, "an item claimed twice")
+        for t in range(nt):
+            got = set(np.nonzero(per[:, t])[0].tolist())
+            assert got in PARTITIONS, (what, "tile", t, "claimed units", sorted(got))
+        n_dealt = int(per.sum())
+    ws = rast.ws.get("render", 0).view(torch.int32)[:NQ * QSTRIDE + 2].cpu().numpy().astype(np.int64)
+    n, nw = int(ws[NQ * QSTRIDE]), int(ws[NQ * QSTRIDE + 1])
+    assert n == n_dealt, (what, n, n_dealt)
     ctr = ws[0:NQ * QSTRIDE:QSTRIDE]
     size = np.array([(n - q - 1) // NQ + 1 if n > q else 0 for q in range(NQ)])
-    assert np.all(ctr >= size), (what, "a queue was not drained", ctr - size)
+    first = np.array([(nw - q - 1) // NQ + 1 if nw > q else 0 for q in range(NQ)])  # taken without a claim
+    assert np.all(ctr + first >= size), (what, "a queue was not drained", ctr + first - size)
     # every counter step past the size is one failed claim of one wave
-    assert int((ctr - size).sum()) <= 256 * 32 * 2 * NQ, (what, int((ctr - size).sum()))
+    assert int(np.maximum(ctr + first - size, 0).sum()) <= nw * NQ, (what, int((ctr + first - size).sum()))
+    return n_dealt
 
 
 @pytest.mark.parametrize("name", ["ragged", "0", "1"])
@@ -67,7 +87,8 @@ def test_forward_claims_every_item_once(rast, name, variant, sub, order):
     cfg.item_claims = claims.data_ptr()
     out = rast.render_fwd(prep, cfg)
     torch.cuda.synchronize()
-    _check_queue(rast, claims, n, f"fwd {name} {variant}/{sub}/{order}")
+    nt = (W + 15) // 16 * ((H + 15) // 16) if sub == 16 else None
+    _check_queue(rast, claims, n, f"fwd {name} {variant}/{sub}/{order}", nt)
     for k in ("color", "alpha", "depth", "final_T"):
         assert bool(torch.isfinite(out[k]).all()), k
     assert int(out["n_contrib"].min()) >= 0
@@ -89,7 +110,8 @@ def test_backward_claims_every_item_once(rast, name, variant, sub, order):
     gC = torch.randn(3, H, W, device="cuda")
     rast.render_bwd(prep, cfg, fwd, gC)
     torch.cuda.synchronize()
-    _check_queue(rast, claims, n, f"bwd {name} {variant}/{sub}/{order}")
+    nt = (W + 15) // 16 * ((H + 15) // 16) if sub == 16 else None
+    _check_queue(rast, claims, n, f"bwd {name} {variant}/{sub}/{order}", nt)
 
 
 def test_static_variants_take_no_claims(rast):
@@ -106,39 +128,41 @@ def test_static_variants_take_no_claims(rast):
     assert int(claims.abs().sum()) == 0
 
 
-@pytest.mark.parametrize("name", ["0", "1"])
-def test_split_walks_claim_both_parts_once(rast, name):
-    """Split backward walks: every tile is claimed once at claims[tile] (its
-    whole walk, or the lower part), and the upper part of exactly the tiles
-    whose walk reaches 128 entries once at claims[n_tiles + tile]."""
+@pytest.mark.parametrize("name", ["0", "1", "1-hotspot"])
+@pytest.mark.parametrize("split", [False, True])
+def test_backward_units_follow_the_walks(rast, name, split):
+    """Cost-ordered wave-per-tile backward: each tile's work is dealt as the
+    units its walk (the deepest n_contrib, within its list) calls for -- four
+    blocks from 512 entries on, and with split walks two parts from 128 on --
+    and every unit is claimed exactly once."""
     from paper_2412_17378_amd import make_cfg
     from paper_2412_17378_amd import bgs as B
     s = _scene(name)
     W, H = s.cameras[0].width, s.cameras[0].height
     prep = rast.prepare_scene(s)
-    cfg = make_cfg("pixel", 16, "cost", tuple(s.bg), flags=B.FLAG_SPLIT_WALKS)
+    cfg = make_cfg("pixel", 16, "cost", tuple(s.bg), flags=B.FLAG_SPLIT_WALKS if split else 0)
     fwd = rast.render_fwd(prep, cfg)
     nt = B.n_tiles(W, H)
-    claims = torch.zeros(2 * nt + 64, dtype=torch.int32, device="cuda")
+    claims = torch.zeros(N_UNITS * nt + 64, dtype=torch.int32, device="cuda")
     cfg.item_claims = claims.data_ptr()
-    print(f"[queue] split case={name}", flush=True)
+    print(f"[queue] units case={name} split={split}", flush=True)
     rast.render_bwd(prep, cfg, fwd, torch.randn(3, H, W, device="cuda"))
     torch.cuda.synchronize()
-    # each tile's walk: the deepest n_contrib of its pixels, within its list
+    _check_queue(rast, claims, N_UNITS * nt, f"bwd units {name} split={split}", nt)
+    # the walk of each tile: the deepest n_contrib of its pixels, within its list
     nc = fwd["n_contrib"].cpu().numpy().astype(np.int64)
     rg = prep.ranges.cpu().numpy().astype(np.int64)
     TX, TY = (W + 15) // 16, (H + 15) // 16
     pad = np.zeros((TY * 16, TX * 16), np.int64)
     pad[:H, :W] = nc
-    walk = pad.reshape(TY, 16, TX, 16).max(axis=(1, 3)).ravel()
-    walk = np.minimum(walk, rg[:, 1] - rg[:, 0])
-    split = walk >= 128
-    c = claims.cpu().numpy()
-    assert np.all(c[:nt] == 1), np.nonzero(c[:nt] != 1)[0][:8]
-    np.testing.assert_array_equal(c[nt:2 * nt], split.astype(np.int32))
-    assert np.all(c[2 * nt:] == 0)
-    n = int(rast.ws.get("render", 0).view(torch.int32)[NQ * QSTRIDE].item())
-    assert n == nt + int(split.sum()), (n, nt, int(split.sum()))
-    print(f"[queue] split case={name}: {int(split.sum())} of {nt} tiles split", flush=True)
-    if name == "1":
-        assert split.any()
+    walk = np.minimum(pad.reshape(TY, 16, TX, 16).max(axis=(1, 3)).ravel(), rg[:, 1] - rg[:, 0])
+    per = claims[:N_UNITS * nt].cpu().numpy().reshape(N_UNITS, nt)
+    blocks, parts = walk >= 512, (walk >= 128) & split
+    expect = np.where(blocks & parts, 3, np.where(blocks, 2, np.where(parts, 1, 0)))
+    got = np.array([next(i for i, P in enumerate(PARTITIONS) if set(np.nonzero(per[:, t])[0].tolist()) == P)
+                    for t in range(nt)])
+    np.testing.assert_array_equal(got, expect)
+    print(f"[queue] units case={name} split={split}: {int(blocks.sum())} tiles as blocks, {int(parts.sum())} "
+          f"split of {nt}", flush=True)
+    if name == "1-hotspot":
+        assert blocks.any()

@@ -194,7 +194,8 @@ class Workload:
         st = self.make_step(default, default)
         st.run()
         torch.cuda.synchronize()
-        fcfg, bcfg, fms, bms = B.bgs_autotune(st.frame, default, st.fwd, self.dL_dcolor, st.grads, st.rws)
+        grads = {k: torch.zeros(tuple(v.shape), device=self.dev) for k, v in st.grads.items()}  # four arrays
+        fcfg, bcfg, fms, bms = B.bgs_autotune(st.frame, default, st.fwd, self.dL_dcolor, grads, st.rws)
         del st
         info = {"forward": B.cfg_name(fcfg), "backward": B.cfg_name(bcfg), "forward_ms": fms, "backward_ms": bms}
         print(f"[bench] autotune {self.scene.name}: forward {info['forward']} ({fms:.3f} ms), backward "
@@ -411,9 +412,13 @@ def main():
         out = dict(means3D=torch.empty(P, 3, device=dev), log_scales=torch.empty(P, 3, device=dev),
                    quats=torch.empty(P, 4, device=dev), opacity=torch.empty(P, device=dev),
                    colors=torch.empty_like(g_in["colors"]))
-        run1 = lambda: B.bgs_project_bwd(wl.cam, g_in["means3D"], g_in["log_scales"], g_in["quats"],
-                                         g_in["colors"], scene.sh_degree, grads["means2D"], grads["conic_opacity"],
-                                         grads["rgb"], grads["depth"], out)
+        if st.grad_records is not None:  # the step's packed gradient records
+            run1 = lambda: B.bgs_project_bwd_packed(wl.cam, g_in["means3D"], g_in["log_scales"], g_in["quats"],
+                                                    g_in["colors"], scene.sh_degree, st.grad_records, out)
+        else:
+            run1 = lambda: B.bgs_project_bwd(wl.cam, g_in["means3D"], g_in["log_scales"], g_in["quats"],
+                                             g_in["colors"], scene.sh_degree, grads["means2D"],
+                                             grads["conic_opacity"], grads["rgb"], grads["depth"], out)
         run1()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -472,15 +477,19 @@ def main():
         for name, c in (("render_fwd", fcfg_), ("render_bwd", bcfg_)):
             cap = 4 * max(B.n_tiles(W, H), 16384)
             rec = torch.zeros(cap, 3, dtype=torch.int64, device=dev)
-            tc = B.make_cfg(c.variant, c.subtile, c.order, bg)
+            packed = name == "render_bwd" and st.grad_records is not None  # as the timed step runs it
+            tc = B.make_cfg(c.variant, c.subtile, c.order, bg, flags=(c.flags & B.FLAG_SPLIT_WALKS) |
+                            (B.FLAG_PACKED_GRADS if packed else 0))
             tc.wg_trace, tc.wg_trace_cap = rec.data_ptr(), cap
             if name == "render_fwd":
                 tc.list_cap = st.list_cap
                 B.bgs_render_fwd(frame, tc, fwd["color"], fwd["alpha"], fwd["depth"], fwd["final_T"],
                                  fwd["n_contrib"], rws)
             else:
-                B.bgs_render_bwd(frame, tc, fwd["final_T"], fwd["n_contrib"], wl.dL_dcolor, None, None,
-                                 grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], rws)
+                tc = B.with_forward_outputs(tc, fwd["color"], fwd["depth"])
+                gouts = ((st.grad_records, None, None, None) if packed else
+                         (grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"]))
+                B.bgs_render_bwd(frame, tc, fwd["final_T"], fwd["n_contrib"], wl.dL_dcolor, None, None, *gouts, rws)
             torch.cuda.synchronize()
             out[name] = balance_stats(rec.cpu().numpy())
         return out

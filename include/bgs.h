@@ -105,7 +105,16 @@ enum {
        the whole walk that the lower part starts from is read off them).
        Halves the heaviest work items, so the queue balances better; the
        gradients equal the unsplit ones up to fp32 rounding. */
-    BGS_FLAG_SPLIT_WALKS = 2
+    BGS_FLAG_SPLIT_WALKS = 2,
+    /* bgs_render_bwd / bgs_render_bwd_det: the gradients go, added (+=), into
+       ONE array of 16-float records, passed as dL_dmeans2D (DEVICE [P][16],
+       64-byte aligned; dL_dconic_opacity, dL_drgb and dL_ddepths must be
+       null).  Record of Gaussian i: floats 0-3 d/d(a, b, c, o) of
+       conic_opacity, 4-5 d/d(means2D), 6-8 d/d(rgb), 9 d/d(depth), 10-15
+       unused (left as they are).  One list entry's ten gradient atomics then
+       fall in one 64-byte segment instead of four arrays' cache lines.
+       bgs_project_bwd_packed reads this layout.  Not for batched plans. */
+    BGS_FLAG_PACKED_GRADS = 4
 };
 
 typedef struct bgs_render_cfg {
@@ -206,6 +215,17 @@ bgs_status bgs_project_bwd(const bgs_camera* cam, int64_t P, const float* means3
                            const float* dL_dconic_opacity, const float* dL_drgb, const float* dL_ddepth,
                            float* dL_dmeans3D, float* dL_dlog_scales, float* dL_dquats, float* dL_dopacity,
                            float* dL_dcolors, hipStream_t stream);
+
+/*
+ * bgs_project_bwd with the screen-space gradients in the 16-float records of
+ * BGS_FLAG_PACKED_GRADS (DEVICE [P][16], 64-byte aligned): the same
+ * arithmetic on the same values, so the results equal bgs_project_bwd's on
+ * the four arrays unpacked from the records bit for bit.
+ */
+bgs_status bgs_project_bwd_packed(const bgs_camera* cam, int64_t P, const float* means3D, const float* log_scales,
+                                  const float* quats, const float* colors, int32_t sh_degree,
+                                  const float* dL_drecords, float* dL_dmeans3D, float* dL_dlog_scales,
+                                  float* dL_dquats, float* dL_dopacity, float* dL_dcolors, hipStream_t stream);
 
 /* Workspace bytes for bgs_bin with P Gaussians. */
 size_t bgs_bin_workspace_bytes(int64_t P);

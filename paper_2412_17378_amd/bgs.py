@@ -23,6 +23,8 @@ STATIC, BALANCED_PIXEL, BALANCED_GAUSS, BALANCED_HYBRID, STATIC_WAVE = 0, 1, 2, 
 ORDER_RASTER, ORDER_COST = 0, 1
 FLAG_QUEUE_READY = 1
 FLAG_SPLIT_WALKS = 2
+FLAG_PACKED_GRADS = 4
+GRAD_RECORD = 16  # floats per Gaussian in packed gradients: conic+opacity 0-3, means2D 4-5, rgb 6-8, depth 9
 TILE = 16
 
 VARIANTS = {"static": STATIC, "pixel": BALANCED_PIXEL, "gauss": BALANCED_GAUSS, "hybrid": BALANCED_HYBRID,
@@ -79,6 +81,8 @@ def lib() -> C.CDLL:
                             C.c_int),
             "bgs_project_bwd": ([_vp, _i64, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                  _vp], C.c_int),
+            "bgs_project_bwd_packed": ([_vp, _i64, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+                                       C.c_int),
             "bgs_bin_workspace_bytes": ([_i64], _sz),
             "bgs_bin": ([_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp], C.c_int),
             "bgs_sort_workspace_bytes": ([_i64], _sz),
@@ -114,7 +118,8 @@ def lib() -> C.CDLL:
 
 def exported_symbols():
     """Names the header declares (used by the load test)."""
-    return ["bgs_last_error", "bgs_version", "bgs_project", "bgs_project_bwd", "bgs_bin_workspace_bytes", "bgs_bin",
+    return ["bgs_last_error", "bgs_version", "bgs_project", "bgs_project_bwd", "bgs_project_bwd_packed",
+            "bgs_bin_workspace_bytes", "bgs_bin",
             "bgs_sort_workspace_bytes", "bgs_sort", "bgs_ranges", "bgs_tile_lists_workspace_bytes", "bgs_tile_lists",
             "bgs_tile_lists_exact", "bgs_render_workspace_bytes", "bgs_queue_build", "bgs_autotune", "bgs_plan_create", "bgs_plan_launch",
             "bgs_plan_destroy",
@@ -273,6 +278,32 @@ def bgs_project_bwd(cam, means3D, log_scales, quats, colors, sh_degree: int, dL_
         C.byref(c), P, _ptr(means3D), _ptr(log_scales), _ptr(quats), _ptr(colors), int(sh_degree),
         _ptr(dL_dmeans2D), _ptr(dL_dconic_opacity), _ptr(dL_drgb), _ptr(dL_ddepth), _ptr(out["means3D"]),
         _ptr(out["log_scales"]), _ptr(out["quats"]), _ptr(out["opacity"]), _ptr(out["colors"]), _stream(stream)))
+
+
+def grad_records(P: int, device) -> torch.Tensor:
+    """Zeroed packed-gradient records [P][16] (64-byte aligned: torch's
+    device allocations are)."""
+    return torch.zeros(P, GRAD_RECORD, dtype=torch.float32, device=device)
+
+
+def record_views(rec: torch.Tensor) -> dict:
+    """The four screen-space gradients inside packed records (strided views)."""
+    return {"means2D": rec[:, 4:6], "conic_opacity": rec[:, 0:4], "rgb": rec[:, 6:9], "depth": rec[:, 9]}
+
+
+def bgs_project_bwd_packed(cam, means3D, log_scales, quats, colors, sh_degree: int, dL_drecords, out: dict,
+                           stream=None):
+    """bgs_project_bwd reading packed gradient records [P][16]."""
+    P = means3D.shape[0]
+    _expect(dL_drecords, (P, GRAD_RECORD), torch.float32, "dL_drecords")
+    _expect(out["quats"], (P, 4), torch.float32, "dL_dquats")
+    if out["colors"].numel() != colors.numel():
+        raise ValueError("dL_dcolors: wrong size")
+    c = make_camera(cam) if not isinstance(cam, Camera) else cam
+    _check("bgs_project_bwd_packed", lib().bgs_project_bwd_packed(
+        C.byref(c), P, _ptr(means3D), _ptr(log_scales), _ptr(quats), _ptr(colors), int(sh_degree),
+        _ptr(dL_drecords), _ptr(out["means3D"]), _ptr(out["log_scales"]), _ptr(out["quats"]), _ptr(out["opacity"]),
+        _ptr(out["colors"]), _stream(stream)))
 
 
 def bgs_bin_workspace_bytes(P: int) -> int:
@@ -453,9 +484,9 @@ def bgs_render_bwd_det(frame: Frame, cfg: RenderCfg, P: int, final_T, n_contrib,
     _expect(dL_ddepth, (H, W), torch.float32, "dL_ddepth")
     n = C.c_int64(0)
     st = lib().bgs_render_bwd_det(C.byref(frame), C.byref(cfg), int(P), _ptr(final_T), _ptr(n_contrib),
-                                  _ptr(dL_dcolor), _ptr(dL_dalpha), _ptr(dL_ddepth), _ptr(_nonempty(dL_dmeans2D)),
-                                  _ptr(_nonempty(dL_dconic_opacity)), _ptr(_nonempty(dL_drgb)),
-                                  None if dL_ddepths is None else _ptr(_nonempty(dL_ddepths)), int(max_occ),
+                                  _ptr(dL_dcolor), _ptr(dL_dalpha), _ptr(dL_ddepth),
+                                  *[None if t is None else _ptr(_nonempty(t))
+                                    for t in (dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepths)], int(max_occ),
                                   C.byref(n), _ptr(ws), ws.numel(), _stream(stream))
     if st != BGS_OK:
         e = BgsError("bgs_render_bwd_det", st, lib().bgs_last_error().decode(errors="replace"))
@@ -472,9 +503,8 @@ def bgs_render_bwd(frame: Frame, cfg: RenderCfg, final_T, n_contrib, dL_dcolor, 
     _expect(dL_dcolor, (3, H, W), torch.float32, "dL_dcolor")
     _expect(dL_dalpha, (H, W), torch.float32, "dL_dalpha")
     _expect(dL_ddepth, (H, W), torch.float32, "dL_ddepth")
+    opt = lambda t: None if t is None else _ptr(_nonempty(t))  # noqa: E731 (packed: the last three are None)
     _check("bgs_render_bwd", lib().bgs_render_bwd(C.byref(frame), C.byref(cfg), _ptr(final_T), _ptr(n_contrib),
                                                   _ptr(dL_dcolor), _ptr(dL_dalpha), _ptr(dL_ddepth),
-                                                  _ptr(_nonempty(dL_dmeans2D)), _ptr(_nonempty(dL_dconic_opacity)),
-                                                  _ptr(_nonempty(dL_drgb)),
-                                                  None if dL_ddepths is None else _ptr(_nonempty(dL_ddepths)),
-                                                  _ptr(ws), ws.numel(), _stream(stream)))
+                                                  opt(dL_dmeans2D), opt(dL_dconic_opacity), opt(dL_drgb),
+                                                  opt(dL_ddepths), _ptr(ws), ws.numel(), _stream(stream)))

@@ -40,6 +40,13 @@ constexpr float ALPHA_MAX = 0.99f;
 constexpr float T_MIN = 1e-4f;
 constexpr float LOG2E = 1.4426950408889634f;
 
+// Gradient record of one Gaussian (packed gradients): d/d(a, b, c, o) at
+// floats 0-3 (16-byte aligned), d/d(u, v) at 4-5, d/d(r, g, b) at 6-8,
+// d/d(depth) at 9, floats 10-15 unused.  A record is one 64-byte segment, so
+// the ten atomic adds of one list entry's gradient land in one cache line
+// instead of four arrays' lines.
+constexpr int GRAD_RECORD = 16;
+
 // floor(a / b) for b > 0
 __host__ __device__ inline int64_t floor_div(int64_t a, int64_t b) {
     int64_t q = a / b;

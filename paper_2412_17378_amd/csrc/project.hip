@@ -304,7 +304,10 @@ __device__ inline void sh_grad(int degree, float x, float y, float z, float g[16
 // where its colour gradient goes, in the same layout.  In the LDS-staged
 // kernels coef and dc are the same row: each coefficient is read before its
 // slot is overwritten.
-template <int D>
+// REC = 0: the screen-space gradients in their four arrays; REC = GRAD_RECORD:
+// in gradient records (g_conic_opacity the record array, g_means2D, g_rgb and
+// g_depth its floats 4, 6 and 9).
+template <int D, int REC = 0>
 __device__ inline void project_bwd_one(const ProjParams& pp, int64_t i, const float* __restrict__ means3D,
                                        const float* __restrict__ log_scales, const float* __restrict__ quats,
                                        const float* coef, const float* __restrict__ g_means2D,
@@ -382,7 +385,8 @@ __device__ inline void project_bwd_one(const ProjParams& pp, int64_t i, const fl
         o0 *= idet;
         o1 *= idet;
     };
-    const float4 gco = reinterpret_cast<const float4*>(g_conic_opacity)[i];
+    const float4 gco = REC ? *reinterpret_cast<const float4*>(g_conic_opacity + (int64_t)REC * i)
+                           : reinterpret_cast<const float4*>(g_conic_opacity)[i];
     const float G00 = gco.x, G01 = 0.5f * gco.y, G11 = gco.z;  // Gamma
     float gR[9], dT[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int b = 0; b < 3; ++b) {
@@ -418,11 +422,12 @@ __device__ inline void project_bwd_one(const ProjParams& pp, int64_t i, const fl
         dp[1] -= dJ[5] * pp.fy * iz2;
         dp[2] += dJ[5] * 2.0f * pp.fy * p[1] * iz2 * iz;
     }
-    const float gu = g_means2D[2 * i], gv = g_means2D[2 * i + 1];
+    const int64_t im = REC ? (int64_t)REC * i : 2 * i;
+    const float gu = g_means2D[im], gv = g_means2D[im + 1];
     dp[0] += gu * pp.fx * iz;
     dp[1] += gv * pp.fy * iz;
     dp[2] -= (gu * pp.fx * p[0] + gv * pp.fy * p[1]) * iz2;
-    if (g_depth) dp[2] += g_depth[i];
+    if (g_depth) dp[2] += g_depth[REC ? (int64_t)REC * i : i];
     float dmu[3];
     for (int k = 0; k < 3; ++k) dmu[k] = R[k] * dp[0] + R[3 + k] * dp[1] + R[6 + k] * dp[2];
     // rotation: a world-frame turn by dtheta moves each axis r_b by dtheta x r_b,
@@ -445,7 +450,7 @@ __device__ inline void project_bwd_one(const ProjParams& pp, int64_t i, const fl
                     k2q * (w * om[1] + om[2] * x - om[0] * z), k2q * (w * om[2] + om[0] * y - om[1] * x));
     d_opacity[i] = gco.w;
     // ---- colour
-    const float* gr = g_rgb + 3 * i;
+    const float* gr = g_rgb + (REC ? (int64_t)REC * i : 3 * i);
     if (D < 0) {
         dc[0] = gr[0];
         dc[1] = gr[1];
@@ -483,7 +488,7 @@ __device__ inline void project_bwd_one(const ProjParams& pp, int64_t i, const fl
     for (int a = 0; a < 3; ++a) d_means3D[3 * i + a] = dmu[a];
 }
 
-template <int D>
+template <int D, int REC = 0>
 __global__ __launch_bounds__(PROJ_THREADS) void k_project_bwd(ProjParams pp, int64_t P, const float* __restrict__ means3D,
                                                               const float* __restrict__ log_scales,
                                                               const float* __restrict__ quats,
@@ -508,8 +513,8 @@ __global__ __launch_bounds__(PROJ_THREADS) void k_project_bwd(ProjParams pp, int
     if (i < P) {
         float* row = S::STAGED ? s_sh + threadIdx.x * S::STRIDE : d_colors + (int64_t)S::NC * i;
         const float* coef = S::STAGED ? row : colors + (int64_t)S::NC * i;
-        project_bwd_one<D>(pp, i, means3D, log_scales, quats, coef, g_means2D, g_conic_opacity, g_rgb, g_depth, d_means3D,
-                           d_log_scales, d_quats, d_opacity, row);
+        project_bwd_one<D, REC>(pp, i, means3D, log_scales, quats, coef, g_means2D, g_conic_opacity, g_rgb, g_depth,
+                                d_means3D, d_log_scales, d_quats, d_opacity, row);
     }
     if (S::STAGED) {
         __syncthreads();
@@ -602,6 +607,44 @@ extern "C" bgs_status bgs_project_bwd(const bgs_camera* cam, int64_t P, const fl
         case 1: launch(k_project_bwd<1>); break;
         case 2: launch(k_project_bwd<2>); break;
         default: launch(k_project_bwd<3>); break;
+    }
+    BGS_HIP(hipGetLastError());
+    return BGS_OK;
+}
+
+extern "C" bgs_status bgs_project_bwd_packed(const bgs_camera* cam, int64_t P, const float* means3D,
+                                             const float* log_scales, const float* quats, const float* colors,
+                                             int32_t sh_degree, const float* dL_drecords, float* dL_dmeans3D,
+                                             float* dL_dlog_scales, float* dL_dquats, float* dL_dopacity,
+                                             float* dL_dcolors, hipStream_t stream) {
+    BGS_REQUIRE(cam != nullptr, "bgs_project_bwd_packed: camera is null");
+    BGS_REQUIRE(P >= 0, "bgs_project_bwd_packed: P < 0");
+    BGS_REQUIRE(cam->width > 0 && cam->height > 0, "bgs_project_bwd_packed: image size must be positive");
+    BGS_REQUIRE(sh_degree >= -1 && sh_degree <= 3, "bgs_project_bwd_packed: sh_degree must be in -1..3");
+    if (P == 0) return BGS_OK;
+    BGS_REQUIRE(means3D && log_scales && quats && colors && dL_drecords && dL_dmeans3D && dL_dlog_scales &&
+                    dL_dquats && dL_dopacity && dL_dcolors,
+                "bgs_project_bwd_packed: null array");
+    BGS_REQUIRE((reinterpret_cast<uintptr_t>(dL_drecords) & 63) == 0 &&
+                    (reinterpret_cast<uintptr_t>(dL_dquats) & 15) == 0,
+                "bgs_project_bwd_packed: dL_drecords must be 64-byte and dL_dquats 16-byte aligned");
+    const ProjParams pp = proj_params(cam);
+    const int threads = PROJ_THREADS;
+    const int64_t blocks = (P + threads - 1) / threads;
+    BGS_REQUIRE(blocks < (int64_t)1 << 31, "bgs_project_bwd_packed: P too large");
+    // record floats 0-3 conic and opacity, 4-5 means2D, 6-8 rgb, 9 depth
+    const float* rec = dL_drecords;
+    auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, pp, P, means3D, log_scales, quats,
+                           colors, rec + 4, rec, rec + 6, rec + 9, dL_dmeans3D, dL_dlog_scales, dL_dquats,
+                           dL_dopacity, dL_dcolors);
+    };
+    switch (sh_degree) {
+        case -1: launch(k_project_bwd<-1, GRAD_RECORD>); break;
+        case 0: launch(k_project_bwd<0, GRAD_RECORD>); break;
+        case 1: launch(k_project_bwd<1, GRAD_RECORD>); break;
+        case 2: launch(k_project_bwd<2, GRAD_RECORD>); break;
+        default: launch(k_project_bwd<3, GRAD_RECORD>); break;
     }
     BGS_HIP(hipGetLastError());
     return BGS_OK;

@@ -80,7 +80,11 @@ struct BwdIO {
     // split walks only: the forward's out_color [3][H][W] and out_depth [H][W]
     const float* __restrict__ out_color;
     const float* __restrict__ out_depth;
+    // 1: the gradients are 16-float records, g_means2D the record array
+    // (GRAD_RECORD layout) and the other three pointers null
+    int packed;
 };
+
 
 // One view of a batched plan: its frame, forward outputs and backward I/O.
 struct ViewDesc {
@@ -977,6 +981,10 @@ struct GradLane {
 
 __device__ __forceinline__ GradLane grad_lane(const BwdIO& B, int slot) {
     if (slot < 0) return GradLane{nullptr, 0u};
+    if (B.packed) {  // slots 0-1 (means) at record floats 4-5, 2-5 (conic, opacity) at 0-3, 6-9 in place
+        const int f = slot < 2 ? slot + 4 : (slot < 6 ? slot - 2 : slot);
+        return GradLane{B.g_means2D + f, (uint32_t)GRAD_RECORD};
+    }
     if (slot < 2) return GradLane{B.g_means2D + slot, 2u};
     if (slot < 6) return GradLane{B.g_conic_opacity + (slot - 2), 4u};
     if (slot < 9) return GradLane{B.g_rgb + (slot - 6), 3u};
@@ -1217,7 +1225,7 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
         const uint32_t end = start + (uint32_t)hi_end;
         if (hi_end > 0) {
             load_raw(F, chunk_id(F, start, end, lane), cur);
-            if (64 < hi_end) idn = chunk_id(F, start + 64, end, lane);
+            idn = chunk_id(F, start + (uint32_t)(64 < hi_end ? 64 : hi_end - 1), end, lane);
         }
         for (int base = 0; base < hi_end; base += 64) {
             const int cnt = hi_end - base < 64 ? hi_end - base : 64;
@@ -1230,8 +1238,9 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
                 mq[q] &= n >= 64 ? ~0ull : (n > 0 ? (1ull << n) - 1ull : 0ull);
             }
             wave_sync();
-            if (base + 64 < hi_end) load_raw(F, idn, nxt);
-            if (base + 128 < hi_end) idn = chunk_id(F, start + (uint32_t)base + 128, end, lane);
+            // branch-free prefetch (past the end: re-reads of the last entry)
+            load_raw(F, idn, nxt);
+            idn = chunk_id(F, start + (uint32_t)(base + 128 < hi_end ? base + 128 : hi_end - 1), end, lane);
             uint64_t todo = chunk_todo(mq, 0xFu);
             while (todo) {
                 const int jj = (int)__builtin_ctzll(todo);
@@ -1283,10 +1292,8 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
     if (hi_end > lo_end) {
         const int lo0 = hi_end - 64 > lo_end ? hi_end - 64 : lo_end;
         load_raw(F, chunk_id(F, start + (uint32_t)lo0, start + (uint32_t)hi_end, lane), cur);
-        if (lo0 > lo_end) {
-            const int nlo = lo0 - 64 > lo_end ? lo0 - 64 : lo_end;
-            idn = chunk_id(F, start + (uint32_t)nlo, start + (uint32_t)lo0, lane);
-        }
+        const int nlo = lo0 - 64 > lo_end ? lo0 - 64 : lo_end;
+        idn = chunk_id(F, start + (uint32_t)nlo, start + (uint32_t)(lo0 > nlo ? lo0 : nlo + 1), lane);
     }
     for (int hi = hi_end; hi > lo_end; hi -= 64) {
         const int lo = hi - 64 > lo_end ? hi - 64 : lo_end;
@@ -1300,13 +1307,15 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
             mq[q] &= n >= 64 ? ~0ull : (n > 0 ? (1ull << n) - 1ull : 0ull);
         }
         wave_sync();
-        if (lo > lo_end) {  // the chunk [max(lo - 64, lo_end), lo)
+        {
+            // prefetch without a branch, so that nothing waits for the loads
+            // before the chunk is done: the chunk [max(lo - 64, lo_end), lo)
+            // and the ids of the one below it; past the walk's last chunk the
+            // loads re-read entry lo_end of the list (a valid id) and go unused
             load_raw(F, idn, nxt);
             const int nlo = lo - 64 > lo_end ? lo - 64 : lo_end;
-            if (nlo > lo_end) {
-                const int nnlo = nlo - 64 > lo_end ? nlo - 64 : lo_end;
-                idn = chunk_id(F, start + (uint32_t)nnlo, start + (uint32_t)nlo, lane);
-            }
+            const int nnlo = nlo - 64 > lo_end ? nlo - 64 : lo_end;
+            idn = chunk_id(F, start + (uint32_t)nnlo, start + (uint32_t)(nlo > nnlo ? nlo : nnlo + 1), lane);
         }
         uint64_t todo = chunk_todo(mq, 0xFu);
         uint64_t wrote = 0;  // DET: entries whose partial slot holds a total
@@ -1952,6 +1961,31 @@ extern "C" bgs_status bgs_render_fwd_noalloc(const bgs_frame* frame, const bgs_r
     return bgs_render_fwd(frame, &c, out_color, out_alpha, out_depth, final_T, n_contrib, ws, L.bytes, stream);
 }
 
+namespace bgs {
+// Gradient outputs of a backward entry point: the four arrays, or with
+// BGS_FLAG_PACKED_GRADS one array of 16-float records in dL_dmeans2D.
+static bgs_status grad_outputs(const bgs_render_cfg* cfg, float* m2, float* co, float* rgb, float* d, BwdIO& B,
+                               const char* who) {
+    const std::string w(who);
+    if (cfg->flags & BGS_FLAG_PACKED_GRADS) {
+        BGS_REQUIRE(m2 && !co && !rgb && !d, w + ": packed gradients go in dL_dmeans2D alone ([P][16] records); "
+                                                 "the other gradient outputs must be null");
+        BGS_REQUIRE((reinterpret_cast<uintptr_t>(m2) & 63) == 0, w + ": gradient records must be 64-byte aligned");
+        B.g_means2D = m2;
+        B.g_conic_opacity = B.g_rgb = B.g_depth = nullptr;
+        B.packed = 1;
+        return BGS_OK;
+    }
+    BGS_REQUIRE(m2 && co && rgb, w + ": null gradient output");
+    B.g_means2D = m2;
+    B.g_conic_opacity = co;
+    B.g_rgb = rgb;
+    B.g_depth = d;
+    B.packed = 0;
+    return BGS_OK;
+}
+}  // namespace bgs
+
 extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cfg* cfg, const float* final_T,
                                      const int32_t* n_contrib, const float* dL_dcolor, const float* dL_dalpha,
                                      const float* dL_ddepth, float* dL_dmeans2D, float* dL_dconic_opacity,
@@ -1961,9 +1995,10 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
     bgs_status st = check_frame(frame, cfg, A, "bgs_render_bwd");
     if (st != BGS_OK) return st;
     BGS_REQUIRE(final_T && n_contrib && dL_dcolor, "bgs_render_bwd: null forward state or dL_dcolor");
-    BGS_REQUIRE(dL_dmeans2D && dL_dconic_opacity && dL_drgb, "bgs_render_bwd: null gradient output");
-    BwdIO B{final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dmeans2D, dL_dconic_opacity, dL_drgb,
-            dL_ddepths, nullptr, nullptr, cfg->split_color, cfg->split_depth};
+    BwdIO B{final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, nullptr, nullptr, nullptr,
+            nullptr, nullptr, nullptr, cfg->split_color, cfg->split_depth, 0};
+    st = grad_outputs(cfg, dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepths, B, "bgs_render_bwd");
+    if (st != BGS_OK) return st;
     if ((cfg->flags & BGS_FLAG_SPLIT_WALKS) && !split_walks(cfg))
         return fail(BGS_EUNSUPPORTED, "bgs_render_bwd: split walks need BGS_BALANCED_PIXEL, subtile 16, cost order");
     if (split_walks(cfg) && !(cfg->split_color && cfg->split_depth))
@@ -2170,7 +2205,10 @@ extern "C" bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_rende
     BGS_REQUIRE(P >= 0 && max_occ >= 0 && n_occ_host, "bgs_render_bwd_det: bad P, max_occ or n_occ_host");
     BGS_REQUIRE(P < ((int64_t)1 << 32) && max_occ < ((int64_t)1 << 32), "bgs_render_bwd_det: sizes must be < 2^32");
     BGS_REQUIRE(final_T && n_contrib && dL_dcolor, "bgs_render_bwd_det: null forward state or dL_dcolor");
-    BGS_REQUIRE(dL_dmeans2D && dL_dconic_opacity && dL_drgb, "bgs_render_bwd_det: null gradient output");
+    BwdIO B{final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+            nullptr, nullptr, 0};
+    st = grad_outputs(cfg, dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepths, B, "bgs_render_bwd_det");
+    if (st != BGS_OK) return st;
     const DetLayout D = det_layout(A.n_tiles, P, max_occ);
     BGS_REQUIRE(ws && ws_bytes >= D.bytes, "bgs_render_bwd_det: workspace too small");
     char* w = static_cast<char*>(ws);
@@ -2196,8 +2234,8 @@ extern "C" bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_rende
                                        std::to_string(max_occ));
     if (K == 0 || P == 0) return BGS_OK;
     auto* partials = reinterpret_cast<float*>(w + D.partials);
-    BwdIO B{final_T, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dmeans2D, dL_dconic_opacity, dL_drgb, dL_ddepths,
-            partials, base};
+    B.det_partials = partials;
+    B.det_base = base;
     auto* ctr = reinterpret_cast<uint32_t*>(w + D.R.ctr);
     auto* items = reinterpret_cast<const uint32_t*>(w + D.R.items);
     const int blocks = persistent_blocks(k_bwd_wide<false, true>, (uint32_t)A.n_tiles);
@@ -2297,6 +2335,8 @@ extern "C" bgs_status bgs_plan_create(bgs_plan** out, int32_t n_views, const bgs
         return fail(BGS_EUNSUPPORTED, "bgs_plan_create: the batched backward uses the balanced pixel-wise variant");
     if (cfg_bwd->order != BGS_ORDER_RASTER && cfg_bwd->order != BGS_ORDER_COST)
         return fail(BGS_EINVAL, "bgs_plan_create: unknown backward order");
+    if ((cfg->flags | cfg_bwd->flags) & BGS_FLAG_PACKED_GRADS)
+        return fail(BGS_EUNSUPPORTED, "bgs_plan_create: plans write the four gradient arrays (no packed records)");
     std::vector<ViewDesc> vd(n_views);
     std::vector<uint32_t> off(n_views + 1, 0);
     for (int v = 0; v < n_views; ++v) {

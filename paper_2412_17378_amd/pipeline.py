@@ -216,18 +216,27 @@ class Rasterizer:
 
     def render_bwd(self, prep: Prepared, cfg: B.RenderCfg, fwd: dict, dL_dcolor, dL_dalpha=None, dL_ddepth=None,
                    grads: Optional[dict] = None, want_depth: bool = True) -> dict:
+        """Gradients of the 2D splats (added into `grads` when given).  With
+        FLAG_PACKED_GRADS in cfg they go into one [P][16] record array
+        (grads["records"]), and the returned dict also holds its views."""
         P = prep.P
         dev = self.device
+        packed = bool(cfg.flags & B.FLAG_PACKED_GRADS)
         if grads is None:
-            grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
-                         rgb=torch.zeros(P, 3, device=dev),
-                         depth=torch.zeros(P, device=dev) if want_depth else None)
+            if packed:
+                rec = B.grad_records(P, dev)
+                grads = dict(B.record_views(rec), records=rec)
+            else:
+                grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
+                             rgb=torch.zeros(P, 3, device=dev),
+                             depth=torch.zeros(P, device=dev) if want_depth else None)
         f = prep.frame()
         ws = self.ws.get("render", B.bgs_render_workspace_bytes(f, cfg))
         if cfg.flags & B.FLAG_SPLIT_WALKS:  # split walks read the forward's colour and depth
             cfg = B.with_forward_outputs(cfg, fwd["color"], fwd["depth"])
-        B.bgs_render_bwd(f, cfg, fwd["final_T"], fwd["n_contrib"], dL_dcolor, dL_dalpha, dL_ddepth,
-                         grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], ws)
+        outs = ((grads["records"], None, None, None) if packed else
+                (grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"]))
+        B.bgs_render_bwd(f, cfg, fwd["final_T"], fwd["n_contrib"], dL_dcolor, dL_dalpha, dL_ddepth, *outs, ws)
         return grads
 
     def render_bwd_det(self, prep: Prepared, cfg: B.RenderCfg, fwd: dict, dL_dcolor, dL_dalpha=None, dL_ddepth=None,
@@ -238,16 +247,23 @@ class Rasterizer:
         demand (one retry)."""
         P = prep.P
         dev = self.device
+        packed = bool(cfg.flags & B.FLAG_PACKED_GRADS)
         if grads is None:
-            grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
-                         rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
+            if packed:
+                rec = B.grad_records(P, dev)
+                grads = dict(B.record_views(rec), records=rec)
+            else:
+                grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
+                             rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
+        outs = ((grads["records"], None, None, None) if packed else
+                (grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"]))
         f = prep.frame()
         cap = getattr(self, "det_capacity", 1 << 20)
         for _ in range(2):
             ws = self.ws.get("render_det", B.bgs_render_bwd_det_workspace_bytes(f, P, cap))
             try:
                 B.bgs_render_bwd_det(f, cfg, P, fwd["final_T"], fwd["n_contrib"], dL_dcolor, dL_dalpha, dL_ddepth,
-                                     grads["means2D"], grads["conic_opacity"], grads["rgb"], grads["depth"], cap, ws)
+                                     *outs, cap, ws)
                 self.det_capacity = cap
                 return grads
             except B.BgsError as e:
@@ -337,6 +353,11 @@ class FrameStep:
     poison_outputs: fill the forward outputs with NaN (n_contrib -1) at the
     start of every step, also inside a captured graph (a debugging aid).
 
+    packed_grads: the backward accumulates into one [P][16] array of gradient
+    records (FLAG_PACKED_GRADS; self.grad_records), one cache line per
+    Gaussian for the ten atomic adds of a list entry, and self.grads holds
+    strided views of it; False: four separate arrays.
+
     list_cap: None builds whole tile lists.  An int K keeps the first K
     entries of each tile's list (bgs_tile_lists max_per_tile); "auto" picks K
     from one uncapped step (twice the deepest contributor, rounded up) and
@@ -346,7 +367,8 @@ class FrameStep:
     rebuilds with set_list_cap (larger K, or None) and runs the step again."""
 
     def __init__(self, cam, params: dict, sh_degree: int, dL_dcolor, fcfg: B.RenderCfg, bcfg: B.RenderCfg,
-                 binning: str = "square", headroom: float = 1.25, list_cap=None, poison_outputs: bool = False):
+                 binning: str = "square", headroom: float = 1.25, list_cap=None, poison_outputs: bool = False,
+                 packed_grads: bool = True):
         if binning not in ("square", "ellipse"):
             raise ValueError(f"unknown binning {binning!r}")
         W, H = int(cam.width), int(cam.height)
@@ -361,8 +383,10 @@ class FrameStep:
         self.P = P
         self.fcfg, self.bcfg = fcfg, bcfg
         self.fcfg_ready = B.make_cfg(fcfg.variant, fcfg.subtile, fcfg.order, tuple(fcfg.bg), flags=B.FLAG_QUEUE_READY)
+        self.packed_grads = bool(packed_grads)
         self.bcfg_ready = B.make_cfg(bcfg.variant, bcfg.subtile, bcfg.order, tuple(bcfg.bg),
-                                     flags=B.FLAG_QUEUE_READY | (bcfg.flags & B.FLAG_SPLIT_WALKS))
+                                     flags=B.FLAG_QUEUE_READY | (bcfg.flags & B.FLAG_SPLIT_WALKS) |
+                                     (B.FLAG_PACKED_GRADS if self.packed_grads else 0))
         self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
         self.list_cap = 0
         self.pr = dict(means2D=torch.empty(P, 2, device=dev), conic_opacity=torch.empty(P, 4, device=dev),
@@ -375,12 +399,16 @@ class FrameStep:
         # split walks read the forward's colour and depth
         self.bcfg_ready.split_color = self.fwd["color"].data_ptr()
         self.bcfg_ready.split_depth = self.fwd["depth"].data_ptr()
-        # separate allocations (the backward's atomics spread better over the
-        # memory channels than with the four in one buffer), zeroed by one
-        # multi-tensor fill
-        self.grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
-                          rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
-        self._grad_list = list(self.grads.values())
+        if self.packed_grads:
+            self.grad_records = B.grad_records(P, dev)
+            self.grads = B.record_views(self.grad_records)
+            self._grad_list = [self.grad_records]
+        else:
+            # separate allocations, zeroed by one multi-tensor fill
+            self.grad_records = None
+            self.grads = dict(means2D=torch.zeros(P, 2, device=dev), conic_opacity=torch.zeros(P, 4, device=dev),
+                              rgb=torch.zeros(P, 3, device=dev), depth=torch.zeros(P, device=dev))
+            self._grad_list = list(self.grads.values())
         self.ranges = torch.empty(B.n_tiles(W, H), 2, dtype=torch.int32, device=dev)
         self.n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         # size the pair buffers: build the lists until the capacity holds M
@@ -478,9 +506,13 @@ class FrameStep:
         if self.bcfg.variant != B.STATIC:
             B.bgs_queue_build(self.frame, self.bcfg, f["n_contrib"], self.rws)
         mark(5)
-        g = self.grads
-        B.bgs_render_bwd(self.frame, self.bcfg_ready, f["final_T"], f["n_contrib"], self.dL_dcolor, None, None,
-                         g["means2D"], g["conic_opacity"], g["rgb"], g["depth"], self.rws)
+        if self.packed_grads:
+            B.bgs_render_bwd(self.frame, self.bcfg_ready, f["final_T"], f["n_contrib"], self.dL_dcolor, None, None,
+                             self.grad_records, None, None, None, self.rws)
+        else:
+            g = self.grads
+            B.bgs_render_bwd(self.frame, self.bcfg_ready, f["final_T"], f["n_contrib"], self.dL_dcolor, None, None,
+                             g["means2D"], g["conic_opacity"], g["rgb"], g["depth"], self.rws)
         mark(6)
 
     def n_pairs(self) -> int:

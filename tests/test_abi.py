@@ -78,6 +78,24 @@ def test_invalid_arguments_are_status_codes():
     sc = B.make_cfg("pixel", 8, "cost", flags=B.FLAG_SPLIT_WALKS)
     st = L.bgs_render_bwd(ctypes.byref(f2), ctypes.byref(sc), p, p, p, None, None, p, p, p, None, p, 1 << 16, None)
     assert st == B.BGS_EUNSUPPORTED
+    # packed gradient records: one 64-byte aligned array in dL_dmeans2D, the other three null
+    pc = B.make_cfg("static", flags=B.FLAG_PACKED_GRADS)
+    a64 = (ctypes.addressof(buf) + 63) // 64 * 64
+    st = L.bgs_render_bwd(ctypes.byref(f2), ctypes.byref(pc), p, p, p, None, None, a64, p, p, None, p, 1 << 16, None)
+    assert st == B.BGS_EINVAL and b"packed" in L.bgs_last_error()
+    st = L.bgs_render_bwd(ctypes.byref(f2), ctypes.byref(pc), p, p, p, None, None, a64 + 4, None, None, None, p,
+                          1 << 16, None)
+    assert st == B.BGS_EINVAL and b"64-byte" in L.bgs_last_error()
+    st = L.bgs_render_bwd_det(ctypes.byref(f2), ctypes.byref(B.make_cfg("pixel", 16, "cost",
+                                                                        flags=B.FLAG_PACKED_GRADS)),
+                              1, p, p, p, None, None, a64, p, None, None, 0, ctypes.byref(ctypes.c_int64()), p,
+                              1 << 16, None)
+    assert st == B.BGS_EINVAL and b"packed" in L.bgs_last_error()
+    cam.width = cam.height = 8
+    st = L.bgs_project_bwd_packed(ctypes.byref(cam), 1, p, p, p, p, -1, None, p, p, a64, p, p, None)
+    assert st == B.BGS_EINVAL and b"null" in L.bgs_last_error()
+    st = L.bgs_project_bwd_packed(ctypes.byref(cam), 1, p, p, p, p, -1, a64 + 16, p, p, a64, p, p, None)
+    assert st == B.BGS_EINVAL and b"64-byte" in L.bgs_last_error()
     st = L.bgs_autotune(None, None, None, None, None, None, None, None, None, None, None, None, 0, None, None, None,
                         None, None, None)
     assert st == B.BGS_EINVAL

@@ -194,8 +194,11 @@ class Workload:
         st = self.make_step(default, default)
         st.run()
         torch.cuda.synchronize()
-        grads = {k: torch.zeros(tuple(v.shape), device=self.dev) for k, v in st.grads.items()}  # four arrays
-        fcfg, bcfg, fms, bms = B.bgs_autotune(st.frame, default, st.fwd, self.dL_dcolor, grads, st.rws)
+        # the backward candidates timed on gradient records, as the step runs them
+        tune_base = B.make_cfg("pixel", 16, "cost", self.bg, flags=B.FLAG_PACKED_GRADS)
+        fcfg, bcfg, fms, bms = B.bgs_autotune(st.frame, tune_base, st.fwd, self.dL_dcolor,
+                                              {"records": torch.zeros_like(st.grad_records)}, st.rws)
+        bcfg.flags &= ~B.FLAG_PACKED_GRADS  # the step adds the flag itself
         del st
         info = {"forward": B.cfg_name(fcfg), "backward": B.cfg_name(bcfg), "forward_ms": fms, "backward_ms": bms}
         print(f"[bench] autotune {self.scene.name}: forward {info['forward']} ({fms:.3f} ms), backward "
@@ -555,9 +558,6 @@ def main():
                 configs[name] = {"error": f"{type(e).__name__}: {e}"}
                 print(f"[bench] config {name} failed: {configs[name]['error']}", flush=True)
             torch.cuda.empty_cache()
-    selection = [{"stage": k, "forward": configs[k]["autotune"]["forward"],
-                  "backward": configs[k]["autotune"]["backward"]}
-                 for k in ("3-early", "3-mid", "3-late") if "autotune" in configs.get(k, {})]
 
     hotspot = None
     if not args.no_hotspot:
@@ -569,6 +569,13 @@ def main():
             hotspot = {"error": f"{type(e).__name__}: {e}"}
             print(f"[bench] hot-spot run failed: {hotspot['error']}", flush=True)
         torch.cuda.empty_cache()
+    # the autotuner's picks as the workload moves: training stages, then the hot spot
+    stage_blocks = [(k, configs.get(k, {})) for k in ("3-early", "3-mid", "3-late")] + [("1-hotspot", hotspot or {})]
+    selection = [{"stage": k, "forward": b["autotune"]["forward"], "backward": b["autotune"]["backward"],
+                  "forward_ms": b["autotune"]["forward_ms"], "backward_ms": b["autotune"]["backward_ms"]}
+                 for k, b in stage_blocks if "autotune" in b]
+    print("[bench] selection: " + " -> ".join(f"{x['stage']} ({x['forward']} / {x['backward']})" for x in selection),
+          flush=True)
 
     batched = None
     if not args.no_batched:

@@ -439,8 +439,10 @@ bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_render_cfg* cfg,
  * two timed runs) and returns the fastest in *best_fwd; then renders once with
  * it and, if dL_dcolor and the gradient buffers are given, times the backward
  * candidates (static; wave per tile dispatched statically; balanced 8x8
- * raster and cost-ordered; wave per 16x16 tile; wave per 32x32 block) into
- * *best_bwd.  The
+ * raster and cost-ordered; wave per 16x16 tile, also with split walks; wave
+ * per 32x32 block) into *best_bwd.  With BGS_FLAG_PACKED_GRADS in base the
+ * backward candidates run on packed gradient records passed in dL_dmeans2D
+ * (dL_dconic_opacity and dL_drgb null), and *best_bwd carries the flag.  The
  * output and gradient buffers are scratch (the gradients end up holding sums
  * of several runs).  When cache_path (HOST string, nullable) names a file,
  * the winners are appended to it under a workload signature (image size and

@@ -417,10 +417,13 @@ def bgs_render_fwd_noalloc_max_bytes() -> int:
 
 def bgs_autotune(frame: Frame, base: RenderCfg, out: dict, dL_dcolor, grads: Optional[dict], ws,
                  cache_path: Optional[str] = None, stream=None):
-    """Returns (best_fwd, best_bwd, fwd_ms, bwd_ms); out / grads are scratch."""
+    """Returns (best_fwd, best_bwd, fwd_ms, bwd_ms); out / grads are scratch.
+    With FLAG_PACKED_GRADS in base, grads is {"records": [P][16] records}."""
     bf, bb = RenderCfg(), RenderCfg()
     fms, bms = C.c_float(0), C.c_float(0)
     g = grads or {}
+    if "records" in g:
+        g = {"means2D": g["records"]}
     _check("bgs_autotune", lib().bgs_autotune(
         C.byref(frame), C.byref(base), _ptr(out["color"]), _ptr(out["alpha"]), _ptr(out["depth"]),
         _ptr(out["final_T"]), _ptr(out["n_contrib"]), _ptr(dL_dcolor) if grads is not None else None,

@@ -174,7 +174,8 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
             bf = c;
         }
     }
-    if (st == BGS_OK && dL_dcolor && dL_dmeans2D && dL_dconic_opacity && dL_drgb) {
+    const int packed = base->flags & BGS_FLAG_PACKED_GRADS;  // backward candidates on gradient records
+    if (st == BGS_OK && dL_dcolor && dL_dmeans2D && (packed || (dL_dconic_opacity && dL_drgb))) {
         // the backward walks the forward's n_contrib: render once with the winner
         bgs_render_cfg cfg = *base;
         cfg.variant = fwd_cands[bf][0];
@@ -187,7 +188,7 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
             bc.variant = bwd_cands[c][0];
             bc.subtile = bwd_cands[c][1];
             bc.order = bwd_cands[c][2];
-            bc.flags = bwd_cands[c][3];
+            bc.flags = bwd_cands[c][3] | packed;
             bc.split_color = out_color;  // the winner forward's outputs, rendered just above
             bc.split_depth = out_depth;
             float ms = 0;
@@ -215,7 +216,7 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
     best_bwd->variant = bwd_cands[bb][0];
     best_bwd->subtile = bwd_cands[bb][1];
     best_bwd->order = bwd_cands[bb][2];
-    best_bwd->flags = bwd_cands[bb][3];  // split walks: the caller sets split_color / split_depth
+    best_bwd->flags = bwd_cands[bb][3] | packed;  // split walks: the caller sets split_color / split_depth
     if (fwd_ms_out) *fwd_ms_out = best_f;
     if (bwd_ms_out) *bwd_ms_out = std::isinf(best_b) ? -1.0f : best_b;
     TuneEntry ne{key, best_fwd->variant, best_fwd->subtile, best_fwd->order, best_bwd->variant, best_bwd->subtile,

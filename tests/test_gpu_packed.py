@@ -148,3 +148,24 @@ def test_step_records_match_arrays():
             scale = max(float(np.abs(y).max()), 1e-30)
             assert float(np.abs(x - y).max()) <= 1e-5 * scale, k
         assert not bool(a.grad_records[:, 10:].any())
+
+
+def test_autotune_on_records(rast):
+    """bgs_autotune with FLAG_PACKED_GRADS times the backward candidates on
+    gradient records and returns a backward configuration carrying the flag."""
+    from paper_2412_17378_amd import make_cfg
+    from paper_2412_17378_amd import bgs as B
+    s = _scene("0")
+    print("[autotune-packed] case=0", flush=True)
+    prep = rast.prepare_scene(s)
+    H, W, P, dev = prep.height, prep.width, prep.P, torch.device("cuda")
+    out = dict(color=torch.empty(3, H, W, device=dev), alpha=torch.empty(H, W, device=dev),
+               depth=torch.empty(H, W, device=dev), final_T=torch.empty(H, W, device=dev),
+               n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
+    f = prep.frame()
+    base = make_cfg("pixel", 16, "cost", tuple(s.bg), flags=B.FLAG_PACKED_GRADS)
+    ws = torch.empty(B.bgs_render_workspace_bytes(f, base), dtype=torch.uint8, device=dev)
+    up = torch.ones(3, H, W, device=dev)
+    bf, bb, fms, bms = B.bgs_autotune(f, base, out, up, {"records": B.grad_records(P, dev)}, ws)
+    assert fms > 0 and bms > 0
+    assert bb.flags & B.FLAG_PACKED_GRADS and not bf.flags & B.FLAG_PACKED_GRADS

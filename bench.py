@@ -104,6 +104,9 @@ def parse():
     return ap.parse_args()
 
 
+STAGE_SLEEP_CYCLES = 10_000_000  # a few ms of GPU clock: longer than the host takes to enqueue one step
+
+
 class Workload:
     """One synthetic frame on the GPU and the FrameStep machinery to time its
     whole step (see the module docstring)."""
@@ -141,12 +144,19 @@ class Workload:
         for _ in range(warmup):
             st.run()
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(steps)]
+        # wall time of the eager step (launches included)
         t0 = time.perf_counter()
         for k in range(steps):
-            st.run(lambda i, e=evs[k]: e[i].record(stream))
+            st.run()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        # stage times: each step queued behind a short GPU sleep, so that the whole step is enqueued before
+        # it starts and the events between stages see GPU time, not the host's launch gaps
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(steps)]
+        for k in range(steps):
+            torch.cuda._sleep(STAGE_SLEEP_CYCLES)
+            st.run(lambda i, e=evs[k]: e[i].record(stream))
+        torch.cuda.synchronize()
         M = st.n_pairs()  # read once the steps are done
         if M > st.capacity:
             raise RuntimeError("pair capacity exceeded")
@@ -235,24 +245,31 @@ def cpu_model():
 
 
 def same_code_comparison(wl, fcfg_bal, bcfg_bal, steps, warmup, B, balanced_run=None):
-    """The step with the wave-per-tile kernels taken from the task pool against
-    the same kernels dispatched grid-statically (BGS_STATIC_WAVE): identical
-    per-tile code, so the ratio isolates the queue's scheduling."""
+    """The wave-per-tile kernels three ways, with identical per-tile code: the
+    dealt items (cost order) as a dispatched grid, the same items through the
+    persistent task pool (FLAG_PERSISTENT), and grid-static dispatch in
+    raster order without a queue (BGS_STATIC_WAVE); the ratios isolate the
+    scheduling."""
     static_wave = B.make_cfg("static_wave", 16, "raster", wl.bg)
     rs = wl.run(static_wave, static_wave, steps, warmup)
     rb = balanced_run if balanced_run is not None else wl.run(fcfg_bal, bcfg_bal, steps, warmup)
-    out = {"balanced": {"forward": B.cfg_name(fcfg_bal), "backward": B.cfg_name(bcfg_bal), "ms_per_step": rb["ms"],
-                        "render_fwd_ms": rb["stages"]["render_fwd"], "render_bwd_ms": rb["stages"]["render_bwd"]},
-           "static_same_code": {"forward": B.cfg_name(static_wave), "backward": B.cfg_name(static_wave),
-                                "ms_per_step": rs["ms"], "render_fwd_ms": rs["stages"]["render_fwd"],
-                                "render_bwd_ms": rs["stages"]["render_bwd"]}}
-    out["queue_speedup"] = {"render_fwd": rs["stages"]["render_fwd"] / rb["stages"]["render_fwd"],
-                            "render_bwd": rs["stages"]["render_bwd"] / rb["stages"]["render_bwd"],
-                            "step": rs["ms"] / rb["ms"]}
-    print(f"[bench] {wl.scene.name} same code: queue fwd {rb['stages']['render_fwd']:.3f} / bwd "
-          f"{rb['stages']['render_bwd']:.3f} ms against grid-static fwd {rs['stages']['render_fwd']:.3f} / bwd "
+    pf, pb = B.copy_cfg(fcfg_bal), B.copy_cfg(bcfg_bal)
+    pf.flags |= B.FLAG_PERSISTENT
+    pb.flags |= B.FLAG_PERSISTENT
+    rp = wl.run(pf, pb, steps, warmup)
+    blk = lambda f, b, r: {"forward": B.cfg_name(f), "backward": B.cfg_name(b), "ms_per_step": r["ms"],  # noqa: E731
+                           "render_fwd_ms": r["stages"]["render_fwd"], "render_bwd_ms": r["stages"]["render_bwd"]}
+    out = {"balanced": blk(fcfg_bal, bcfg_bal, rb), "persistent_pool": blk(pf, pb, rp),
+           "static_same_code": blk(static_wave, static_wave, rs)}
+    ratio = lambda r: {"render_fwd": rs["stages"]["render_fwd"] / r["stages"]["render_fwd"],  # noqa: E731
+                       "render_bwd": rs["stages"]["render_bwd"] / r["stages"]["render_bwd"], "step": rs["ms"] / r["ms"]}
+    out["queue_speedup"] = ratio(rb)
+    out["pool_speedup"] = ratio(rp)
+    print(f"[bench] {wl.scene.name} same code: dispatched queue fwd {rb['stages']['render_fwd']:.3f} / bwd "
+          f"{rb['stages']['render_bwd']:.3f} ms, persistent pool fwd {rp['stages']['render_fwd']:.3f} / bwd "
+          f"{rp['stages']['render_bwd']:.3f} ms, grid-static fwd {rs['stages']['render_fwd']:.3f} / bwd "
           f"{rs['stages']['render_bwd']:.3f} ms", flush=True)
-    del rs
+    del rs, rp
     return out
 
 
@@ -358,7 +375,7 @@ def main():
               f"bwd {static['render_bwd_ms']:.3f} ms", flush=True)
         # the queue against grid-static dispatch of the same wave-per-tile code
         wide_f = fcfg if (fcfg.variant == B.BALANCED_PIXEL and fcfg.subtile == 16) else \
-            B.make_cfg("pixel", 16, "raster", bg)
+            B.make_cfg("pixel", 16, "cost", bg)
         wide_b = bcfg if (bcfg.variant == B.BALANCED_PIXEL and bcfg.subtile == 16) else \
             B.make_cfg("pixel", 16, "cost", bg)
         same = main_run if (wide_f is fcfg and wide_b is bcfg) else None
@@ -498,15 +515,19 @@ def main():
         return out
 
     naive_cfg, sw_cfg = B.make_cfg("static", 16, "raster", bg), B.make_cfg("static_wave", 16, "raster", bg)
+    q_cfg, p_cfg = B.make_cfg("pixel", 16, "cost", bg), B.make_cfg("pixel", 16, "cost", bg, flags=B.FLAG_PERSISTENT)
     balance = cu_balance(fcfg, bcfg)
     balance_static = cu_balance(naive_cfg, naive_cfg)
     balance_static_wave = cu_balance(sw_cfg, sw_cfg)
+    balance_queue = cu_balance(q_cfg, q_cfg)
+    balance_pool = cu_balance(p_cfg, p_cfg)
     for k in balance:
         print(f"[bench] {k} per-CU finish spread: tuned {balance[k]['spread']:.3f} "
               f"(CU busy {balance[k]['mean_busy']:.3f}), static {balance_static[k]['spread']:.3f} "
               f"(CU busy {balance_static[k]['mean_busy']:.3f}), grid-static same code "
-              f"{balance_static_wave[k]['spread']:.3f} (CU busy {balance_static_wave[k]['mean_busy']:.3f})",
-              flush=True)
+              f"{balance_static_wave[k]['spread']:.3f} (CU busy {balance_static_wave[k]['mean_busy']:.3f}), "
+              f"dispatched cost queue {balance_queue[k]['spread']:.3f}, persistent pool "
+              f"{balance_pool[k]['spread']:.3f}", flush=True)
 
     # roofline of the dominant kernel
     def roof(stage):
@@ -625,7 +646,8 @@ def main():
         "static": static,
         "same_code": same_code,
         "exact_binning": exact,
-        "cu_balance": {"tuned": balance, "static": balance_static, "static_same_code": balance_static_wave},
+        "cu_balance": {"tuned": balance, "static": balance_static, "static_same_code": balance_static_wave,
+                       "dispatched_cost_queue": balance_queue, "persistent_pool": balance_pool},
         "project_bwd_ms": pbwd_ms,
         "deterministic_backward": det,
         "configs": configs,
@@ -762,19 +784,27 @@ def balance_stats(rec):
 
 
 def kernel_of(stage, cfg, B):
-    """Name of the kernel a stage launches for a render configuration."""
+    """Name of the kernel a stage launches for a render configuration, as the
+    profiler prints it (template arguments included, namespace dropped)."""
     if stage == "project":
         return "k_project"
     wide = (cfg.variant == B.BALANCED_PIXEL and cfg.subtile in (16, 32)) or cfg.variant == B.STATIC_WAVE
+    persistent = "true" if cfg.variant == B.BALANCED_PIXEL and cfg.flags & B.FLAG_PERSISTENT else "false"
+    tpi = 4 if cfg.subtile == 32 else 1
     if stage == "render_fwd":
         if cfg.variant == B.STATIC:
             return "k_fwd_static"
         if wide:
-            return "k_fwd_wide"
-        return "k_fwd_pixel" if cfg.variant == B.BALANCED_PIXEL else "k_fwd_hybrid"
+            return f"k_fwd_wide<false, false, {persistent}, {tpi}>"
+        if cfg.variant == B.BALANCED_PIXEL:
+            return "k_fwd_pixel<true, false>"
+        return "k_fwd_hybrid<64>" if cfg.variant == B.VARIANTS["gauss"] else "k_fwd_hybrid<16>"
     if cfg.variant == B.STATIC:
-        return "k_bwd_pixel<false>"
-    return "k_bwd_wide" if wide else "k_bwd_pixel<true>"
+        return "k_bwd_pixel<false, false>"
+    if wide:
+        split = "true" if cfg.flags & B.FLAG_SPLIT_WALKS else "false"
+        return f"k_bwd_wide<false, false, {persistent}, {tpi}, {split}>"
+    return "k_bwd_pixel<true, false>"
 
 
 KERNEL_SOURCES = {"k_project": ["project.hip", "common.h"]}
@@ -783,7 +813,7 @@ KERNEL_SOURCES = {"k_project": ["project.hip", "common.h"]}
 def source_digest(kernel):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES.get(kernel, ["render.hip", "common.h"]):
+    for f in KERNEL_SOURCES.get(kernel.split("<")[0], ["render.hip", "common.h"]):
         with open(os.path.join(ROOT, "paper_2412_17378_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -77,7 +77,10 @@ typedef struct bgs_frame {
 /* Forward / backward kernel variants. */
 typedef enum bgs_variant {
     BGS_STATIC = 0,           /* one 256-lane workgroup per 16x16 tile, grid-static */
-    BGS_BALANCED_PIXEL = 1,   /* persistent waves, atomic sub-tile queue, lane = pixel */
+    BGS_BALANCED_PIXEL = 1,   /* balanced task distribution from the dealt queue, lane =
+                                 pixel: subtile 8 persistent waves on the atomic sub-tile
+                                 queue; subtile 16 / 32 the dealt items as a dispatched
+                                 grid, or persistent waves with BGS_FLAG_PERSISTENT */
     BGS_BALANCED_GAUSS = 2,   /* persistent waves, atomic sub-tile queue, lane = Gaussian */
     BGS_BALANCED_HYBRID = 3,  /* lane = pixel, stragglers finished lane = Gaussian */
     BGS_STATIC_WAVE = 4       /* the wave-per-tile code of BGS_BALANCED_PIXEL with
@@ -114,7 +117,16 @@ enum {
        unused (left as they are).  One list entry's ten gradient atomics then
        fall in one 64-byte segment instead of four arrays' cache lines.
        bgs_project_bwd_packed reads this layout.  Not for batched plans. */
-    BGS_FLAG_PACKED_GRADS = 4
+    BGS_FLAG_PACKED_GRADS = 4,
+    /* BGS_BALANCED_PIXEL with subtile 16 or 32: persistent waves take the
+       dealt work items from the task pool's 64 fetch counters (Alg. 1's
+       atomic task fetch).  Without the flag the dealt items go out as a plain
+       grid in rank order -- four items per 256-lane workgroup -- and the
+       hardware's workgroup dispatcher hands them to compute units as slots
+       free up, heaviest first in cost order: the same dynamic distribution
+       without atomics or a resident loop (and the register budget of the
+       grid-static kernel).  Either way every dealt item is rendered once. */
+    BGS_FLAG_PERSISTENT = 8
 };
 
 typedef struct bgs_render_cfg {
@@ -348,7 +360,9 @@ size_t bgs_render_workspace_bytes(const bgs_frame* frame, const bgs_render_cfg* 
  * backward's exact walk); a block costs the sum of its tiles.
  * bgs_render_fwd / bgs_render_bwd call this themselves.  The workspace
  * begins with the queue's state: 64 uint32 fetch counters 128 bytes apart
- * (counter q at byte 128 q), then at byte 8192 the number of items.
+ * (counter q at byte 128 q), then at byte 8192 the number of items.  The
+ * static variants (BGS_STATIC, BGS_STATIC_WAVE) take no queue: for them the
+ * call checks its arguments and returns BGS_OK without launching anything.
  */
 bgs_status bgs_queue_build(const bgs_frame* frame, const bgs_render_cfg* cfg, const int32_t* n_contrib,
                            void* ws, size_t ws_bytes, hipStream_t stream);
@@ -434,13 +448,15 @@ bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_render_cfg* cfg,
  * Variant selection by measurement (the self-adaptive kernel selection of
  * Sec. 4.4, generalized): runs every forward candidate (static; one wave per
  * tile dispatched statically; pixel-wise 8x8 raster and cost-ordered; one wave
- * per 16x16 tile; one wave per 32x32 block; hybrid; Gaussian-wise) on
+ * per 16x16 tile, raster and cost-ordered, the latter also through the
+ * persistent pool; one wave per 32x32 block; hybrid; Gaussian-wise) on
  * `frame` with base's background, times each with HIP events (one warm-up,
  * two timed runs) and returns the fastest in *best_fwd; then renders once with
  * it and, if dL_dcolor and the gradient buffers are given, times the backward
  * candidates (static; wave per tile dispatched statically; balanced 8x8
- * raster and cost-ordered; wave per 16x16 tile, also with split walks; wave
- * per 32x32 block) into *best_bwd.  With BGS_FLAG_PACKED_GRADS in base the
+ * raster and cost-ordered; wave per 16x16 tile, raster and cost-ordered, the
+ * latter also through the persistent pool and with split walks; wave per
+ * 32x32 block) into *best_bwd.  With BGS_FLAG_PACKED_GRADS in base the
  * backward candidates run on packed gradient records passed in dL_dmeans2D
  * (dL_dconic_opacity and dL_drgb null), and *best_bwd carries the flag.  The
  * output and gradient buffers are scratch (the gradients end up holding sums

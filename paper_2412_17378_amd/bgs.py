@@ -24,6 +24,7 @@ ORDER_RASTER, ORDER_COST = 0, 1
 FLAG_QUEUE_READY = 1
 FLAG_SPLIT_WALKS = 2
 FLAG_PACKED_GRADS = 4
+FLAG_PERSISTENT = 8
 GRAD_RECORD = 16  # floats per Gaussian in packed gradients: conic+opacity 0-3, means2D 4-5, rgb 6-8, depth 9
 TILE = 16
 
@@ -467,7 +468,8 @@ def bgs_plan_destroy(plan):
 def cfg_name(c: RenderCfg) -> str:
     names = {v: k for k, v in VARIANTS.items()}
     base = f"{names.get(c.variant, c.variant)}{c.subtile}/{'cost' if c.order == ORDER_COST else 'raster'}"
-    return base + ("/split" if c.flags & FLAG_SPLIT_WALKS else "")
+    return base + ("/split" if c.flags & FLAG_SPLIT_WALKS else "") + ("/persistent" if c.flags & FLAG_PERSISTENT
+                                                                      else "")
 
 
 def bgs_render_bwd_det_workspace_bytes(frame: Frame, P: int, max_occ: int) -> int:

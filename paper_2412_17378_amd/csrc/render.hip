@@ -331,6 +331,19 @@ __device__ __forceinline__ void note_claim(const WorkQueue& Q, int lane, uint32_
     }
 }
 
+// Item `rank` of the dealt list for a wave of a plain grid (the dealt items
+// handed out by the hardware's workgroup dispatcher, lowest rank first):
+// false past the item count.  With claims, lane 0 counts the claim as
+// note_claim does.
+__device__ __forceinline__ bool grid_item(const uint32_t* __restrict__ ctr, const uint32_t* __restrict__ items,
+                                          uint32_t rank, uint32_t* claims, uint32_t n_tiles, int lane,
+                                          uint32_t& item) {
+    if (rank >= __builtin_amdgcn_readfirstlane(ctr[NQ * QSTRIDE])) return false;
+    item = __builtin_amdgcn_readfirstlane(items[rank]);
+    if (claims && lane == 0) atomicAdd(&claims[(item & ((1u << 24) - 1u)) + (item >> 24) * n_tiles], 1u);
+    return true;
+}
+
 // Counter value t of queue q -> the item, if q still holds one.
 __device__ __forceinline__ bool queue_slot(const WorkQueue& Q, int q, uint32_t t, int lane, uint32_t& item) {
     const uint32_t i = t + Q.first(q);
@@ -943,7 +956,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     __shared__ WaveStage s_st[4];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     WorkQueue Q;
-    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv, MV ? nullptr : F0.item_claims);
+    if (PERSISTENT) Q = make_queue(ctr, items, blockIdx.x * 4 + wv, MV ? nullptr : F0.item_claims, (uint32_t)F0.n_tiles);
     for (bool first = true;; first = false) {
         uint32_t item;
         if (PERSISTENT) {
@@ -951,6 +964,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         } else {
             item = blockIdx.x * 4 + wv;
             if (item >= n_static) break;
+            // the dealt items in rank order, handed out by the workgroup dispatcher
+            if (items && !grid_item(ctr, items, item, F0.item_claims, (uint32_t)F0.n_tiles, lane, item)) break;
         }
         const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
         const FwdOut O = MV ? views[item >> VIEW_SHIFT].O : O0;
@@ -1392,6 +1407,8 @@ __global__ __launch_bounds__(256) void k_bwd_wide(FrameArgs F0, BwdIO B0, const 
         } else {
             item = blockIdx.x * 4 + wv;
             if (item >= n_static) break;
+            // the dealt items in rank order, handed out by the workgroup dispatcher
+            if (items && !grid_item(ctr, items, item, F0.item_claims, (uint32_t)F0.n_tiles, lane, item)) break;
         }
         const FrameArgs F = MV ? views[item >> VIEW_SHIFT].F : F0;
         const BwdIO B = MV ? views[item >> VIEW_SHIFT].B : B0;
@@ -1782,6 +1799,10 @@ static bool block_items(const bgs_render_cfg* cfg) {
     return cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 32;
 }
 
+// The wave-per-tile variants take their dealt items through the persistent
+// task pool with BGS_FLAG_PERSISTENT, else as a plain grid in rank order.
+static bool pool_waves(const bgs_render_cfg* cfg) { return (cfg->flags & BGS_FLAG_PERSISTENT) != 0; }
+
 // Split backward walks: the wave-per-tile backward with cost order and the flag.
 static bool split_walks(const bgs_render_cfg* cfg) {
     return (cfg->flags & BGS_FLAG_SPLIT_WALKS) && cfg->variant == BGS_BALANCED_PIXEL && cfg->subtile == 16 &&
@@ -1841,6 +1862,8 @@ extern "C" bgs_status bgs_queue_build(const bgs_frame* frame, const bgs_render_c
     FrameArgs A;
     bgs_status st = check_frame(frame, cfg, A, "bgs_queue_build");
     if (st != BGS_OK) return st;
+    // the static variants take no queue
+    if (cfg->variant == BGS_STATIC || cfg->variant == BGS_STATIC_WAVE) return BGS_OK;
     const RenderLayout L = render_layout(A.n_tiles);
     BGS_REQUIRE(ws && ws_bytes >= L.bytes, "bgs_queue_build: workspace too small");
     return build_queue(A, cfg, n_contrib, static_cast<char*>(ws), L, stream);
@@ -1879,18 +1902,32 @@ extern "C" bgs_status bgs_render_fwd(const bgs_frame* frame, const bgs_render_cf
     auto* ctr = reinterpret_cast<uint32_t*>(w + L.ctr);
     auto* items = reinterpret_cast<const uint32_t*>(w + L.items);
     const uint32_t n_items = queue_items(A, cfg);
+    // wave-per-tile kernels: n_max = the most items the queue can hold (up
+    // to four block units per tile); a plain grid of n_max / 4 workgroups in
+    // rank order, or the persistent pool
+    const bool pool = pool_waves(cfg);
     if (block_items(cfg)) {
-        const int blocks = persistent_blocks(k_fwd_wide<false, false, true, 4>, n_items);
-        hipLaunchKernelGGL((k_fwd_wide<false, false, true, 4>), dim3(blocks), dim3(256), 0, stream, A, O,
-                           (const ViewDesc*)nullptr, items, ctr, 0u);
+        if (pool)
+            hipLaunchKernelGGL((k_fwd_wide<false, false, true, 4>), dim3(persistent_blocks(k_fwd_wide<false, false,
+                               true, 4>, n_items)), dim3(256), 0, stream, A, O, (const ViewDesc*)nullptr, items, ctr,
+                               0u);
+        else
+            hipLaunchKernelGGL((k_fwd_wide<false, false, false, 4>), dim3((n_items + 3) / 4), dim3(256), 0, stream,
+                               A, O, (const ViewDesc*)nullptr, items, ctr, n_items);
     } else if (tile_items(cfg) && A.n_examined) {
-        const int blocks = persistent_blocks(k_fwd_wide<false, true>, 4 * n_items);
-        hipLaunchKernelGGL((k_fwd_wide<false, true>), dim3(blocks), dim3(256), 0, stream, A, O,
-                           (const ViewDesc*)nullptr, items, ctr, 0u);
+        if (pool)
+            hipLaunchKernelGGL((k_fwd_wide<false, true>), dim3(persistent_blocks(k_fwd_wide<false, true>,
+                               4 * n_items)), dim3(256), 0, stream, A, O, (const ViewDesc*)nullptr, items, ctr, 0u);
+        else
+            hipLaunchKernelGGL((k_fwd_wide<false, true, false>), dim3(n_items), dim3(256), 0, stream, A, O,
+                               (const ViewDesc*)nullptr, items, ctr, 4 * n_items);
     } else if (tile_items(cfg)) {
-        const int blocks = persistent_blocks(k_fwd_wide<false>, 4 * n_items);  // up to four blocks per tile
-        hipLaunchKernelGGL(k_fwd_wide<false>, dim3(blocks), dim3(256), 0, stream, A, O, (const ViewDesc*)nullptr,
-                           items, ctr, 0u);
+        if (pool)
+            hipLaunchKernelGGL(k_fwd_wide<false>, dim3(persistent_blocks(k_fwd_wide<false>, 4 * n_items)),
+                               dim3(256), 0, stream, A, O, (const ViewDesc*)nullptr, items, ctr, 0u);
+        else
+            hipLaunchKernelGGL((k_fwd_wide<false, false, false>), dim3(n_items), dim3(256), 0, stream, A, O,
+                               (const ViewDesc*)nullptr, items, ctr, 4 * n_items);
     } else if (cfg->variant == BGS_BALANCED_GAUSS) {
         const int blocks = persistent_blocks(k_fwd_hybrid<64>, L.n_items);
         hipLaunchKernelGGL(k_fwd_hybrid<64>, dim3(blocks), dim3(256), 0, stream, A, O, items, ctr);
@@ -2028,18 +2065,32 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
     auto* ctr = reinterpret_cast<uint32_t*>(w + L.ctr);
     auto* items = reinterpret_cast<const uint32_t*>(w + L.items);
     const uint32_t n_items = queue_items(A, cfg);
+    // wave-per-tile kernels as in bgs_render_fwd: up to four block units per
+    // tile, eight with split walks
+    const bool pool = pool_waves(cfg);
     if (block_items(cfg)) {
-        const int blocks = persistent_blocks(k_bwd_wide<false, false, true, 4>, n_items);
-        hipLaunchKernelGGL((k_bwd_wide<false, false, true, 4>), dim3(blocks), dim3(256), 0, stream, A, B,
-                           (const ViewDesc*)nullptr, items, ctr, 0u);
-    } else if (split_walks(cfg)) {  // up to eight units per tile
-        const int blocks = persistent_blocks(k_bwd_wide<false, false, true, 1, true>, 8 * n_items);
-        hipLaunchKernelGGL((k_bwd_wide<false, false, true, 1, true>), dim3(blocks), dim3(256), 0, stream, A, B,
-                           (const ViewDesc*)nullptr, items, ctr, 0u);
+        if (pool)
+            hipLaunchKernelGGL((k_bwd_wide<false, false, true, 4>), dim3(persistent_blocks(k_bwd_wide<false, false,
+                               true, 4>, n_items)), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr, items, ctr,
+                               0u);
+        else
+            hipLaunchKernelGGL((k_bwd_wide<false, false, false, 4>), dim3((n_items + 3) / 4), dim3(256), 0, stream,
+                               A, B, (const ViewDesc*)nullptr, items, ctr, n_items);
+    } else if (split_walks(cfg)) {
+        if (pool)
+            hipLaunchKernelGGL((k_bwd_wide<false, false, true, 1, true>), dim3(persistent_blocks(k_bwd_wide<false,
+                               false, true, 1, true>, 8 * n_items)), dim3(256), 0, stream, A, B,
+                               (const ViewDesc*)nullptr, items, ctr, 0u);
+        else
+            hipLaunchKernelGGL((k_bwd_wide<false, false, false, 1, true>), dim3(2 * n_items), dim3(256), 0, stream,
+                               A, B, (const ViewDesc*)nullptr, items, ctr, 8 * n_items);
     } else if (tile_items(cfg)) {
-        const int blocks = persistent_blocks(k_bwd_wide<false>, 4 * n_items);  // up to four blocks per tile
-        hipLaunchKernelGGL(k_bwd_wide<false>, dim3(blocks), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,
-                           items, ctr, 0u);
+        if (pool)
+            hipLaunchKernelGGL(k_bwd_wide<false>, dim3(persistent_blocks(k_bwd_wide<false>, 4 * n_items)),
+                               dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr, items, ctr, 0u);
+        else
+            hipLaunchKernelGGL((k_bwd_wide<false, false, false>), dim3(n_items), dim3(256), 0, stream, A, B,
+                               (const ViewDesc*)nullptr, items, ctr, 4 * n_items);
     } else {
         const int blocks = persistent_blocks(k_bwd_pixel<true>, L.n_items);
         hipLaunchKernelGGL(k_bwd_pixel<true>, dim3(blocks), dim3(256), 0, stream, A, B, (const ViewDesc*)nullptr,

@@ -113,8 +113,8 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
         *best_fwd = *base;
         best_fwd->variant = e.fv;
         best_fwd->subtile = e.fs;
-        best_fwd->order = e.fo;
-        best_fwd->flags = 0;
+        best_fwd->order = e.fo & 15;  // flags ride in the order fields' upper bits
+        best_fwd->flags = e.fo >> 4;
         *best_bwd = *base;
         best_bwd->variant = e.bv;
         best_bwd->subtile = e.bs;
@@ -124,18 +124,24 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
         if (bwd_ms_out) *bwd_ms_out = e.bms;
         return BGS_OK;
     }
-    const int fwd_cands[][3] = {{BGS_STATIC, 16, BGS_ORDER_RASTER},        {BGS_STATIC_WAVE, 16, BGS_ORDER_RASTER},
-                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_RASTER},  {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST},
-                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_RASTER}, {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST},
-                                {BGS_BALANCED_PIXEL, 32, BGS_ORDER_COST},   {BGS_BALANCED_HYBRID, 8, BGS_ORDER_COST},
-                                {BGS_BALANCED_GAUSS, 8, BGS_ORDER_COST}};
     // variant, sub-tile, order, flags
+    const int fwd_cands[][4] = {{BGS_STATIC, 16, BGS_ORDER_RASTER, 0},
+                                {BGS_STATIC_WAVE, 16, BGS_ORDER_RASTER, 0},
+                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_RASTER, 0},
+                                {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST, 0},
+                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_RASTER, 0},
+                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST, 0},
+                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST, BGS_FLAG_PERSISTENT},
+                                {BGS_BALANCED_PIXEL, 32, BGS_ORDER_COST, 0},
+                                {BGS_BALANCED_HYBRID, 8, BGS_ORDER_COST, 0},
+                                {BGS_BALANCED_GAUSS, 8, BGS_ORDER_COST, 0}};
     const int bwd_cands[][4] = {{BGS_STATIC, 16, BGS_ORDER_RASTER, 0},
                                 {BGS_STATIC_WAVE, 16, BGS_ORDER_RASTER, 0},
                                 {BGS_BALANCED_PIXEL, 8, BGS_ORDER_RASTER, 0},
                                 {BGS_BALANCED_PIXEL, 8, BGS_ORDER_COST, 0},
                                 {BGS_BALANCED_PIXEL, 16, BGS_ORDER_RASTER, 0},
                                 {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST, 0},
+                                {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST, BGS_FLAG_PERSISTENT},
                                 {BGS_BALANCED_PIXEL, 16, BGS_ORDER_COST, BGS_FLAG_SPLIT_WALKS},
                                 {BGS_BALANCED_PIXEL, 32, BGS_ORDER_COST, 0}};
     hipEvent_t e0, e1;
@@ -162,7 +168,7 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
         cfg.variant = fwd_cands[c][0];
         cfg.subtile = fwd_cands[c][1];
         cfg.order = fwd_cands[c][2];
-        cfg.flags = 0;
+        cfg.flags = fwd_cands[c][3];
         float ms = 0;
         st = timed([&] {
             return bgs_render_fwd(frame, &cfg, out_color, out_alpha, out_depth, final_T, n_contrib, ws, ws_bytes,
@@ -181,7 +187,7 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
         cfg.variant = fwd_cands[bf][0];
         cfg.subtile = fwd_cands[bf][1];
         cfg.order = fwd_cands[bf][2];
-        cfg.flags = 0;
+        cfg.flags = fwd_cands[bf][3];
         st = bgs_render_fwd(frame, &cfg, out_color, out_alpha, out_depth, final_T, n_contrib, ws, ws_bytes, stream);
         for (int c = 0; st == BGS_OK && c < (int)(sizeof(bwd_cands) / sizeof(bwd_cands[0])); ++c) {
             bgs_render_cfg bc = *base;
@@ -211,7 +217,7 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
     best_fwd->variant = fwd_cands[bf][0];
     best_fwd->subtile = fwd_cands[bf][1];
     best_fwd->order = fwd_cands[bf][2];
-    best_fwd->flags = 0;
+    best_fwd->flags = fwd_cands[bf][3];
     *best_bwd = *base;
     best_bwd->variant = bwd_cands[bb][0];
     best_bwd->subtile = bwd_cands[bb][1];
@@ -219,8 +225,9 @@ extern "C" bgs_status bgs_autotune(const bgs_frame* frame, const bgs_render_cfg*
     best_bwd->flags = bwd_cands[bb][3] | packed;  // split walks: the caller sets split_color / split_depth
     if (fwd_ms_out) *fwd_ms_out = best_f;
     if (bwd_ms_out) *bwd_ms_out = std::isinf(best_b) ? -1.0f : best_b;
-    TuneEntry ne{key, best_fwd->variant, best_fwd->subtile, best_fwd->order, best_bwd->variant, best_bwd->subtile,
-                 best_bwd->order | (best_bwd->flags << 4), best_f, std::isinf(best_b) ? -1.0f : best_b};
+    TuneEntry ne{key, best_fwd->variant, best_fwd->subtile, best_fwd->order | (best_fwd->flags << 4),
+                 best_bwd->variant, best_bwd->subtile, best_bwd->order | (best_bwd->flags << 4), best_f,
+                 std::isinf(best_b) ? -1.0f : best_b};
     if (!std::isinf(best_b)) cache_store(cache_path, ne);
     return BGS_OK;
 }

@@ -382,10 +382,11 @@ class FrameStep:
         P = params["means3D"].shape[0]
         self.P = P
         self.fcfg, self.bcfg = fcfg, bcfg
-        self.fcfg_ready = B.make_cfg(fcfg.variant, fcfg.subtile, fcfg.order, tuple(fcfg.bg), flags=B.FLAG_QUEUE_READY)
+        self.fcfg_ready = B.make_cfg(fcfg.variant, fcfg.subtile, fcfg.order, tuple(fcfg.bg),
+                                     flags=B.FLAG_QUEUE_READY | (fcfg.flags & B.FLAG_PERSISTENT))
         self.packed_grads = bool(packed_grads)
         self.bcfg_ready = B.make_cfg(bcfg.variant, bcfg.subtile, bcfg.order, tuple(bcfg.bg),
-                                     flags=B.FLAG_QUEUE_READY | (bcfg.flags & B.FLAG_SPLIT_WALKS) |
+                                     flags=B.FLAG_QUEUE_READY | (bcfg.flags & (B.FLAG_SPLIT_WALKS | B.FLAG_PERSISTENT)) |
                                      (B.FLAG_PACKED_GRADS if self.packed_grads else 0))
         self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
         self.list_cap = 0
@@ -493,7 +494,7 @@ class FrameStep:
         mark(1)
         self._lists()
         mark(2)
-        if self.fcfg.variant != B.STATIC:
+        if self.fcfg.variant not in (B.STATIC, B.STATIC_WAVE):  # the static variants take no queue
             B.bgs_queue_build(self.frame, self.fcfg, None, self.rws)
         mark(3)
         f = self.fwd
@@ -503,7 +504,7 @@ class FrameStep:
                          f["n_contrib"], self.rws)
         mark(4)
         torch._foreach_zero_(self._grad_list)
-        if self.bcfg.variant != B.STATIC:
+        if self.bcfg.variant not in (B.STATIC, B.STATIC_WAVE):
             B.bgs_queue_build(self.frame, self.bcfg, f["n_contrib"], self.rws)
         mark(5)
         if self.packed_grads:

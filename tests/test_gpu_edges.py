@@ -17,15 +17,18 @@ from workloads import scenes
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+# (variant, sub-tile, order[, "split" / "pool": split walks / the persistent task pool])
 VARIANTS = [("static", 16, "raster"), ("pixel", 8, "raster"), ("pixel", 8, "cost"), ("pixel", 16, "cost"),
-            ("pixel", 32, "cost"), ("static_wave", 16, "raster"), ("gauss", 8, "cost"), ("hybrid", 8, "cost")]
+            ("pixel", 16, "cost", "pool"), ("pixel", 32, "cost"), ("pixel", 32, "cost", "pool"),
+            ("static_wave", 16, "raster"), ("gauss", 8, "cost"), ("hybrid", 8, "cost")]
 BWD_VARIANTS = [v for v in VARIANTS if v[0] in ("static", "pixel", "static_wave")] + [("pixel", 16, "cost", "split")]
 
 
 def _cfg(v, bg=(0.0, 0.0, 0.0)):
     from paper_2412_17378_amd import make_cfg
     from paper_2412_17378_amd import bgs as B
-    return make_cfg(*v[:3], bg, flags=B.FLAG_SPLIT_WALKS if "split" in v[3:] else 0)
+    flags = (B.FLAG_SPLIT_WALKS if "split" in v[3:] else 0) | (B.FLAG_PERSISTENT if "pool" in v[3:] else 0)
+    return make_cfg(*v[:3], bg, flags=flags)
 
 
 @pytest.fixture(scope="module")
@@ -35,10 +38,9 @@ def rast():
 
 
 def _render_all(rast, prep, bg=(0.0, 0.0, 0.0)):
-    from paper_2412_17378_amd import make_cfg
     outs = {}
-    for v, sub, o in VARIANTS:
-        outs[(v, sub, o)] = rast.render_fwd(prep, make_cfg(v, sub, o, bg))
+    for v in VARIANTS:
+        outs[v] = rast.render_fwd(prep, _cfg(v, bg))
     torch.cuda.synchronize()
     return outs
 

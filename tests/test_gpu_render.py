@@ -17,10 +17,17 @@ from workloads import scenes
 
 pytestmark = pytest.mark.gpu
 
-# (variant, sub-tile, queue order)
+# (variant, sub-tile, queue order[, "pool": the persistent task pool])
 VARIANTS = [("static", 16, "raster"), ("pixel", 8, "raster"), ("pixel", 8, "cost"), ("pixel", 16, "cost"),
             ("pixel", 16, "raster"), ("pixel", 32, "cost"), ("static_wave", 16, "raster"), ("gauss", 8, "cost"),
-            ("hybrid", 8, "cost")]
+            ("hybrid", 8, "cost"), ("pixel", 16, "cost", "pool"), ("pixel", 32, "cost", "pool")]
+
+
+def _cfg(v, bg=(0.0, 0.0, 0.0)):
+    """(variant, sub-tile, order[, "pool": the persistent task pool])"""
+    from paper_2412_17378_amd import make_cfg
+    from paper_2412_17378_amd import bgs as B
+    return make_cfg(*v[:3], bg, flags=B.FLAG_PERSISTENT if "pool" in v[3:] else 0)
 
 
 @pytest.fixture(scope="module")
@@ -38,17 +45,16 @@ def _scene(name):
 
 
 @pytest.mark.parametrize("name", ["tiny-60", "ragged", "0", "sh3"])
-@pytest.mark.parametrize("variant,sub,order", VARIANTS)
-def test_forward_parity(rast, name, variant, sub, order):
-    from paper_2412_17378_amd import make_cfg
+@pytest.mark.parametrize("v", VARIANTS)
+def test_forward_parity(rast, name, v):
     s = _scene(name)
     bg = (0.1, 0.2, 0.3)
-    print(f"[fwd] case={name} variant={variant}/{sub} order={order}", flush=True)
+    print(f"[fwd] case={name} cfg={v}", flush=True)
     prep = rast.prepare_scene(s)
-    out = rast.render_fwd(prep, make_cfg(variant, sub, order, bg))
+    out = rast.render_fwd(prep, _cfg(v, bg))
     torch.cuda.synchronize()
     orc = oracle_render_from_gpu(prep, bg=bg)
-    compare_forward(out, orc, name=f"{name}/{variant}/{sub}/{order}")
+    compare_forward(out, orc, name=f"{name}/{v}")
 
 
 @pytest.mark.parametrize("name", ["tiny-60", "ragged", "0"])
@@ -58,22 +64,22 @@ def test_static_and_balanced_bit_identical(rast, name):
     print(f"[fwd-bitwise] case={name}", flush=True)
     prep = rast.prepare_scene(s)
     a = rast.render_fwd(prep, make_cfg("static"))
-    for v, sub in (("pixel", 8), ("pixel", 16), ("pixel", 32), ("static_wave", 16)):
-        b = rast.render_fwd(prep, make_cfg(v, sub, "cost"))
+    for v in (("pixel", 8, "cost"), ("pixel", 16, "cost"), ("pixel", 16, "raster"), ("pixel", 32, "cost"),
+              ("static_wave", 16, "raster"), ("pixel", 16, "cost", "pool"), ("pixel", 32, "cost", "pool")):
+        b = rast.render_fwd(prep, _cfg(v))
         torch.cuda.synchronize()
         for k in a:
-            assert torch.equal(a[k], b[k]), (k, v, sub)
+            assert torch.equal(a[k], b[k]), (k, v)
 
 
 @pytest.mark.parametrize("name", ["tiny-60", "ragged", "0", "sh3"])
-@pytest.mark.parametrize("variant,sub,order", [v for v in VARIANTS if v[0] in ("static", "pixel", "static_wave")])
-def test_backward_parity(rast, name, variant, sub, order):
-    from paper_2412_17378_amd import make_cfg
+@pytest.mark.parametrize("v", [v for v in VARIANTS if v[0] in ("static", "pixel", "static_wave")])
+def test_backward_parity(rast, name, v):
     s = _scene(name)
     bg = (0.3, 0.1, 0.2)
-    print(f"[bwd] case={name} variant={variant}/{sub} order={order}", flush=True)
+    print(f"[bwd] case={name} cfg={v}", flush=True)
     prep = rast.prepare_scene(s)
-    cfg = make_cfg(variant, sub, order, bg)
+    cfg = _cfg(v, bg)
     fwd = rast.render_fwd(prep, cfg)
     torch.cuda.synchronize()
     orc_f = oracle_render_from_gpu(prep, bg=bg)
@@ -90,7 +96,7 @@ def test_backward_parity(rast, name, variant, sub, order):
                             torch.from_numpy(gD).to(dev))
     torch.cuda.synchronize()
     orc = oracle_bwd_from_gpu(prep, gC, gA, gD, bg=bg)
-    compare_grads(grads, orc, name=f"{name}/{variant}/{sub}/{order}")
+    compare_grads(grads, orc, name=f"{name}/{v}")
 
 
 @pytest.mark.parametrize("name", ["tiny-60", "ragged", "0", "sh3"])

@@ -50,29 +50,60 @@ __device__ __forceinline__ void ds_hist_store(uint32_t* s_hist, uint32_t* __rest
     if (threadIdx.x < DS_RADIX) cnt[(size_t)threadIdx.x * nb + blockIdx.x] = s_hist[threadIdx.x];
 }
 
+// Also stores the AND and the OR of the block's keys of listed Gaussians at
+// andor[2 b], [2 b + 1] (k_ds_colscan of the first pass folds them into the
+// mask of key bits that vary: a later pass whose byte does not vary keeps
+// the listed Gaussians' order; the others, which emit no pairs, may end up
+// anywhere).
 __global__ __launch_bounds__(DS_THREADS) void k_ds_keys(int64_t P, const float* __restrict__ depth,
                                                         const uint32_t* __restrict__ tiles_touched,
                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ ids,
-                                                        uint32_t* __restrict__ cnt, int nb) {
+                                                        uint32_t* __restrict__ cnt, int nb,
+                                                        uint32_t* __restrict__ andor) {
     __shared__ uint32_t s_hist[DS_RADIX];
+    __shared__ uint32_t s_and, s_or;
     if (threadIdx.x < DS_RADIX) s_hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
+        s_and = ~0u;
+        s_or = 0u;
+    }
     __syncthreads();
     const int64_t b0 = (int64_t)blockIdx.x * DS_TILE;
+    uint32_t a = ~0u, o = 0u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t i = b0 + ds_item(j);
         if (i < P) {
-            const uint32_t k = tiles_touched[i] ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
+            const bool listed = tiles_touched[i] != 0u;
+            const uint32_t k = listed ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
             keys[i] = k;
             ids[i] = (uint32_t)i;
             atomicAdd(&s_hist[k & 0xFFu], 1u);
+            if (listed) {  // a Gaussian with no pairs may sit anywhere in the order
+                a &= k;
+                o |= k;
+            }
         }
     }
-    ds_hist_store(s_hist, cnt, nb);
+    atomicAnd(&s_and, a);
+    atomicOr(&s_or, o);
+    ds_hist_store(s_hist, cnt, nb);  // (synchronizes)
+    if (threadIdx.x == 0) {
+        andor[2 * blockIdx.x] = s_and;
+        andor[2 * blockIdx.x + 1] = s_or;
+    }
+}
+
+// Whether the byte of the keys at `shift` varies (vary: the mask of key bits
+// that differ between keys; null: sort every pass).
+__device__ __forceinline__ bool ds_byte_varies(const uint32_t* vary, int shift) {
+    return !vary || ((*vary >> shift) & 0xFFu) != 0u;
 }
 
 __global__ __launch_bounds__(DS_THREADS) void k_ds_hist(int64_t P, const uint32_t* __restrict__ keys, int shift,
-                                                        uint32_t* __restrict__ cnt, int nb) {
+                                                        uint32_t* __restrict__ cnt, int nb,
+                                                        const uint32_t* __restrict__ vary) {
+    if (!ds_byte_varies(vary, shift)) return;  // an identity pass
     __shared__ uint32_t s_hist[DS_RADIX];
     if (threadIdx.x < DS_RADIX) s_hist[threadIdx.x] = 0u;
     __syncthreads();
@@ -87,9 +118,32 @@ __global__ __launch_bounds__(DS_THREADS) void k_ds_hist(int64_t P, const uint32_
 
 // One workgroup per digit d: exclusive scan of cnt[d][0..nb) in place,
 // tot[d] = the digit's total.
-__global__ __launch_bounds__(256) void k_ds_colscan(int nb, uint32_t* __restrict__ cnt, uint32_t* __restrict__ tot) {
+// First pass (andor given): workgroup 0 also folds the blocks' key ANDs and
+// ORs into tot[DS_RADIX] = the mask of key bits that vary.  Later passes
+// (vary given) leave an identity pass alone.
+__global__ __launch_bounds__(256) void k_ds_colscan(int nb, uint32_t* __restrict__ cnt, uint32_t* __restrict__ tot,
+                                                    const uint32_t* __restrict__ andor, int shift,
+                                                    const uint32_t* __restrict__ vary) {
     using Scan = rocprim::block_scan<uint32_t, 256>;
     __shared__ typename Scan::storage_type s_scan;
+    if (!ds_byte_varies(vary, shift)) return;
+    if (andor && blockIdx.x == 0) {
+        __shared__ uint32_t s_and, s_or;
+        if (threadIdx.x == 0) {
+            s_and = ~0u;
+            s_or = 0u;
+        }
+        __syncthreads();
+        uint32_t a = ~0u, o = 0u;
+        for (int b = threadIdx.x; b < nb; b += 256) {
+            a &= andor[2 * b];
+            o |= andor[2 * b + 1];
+        }
+        atomicAnd(&s_and, a);
+        atomicOr(&s_or, o);
+        __syncthreads();
+        if (threadIdx.x == 0) tot[DS_RADIX] = s_and ^ s_or;
+    }
     uint32_t* c = cnt + (size_t)blockIdx.x * nb;
     const int per = (nb + 255) / 256;
     const int t0 = min(nb, (int)threadIdx.x * per), t1 = min(nb, t0 + per);
@@ -115,7 +169,19 @@ __global__ __launch_bounds__(DS_THREADS) void k_ds_scatter(int64_t P, const uint
                                                            uint32_t* __restrict__ keys_out,
                                                            uint32_t* __restrict__ vals_out, int shift,
                                                            const uint32_t* __restrict__ cnt,
-                                                           const uint32_t* __restrict__ tot, int nb) {
+                                                           const uint32_t* __restrict__ tot, int nb,
+                                                           const uint32_t* __restrict__ vary) {
+    if (!ds_byte_varies(vary, shift)) {  // every key has this byte: the pass keeps the order
+        const int64_t b0 = (int64_t)blockIdx.x * DS_TILE;
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = b0 + ds_item(j);
+            if (i < P) {
+                if (KEYS) keys_out[i] = keys_in[i];
+                vals_out[i] = vals_in[i];
+            }
+        }
+        return;
+    }
     using Scan = rocprim::block_scan<uint32_t, DS_THREADS>;
     __shared__ typename Scan::storage_type s_scan;
     __shared__ uint32_t s_wcnt[DS_WAVES][DS_RADIX];  // per-wave digit counts, then their offsets
@@ -200,12 +266,15 @@ bgs_status radix_sort_pairs_u32(int64_t n, int bits, uint32_t* k0, uint32_t* v0,
     uint32_t *kin = k0, *vin = v0, *kout = k1, *vout = v1;
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_ds_hist, dim3(nb), dim3(DS_THREADS), 0, stream, n, (const uint32_t*)kin, shift, cnt, nb);
+        const uint32_t* no_skip = nullptr;
+        hipLaunchKernelGGL(k_ds_hist, dim3(nb), dim3(DS_THREADS), 0, stream, n, (const uint32_t*)kin, shift, cnt, nb,
+                           no_skip);
         BGS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_ds_colscan, dim3(DS_RADIX), dim3(256), 0, stream, nb, cnt, tot);
+        hipLaunchKernelGGL(k_ds_colscan, dim3(DS_RADIX), dim3(256), 0, stream, nb, cnt, tot, no_skip, shift, no_skip);
         BGS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_ds_scatter<true>, dim3(nb), dim3(DS_THREADS), 0, stream, n, (const uint32_t*)kin,
-                           (const uint32_t*)vin, kout, vout, shift, (const uint32_t*)cnt, (const uint32_t*)tot, nb);
+                           (const uint32_t*)vin, kout, vout, shift, (const uint32_t*)cnt, (const uint32_t*)tot, nb,
+                           no_skip);
         BGS_HIP(hipGetLastError());
         std::swap(kin, kout);
         std::swap(vin, vout);
@@ -216,15 +285,23 @@ bgs_status radix_sort_pairs_u32(int64_t n, int bits, uint32_t* k0, uint32_t* v0,
 
 size_t radix_sort_pairs_u32_scratch(int64_t n) { return 4 * ((size_t)DS_RADIX * ds_blocks(n > 0 ? n : 1) + DS_RADIX); }
 
+// Words of tot for depth_order: the digit totals, the mask of varying key
+// bits, and two words per block.
+static size_t depth_order_tot_words(int64_t P) { return DS_RADIX + 1 + 2 * (size_t)ds_blocks(P > 0 ? P : 1); }
+
 // Sorted Gaussian ids into order[P]; keys / keys2 / ids2 [P] are scratch,
-// cnt [256 ds_blocks(P)] and tot [256] the histograms.
+// cnt [256 ds_blocks(P)] and tot [depth_order_tot_words(P)] the histograms.
+// A pass whose byte is the same in every key (typically the top one: depths
+// within one or two binades share it) is an identity pass and runs as a copy.
 static bgs_status depth_order(int64_t P, const float* depth, const uint32_t* tiles_touched, uint32_t* keys,
                               uint32_t* order, uint32_t* keys2, uint32_t* ids2, uint32_t* cnt, uint32_t* tot,
                               hipStream_t stream) {
     if (P == 0) return BGS_OK;
     const int nb = ds_blocks(P);
+    uint32_t* andor = tot + DS_RADIX + 1;
+    const uint32_t* vary = tot + DS_RADIX;
     hipLaunchKernelGGL(k_ds_keys, dim3(nb), dim3(DS_THREADS), 0, stream, P, depth, tiles_touched, keys, order, cnt,
-                       nb);
+                       nb, andor);
     BGS_HIP(hipGetLastError());
     // (keys, order) -> (keys2, ids2) -> (keys, order) -> ... : four passes end in order
     uint32_t* kin = keys;
@@ -233,19 +310,24 @@ static bgs_status depth_order(int64_t P, const float* depth, const uint32_t* til
     uint32_t* vout = ids2;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
+        // the first pass sorts always (its histogram came with the keys) and finds the varying bits
+        const uint32_t* skip = pass > 0 ? vary : nullptr;
         if (pass > 0) {
             hipLaunchKernelGGL(k_ds_hist, dim3(nb), dim3(DS_THREADS), 0, stream, P, (const uint32_t*)kin, shift, cnt,
-                               nb);
+                               nb, skip);
             BGS_HIP(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_ds_colscan, dim3(DS_RADIX), dim3(256), 0, stream, nb, cnt, tot);
+        hipLaunchKernelGGL(k_ds_colscan, dim3(DS_RADIX), dim3(256), 0, stream, nb, cnt, tot,
+                           pass == 0 ? (const uint32_t*)andor : nullptr, shift, skip);
         BGS_HIP(hipGetLastError());
         if (pass < 3)
             hipLaunchKernelGGL(k_ds_scatter<true>, dim3(nb), dim3(DS_THREADS), 0, stream, P, (const uint32_t*)kin,
-                               (const uint32_t*)vin, kout, vout, shift, (const uint32_t*)cnt, (const uint32_t*)tot, nb);
+                               (const uint32_t*)vin, kout, vout, shift, (const uint32_t*)cnt, (const uint32_t*)tot, nb,
+                               skip);
         else
             hipLaunchKernelGGL(k_ds_scatter<false>, dim3(nb), dim3(DS_THREADS), 0, stream, P, (const uint32_t*)kin,
-                               (const uint32_t*)vin, kout, vout, shift, (const uint32_t*)cnt, (const uint32_t*)tot, nb);
+                               (const uint32_t*)vin, kout, vout, shift, (const uint32_t*)cnt, (const uint32_t*)tot, nb,
+                               skip);
         BGS_HIP(hipGetLastError());
         std::swap(kin, kout);
         std::swap(vin, vout);
@@ -358,7 +440,7 @@ static BinLayout bin_layout(int64_t P) {
     L.offsets = take(8 * n);
     L.total = take(8);
     L.dcnt = take(4 * (size_t)DS_RADIX * ds_blocks((int64_t)n));
-    L.dtot = take(4 * (size_t)DS_RADIX);
+    L.dtot = take(4 * depth_order_tot_words((int64_t)n));
     L.temp_bytes = scan_bytes;
     L.temp = take(L.temp_bytes);
     L.bytes = off;
@@ -1287,7 +1369,7 @@ static ListsLayout lists_layout(int32_t width, int32_t height, int64_t P, size_t
     L.segmap = take(8 * L.max_segs);
     L.segcnt = take(4 * 64 * L.max_segs);  // one count per (segment, tile of the group)
     L.dcnt = take(4 * (size_t)DS_RADIX * ds_blocks((int64_t)n));
-    L.dtot = take(4 * (size_t)DS_RADIX);
+    L.dtot = take(4 * depth_order_tot_words((int64_t)n));
     L.bytes = off;
     return L;
 }

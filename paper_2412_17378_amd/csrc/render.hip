@@ -1434,35 +1434,39 @@ __device__ __forceinline__ int cost_bucket(uint32_t c) {
     return b < NBUCKET - 1 ? b : NBUCKET - 1;
 }
 
-// Backward cost of every work item (one workgroup per item): a tile costs
+// Backward cost of every work item (one wave per item): a tile costs
 // the largest n_contrib among its 256 pixels (clamped into its list, as the
 // backward clamps it) -- the length of the walk; with block2 the item is a
 // 32x32 block and costs the sum over its tiles.
 __global__ __launch_bounds__(256) void k_tile_costs(FrameArgs F, const int* __restrict__ n_contrib, int block2,
-                                                    uint32_t* __restrict__ cost) {
-    __shared__ int wmax[4];
+                                                    int n_items, uint32_t* __restrict__ cost) {
+    // one wave per item; lane l reads the tile's pixels (l mod 16, l / 16 + 4q), q = 0..3
+    const int item = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (item >= n_items) return;  // whole waves
     int tiles[4];
     int nt = 1;
     if (block2) {
-        nt = item_tiles<4>(F, blockIdx.x, tiles);
+        nt = item_tiles<4>(F, (uint32_t)item, tiles);
     } else {
-        tiles[0] = blockIdx.x;
+        tiles[0] = item;
     }
     uint32_t c = 0;
     for (int k = 0; k < nt; ++k) {
         const int tile = tiles[k];
         const int tx = tile % F.TX, ty = tile / F.TX;
-        const int px = tx * TILE + (threadIdx.x & 15), py = ty * TILE + (threadIdx.x >> 4);
+        const int px = tx * TILE + (lane & 15);
         const int len = (int)(F.ranges[2 * tile + 1] - F.ranges[2 * tile]);
-        int nc = (px < F.W && py < F.H) ? n_contrib[(int64_t)py * F.W + px] : 0;
-        nc = nc < 0 ? 0 : (nc > len ? len : nc);
-        const int m = wave_max(nc);
-        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-        __syncthreads();
-        c += (uint32_t)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
-        __syncthreads();
+        int m = 0;
+#pragma unroll
+        for (int q = 0; q < WQ; ++q) {
+            const int py = ty * TILE + (lane >> 4) + 4 * q;
+            int nc = (px < F.W && py < F.H) ? n_contrib[(int64_t)py * F.W + px] : 0;
+            nc = nc < 0 ? 0 : (nc > len ? len : nc);
+            m = nc > m ? nc : m;
+        }
+        c += (uint32_t)wave_max(m);
     }
-    if (threadIdx.x == 0) cost[blockIdx.x] = c;
+    if (lane == 0) cost[item] = c;
 }
 
 // Forward cost estimate of a work item, one wave per item: the list position
@@ -1828,7 +1832,8 @@ static bgs_status build_queue(const FrameArgs& A, const bgs_render_cfg* cfg, con
     const int n_cost = blocks ? (int)queue_items(A, cfg) : A.n_tiles;
     if (by_cost && n_cost > 0) {
         if (n_contrib)  // backward: the exact walk
-            hipLaunchKernelGGL(k_tile_costs, dim3(n_cost), dim3(256), 0, stream, A, n_contrib, blocks ? 1 : 0, cost);
+            hipLaunchKernelGGL(k_tile_costs, dim3((n_cost + 3) / 4), dim3(256), 0, stream, A, n_contrib, blocks ? 1 : 0,
+                               n_cost, cost);
         else  // forward: the opacity-budget estimate
             hipLaunchKernelGGL(k_fwd_costs, dim3((n_cost + 3) / 4), dim3(256), 0, stream, A, blocks ? 1 : 0, n_cost,
                                cost);
@@ -2113,25 +2118,6 @@ extern "C" bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cf
 // ======================================================================
 namespace bgs {
 
-// cnt[t] = the entries the wide backward walks in tile t: the largest
-// n_contrib of its pixels, clamped to its list (one workgroup per tile)
-__global__ __launch_bounds__(256) void k_det_count(FrameArgs F, const int* __restrict__ n_contrib,
-                                                   uint32_t* __restrict__ cnt) {
-    __shared__ int wmax[4];
-    const int t = blockIdx.x;
-    const int px = (t % F.TX) * TILE + (threadIdx.x & 15), py = (t / F.TX) * TILE + (threadIdx.x >> 4);
-    const int len = (int)(F.ranges[2 * t + 1] - F.ranges[2 * t]);
-    int n = 0;
-    if (px < F.W && py < F.H) {
-        n = n_contrib[(int64_t)py * F.W + px];
-        n = n < 0 ? 0 : (n > len ? len : n);
-    }
-    n = wave_max(n);
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = n;
-    __syncthreads();
-    if (threadIdx.x == 0) cnt[t] = (uint32_t)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
-}
-
 // base = exclusive scan of cnt over the tiles; total[0] = the sum (one workgroup)
 __global__ __launch_bounds__(1024) void k_det_scan(int nt, const uint32_t* __restrict__ cnt,
                                                    uint32_t* __restrict__ base, uint64_t* __restrict__ total) {
@@ -2272,7 +2258,9 @@ extern "C" bgs_status bgs_render_bwd_det(const bgs_frame* frame, const bgs_rende
     auto* base = reinterpret_cast<uint32_t*>(w + D.base);
     auto* total = reinterpret_cast<uint64_t*>(w + D.total);
     if (A.n_tiles == 0) return BGS_OK;
-    hipLaunchKernelGGL(k_det_count, dim3(A.n_tiles), dim3(256), 0, stream, A, n_contrib, cnt);
+    // cnt[t] = the entries the wide backward walks in tile t (its walk cost)
+    hipLaunchKernelGGL(k_tile_costs, dim3((A.n_tiles + 3) / 4), dim3(256), 0, stream, A, n_contrib, 0, A.n_tiles,
+                       cnt);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_det_scan, dim3(1), dim3(1024), 0, stream, A.n_tiles, cnt, base, total);
     BGS_HIP(hipGetLastError());

@@ -5,8 +5,10 @@ One step = the whole path on one synthetic frame, inputs resident in HBM:
     project -> tile lists (bin + sort + ranges) -> queue -> render_fwd -> queue -> render_bwd
 (gradient buffers zeroed each step), issued without host synchronization
 (pipeline.FrameStep).  The timed steps replay the step captured once as a
-hipGraph; the same step launched eagerly, call by call, is timed too and
-gives the per-stage times, and the replays must reproduce its outputs.  By
+hipGraph; the same step launched eagerly, call by call, is timed too, and
+the replays must reproduce its outputs.  Per-stage times are medians over
+eager steps each queued behind a short GPU sleep (so the whole step is
+enqueued before it starts and the events see GPU time only).  By
 default the tile lists keep only the front-most K entries per tile, K picked
 by FrameStep from one whole-list step; every timed step is checked for a
 pixel running off a capped list (the run fails if one does), so the
@@ -23,9 +25,10 @@ the oracle run once on the GPU's own lists, outside the timed region.
 
 Also reported: per-stage milliseconds (HIP events on the launch stream); the
 same step with the static one-workgroup-per-tile kernels (the paper's naive
-kernel) and with the wave-per-tile code dispatched grid-statically (the same
-per-tile code as the balanced kernels, no queue: the comparison that isolates
-the task pool); the step on whole (uncapped) tile lists; the roofline
+kernel) and with the wave-per-tile code three ways -- the dealt items as a
+dispatched grid, the persistent task pool, grid-static in raster order with no
+queue (the same per-tile code: the comparison that isolates the scheduling);
+the step on whole (uncapped) tile lists; the roofline
 fraction of the dominant kernel; the FP64 oracle timed on the host over a
 bounded window of the same frame; and, each in its own block, the other
 workloads' steps with the autotuner's picks (the 3M-Gaussian SH-3 scene, the
@@ -163,7 +166,7 @@ class Workload:
         if st.overflowed():
             raise RuntimeError("a pixel ran off a capped tile list: rerun with a larger --list-cap or 'none'")
         names = ["project", "lists", "queue_fwd", "render_fwd", "queue_bwd", "render_bwd"]
-        stages = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
+        stages = {n: float(np.median([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
                   for i, n in enumerate(names)}
         r = {"step": st, "M": M, "M_whole": st.M_whole, "list_cap": st.list_cap, "stages": stages,
              "eager_ms": (t1 - t0) * 1e3 / steps, "whole_list_len": st.whole_list_len.cpu().numpy(),

@@ -85,8 +85,14 @@ __global__ __launch_bounds__(DS_THREADS) void k_ds_keys(int64_t P, const float* 
             }
         }
     }
-    atomicAnd(&s_and, a);
-    atomicOr(&s_or, o);
+    for (int off = 32; off >= 1; off >>= 1) {  // over the wave first: one LDS atomic per wave
+        a &= (uint32_t)__shfl_xor((int)a, off, 64);
+        o |= (uint32_t)__shfl_xor((int)o, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAnd(&s_and, a);
+        atomicOr(&s_or, o);
+    }
     ds_hist_store(s_hist, cnt, nb);  // (synchronizes)
     if (threadIdx.x == 0) {
         andor[2 * blockIdx.x] = s_and;

@@ -410,9 +410,15 @@ size_t bgs_render_fwd_noalloc_max_bytes(void);
  * the caller's buffers (zero them first):
  *   dL_dmeans2D [P][2]; dL_dconic_opacity [P][4] laid out like
  *   conic_opacity: d/da, d/db, d/dc of power = -(a dx^2 + c dy^2)/2 - b dx dy,
- *   then d/do; dL_drgb [P][3]; dL_ddepths [P] (nullable).
+ *   then d/do; dL_drgb [P][3]; dL_ddepths [P] (nullable);
+ * or, with BGS_FLAG_PACKED_GRADS, one [P][16] record array in dL_dmeans2D
+ * (the other three null; layout at the flag).  A long walk may be split
+ * (BGS_FLAG_SPLIT_WALKS), the lower part walked front to back from T = 1.
  * dL_dalpha and dL_ddepth are nullable (zero).  final_T and n_contrib are the
- * forward's outputs for the same frame.
+ * forward's outputs for the same frame.  Errors: BGS_EINVAL for null or
+ * misaligned required arrays, a workspace too small, or split walks without
+ * split_color / split_depth; BGS_EUNSUPPORTED for split walks on another
+ * variant.
  */
 bgs_status bgs_render_bwd(const bgs_frame* frame, const bgs_render_cfg* cfg, const float* final_T,
                           const int32_t* n_contrib, const float* dL_dcolor, const float* dL_dalpha,

@@ -337,7 +337,8 @@ bgs_status bgs_tile_lists(int32_t width, int32_t height, int32_t tile, int64_t P
  * 1/255 gets no pair.
  *   conic_opacity [P][4] (DEVICE, 16-byte aligned), everything else, the
  *   workspace size, max_per_tile and the overflow behaviour as for
- *   bgs_tile_lists.
+ *   bgs_tile_lists.  Images over 16384 pixels high (1024 tile rows) return
+ *   BGS_EUNSUPPORTED: the emit keeps a Gaussian's row intervals in LDS.
  */
 bgs_status bgs_tile_lists_exact(int32_t width, int32_t height, int32_t tile, int64_t P, const float* means2D,
                                 const float* conic_opacity, const int32_t* radius, const float* depth,

@@ -630,11 +630,14 @@ __device__ __forceinline__ Ellipse make_ellipse(float4 co, float mx, float my) {
     return e;
 }
 
-// x of the ellipse boundary at height y (right or left end of its chord)
+// x of the ellipse boundary at height y (right or left end of its chord).
+// The hardware square root (within 1 ulp, denormals may flush to zero) is
+// far inside the padding that row_interval adds, 2^-6 px + 2^-11 of the
+// half extent, so the interval stays conservative.
 __device__ __forceinline__ float chord_end(const Ellipse& e, float y, float sign) {
     const float ay = fabsf(y);
     const float D = fmaxf(0.0f, e.det * (e.ye - ay) * (e.ye + ay));  // = a lim' - det y^2
-    return (-e.b * y + sign * sqrtf(D)) * e.inv_a;
+    return (-e.b * y + sign * __builtin_amdgcn_sqrtf(D)) * e.inv_a;
 }
 
 // The run of tile columns of tile row ty that the ellipse meets, clamped to
@@ -837,173 +840,34 @@ __device__ __forceinline__ uint64_t spread_rows(uint32_t rows) {  // bit y -> bi
     return m;
 }
 
-template <bool EXACT>
-__global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, const uint32_t* __restrict__ order,
-                                                   const uint2* __restrict__ rect, const uint32_t* __restrict__ base,
-                                                   uint4* __restrict__ coarse, const uint64_t* __restrict__ coarse_n,
-                                                   uint64_t coarse_cap, const float* __restrict__ means2D,
-                                                   const float4* __restrict__ conic_opacity) {
-    extern __shared__ uint32_t nextpos[];  // ng running slots, then (EXACT) the row runs of 16 Gaussians
-    __shared__ uint32_t s_roff[EXACT ? 16 : 1];
-    __shared__ uint2 s_rect[EXACT ? 16 : 1];
-    __shared__ Ellipse s_ell[EXACT ? 16 : 1];
-    if (coarse_n[0] > coarse_cap) return;  // the coarse lists do not fit: nothing is written
-    const int ng = GX * GY;
-    uint32_t* rowiv = nextpos + ng;
-    const int lane = threadIdx.x;
-    const int c = blockIdx.x;
-    const uint32_t* bc = base + (int64_t)c * ng;
-    for (int t = lane; t < ng; t += 64) nextpos[t] = bc[t];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int m = 0; m < CHUNK / 64; ++m) {
-        const int64_t k0 = (int64_t)c * CHUNK + m * 64;
-        if (k0 >= P) break;
-        const int64_t k = k0 + lane;
-        uint32_t g = 0, n = 0;
-        uint2 rr = make_uint2(1u, 0u);
-        int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
-        Ellipse el{};
-        if (k < P) {
-            g = order[k];
-            rr = rect[g];
-            if (group_rect(rr, x0, y0, x1, y1)) n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
-            if (EXACT && n) el = make_ellipse(conic_opacity[g], means2D[2 * g], means2D[2 * g + 1]);
-        }
-        const int cntk = (int)((P - k0) < 64 ? (P - k0) : 64);
-        uint32_t roff = 0;  // EXACT: where this lane's Gaussian's row runs start in rowiv
-        for (int i = 0; i < cntk; ++i) {
-            if (EXACT && (i & 15) == 0) {
-                // the column run of every tile row of Gaussians i .. i + 15, one
-                // (Gaussian, row) pair per lane, into rowiv
-                const bool mine = lane >= i && lane < i + 16 && el.proper;
-                const uint32_t nr = mine ? (rr.y >> 16) - (rr.x >> 16) + 1u : 0u;
-                uint32_t incl = nr;
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint32_t y = __shfl_up(incl, off, 64);
-                    if (lane >= off) incl += y;
-                }
-                const uint32_t nrows = __builtin_amdgcn_readlane(incl, 63);
-                roff = incl - nr;
-                if (lane >= i && lane < i + 16) {
-                    const int kk = lane - i;
-                    s_roff[kk] = roff;  // lanes past the Gaussians have nr = 0: offset nrows
-                    s_rect[kk] = rr;
-                    s_ell[kk] = el;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                for (uint32_t pr = lane; pr < nrows; pr += 64) {
-                    int kk = 0;  // the last of the 16 whose rows start at or before pr (s_roff[0] = 0)
-#pragma unroll
-                    for (int step = 8; step > 0; step >>= 1)
-                        if (s_roff[kk + step] <= pr) kk += step;  // kk + step <= 15
-                    const uint2 rk = s_rect[kk];
-                    const int row = (int)(rk.x >> 16) + (int)(pr - s_roff[kk]);
-                    rowiv[pr] = row_interval(s_ell[kk], row, (int)(rk.x & 0xFFFFu), (int)(rk.y & 0xFFFFu));
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-            const uint32_t ni = __builtin_amdgcn_readlane(n, i);
-            if (ni == 0) continue;
-            const uint32_t gi = __builtin_amdgcn_readlane(g, i);
-            const int xi = __builtin_amdgcn_readlane(x0, i), yi = __builtin_amdgcn_readlane(y0, i);
-            const int wi = __builtin_amdgcn_readlane(x1, i) - xi + 1;
-            const uint32_t ra = __builtin_amdgcn_readlane(rr.x, i), rb = __builtin_amdgcn_readlane(rr.y, i);
-            const int tx0 = (int)(ra & 0xFFFF), ty0 = (int)(ra >> 16), tx1 = (int)(rb & 0xFFFF), ty1 = (int)(rb >> 16);
-            const bool exact_i = EXACT && __builtin_amdgcn_readlane((int)el.proper, i) != 0;
-            const uint32_t roff_i = EXACT ? __builtin_amdgcn_readlane(roff, i) : 0u;  // row ty0's run in rowiv
-            const float inv_w = 1.0f / (float)wi;
-            if (EXACT && exact_i && ni <= 8) {
-                // at most 8 groups: one (group, row) pair per lane, lanes 8 k ..
-                // 8 k + 7 holding the rows of group k; their column bits are
-                // OR-combined over the 8 lanes and lane 8 k writes the entry
-                const uint32_t jg = (uint32_t)lane >> 3;
-                const int rr8 = lane & 7;
-                uint32_t mlo = 0u, mhi = 0u;
-                int t = 0;
-                if (jg < ni) {
-                    int q = (int)((float)jg * inv_w);
-                    int r = (int)jg - q * wi;
-                    if (r >= wi) { ++q; r -= wi; }
-                    if (r < 0) { --q; r += wi; }
-                    const int gx = xi + r, gy = yi + q;
-                    t = gy * GX + gx;
-                    const int bx = gx * GTILES, row = gy * GTILES + rr8;
-                    if (row >= ty0 && row <= ty1) {
-                        const uint32_t iv = rowiv[roff_i + (uint32_t)(row - ty0)];
-                        const int c0 = max((int)(iv & 0xFFFFu) - bx, 0), c1 = min((int)(iv >> 16) - bx, GTILES);
-                        const uint32_t bits = c0 < c1 ? (((1u << c1) - 1u) & ~((1u << c0) - 1u)) : 0u;
-                        if (rr8 < 4) mlo = bits << (GTILES * rr8);
-                        else mhi = bits << (GTILES * (rr8 - 4));
-                    }
-                }
-#pragma unroll
-                for (int off = 1; off < 8; off <<= 1) {
-                    mlo |= (uint32_t)__shfl_xor((int)mlo, off, 64);
-                    mhi |= (uint32_t)__shfl_xor((int)mhi, off, 64);
-                }
-                if (jg < ni && rr8 == 0) {
-                    const uint32_t pos = nextpos[t];
-                    nextpos[t] = pos + 1;
-                    coarse[pos] = make_uint4(gi, mlo, mhi, 0u);
-                }
-                continue;
-            }
-            for (uint32_t j = lane; j < ni; j += 64) {
-                int q = (int)((float)j * inv_w);
-                int r = (int)j - q * wi;
-                if (r >= wi) { ++q; r -= wi; }
-                if (r < 0) { --q; r += wi; }
-                const int gx = xi + r, gy = yi + q;
-                const int t = gy * GX + gx;
-                // the tile rectangle is clamped to the image, so the mask
-                // only holds tiles inside it
-                const int bx = gx * GTILES, by = gy * GTILES;
-                const int cl = max(tx0 - bx, 0), ch = min(tx1 - bx + 1, GTILES);
-                const int rl = max(ty0 - by, 0), rh = min(ty1 - by + 1, GTILES);
-                const uint32_t cols = ((1u << ch) - 1u) & ~((1u << cl) - 1u);
-                const uint32_t rows = ((1u << rh) - 1u) & ~((1u << rl) - 1u);
-                uint64_t mask = (uint64_t)cols * spread_rows(rows);
-                if (EXACT && exact_i) {
-                    mask = 0u;
-                    for (int r = rl; r < rh; ++r) {
-                        const uint32_t iv = rowiv[roff_i + (uint32_t)(by + r - ty0)];
-                        const int c0 = max((int)(iv & 0xFFFFu) - bx, 0), c1 = min((int)(iv >> 16) - bx, GTILES);
-                        if (c0 < c1) mask |= (uint64_t)(((1u << c1) - 1u) & ~((1u << c0) - 1u)) << (GTILES * r);
-                    }
-                }
-                const uint32_t pos = nextpos[t];
-                nextpos[t] = pos + 1;
-                coarse[pos] = make_uint4(gi, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
-            }
-        }
-    }
-}
+// The chunk's (Gaussian, group) pairs are flattened over the lanes, 64 at a
+// time in (Gaussian, group) order.  A pair's slot is its group's running
+// position plus the number of lower lanes of the batch with the same group
+// id (found with one ballot per bit of the id), and the last such lane
+// advances the running position, so a group receives the chunk's Gaussians in
+// depth order.  EXACT: the run of tile columns that a proper ellipse meets on
+// each tile row of its rectangle (row_interval) is evaluated once, one
+// (Gaussian, row) per lane, into an LDS buffer of EMIT_ROWS rows; the pairs
+// OR their group's rows from it.  The chunk is taken in windows of
+// consecutive Gaussians whose rows fit the buffer; the host admits at most
+// EMIT_ROWS tile rows, so every Gaussian's rows fit one window.
+constexpr int EMIT_ROWS = 1024;
 
-// The square rule's emit with the chunk's (Gaussian, group) pairs flattened
-// over the lanes, 64 at a time in (Gaussian, group) order -- the order in
-// which the one-Gaussian-at-a-time emit above writes them.  A pair's slot is
-// its group's running position plus the number of lower lanes of the batch
-// with the same group id (found with one ballot per bit of the id), and the
-// last such lane advances the running position.  Same entries at the same
-// slots, with a lane per pair instead of a loop over the Gaussians.
-__global__ __launch_bounds__(64) void k_chunk_emit_flat(int64_t P, int GX, int GY, int gbits,
-                                                        const uint32_t* __restrict__ order,
-                                                        const uint2* __restrict__ rect,
-                                                        const uint32_t* __restrict__ base, uint4* __restrict__ coarse,
-                                                        const uint64_t* __restrict__ coarse_n, uint64_t coarse_cap) {
+template <bool EXACT>
+__global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, int gbits,
+                                                   const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
+                                                   const uint32_t* __restrict__ base, uint4* __restrict__ coarse,
+                                                   const uint64_t* __restrict__ coarse_n, uint64_t coarse_cap,
+                                                   const float* __restrict__ means2D,
+                                                   const float4* __restrict__ conic_opacity) {
     extern __shared__ uint32_t nextpos[];  // ng running slots
     __shared__ uint32_t s_off[65];         // first pair of each Gaussian of the chunk; s_off[64] = pairs
     __shared__ uint32_t s_g[64];
     __shared__ uint2 s_rr[64];
     __shared__ int4 s_grp[64];  // group rectangle: x0, y0, width, -
     __shared__ float s_invw[64];
+    __shared__ uint32_t s_roff[EXACT ? 65 : 1];  // first row of each Gaussian (0 rows: not proper)
+    __shared__ uint32_t s_rows[EXACT ? EMIT_ROWS : 1];
     if (coarse_n[0] > coarse_cap) return;  // the coarse lists do not fit: nothing is written
     static_assert(CHUNK == 64, "one Gaussian per lane");
     const int ng = GX * GY;
@@ -1033,56 +897,125 @@ __global__ __launch_bounds__(64) void k_chunk_emit_flat(int64_t P, int GX, int G
     s_rr[lane] = rr;
     s_grp[lane] = make_int4(x0, y0, x1 - x0 + 1, 0);
     s_invw[lane] = 1.0f / (float)(x1 - x0 + 1 > 0 ? x1 - x0 + 1 : 1);
+    Ellipse el{};  // EXACT: this lane's Gaussian; proper stays false for the square rule's mask
+    if (EXACT) {
+        if (n) el = make_ellipse(conic_opacity[g], means2D[2 * g], means2D[2 * g + 1]);
+        const uint32_t nr = el.proper ? (rr.y >> 16) - (rr.x >> 16) + 1u : 0u;
+        uint32_t ri = nr;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(ri, off, 64);
+            if (lane >= off) ri += y;
+        }
+        s_roff[lane] = ri - nr;
+        if (lane == 63) s_roff[64] = ri;
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (uint32_t p0 = 0; p0 < total; p0 += 64) {
-        const uint32_t p = p0 + lane;
-        const bool valid = p < total;
-        int i = 0;  // the pair's Gaussian: the last lane whose first pair is at or before p
+    int ga = 0;  // first Gaussian of the window
+    while (ga < 64) {
+        int gb = 64;
+        uint32_t rbase = 0, nw = 0;  // the window's first row and the rows held in s_rows
+        if (EXACT) {
+            rbase = __builtin_amdgcn_readfirstlane(s_roff[ga]);
+            // s_roff is nondecreasing: the Gaussians from ga whose rows end within the buffer are a run
+            const uint64_t fits = ballot(lane >= ga && s_roff[lane + 1] - rbase <= (uint32_t)EMIT_ROWS);
+            gb = max(ga + 1, ga + __builtin_popcountll(fits));
+            nw = min(__builtin_amdgcn_readfirstlane(s_roff[gb]) - rbase, (uint32_t)EMIT_ROWS);
+            for (uint32_t pr0 = 0; pr0 < nw; pr0 += 64) {  // every lane takes part in the shuffles
+                const uint32_t pr = pr0 + lane, rg = rbase + pr;
+                int kk = 0;  // the row's Gaussian: the last whose rows start at or before it
 #pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-            if (s_off[i + step] <= p) i += step;  // i + step <= 63
-        int t = 0;
-        uint64_t mask = 0;
-        if (valid) {
-            const int4 gr = s_grp[i];
-            const int wi = gr.z;
-            const int j = (int)(p - s_off[i]);
-            int q = (int)((float)j * s_invw[i]);
-            int r = j - q * wi;
-            if (r >= wi) { ++q; r -= wi; }
-            if (r < 0) { --q; r += wi; }
-            const int gx = gr.x + r, gy = gr.y + q;
-            t = gy * GX + gx;
-            const uint2 rk = s_rr[i];
-            const int tx0 = (int)(rk.x & 0xFFFF), ty0 = (int)(rk.x >> 16), tx1 = (int)(rk.y & 0xFFFF),
-                      ty1 = (int)(rk.y >> 16);
-            // the tile rectangle is clamped to the image, so the mask only
-            // holds tiles inside it
-            const int bx = gx * GTILES, by = gy * GTILES;
-            const int cl = max(tx0 - bx, 0), ch = min(tx1 - bx + 1, GTILES);
-            const int rl = max(ty0 - by, 0), rh = min(ty1 - by + 1, GTILES);
-            const uint32_t cols = ((1u << ch) - 1u) & ~((1u << cl) - 1u);
-            const uint32_t rows = ((1u << rh) - 1u) & ~((1u << rl) - 1u);
-            mask = (uint64_t)cols * spread_rows(rows);
+                for (int step = 32; step > 0; step >>= 1)
+                    if (s_roff[kk + step] <= rg) kk += step;  // kk + step <= 63
+                Ellipse ek{};  // lane kk's ellipse
+                ek.b = __shfl(el.b, kk, 64);
+                ek.inv_a = __shfl(el.inv_a, kk, 64);
+                ek.det = __shfl(el.det, kk, 64);
+                ek.xe = __shfl(el.xe, kk, 64);
+                ek.ye = __shfl(el.ye, kk, 64);
+                ek.yr = __shfl(el.yr, kk, 64);
+                ek.mx = __shfl(el.mx, kk, 64);
+                ek.my = __shfl(el.my, kk, 64);
+                const uint2 rk = s_rr[kk];
+                const int row = (int)(rk.x >> 16) + (int)(rg - s_roff[kk]);
+                if (pr < nw) s_rows[pr] = row_interval(ek, row, (int)(rk.x & 0xFFFFu), (int)(rk.y & 0xFFFFu));
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        uint64_t eq = ballot(valid);  // lanes of the batch with this lane's group id
-        for (int b = 0; b < gbits; ++b) {
-            const bool bit = ((t >> b) & 1) != 0;
-            const uint64_t m = ballot(bit);
-            eq &= bit ? m : ~m;
+        const uint32_t pa = __builtin_amdgcn_readfirstlane(s_off[ga]), pb = __builtin_amdgcn_readfirstlane(s_off[gb]);
+        for (uint32_t p0 = pa; p0 < pb; p0 += 64) {
+            const uint32_t p = p0 + lane;
+            const bool valid = p < pb;
+            int i = 0;  // the pair's Gaussian: the last lane whose first pair is at or before p
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+                if (s_off[i + step] <= p) i += step;  // i + step <= 63
+            int t = 0;
+            uint64_t mask = 0;
+            if (valid) {
+                const int4 gr = s_grp[i];
+                const int wi = gr.z;
+                const int j = (int)(p - s_off[i]);
+                int q = (int)((float)j * s_invw[i]);
+                int r = j - q * wi;
+                if (r >= wi) { ++q; r -= wi; }
+                if (r < 0) { --q; r += wi; }
+                const int gx = gr.x + r, gy = gr.y + q;
+                t = gy * GX + gx;
+                const uint2 rk = s_rr[i];
+                const int tx0 = (int)(rk.x & 0xFFFF), ty0 = (int)(rk.x >> 16), tx1 = (int)(rk.y & 0xFFFF),
+                          ty1 = (int)(rk.y >> 16);
+                // the tile rectangle is clamped to the image, so the mask only
+                // holds tiles inside it
+                const int bx = gx * GTILES, by = gy * GTILES;
+                const int cl = max(tx0 - bx, 0), ch = min(tx1 - bx + 1, GTILES);
+                const int rl = max(ty0 - by, 0), rh = min(ty1 - by + 1, GTILES);
+                const uint32_t cols = ((1u << ch) - 1u) & ~((1u << cl) - 1u);
+                const uint32_t rows = ((1u << rh) - 1u) & ~((1u << rl) - 1u);
+                mask = (uint64_t)cols * spread_rows(rows);
+                if (EXACT && s_roff[i + 1] > s_roff[i]) {  // a proper ellipse: its rows
+                    // s_rows index of group row rw (wraps below for rw < rl; clamped, then unused)
+                    const uint32_t r0 = s_roff[i] - rbase + (uint32_t)(by - ty0);
+                    uint32_t iv[GTILES];
+#pragma unroll
+                    for (int rw = 0; rw < GTILES; ++rw) iv[rw] = s_rows[min(r0 + (uint32_t)rw, EMIT_ROWS - 1u)];
+                    mask = 0u;
+#pragma unroll
+                    for (int rw = 0; rw < GTILES; ++rw) {
+                        const int c0 = max((int)(iv[rw] & 0xFFFFu) - bx, 0), c1 = min((int)(iv[rw] >> 16) - bx, GTILES);
+                        if (rw >= rl && rw < rh && c0 < c1)
+                            mask |= (uint64_t)(((1u << c1) - 1u) & ~((1u << c0) - 1u)) << (GTILES * rw);
+                    }
+                }
+            }
+            uint64_t eq = ballot(valid);  // lanes of the batch with this lane's group id
+            for (int b = 0; b < gbits; ++b) {
+                const bool bit = ((t >> b) & 1) != 0;
+                const uint64_t m = ballot(bit);
+                eq &= bit ? m : ~m;
+            }
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(eq >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)eq, 0u));
+            const uint32_t pos = valid ? nextpos[t] + rank : 0u;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (valid && rank + 1 == (uint32_t)__builtin_popcountll(eq)) nextpos[t] = pos + 1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (valid) coarse[pos] = make_uint4(s_g[i], (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
         }
-        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(eq >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)eq, 0u));
-        const uint32_t pos = valid ? nextpos[t] + rank : 0u;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (valid && rank + 1 == (uint32_t)__builtin_popcountll(eq)) nextpos[t] = pos + 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (valid) coarse[pos] = make_uint4(s_g[i], (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
+        if (EXACT) {  // the next window overwrites s_rows
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        ga = gb;
     }
 }
 
@@ -1407,8 +1340,8 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
     if (L.ng > MAX_GROUPS || (size_t)(L.GX + 1) * (L.GY + 1) * sizeof(int) > 65536 || TX > 65535 || TY > 65535)
         return fail(BGS_EUNSUPPORTED, "bgs_tile_lists: tile grid too large (over 8192 groups of 8x8 tiles); use "
                                       "bgs_bin + bgs_sort + bgs_ranges");
-    if (conic_opacity && sizeof(uint32_t) * ((size_t)L.ng + 16 * (size_t)TY) > 60000)
-        return fail(BGS_EUNSUPPORTED, "bgs_tile_lists_exact: tile grid too large for the exact rule");
+    if (conic_opacity && TY > EMIT_ROWS)
+        return fail(BGS_EUNSUPPORTED, "bgs_tile_lists_exact: images over 16384 pixels high are not supported");
     BGS_REQUIRE(ws && ws_bytes >= L.bytes, "bgs_tile_lists: workspace too small");
     const bool gather = max_per_tile && max_per_tile <= GATHER_MAX_K;
     if (gather && (int64_t)L.nt * max_per_tile > capacity)
@@ -1469,13 +1402,16 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(nbg)), dim3(256), 0, stream, L.C, L.ng, gstart, part, h);
     BGS_HIP(hipGetLastError());
-    if (conic_opacity)
-        hipLaunchKernelGGL(k_chunk_emit<true>, dim3(L.C), dim3(64), sizeof(uint32_t) * ((size_t)L.ng + 16 * TY), stream, P,
-                           L.GX, L.GY, order, rect, h, coarse, (const uint64_t*)mg, ccap, means2D, co4);
-    else
-        hipLaunchKernelGGL(k_chunk_emit_flat, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P, L.GX,
-                           L.GY, L.ng > 1 ? 32 - __builtin_clz((unsigned)(L.ng - 1)) : 0, order, rect, h, coarse,
-                           (const uint64_t*)mg, ccap);
+    {
+        const int gbits = L.ng > 1 ? 32 - __builtin_clz((unsigned)(L.ng - 1)) : 0;
+        if (conic_opacity)
+            hipLaunchKernelGGL(k_chunk_emit<true>, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P,
+                               L.GX, L.GY, gbits, order, rect, h, coarse, (const uint64_t*)mg, ccap, means2D, co4);
+        else
+            hipLaunchKernelGGL(k_chunk_emit<false>, dim3(L.C), dim3(64), sizeof(uint32_t) * (size_t)L.ng, stream, P,
+                               L.GX, L.GY, gbits, order, rect, h, coarse, (const uint64_t*)mg, ccap,
+                               (const float*)nullptr, (const float4*)nullptr);
+    }
     BGS_HIP(hipGetLastError());
     if (gather) {  // lists capped at a small K: gathered per tile at fixed slots
         hipLaunchKernelGGL(k_tile_gather, dim3((unsigned)((L.nt + 3) / 4)), dim3(256), 0, stream, TX, TY, L.GX,

@@ -96,6 +96,10 @@ def test_invalid_arguments_are_status_codes():
     assert st == B.BGS_EINVAL and b"null" in L.bgs_last_error()
     st = L.bgs_project_bwd_packed(ctypes.byref(cam), 1, p, p, p, p, -1, a64 + 16, p, p, a64, p, p, None)
     assert st == B.BGS_EINVAL and b"64-byte" in L.bgs_last_error()
+    # exact binning keeps a Gaussian's tile rows in one LDS buffer: at most 1024 tile rows
+    a16 = (ctypes.addressof(buf) + 15) // 16 * 16
+    st = L.bgs_tile_lists_exact(16, 16 * 1025, 16, 1, p, a16, p, p, p, p, 1, 0, p, p, p, 1 << 16, None)
+    assert st == B.BGS_EUNSUPPORTED and b"16384" in L.bgs_last_error()
     st = L.bgs_autotune(None, None, None, None, None, None, None, None, None, None, None, None, 0, None, None, None,
                         None, None, None)
     assert st == B.BGS_EINVAL

@@ -21,13 +21,18 @@ from workloads import scenes
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["tiny-300", "0", "sh3-tiny"]
+# "tall": 300 Gaussians about 50 tile rows high on a 48 x 1600 image, so that a
+# chunk's row intervals (64 Gaussians) overflow the emit's 1024-row buffer and
+# are taken in several windows
+CASES = ["tiny-300", "0", "sh3-tiny", "tall"]
 PX_SLACK = 1.0 / 64.0
 
 
 def _scene(name):
     if name == "sh3-tiny":
         return scenes.scene_tiny(n=200, seed=11, width=80, height=56, sh_degree=3)
+    if name == "tall":
+        return scenes.scene_tiny(n=300, seed=9, width=48, height=1600, log_scale_mu=2.4)
     return scenes.make(name)
 
 

@@ -6,7 +6,11 @@ One step = the whole path on one synthetic frame, inputs resident in HBM:
 (gradient buffers zeroed each step), issued without host synchronization
 (pipeline.FrameStep).  The timed steps replay the step captured once as a
 hipGraph; the same step launched eagerly, call by call, is timed too, and
-the replays must reproduce its outputs.  Per-stage times are medians over
+the replays must reproduce its outputs.  The W warm-up steps (default 30)
+come before each timed run of K steps, eager and replayed alike: a freshly
+captured graph's first 20-40 replays run about 5% slower than later ones
+(one-time costs after capture), so the timed steps are the steady state a
+training loop sees.  Per-stage times are medians over
 eager steps each queued behind a short GPU sleep (so the whole step is
 enqueued before it starts and the events see GPU time only).  By
 default the tile lists keep only the front-most K entries per tile, K picked
@@ -78,7 +82,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--scene", default="1", help="workload scene id (default: the imbalanced 1080p scene)")
     ap.add_argument("--variant", default="auto",
                     help="auto (bgs_autotune picks the forward and backward variants on this frame), or a fixed "

@@ -739,19 +739,29 @@ __global__ __launch_bounds__(256) void k_chunk_hist(int64_t P, int GX, int GY, c
     for (int t = threadIdx.x; t < ng; t += blockDim.x) hc[t] = (uint32_t)d[(t / GX) * W1 + (t % GX)];
 }
 
-// part[b][t] = sum of h[c][t] over the chunks c of block b
+// part[b][t] = sum of h[c][t] over the chunks c of block b.  Workgroup
+// (b, 64-column slice): wave w sums chunks c0 + 8 w .. c0 + 8 w + 7 of the
+// slice's 64 columns (coalesced rows), and the four partial sums meet in LDS.
+constexpr int PS_COLS = 64;
+
 __global__ __launch_bounds__(256) void k_part_sums(int C, int nt, const uint32_t* __restrict__ h,
                                                    uint32_t* __restrict__ part) {
-    const int nb = (C + PART - 1) / PART;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)nb * nt) return;
-    const int b = (int)(i / nt), t = (int)(i % nt);
-    const int c0 = b * PART, n = min(C - c0, PART);
-    uint32_t s = 0;
+    static_assert(PART == 4 * 8, "four waves of eight chunks");
+    __shared__ uint32_t s_sum[4][PS_COLS];
+    const int slices = (nt + PS_COLS - 1) / PS_COLS;
+    const int b = blockIdx.x / slices, t = (blockIdx.x % slices) * PS_COLS + (threadIdx.x & 63);
+    const int w = threadIdx.x >> 6;
+    const int c0 = b * PART + 8 * w, n = max(0, min(C - c0, 8));
+    uint32_t sum = 0;
+    if (t < nt) {
 #pragma unroll
-    for (int c = 0; c < PART; ++c)
-        if (c < n) s += h[(int64_t)(c0 + c) * nt + t];
-    part[i] = s;
+        for (int c = 0; c < 8; ++c)
+            if (c < n) sum += h[(int64_t)(c0 + c) * nt + t];
+    }
+    s_sum[w][threadIdx.x & 63] = sum;
+    __syncthreads();
+    if (w == 0 && t < nt)
+        part[(int64_t)b * nt + t] = sum + s_sum[1][threadIdx.x] + s_sum[2][threadIdx.x] + s_sum[3][threadIdx.x];
 }
 
 // exclusive scan of part[.][t] over the nb blocks, one wave per column t;
@@ -1388,7 +1398,8 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
                        L.GX, L.GY, order, rect, h);
     BGS_HIP(hipGetLastError());
     const int64_t nbg = (int64_t)L.nb * L.ng;
-    hipLaunchKernelGGL(k_part_sums, dim3(blocks_for(nbg)), dim3(256), 0, stream, L.C, L.ng, h, part);
+    hipLaunchKernelGGL(k_part_sums, dim3((unsigned)(L.nb * ((L.ng + PS_COLS - 1) / PS_COLS))), dim3(256), 0, stream,
+                       L.C, L.ng, h, part);
     BGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_part_scan, dim3((unsigned)((L.ng + 3) / 4)), dim3(256), 0, stream, L.nb, L.ng, part, gtotal);
     BGS_HIP(hipGetLastError());

@@ -1152,21 +1152,59 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(FrameArgs F0, BwdIO B0, const
 // queue builder and the kernel compute it from the same N.
 
 
-// Gradient terms of one (pixel, entry) pair added into the lane's ten sums.
-__device__ __forceinline__ void add_terms(float (&v)[10], float w, float dA, float G, float ga, bool unclamped,
-                                          float gC0, float gC1, float gC2, float gD, float dx, float dy,
-                                          float4 abc) {
+// Gradient terms of one (pixel, entry) pair added into the lane's ten sums,
+// in factored form.  With h = G dL/dalpha where alpha is not clamped (else
+// 0), the entry's terms at a pixel are dL/dopacity = h and, since dL/dpower =
+// o h, dL/dmean = o h (a dx + b dy, b dx + c dy) and dL/d(a, b, c) =
+// -o h (dx^2 / 2, dx dy, dy^2 / 2): all of them are o, a, b, c (the entry's)
+// times h, dx h, dy h, dx^2 h, dx dy h, dy^2 h, and dx is the same for the
+// four pixels of a lane.  So per pixel only h, dy h and dy^2 h are summed
+// (v[5], v[1], v[4]); finish_terms forms the dx moments once per entry
+// (v[0] = dx h, v[2] = dx^2 h, v[3] = dx dy h, summed over the lane's
+// pixels), and after the wave reduction slot_value applies the entry's
+// o, a, b, c to the totals.  v[6..9] are the colour and depth terms.
+__device__ __forceinline__ void add_terms(float (&v)[10], float w, float dA, float G, bool unclamped, float gC0,
+                                          float gC1, float gC2, float gD, float dy) {
     v[6] = __builtin_fmaf(w, gC0, v[6]);
     v[7] = __builtin_fmaf(w, gC1, v[7]);
     v[8] = __builtin_fmaf(w, gC2, v[8]);
     v[9] = __builtin_fmaf(w, gD, v[9]);
-    const float dP = unclamped ? ga * dA : 0.0f;  // dL/dpower
-    v[5] += unclamped ? G * dA : 0.0f;            // dL/dopacity
-    v[2] += -0.5f * dx * dx * dP;
-    v[3] += -dx * dy * dP;
-    v[4] += -0.5f * dy * dy * dP;
-    v[0] += (abc.x * dx + abc.y * dy) * dP;
-    v[1] += (abc.y * dx + abc.z * dy) * dP;
+    const float h = unclamped ? G * dA : 0.0f;
+    v[5] += h;
+    const float u = dy * h;
+    v[1] += u;
+    v[4] = __builtin_fmaf(u, dy, v[4]);
+}
+
+__device__ __forceinline__ void finish_terms(float (&v)[10], float dx) {
+    v[0] = dx * v[5];
+    v[2] = dx * v[0];
+    v[3] = dx * v[1];
+}
+
+// Per-lane coefficients of slot_value for the gradient slot the lane holds
+// after wave_reduce_scatter10 (slot 0 / 1 also need the total of the other,
+// which sits in the lane xor 4).
+struct SlotCoef {
+    float fa, fc, fo, f1, fb;
+};
+
+__device__ __forceinline__ SlotCoef slot_coef(int slot) {
+    switch (slot) {
+        case 0: return SlotCoef{1.0f, 0.0f, 0.0f, 0.0f, 1.0f};   // dL/du = o (a X + b Y)
+        case 1: return SlotCoef{0.0f, 1.0f, 0.0f, 0.0f, 1.0f};   // dL/dv = o (c Y + b X)
+        case 2: return SlotCoef{0.0f, 0.0f, -0.5f, 0.0f, 0.0f};  // dL/da = -o XX / 2
+        case 3: return SlotCoef{0.0f, 0.0f, -1.0f, 0.0f, 0.0f};  // dL/db = -o XY
+        case 4: return SlotCoef{0.0f, 0.0f, -0.5f, 0.0f, 0.0f};  // dL/dc = -o YY / 2
+        default: return SlotCoef{0.0f, 0.0f, 0.0f, 1.0f, 0.0f};  // opacity, colour, depth as summed
+    }
+}
+
+// The lane's gradient component from its reduced total e (all lanes active).
+__device__ __forceinline__ float slot_value(const SlotCoef& k, float e, float4 abc, float o) {
+    const float other = xor4(e);
+    const float ka = __builtin_fmaf(o, __builtin_fmaf(k.fa, abc.x, __builtin_fmaf(k.fc, abc.z, k.fo)), k.f1);
+    return __builtin_fmaf(ka, e, o * abc.y * k.fb * other);
 }
 
 // DET: instead of adding its per-entry totals to the gradients, the wave
@@ -1184,6 +1222,7 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
     const int len = (int)(__builtin_amdgcn_readfirstlane(F.ranges[2 * tile + 1]) - start);
     const GradLane GL = grad_lane(B, scatter10_slot(lane));
     const int dslot = scatter10_slot(lane);
+    const SlotCoef kc = slot_coef(dslot);
     float* const dpart = DET ? B.det_partials + (size_t)B.det_base[tile] * 10 + dslot : nullptr;
     // S[q]: dL/dC . (colour, depth accumulated behind the entry) + the
     // entry-independent part of dL/dalpha, as in k_bwd_pixel (lower part:
@@ -1290,12 +1329,14 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
                     const float dA = Tb * gc - inv * (S[q] - Pn);  // S[q] - Pn: the sum behind the entry
                     Pf[q] = Pn;
                     T[q] = contrib ? Tb - w : T[q];  // as the forward advances T
-                    add_terms(v, w, dA, G, ga, lane_bit(cm & ballot(ga <= ALPHA_MAX)), gC0[q], gC1[q], gC2[q],
-                              gD[q], dx, dy, abc);
+                    add_terms(v, w, dA, G, lane_bit(cm & ballot(ga <= ALPHA_MAX)), gC0[q], gC1[q], gC2[q], gD[q],
+                              dy);
                 }
                 if (!any) continue;
+                finish_terms(v, dx);
                 float tot;
                 wave_reduce_scatter10(v, lane, tot);
+                tot = slot_value(kc, tot, abc, co.w);
                 if (GL.base) unsafeAtomicAdd(GL.base + (size_t)__float_as_uint(xym.w) * GL.stride, tot);
             }
             wave_sync();
@@ -1367,12 +1408,13 @@ __device__ __forceinline__ void bwd_tile(const FrameArgs& F, const BwdIO& B, int
                 const float dA = Tb * gc - inv * S[q];
                 S[q] = __builtin_fmaf(gc, w, S[q]);
                 T[q] = contrib ? Tb : T[q];
-                add_terms(v, w, dA, G, ga, lane_bit(cm & ballot(ga <= ALPHA_MAX)), gC0[q], gC1[q], gC2[q], gD[q],
-                          dx, dy, abc);
+                add_terms(v, w, dA, G, lane_bit(cm & ballot(ga <= ALPHA_MAX)), gC0[q], gC1[q], gC2[q], gD[q], dy);
             }
             if (!any) continue;
+            finish_terms(v, dx);
             float tot;
             wave_reduce_scatter10(v, lane, tot);
+            tot = slot_value(kc, tot, abc, co.w);
             if (DET) {
                 if (dslot >= 0) dpart[(size_t)j * 10] = tot;
                 wrote |= 1ull << jj;

@@ -61,7 +61,8 @@ PEAK_VALU_TOPS = N_CU * LANES * CLOCK_GHZ / 1000.0  # 39.3 T lane-ops/s (fp32, n
 # derivations in the design notes)
 OPS_SKIP_TEST = 16.0          # per examined / walked (pixel, entry) pair: offset, power, exp, alpha, skip tests
 OPS_FWD_BLEND = 10.0          # more per forward entry that blends: T update, stop test, colour/depth/alpha sums
-OPS_BWD_CONTRIB = 41.0        # more per backward contributor: T recovery, colour/depth/opacity/conic/mean terms
+OPS_BWD_CONTRIB = 33.0        # more per backward contributor: T recovery, colour/depth/opacity terms, the
+                              # factored conic/mean sums
 
 
 def fwd_ops(examined: int, contributors: int) -> float:

@@ -50,16 +50,33 @@ __device__ __forceinline__ void ds_hist_store(uint32_t* s_hist, uint32_t* __rest
     if (threadIdx.x < DS_RADIX) cnt[(size_t)threadIdx.x * nb + blockIdx.x] = s_hist[threadIdx.x];
 }
 
+// Tile rectangles of the fused list builder, computed with the depth keys
+// (both are one pass over the projected Gaussians): rect[g] for every g, or
+// nothing when rect is null.  conic_opacity non-null: the exact ellipse-tile
+// rule.  gaussian_rect is defined with the binning rules below.
+struct RectArgs {
+    int TX, TY;
+    const float* means2D;
+    const int* radius;
+    const float4* conic_opacity;
+    uint2* rect;
+};
+
+template <bool EXACT>
+__device__ uint2 gaussian_rect(int64_t g, const RectArgs& R, bool listed);
+
 // Also stores the AND and the OR of the block's keys of listed Gaussians at
 // andor[2 b], [2 b + 1] (k_ds_colscan of the first pass folds them into the
 // mask of key bits that vary: a later pass whose byte does not vary keeps
 // the listed Gaussians' order; the others, which emit no pairs, may end up
 // anywhere).
+// RECT: 0 no rectangles, 1 the square rule's, 2 the exact rule's (R).
+template <int RECT>
 __global__ __launch_bounds__(DS_THREADS) void k_ds_keys(int64_t P, const float* __restrict__ depth,
                                                         const uint32_t* __restrict__ tiles_touched,
                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ ids,
                                                         uint32_t* __restrict__ cnt, int nb,
-                                                        uint32_t* __restrict__ andor) {
+                                                        uint32_t* __restrict__ andor, RectArgs R) {
     __shared__ uint32_t s_hist[DS_RADIX];
     __shared__ uint32_t s_and, s_or;
     if (threadIdx.x < DS_RADIX) s_hist[threadIdx.x] = 0u;
@@ -78,6 +95,7 @@ __global__ __launch_bounds__(DS_THREADS) void k_ds_keys(int64_t P, const float* 
             const uint32_t k = listed ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
             keys[i] = k;
             ids[i] = (uint32_t)i;
+            if (RECT) R.rect[i] = gaussian_rect<RECT == 2>(i, R, listed);
             atomicAdd(&s_hist[k & 0xFFu], 1u);
             if (listed) {  // a Gaussian with no pairs may sit anywhere in the order
                 a &= k;
@@ -301,13 +319,20 @@ static size_t depth_order_tot_words(int64_t P) { return DS_RADIX + 1 + 2 * (size
 // within one or two binades share it) is an identity pass and runs as a copy.
 static bgs_status depth_order(int64_t P, const float* depth, const uint32_t* tiles_touched, uint32_t* keys,
                               uint32_t* order, uint32_t* keys2, uint32_t* ids2, uint32_t* cnt, uint32_t* tot,
-                              hipStream_t stream) {
+                              const RectArgs& R, hipStream_t stream) {
     if (P == 0) return BGS_OK;
     const int nb = ds_blocks(P);
     uint32_t* andor = tot + DS_RADIX + 1;
     const uint32_t* vary = tot + DS_RADIX;
-    hipLaunchKernelGGL(k_ds_keys, dim3(nb), dim3(DS_THREADS), 0, stream, P, depth, tiles_touched, keys, order, cnt,
-                       nb, andor);
+    if (!R.rect)
+        hipLaunchKernelGGL(k_ds_keys<0>, dim3(nb), dim3(DS_THREADS), 0, stream, P, depth, tiles_touched, keys, order,
+                           cnt, nb, andor, R);
+    else if (R.conic_opacity)
+        hipLaunchKernelGGL(k_ds_keys<2>, dim3(nb), dim3(DS_THREADS), 0, stream, P, depth, tiles_touched, keys, order,
+                           cnt, nb, andor, R);
+    else
+        hipLaunchKernelGGL(k_ds_keys<1>, dim3(nb), dim3(DS_THREADS), 0, stream, P, depth, tiles_touched, keys, order,
+                           cnt, nb, andor, R);
     BGS_HIP(hipGetLastError());
     // (keys, order) -> (keys2, ids2) -> (keys, order) -> ... : four passes end in order
     uint32_t* kin = keys;
@@ -488,7 +513,7 @@ extern "C" bgs_status bgs_bin(int32_t width, int32_t height, int32_t tile, int64
     {
         const bgs_status st = depth_order(P, depth, tiles_touched, dkeys, order, dkeys2, ids,
                                           reinterpret_cast<uint32_t*>(w + L.dcnt),
-                                          reinterpret_cast<uint32_t*>(w + L.dtot), stream);
+                                          reinterpret_cast<uint32_t*>(w + L.dtot), RectArgs{}, stream);
         if (st != BGS_OK) return st;
     }
     hipLaunchKernelGGL(k_gather_counts, dim3(blocks_for(P)), dim3(256), 0, stream, P, order, tiles_touched, counts);
@@ -657,22 +682,17 @@ __device__ __forceinline__ uint32_t row_interval(const Ellipse& e, int ty, int t
     return (uint32_t)c0 | ((uint32_t)(c1 + 1) << 16);
 }
 
-// rect[g] = (x0 | y0 << 16, x1 | y1 << 16) of Gaussian g's tile rectangle;
-// an empty one has x0 > x1.  EXACT: cut to the tiles that the ellipse's
-// bounding box meets.
+// (x0 | y0 << 16, x1 | y1 << 16) of Gaussian g's tile rectangle; an empty
+// one has x0 > x1.  EXACT: cut to the tiles that the ellipse's bounding box
+// meets.
 template <bool EXACT>
-__global__ __launch_bounds__(256) void k_rects(int64_t P, int TX, int TY, const float* __restrict__ means2D,
-                                               const int* __restrict__ radius,
-                                               const uint32_t* __restrict__ tiles_touched,
-                                               const float4* __restrict__ conic_opacity, uint2* __restrict__ rect) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= P) return;
+__device__ uint2 gaussian_rect(int64_t g, const RectArgs& R, bool listed) {
     int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
-    const float mx = means2D[2 * g], my = means2D[2 * g + 1];
-    if (tiles_touched[g] == 0 || !tile_rect(mx, my, radius[g], TX, TY, x0, y0, x1, y1)) {
+    const float mx = R.means2D[2 * g], my = R.means2D[2 * g + 1];
+    if (!listed || !tile_rect(mx, my, R.radius[g], R.TX, R.TY, x0, y0, x1, y1)) {
         x0 = 1; y0 = 0; x1 = 0; y1 = 0;
     } else if (EXACT) {
-        const Ellipse e = make_ellipse(conic_opacity[g], mx, my);
+        const Ellipse e = make_ellipse(R.conic_opacity[g], mx, my);
         if (!e.blends) {
             x0 = 1; y0 = 0; x1 = 0; y1 = 0;
         } else if (e.proper) {
@@ -690,7 +710,7 @@ __global__ __launch_bounds__(256) void k_rects(int64_t P, int TX, int TY, const 
             }
         }
     }
-    rect[g] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
+    return make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
 }
 
 __device__ __forceinline__ bool group_rect(uint2 r, int& x0, int& y0, int& x1, int& y1) {
@@ -1379,20 +1399,15 @@ static bgs_status tile_lists(int32_t width, int32_t height, int32_t tile, int64_
         BGS_HIP(hipGetLastError());
         return BGS_OK;
     }
+    const auto* co4 = reinterpret_cast<const float4*>(conic_opacity);
     {
+        // the depth keys and every Gaussian's tile rectangle in one pass
+        const RectArgs R{TX, TY, means2D, radius, co4, rect};
         const bgs_status st = depth_order(P, depth, tiles_touched, dkeys, order, dkeys2, ids,
                                           reinterpret_cast<uint32_t*>(w + L.dcnt),
-                                          reinterpret_cast<uint32_t*>(w + L.dtot), stream);
+                                          reinterpret_cast<uint32_t*>(w + L.dtot), R, stream);
         if (st != BGS_OK) return st;
     }
-    const auto* co4 = reinterpret_cast<const float4*>(conic_opacity);
-    if (conic_opacity)
-        hipLaunchKernelGGL(k_rects<true>, dim3(blocks_for(P)), dim3(256), 0, stream, P, TX, TY, means2D, radius,
-                           tiles_touched, co4, rect);
-    else
-        hipLaunchKernelGGL(k_rects<false>, dim3(blocks_for(P)), dim3(256), 0, stream, P, TX, TY, means2D, radius,
-                           tiles_touched, co4, rect);
-    BGS_HIP(hipGetLastError());
     // coarse (group) lists
     hipLaunchKernelGGL(k_chunk_hist, dim3(L.C), dim3(CHUNK), sizeof(int) * (size_t)(L.GX + 1) * (L.GY + 1), stream, P,
                        L.GX, L.GY, order, rect, h);

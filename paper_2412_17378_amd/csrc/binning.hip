@@ -863,11 +863,14 @@ __global__ __launch_bounds__(256) void k_chunk_base(int C, int nt, const uint32_
 // kept in LDS.  An entry is (Gaussian id, 64-bit mask of the group's tiles
 // the Gaussian covers, bit (x mod 8) + 8 (y mod 8), 0), so the split into
 // tile lists streams the coarse lists without a gather.
-__device__ __forceinline__ uint64_t spread_rows(uint32_t rows) {  // bit y -> bit 8y
-    uint64_t m = 0;
-#pragma unroll
-    for (int y = 0; y < GTILES; ++y) m |= (uint64_t)((rows >> y) & 1u) << (GTILES * y);
-    return m;
+// The 64-bit mask of a group's tiles with columns cols (8 bits) in the rows
+// rl .. rh - 1 (0 <= rl < rh <= 8): cols copied into every row by one
+// multiply (no carries, cols < 256), then the rows outside cut away.
+__device__ __forceinline__ uint64_t rect_mask(uint32_t cols, int rl, int rh) {
+    const uint64_t every_row = (uint64_t)cols * 0x0101010101010101ull;
+    const uint64_t below_hi = rh >= GTILES ? ~0ull : (1ull << (GTILES * rh)) - 1ull;
+    const uint64_t below_lo = (1ull << (GTILES * rl)) - 1ull;
+    return every_row & below_hi & ~below_lo;
 }
 
 // The chunk's (Gaussian, group) pairs are flattened over the lanes, 64 at a
@@ -1005,8 +1008,7 @@ __global__ __launch_bounds__(64) void k_chunk_emit(int64_t P, int GX, int GY, in
                 const int cl = max(tx0 - bx, 0), ch = min(tx1 - bx + 1, GTILES);
                 const int rl = max(ty0 - by, 0), rh = min(ty1 - by + 1, GTILES);
                 const uint32_t cols = ((1u << ch) - 1u) & ~((1u << cl) - 1u);
-                const uint32_t rows = ((1u << rh) - 1u) & ~((1u << rl) - 1u);
-                mask = (uint64_t)cols * spread_rows(rows);
+                mask = rect_mask(cols, rl, rh);
                 if (EXACT && s_roff[i + 1] > s_roff[i]) {  // a proper ellipse: its rows
                     // s_rows index of group row rw (wraps below for rw < rl; clamped, then unused)
                     const uint32_t r0 = s_roff[i] - rbase + (uint32_t)(by - ty0);

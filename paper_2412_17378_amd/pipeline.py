@@ -364,7 +364,10 @@ class FrameStep:
     doubles it until a capped step runs without overflow.  With a cap, a
     step's outputs equal the uncapped step's unless overflowed() (a host
     read) reports that a pixel ran off a capped list; the caller then
-    rebuilds with set_list_cap (larger K, or None) and runs the step again."""
+    rebuilds with set_list_cap (larger K, or None) and runs the step again.
+    The report covers every step since the cap was set or clear_overflow()
+    was called (the flag is not cleared per step), so checking every few
+    steps misses none."""
 
     def __init__(self, cam, params: dict, sh_degree: int, dL_dcolor, fcfg: B.RenderCfg, bcfg: B.RenderCfg,
                  binning: str = "square", headroom: float = 1.25, list_cap=None, poison_outputs: bool = False,
@@ -459,9 +462,14 @@ class FrameStep:
         self.overflow.zero_()
 
     def overflowed(self) -> bool:
-        """Whether a pixel of the last step ran off a capped list (reads the
-        device; synchronizes).  Always False with whole lists."""
+        """Whether a pixel ran off a capped list in a step since the cap was
+        set or clear_overflow() was called (reads the device; synchronizes).
+        Always False with whole lists."""
         return bool(self.list_cap) and bool(self.overflow.item())
+
+    def clear_overflow(self):
+        """Clear the overflow report (on the current stream)."""
+        self.overflow.zero_()
 
     def _alloc_lists(self, cap):
         dev = self.dL_dcolor.device
@@ -488,8 +496,6 @@ class FrameStep:
         (gradients zeroed), after the backward."""
         mark = mark or (lambda i: None)
         mark(0)
-        if self.list_cap:
-            self.overflow.zero_()
         self._project()
         mark(1)
         self._lists()

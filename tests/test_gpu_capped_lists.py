@@ -210,6 +210,10 @@ def test_frame_step_capped(name):
     capped.set_list_cap(8)
     capped.run()
     assert capped.overflowed()
+    capped.run()
+    assert capped.overflowed()  # the report holds until cleared
+    capped.clear_overflow()
+    assert not capped.overflowed()
     capped.set_list_cap(None)
     capped.run()
     assert not capped.overflowed() and capped.n_pairs() == M

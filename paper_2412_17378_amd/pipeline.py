@@ -509,7 +509,10 @@ class FrameStep:
         B.bgs_render_fwd(self.frame, self.fcfg_ready, f["color"], f["alpha"], f["depth"], f["final_T"],
                          f["n_contrib"], self.rws)
         mark(4)
-        torch._foreach_zero_(self._grad_list)
+        if len(self._grad_list) == 1:  # the gradient records: one plain fill
+            self._grad_list[0].zero_()
+        else:
+            torch._foreach_zero_(self._grad_list)
         if self.bcfg.variant not in (B.STATIC, B.STATIC_WAVE):
             B.bgs_queue_build(self.frame, self.bcfg, f["n_contrib"], self.rws)
         mark(5)
